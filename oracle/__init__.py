@@ -1,0 +1,387 @@
+"""ctypes front-end of the CPU oracle (``oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke``
+and by the CPU-baseline leg of ``bench.py``.  The product package never
+imports it.  The oracle is a plain, slow CPU implementation of transient path
+tracing written from the paper (arXiv 2510.25660, Sec. 3 and Sec. 4); see the
+header of ``oracle.c`` for what each part follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SRC_PATH = os.path.join(_HERE, "oracle.c")
+
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-pthread", "-std=gnu99"]
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (FP contraction off, no fast-math)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, SRC_PATH, "-lm"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class _Scene(C.Structure):
+    _fields_ = [
+        ("n_tris", C.c_int),
+        ("tri", C.POINTER(C.c_float)),
+        ("mat", C.POINTER(C.c_uint8)),
+        ("albedo", C.POINTER(C.c_float)),
+        ("roughness", C.POINTER(C.c_float)),
+        ("light_pos", C.c_float * 3),
+        ("light_intensity", C.c_float),
+        ("sensor", C.c_int),
+        ("cam_origin", C.c_float * 3),
+        ("cam_right", C.c_float * 3),
+        ("cam_up", C.c_float * 3),
+        ("cam_fwd", C.c_float * 3),
+        ("tan_x", C.c_float),
+        ("tan_y", C.c_float),
+        ("width", C.c_int),
+        ("height", C.c_int),
+        ("scan_points", C.POINTER(C.c_float)),
+        ("wall_normal", C.c_float * 3),
+        ("wall_albedo", C.c_float),
+        ("laser_power", C.c_float),
+        ("sigma_t", C.c_float),
+        ("medium_albedo", C.c_float),
+        ("n_bins", C.c_int),
+        ("bin_width", C.c_float),
+        ("bin_start", C.c_float),
+        ("camera_unwarp", C.c_int),
+    ]
+
+
+class _Render(C.Structure):
+    _fields_ = [
+        ("spp", C.c_int),
+        ("sample_offset", C.c_uint32),
+        ("max_depth", C.c_int),
+        ("seed", C.c_uint64),
+        ("stream_id", C.c_uint32),
+        ("pixel_centre", C.c_int),
+        ("frozen_proposal", C.c_int),
+        ("albedo", C.POINTER(C.c_float)),
+        ("roughness", C.POINTER(C.c_float)),
+    ]
+
+
+class _Vertex(C.Structure):
+    _fields_ = [
+        ("tri", C.c_int), ("has_c", C.c_int), ("has_cont", C.c_int), ("bin", C.c_int),
+        ("c", C.c_float), ("opl_c", C.c_float),
+        ("dn_alb", C.c_double), ("dn_rough", C.c_double), ("dc_alb", C.c_double), ("dc_rough", C.c_double),
+    ]
+
+
+class _Path(C.Structure):
+    _fields_ = [("n_vert", C.c_int), ("v", _Vertex * 64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        fp = C.POINTER(C.c_float)
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int32)
+        up = C.POINTER(C.c_uint32)
+        L.orc_prepare.restype = C.c_void_p
+        L.orc_prepare.argtypes = [C.POINTER(_Scene)]
+        L.orc_release.argtypes = [C.c_void_p]
+        L.orc_pad.restype = C.c_float
+        L.orc_pad.argtypes = [C.c_void_p]
+        L.orc_trace_path.argtypes = [C.c_void_p, C.POINTER(_Render), C.c_uint32, C.c_uint32, C.POINTER(_Path)]
+        L.orc_render_film.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, dp, dp, dp, C.c_int]
+        L.orc_backward.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, fp, dp, dp, dp, C.c_int]
+        L.orc_closest_hit.argtypes = [C.c_void_p, fp, fp, C.c_int, C.c_int, fp, ip]
+        L.orc_philox_n.argtypes = [C.c_int64, up, up, up]
+        L.orc_sincos2pi_n.argtypes = [C.c_int64, fp, fp, fp]
+        L.orc_log1m_n.argtypes = [C.c_int64, fp, fp]
+        L.orc_ggx_f.restype = C.c_float
+        L.orc_ggx_f.argtypes = [fp, fp, C.c_float, C.c_float]
+        L.orc_ggx_pdf.restype = C.c_float
+        L.orc_ggx_pdf.argtypes = [fp, fp, C.c_float]
+        L.orc_ggx_sample.argtypes = [fp, C.c_float, C.c_float, C.c_float, fp]
+        L.orc_ggx_dlogf_dalpha.restype = C.c_double
+        L.orc_ggx_dlogf_dalpha.argtypes = [fp, fp, C.c_double]
+        L.orc_cosine_sample.argtypes = [C.c_float, C.c_float, fp]
+        L.orc_ggx_eval_n.argtypes = [C.c_int64, fp, fp, fp, fp, fp, fp]
+        L.orc_ggx_sample_n.argtypes = [C.c_int64, fp, fp, fp, fp, C.c_int, fp, fp, fp, fp]
+        L.orc_cosine_sample_n.argtypes = [C.c_int64, fp, fp, fp]
+        _lib = L
+    return _lib
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def _f3(v):
+    return (C.c_float * 3)(*[float(x) for x in v])
+
+
+# --------------------------------------------------------------------------
+# unit functions
+# --------------------------------------------------------------------------
+def philox(ctr: np.ndarray, key: np.ndarray) -> np.ndarray:
+    ctr = np.ascontiguousarray(ctr, np.uint32).reshape(-1, 4)
+    key = np.ascontiguousarray(key, np.uint32).reshape(-1, 2)
+    out = np.empty_like(ctr)
+    P = C.POINTER(C.c_uint32)
+    lib().orc_philox_n(len(ctr), ctr.ctypes.data_as(P), key.ctypes.data_as(P), out.ctypes.data_as(P))
+    return out
+
+
+def sincos2pi(u: np.ndarray):
+    u = np.ascontiguousarray(u, np.float32)
+    s = np.empty_like(u)
+    c = np.empty_like(u)
+    lib().orc_sincos2pi_n(u.size, _fptr(u), _fptr(s), _fptr(c))
+    return s, c
+
+
+def log1m(u: np.ndarray) -> np.ndarray:
+    u = np.ascontiguousarray(u, np.float32)
+    out = np.empty_like(u)
+    lib().orc_log1m_n(u.size, _fptr(u), _fptr(out))
+    return out
+
+
+def _f32c(a, n=None):
+    a = np.asarray(a, np.float32)
+    if n is not None and a.ndim == 0:
+        a = np.full(n, a, np.float32)
+    return np.ascontiguousarray(a)
+
+
+def ggx_eval_n(wo, wi, alpha, F):
+    """Vectorised GGX f and visible-normal pdf (local frame)."""
+    wo = _f32c(wo).reshape(-1, 3)
+    wi = _f32c(wi).reshape(-1, 3)
+    n = len(wo)
+    alpha = _f32c(alpha, n)
+    F = _f32c(F, n)
+    f = np.empty(n, np.float32)
+    p = np.empty(n, np.float32)
+    lib().orc_ggx_eval_n(n, _fptr(wo), _fptr(wi), _fptr(alpha), _fptr(F), _fptr(f), _fptr(p))
+    return f, p
+
+
+def ggx_sample_n(wo, alpha, F, u0, u1, alpha_s=None, frozen=False):
+    """Vectorised visible-normal sample: (wi [n,3], weight [n])."""
+    wo = _f32c(wo).reshape(-1, 3)
+    n = len(wo)
+    alpha = _f32c(alpha, n)
+    alpha_s = alpha if alpha_s is None else _f32c(alpha_s, n)
+    F = _f32c(F, n)
+    u0 = _f32c(u0, n)
+    u1 = _f32c(u1, n)
+    wi = np.empty((n, 3), np.float32)
+    w = np.empty(n, np.float32)
+    lib().orc_ggx_sample_n(n, _fptr(wo), _fptr(alpha), _fptr(alpha_s), _fptr(F), int(bool(frozen)),
+                           _fptr(u0), _fptr(u1), _fptr(wi), _fptr(w))
+    return wi, w
+
+
+def cosine_sample_n(u0, u1):
+    u0 = _f32c(u0)
+    u1 = _f32c(u1)
+    out = np.empty((len(u0), 3), np.float32)
+    lib().orc_cosine_sample_n(len(u0), _fptr(u0), _fptr(u1), _fptr(out))
+    return out
+
+
+def ggx_f(wo, wi, alpha, F):
+    return lib().orc_ggx_f(_f3(wo), _f3(wi), float(alpha), float(F))
+
+
+def ggx_pdf(wo, wi, alpha):
+    return lib().orc_ggx_pdf(_f3(wo), _f3(wi), float(alpha))
+
+
+def ggx_sample(wo, alpha, u0, u1):
+    out = (C.c_float * 3)()
+    lib().orc_ggx_sample(_f3(wo), float(alpha), float(u0), float(u1), out)
+    return np.array(out[:], np.float32)
+
+
+def ggx_dlogf_dalpha(wo, wi, alpha):
+    return lib().orc_ggx_dlogf_dalpha(_f3(wo), _f3(wi), float(alpha))
+
+
+def cosine_sample(u0, u1):
+    out = (C.c_float * 3)()
+    lib().orc_cosine_sample(float(u0), float(u1), out)
+    return np.array(out[:], np.float32)
+
+
+# --------------------------------------------------------------------------
+# scenes and renders
+# --------------------------------------------------------------------------
+class Oracle:
+    """A prepared scene.  ``scene`` is a ``paper_2510_25660_amd.scenes.Scene``
+    (or anything with the same fields)."""
+
+    def __init__(self, scene):
+        self.scene = scene
+        self._tri = scene.triangles()
+        self._mat = np.ascontiguousarray(scene.mat_type, np.uint8)
+        self._alb = np.ascontiguousarray(scene.albedo, np.float32)
+        self._rough = np.ascontiguousarray(scene.roughness, np.float32)
+        self._scan = (np.ascontiguousarray(scene.scan_points, np.float32)
+                      if scene.scan_points is not None else None)
+        s = _Scene()
+        s.n_tris = scene.n_tris
+        s.tri = _fptr(self._tri)
+        s.mat = self._mat.ctypes.data_as(C.POINTER(C.c_uint8))
+        s.albedo = _fptr(self._alb)
+        s.roughness = _fptr(self._rough)
+        s.light_pos = _f3(scene.light_pos)
+        s.light_intensity = scene.light_intensity
+        s.sensor = int(scene.sensor)
+        s.cam_origin = _f3(scene.cam_origin)
+        s.cam_right = _f3(scene.cam_right)
+        s.cam_up = _f3(scene.cam_up)
+        s.cam_fwd = _f3(scene.cam_fwd)
+        s.tan_x = scene.tan_x
+        s.tan_y = scene.tan_y
+        s.width = scene.width
+        s.height = scene.height
+        s.scan_points = _fptr(self._scan) if self._scan is not None else None
+        s.wall_normal = _f3(scene.wall_normal)
+        s.wall_albedo = scene.wall_albedo
+        s.laser_power = scene.laser_power
+        s.sigma_t = scene.sigma_t
+        s.medium_albedo = scene.medium_albedo
+        s.n_bins = scene.n_bins
+        s.bin_width = scene.bin_width
+        s.bin_start = scene.bin_start
+        s.camera_unwarp = int(bool(scene.camera_unwarp))
+        self._s = s
+        self._h = lib().orc_prepare(C.byref(s))
+        if not self._h:
+            raise ValueError("oracle: invalid scene")
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.orc_release(self._h)
+            self._h = None
+
+    @property
+    def pad(self) -> float:
+        return lib().orc_pad(self._h)
+
+    def _render_desc(self, spp, seed, max_depth, sample_offset=0, stream_id=0, pixel_centre=False,
+                     frozen=False, albedo=None, roughness=None):
+        r = _Render()
+        r.spp = int(spp)
+        r.sample_offset = int(sample_offset)
+        r.max_depth = int(max_depth)
+        r.seed = int(seed)
+        r.stream_id = int(stream_id)
+        r.pixel_centre = int(bool(pixel_centre))
+        r.frozen_proposal = int(bool(frozen))
+        keep = []
+        if albedo is not None:
+            a = np.ascontiguousarray(albedo, np.float32)
+            keep.append(a)
+            r.albedo = _fptr(a)
+        if roughness is not None:
+            g = np.ascontiguousarray(roughness, np.float32)
+            keep.append(g)
+            r.roughness = _fptr(g)
+        return r, keep
+
+    def render(self, spp=None, seed=None, max_depth=None, pixels: Optional[Sequence[int]] = None,
+               threads: int = 0, **kw):
+        """Returns (film [n_pix, T], steady [n_pix], oow [n_pix]) in float64 for
+        the listed pixels (all pixels by default)."""
+        sc = self.scene
+        spp = sc.spp if spp is None else spp
+        seed = sc.seed if seed is None else seed
+        max_depth = sc.max_depth if max_depth is None else max_depth
+        if pixels is None:
+            pixels = np.arange(sc.n_pixels, dtype=np.int32)
+        pixels = np.ascontiguousarray(pixels, np.int32)
+        n = len(pixels)
+        film = np.zeros((n, sc.n_bins), np.float64)
+        steady = np.zeros(n, np.float64)
+        oow = np.zeros(n, np.float64)
+        r, keep = self._render_desc(spp, seed, max_depth, **kw)
+        if threads <= 0:
+            threads = os.cpu_count() or 1
+        D = C.POINTER(C.c_double)
+        rc = lib().orc_render_film(self._h, C.byref(r), pixels.ctypes.data_as(C.POINTER(C.c_int32)), n,
+                                   film.ctypes.data_as(D), steady.ctypes.data_as(D), oow.ctypes.data_as(D),
+                                   int(threads))
+        if rc != 0:
+            raise ValueError("oracle render failed")
+        return film, steady, oow
+
+    def backward(self, grad_film: np.ndarray, spp=None, seed=None, max_depth=None, pixels=None,
+                 threads: int = 0, want_primal=False, **kw):
+        """Adjoint of the film w.r.t. per-triangle albedo and roughness.
+        grad_film is dL/dfilm in the full film layout [n_pixels, T]."""
+        sc = self.scene
+        spp = sc.spp if spp is None else spp
+        seed = sc.seed if seed is None else seed
+        max_depth = sc.max_depth if max_depth is None else max_depth
+        if pixels is None:
+            pixels = np.arange(sc.n_pixels, dtype=np.int32)
+        pixels = np.ascontiguousarray(pixels, np.int32)
+        g = np.ascontiguousarray(grad_film, np.float32).reshape(sc.n_pixels, sc.n_bins)
+        ga = np.zeros(sc.n_tris, np.float64)
+        gr = np.zeros(sc.n_tris, np.float64)
+        primal = np.zeros((len(pixels), sc.n_bins), np.float64) if want_primal else None
+        r, keep = self._render_desc(spp, seed, max_depth, **kw)
+        if threads <= 0:
+            threads = os.cpu_count() or 1
+        D = C.POINTER(C.c_double)
+        rc = lib().orc_backward(self._h, C.byref(r), pixels.ctypes.data_as(C.POINTER(C.c_int32)),
+                                len(pixels), _fptr(g), ga.ctypes.data_as(D), gr.ctypes.data_as(D),
+                                primal.ctypes.data_as(D) if primal is not None else None, int(threads))
+        if rc != 0:
+            raise ValueError("oracle backward failed")
+        if want_primal:
+            return ga, gr, primal
+        return ga, gr
+
+    def trace(self, pix: int, sample: int, spp_seed=None, max_depth=None, **kw):
+        """One path: list of dict per vertex."""
+        sc = self.scene
+        r, keep = self._render_desc(1, sc.seed if spp_seed is None else spp_seed,
+                                    sc.max_depth if max_depth is None else max_depth, **kw)
+        p = _Path()
+        n = lib().orc_trace_path(self._h, C.byref(r), int(pix), int(sample), C.byref(p))
+        out = []
+        for i in range(n):
+            v = p.v[i]
+            out.append(dict(tri=v.tri, has_c=v.has_c, has_cont=v.has_cont, bin=v.bin, c=v.c,
+                            opl_c=v.opl_c, dn_alb=v.dn_alb, dn_rough=v.dn_rough, dc_alb=v.dc_alb,
+                            dc_rough=v.dc_rough))
+        return out
+
+    def closest_hit(self, o, d, exclude=-1, use_bvh=True):
+        t = C.c_float(0)
+        k = C.c_int32(-1)
+        o = np.ascontiguousarray(o, np.float32)
+        d = np.ascontiguousarray(d, np.float32)
+        hit = lib().orc_closest_hit(self._h, _fptr(o), _fptr(d), int(exclude), int(bool(use_bvh)),
+                                    C.byref(t), C.byref(k))
+        return (t.value, k.value) if hit else (None, -1)
