@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Throughput of transient path tracing on one MI355X.
+
+One step = one transient render of the whole workload (every path sample
+traced with BVH traversal, BSDF sampling and next-event estimation, every
+contribution histogrammed into the pixel x time film), inputs resident in
+HBM.  Default workload: confocal NLOS, 64x64 scan points on a 1x1 m relay
+wall, 9,680-triangle hidden blob, 512 bins of 2.4 mm from 0.9 m, 4096 spp,
+3 bounces (16,777,216 path samples per step).
+
+Prints one JSON line: Mpath-samples/s, the backward/forward time ratio of
+the differentiable box-room workload, the roofline of the render kernel and
+the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T VALU lane-ops/s
+# (non-packed FP32 / INT32; an FMA counts as one op).
+PEAK_VALU_LANE_OPS = 256 * 64 * 2.4e9
+
+# Algorithmic lane-ops per counted event, from the operation counts of the
+# formulas the kernel evaluates (one add / mul / fma / min / max / compare /
+# select / divide / square root / integer op = 1); see the design doc.
+OPS_PER = {
+    "nodes": 46,          # two slab tests (12 fma, 12 min/max, 8 reductions, 6 compares) + ordering
+    "tris": 46,           # Moller-Trumbore + box-entry acceptance + closest/tie update
+    "rays": 15,           # reciprocal direction (3 guards, 3 divides) and o/d (3 mul)
+    "shadow_rays": 15,
+    "vertices": 170,      # hit point, NEE geometry, normal, frame, BSDF, bin, continuation, offsets
+    "draws": 112,         # Philox4x32-10 (10 rounds x 10 ops) + 4 uniform conversions
+    "contributions": 12,  # contribution product, transmittance/scale, LDS add
+}
+
+WORKLOADS = {
+    "confocal": dict(desc="confocal NLOS 64x64 scan, 9,682 tris (9,680-tri blob + 2-tri wall), 512 bins x 2.4 mm "
+                          "from 0.9 m, 4096 spp, 3 bounces, FP32"),
+    "box": dict(desc="box room 34 tris, 64x64 pinhole, 256 bins x 0.01 m from 0, 16 spp, max depth 4, FP32"),
+    "large": dict(desc="terrain + 49 displaced spheres 998,608 tris, fog sigma_t 0.1, 512x512, 1024 bins x 5 mm "
+                       "from 4.5 m, 64 spp, max depth 8, FP32"),
+}
+
+
+def make_scene(name):
+    from paper_2510_25660_amd import scenes
+    if name == "confocal":
+        return scenes.confocal_nlos()
+    if name == "box":
+        return scenes.box_scene()
+    if name == "large":
+        return scenes.large_scene()
+    raise ValueError(name)
+
+
+def time_launches(fn, steps, warmup):
+    """Per-launch durations (ms) with HIP events on the launch stream."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t_all0 = torch.cuda.Event(enable_timing=True)
+    t_all1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_all0.record(stream)
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    t_all1.record(stream)
+    torch.cuda.synchronize()
+    per = [a.elapsed_time(b) for a, b in ev]
+    return t_all0.elapsed_time(t_all1), per
+
+
+def backward_forward_ratio(tr, steps=5, warmup=1):
+    """Backward (path-replay adjoint) over forward time on the differentiable
+    box room (9,826 triangles, 64x64, 256 bins, 1024 spp, depth 4)."""
+    import torch
+    from paper_2510_25660_amd import scenes
+    sc = scenes.diff_scene()
+    with tr.upload(sc) as dev:
+        a = torch.from_numpy(sc.albedo).cuda()
+        r = torch.from_numpy(sc.roughness).cuda()
+        _, film = tr.render_transient(dev, albedo=a, roughness=r)
+        delta = torch.randn_like(film) * 1e-3
+        fwd_ms, _ = time_launches(lambda: tr.render_transient(dev, film=film, albedo=a, roughness=r), steps, warmup)
+        bwd_ms, _ = time_launches(lambda: tr.render_transient_backward(dev, delta, albedo=a, roughness=r), steps,
+                                  warmup)
+    return bwd_ms / fwd_ms, fwd_ms / steps, bwd_ms / steps
+
+
+def cpu_baseline(sc, max_threads=16):
+    """The oracle on the host cores over a bounded sample of the workload."""
+    import oracle
+    threads = max(1, min(max_threads, os.cpu_count() or 1))
+    O = oracle.Oracle(sc)
+    if sc.sensor == 1:
+        pix = np.arange(0, sc.n_pixels, 2, dtype=np.int32)
+        spp = sc.spp
+        sample = f"every other scan point ({len(pix)} of {sc.n_pixels}) at the full {spp} spp"
+    else:
+        pix = np.arange(0, sc.n_pixels, max(1, sc.n_pixels // 4096), dtype=np.int32)
+        spp = min(sc.spp, 16)
+        sample = f"{len(pix)} of {sc.n_pixels} pixels at {spp} spp"
+    t0 = time.perf_counter()
+    O.render(pixels=pix, spp=spp, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": round(len(pix) * spp / dt / 1e6, 4), "unit": "Mpath-samples/s", "cores": threads,
+            "kind": "oracle", "sample": sample, "seconds": round(dt, 2)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="confocal", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--tile-pixels", type=int, default=0)
+    ap.add_argument("--block-size", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the path shards by pixel tiles or sample ranges, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2510_25660_amd as tr
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    sc = make_scene(args.workload)
+    shape = dict(tile_pixels=args.tile_pixels, block_size=args.block_size)
+    with tr.upload(sc) as dev:
+        info = dev.info()
+        steady = torch.empty((sc.height, sc.width), device="cuda", dtype=torch.float32)
+        film = torch.empty((sc.height, sc.width, sc.n_bins), device="cuda", dtype=torch.float32)
+        step = lambda: tr.render_transient(dev, film=film, steady=steady, **shape)
+        total_ms, per = time_launches(step, args.steps, args.warmup)
+        _, _, counts = tr.render_transient_counted(dev, **shape)
+    paths = sc.n_pixels * sc.spp
+    ms_per_step = total_ms / args.steps
+    value = paths / (ms_per_step * 1e-3) / 1e6
+    launch_ms = float(np.mean(per))
+    ops = sum(OPS_PER[k] * v for k, v in counts.items())
+    achieved = ops / (launch_ms * 1e-3)
+    out = {
+        "metric": "Mpath-samples/s into transient film at 1 GPU; backward/forward time ratio",
+        "value": round(value, 3),
+        "unit": "Mpath-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded scene generators)",
+        "config": {"workload": WORKLOADS[args.workload]["desc"], "paths_per_step": paths,
+                   "triangles": info["n_triangles"], "bvh_depth": info["bvh_depth"]},
+        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(PEAK_VALU_LANE_OPS / 1e12, 2),
+                     "unit": "T lane-ops/s", "frac": round(achieved / PEAK_VALU_LANE_OPS, 4), "traffic": None,
+                     "kernel": "k_render", "launch_ms": round(launch_ms, 4),
+                     "ops_per_launch": int(ops), "counts": counts},
+    }
+    if not args.no_backward:
+        ratio, f_ms, b_ms = backward_forward_ratio(tr)
+        out["backward_forward_ratio"] = round(ratio, 3)
+        out["backward_forward_ms"] = [round(f_ms, 3), round(b_ms, 3)]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,239 @@
+/*
+ * trhip.h -- C ABI of the MI355X (gfx950) transient path tracer.
+ *
+ * The library renders time-resolved (transient) images by Monte Carlo path
+ * tracing, after arXiv 2510.25660 ("mitransient"), Sec. 3: light paths
+ * x0 -> ... -> xk (Eq. 1) are sampled with BSDF sampling and next-event
+ * estimation; the Monte Carlo estimator of Eq. 9 is histogrammed per pixel
+ * into time bins floor((tof - b_start) / b_width) (Sec. 3, "Path reuse and
+ * histogramming"), where tof is the summed segment length of the path
+ * (Eqs. 3-4, eta = 1, c = 1, so time is optical path length in metres) and
+ * emitters pulse at t = 0 (Eq. 5).  The steady image of the same paths is
+ * produced alongside (the (steady, transient) pair of the paper's Sec. 2
+ * example).  Backward mode (Sec. 4.4, Eqs. 15-17) propagates dL/dfilm to
+ * per-triangle albedo and roughness.
+ *
+ * Conventions for every entry point:
+ *  - every function returns trhip_status (0 = TRHIP_OK); no exception or
+ *    abort crosses the ABI; trhip_last_error() gives a thread-local message;
+ *  - arguments are validated on the host before any HIP call, so invalid
+ *    input is reported without touching the GPU;
+ *  - "host pointer" arguments are read during the call only; "device
+ *    pointer" arguments are HBM buffers owned by the caller, which must stay
+ *    valid until the work enqueued on `stream` has completed;
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream);
+ *    all device work is enqueued on it, asynchronously;
+ *  - the library never keeps a caller pointer after a call returns;
+ *  - a scene may be used by one stream at a time.
+ */
+#ifndef TRHIP_H
+#define TRHIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int trhip_status;
+
+enum {
+    TRHIP_OK = 0,
+    TRHIP_ERR_INVALID_ARG = 1, /* a bad pointer, size, enum or value */
+    TRHIP_ERR_OOM = 2,         /* a device or host allocation failed */
+    TRHIP_ERR_HIP = 3,         /* a HIP runtime call failed (message has the hipError_t) */
+    TRHIP_ERR_UNSUPPORTED = 4, /* a valid request this build cannot serve (e.g. LDS budget) */
+    TRHIP_ERR_BAD_HANDLE = 5   /* NULL, destroyed or foreign handle */
+};
+
+enum { TRHIP_SENSOR_PINHOLE = 0, TRHIP_SENSOR_CONFOCAL = 1 };
+enum { TRHIP_MAT_LAMBERT = 0, TRHIP_MAT_GGX = 1 };
+
+/* render flags */
+enum {
+    TRHIP_FLAG_PIXEL_CENTRE = 1u << 0,    /* no sub-pixel jitter (pinhole) */
+    TRHIP_FLAG_ACCUMULATE = 1u << 1,      /* add into the output buffers instead of overwriting */
+    TRHIP_FLAG_FROZEN_PROPOSAL = 1u << 2  /* GGX: sample with the scene's roughness, evaluate
+                                             with roughness_override (finite-difference mode) */
+};
+
+/*
+ * Scene description (all pointers are HOST pointers, read during
+ * trhip_scene_create only).
+ *
+ * Geometry: vertices float[n_vertices][3], indices uint32[n_triangles][3]
+ * (every index < n_vertices).  Triangles are two-sided.  Zero-area or
+ * non-finite triangles are rejected (TRHIP_ERR_INVALID_ARG).
+ * Materials per triangle: mat_type (TRHIP_MAT_*), albedo (Lambertian albedo,
+ * or the constant reflectance F of the GGX conductor), roughness (GGX alpha,
+ * unused for Lambertian).  Albedo must lie in (0, 1], roughness in (0, 1].
+ *
+ * Emitter: an isotropic point light of intensity light_intensity (W/sr) at
+ * light_pos (pinhole sensor).  For the confocal sensor the emitter is the
+ * laser spot on the relay wall, a Lambertian point emitter of power
+ * laser_power * wall_albedo at each scan point.
+ *
+ * Sensor:
+ *  - TRHIP_SENSOR_PINHOLE: camera at cam_origin with unit right/up/forward
+ *    vectors and the tangents of the half fields of view; the film has
+ *    width x height pixels, row-major, row 0 at the top.
+ *  - TRHIP_SENSOR_CONFOCAL: laser and detector co-located at each of the
+ *    width*height scan points (scan_points float[width*height][3], on the
+ *    relay wall whose unit normal wall_normal faces the hidden scene);
+ *    the film row p belongs to scan point p.  The segments between the
+ *    devices and the wall are excluded from the time of flight.
+ *
+ * Medium: homogeneous, filling space, extinction sigma_t (1/m) and
+ * single-scattering albedo medium_albedo; sigma_t == 0 disables it
+ * (Sec. 4.1, "Volumetric scattering").
+ *
+ * Film: n_bins bins of bin_width metres of optical path length starting at
+ * bin_start (the sensor window of Eq. 6, half-open at its end).
+ * camera_unwarp != 0 omits the camera segment (Sec. 3, "Camera warp and
+ * unwarping"); pinhole only.
+ */
+typedef struct {
+    const float* vertices;
+    uint32_t n_vertices;
+    const uint32_t* indices;
+    uint32_t n_triangles;
+    const uint8_t* mat_type;
+    const float* albedo;
+    const float* roughness;
+
+    float light_pos[3];
+    float light_intensity;
+
+    int32_t sensor;
+    uint32_t width, height;
+    float cam_origin[3], cam_right[3], cam_up[3], cam_fwd[3];
+    float tan_x, tan_y;
+    const float* scan_points;
+    float wall_normal[3];
+    float wall_albedo;
+    float laser_power;
+
+    float sigma_t;
+    float medium_albedo;
+
+    uint32_t n_bins;
+    float bin_width;
+    float bin_start;
+    int32_t camera_unwarp;
+} trhip_scene_desc;
+
+/*
+ * Render description.
+ * spp: samples per pixel N of the estimator (Eq. 9), >= 1.
+ * sample_offset: first sample index; samples [sample_offset, +spp) are drawn,
+ *   so disjoint ranges rendered with TRHIP_FLAG_ACCUMULATE reproduce one
+ *   render over the union.
+ * norm_spp: divisor of the film (0 = spp); set it to the total sample count
+ *   when accumulating several ranges.
+ * max_depth: number of path segments including the device segments
+ *   (a pinhole path has at most max_depth - 1 scattering vertices, a
+ *   confocal path at most max_depth - 3 hidden-scene vertices), >= 1.
+ * seed: 64-bit Philox key; stream_id: fourth Philox counter word
+ *   (e.g. 0 for renders, 1 for targets).
+ * albedo_override / roughness_override: optional DEVICE pointers to
+ *   float[n_triangles] replacing the scene's values for this call.
+ * tile_pixels / block_size: launch shape (0 = automatic choice).
+ */
+typedef struct {
+    uint32_t spp;
+    uint32_t sample_offset;
+    uint32_t norm_spp;
+    uint32_t max_depth;
+    uint64_t seed;
+    uint32_t stream_id;
+    uint32_t flags;
+    const float* albedo_override;
+    const float* roughness_override;
+    uint32_t tile_pixels;
+    uint32_t block_size;
+} trhip_render_desc;
+
+typedef struct trhip_scene trhip_scene;
+
+/* Read-only facts about an uploaded scene. */
+typedef struct {
+    uint32_t n_triangles;
+    uint32_t n_pixels;
+    uint32_t n_bins;
+    uint32_t bvh_internal_nodes;
+    uint32_t bvh_depth;         /* longest root-to-leaf path, in edges */
+    float box_pad;              /* inflation of every triangle box (metres) */
+    size_t device_bytes;        /* scene + BVH bytes held on the device */
+} trhip_scene_info;
+
+/*
+ * Upload a scene and build its BVH (a linear BVH over 30-bit Morton codes,
+ * built on the device) on `stream`; blocks until the build has finished.
+ * On success *out owns all scene memory until trhip_scene_destroy.
+ * Errors: INVALID_ARG (NULL desc/out, bad sizes or values, degenerate or
+ * non-finite triangles, index out of range), OOM, HIP.
+ */
+trhip_status trhip_scene_create(const trhip_scene_desc* desc, void* stream, trhip_scene** out);
+
+/* Free a scene (waits for the device).  NULL is accepted.  Errors: BAD_HANDLE. */
+trhip_status trhip_scene_destroy(trhip_scene* scene);
+
+/* Fill *info.  Errors: BAD_HANDLE, INVALID_ARG (NULL info). */
+trhip_status trhip_scene_get_info(const trhip_scene* scene, trhip_scene_info* info);
+
+/*
+ * Forward transient render (Sec. 3, Eqs. 1-9 and the histogram rule).
+ * film: DEVICE float[n_pixels][n_bins] (time fastest).  steady, oow:
+ * optional DEVICE float[n_pixels]: the steady image (every contribution)
+ * and the mass that fell outside the film window.  All three are
+ * normalised by 1/norm_spp and overwritten unless TRHIP_FLAG_ACCUMULATE.
+ * Errors: BAD_HANDLE, INVALID_ARG, UNSUPPORTED (launch shape beyond LDS), HIP.
+ */
+trhip_status trhip_render_transient(trhip_scene* scene, const trhip_render_desc* render, float* film,
+                                    float* steady, float* oow, void* stream);
+
+/*
+ * Backward mode (Sec. 4.4, Eqs. 15-17): given grad_film = dL/dfilm (DEVICE,
+ * same layout as the film), writes dL/d(albedo) and dL/d(roughness) per
+ * triangle (DEVICE float[n_triangles], overwritten; roughness gradients of
+ * Lambertian triangles are 0).  The gradient is that of the estimator at
+ * the given seed with the sampling pdf held fixed (path replay: each path
+ * is traced twice with the same random numbers).  primal_film (optional,
+ * DEVICE, film layout) receives the film of the replayed paths.
+ * Errors: BAD_HANDLE, INVALID_ARG, UNSUPPORTED, OOM, HIP.
+ */
+trhip_status trhip_render_transient_backward(trhip_scene* scene, const trhip_render_desc* render,
+                                             const float* grad_film, float* grad_albedo,
+                                             float* grad_roughness, float* primal_film, void* stream);
+
+/*
+ * Diagnostic variant of trhip_render_transient: the same render (same
+ * output, same paths) by a build of the kernel that also counts its work.
+ * counts: HOST uint64[TRHIP_COUNT_N], overwritten, indexed by TRHIP_COUNT_*.
+ * Synchronous (returns after the render has finished); allocates a small
+ * device buffer.  Errors: as trhip_render_transient, plus INVALID_ARG for
+ * a NULL counts.
+ */
+enum {
+    TRHIP_COUNT_NODES = 0,    /* BVH internal-node visits (both child boxes tested) */
+    TRHIP_COUNT_TRIS = 1,     /* ray-triangle tests */
+    TRHIP_COUNT_RAYS = 2,     /* closest-hit rays */
+    TRHIP_COUNT_SHADOW = 3,   /* shadow (any-hit) rays */
+    TRHIP_COUNT_VERTS = 4,    /* scattering vertices (surface or medium) */
+    TRHIP_COUNT_DRAWS = 5,    /* Philox4x32-10 evaluations */
+    TRHIP_COUNT_CONTRIB = 6,  /* contributions scattered into the film */
+    TRHIP_COUNT_N = 7
+};
+trhip_status trhip_render_transient_counted(trhip_scene* scene, const trhip_render_desc* render, float* film,
+                                            float* steady, float* oow, uint64_t* counts, void* stream);
+
+/* Static strings; never NULL. */
+const char* trhip_status_string(trhip_status status);
+const char* trhip_last_error(void);
+const char* trhip_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TRHIP_H */

@@ -1,0 +1,287 @@
+"""MI355X-native transient path tracer (arXiv 2510.25660, "mitransient").
+
+Python front-end over the C ABI of libtrhip.so (include/trhip.h).  PyTorch
+provides device memory and streams; every step of rendering runs in the HIP
+kernels of the library.
+
+    import paper_2510_25660_amd as tr
+    from paper_2510_25660_amd import scenes
+    dev = tr.upload(scenes.box_scene())
+    steady, film = tr.render_transient(dev, spp=16)    # (H, W), (H, W, T)
+
+``TransientRender`` is a ``torch.autograd.Function`` whose backward is the
+library's path-replay adjoint (Sec. 4.4 of the paper).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+
+from . import scenes
+from ._binding import (FLAG_ACCUMULATE, FLAG_FROZEN_PROPOSAL, FLAG_PIXEL_CENTRE, RenderDesc, SceneDesc,
+                       SceneInfo, TrhipError, check, lib)
+
+__all__ = [
+    "scenes", "upload", "DeviceScene", "render_transient", "render_transient_backward", "render_transient_counted",
+    "TransientRender",
+    "TrhipError", "FLAG_PIXEL_CENTRE", "FLAG_ACCUMULATE", "FLAG_FROZEN_PROPOSAL", "version",
+]
+
+
+def version() -> str:
+    return lib().trhip_version().decode()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream) -> Optional[int]:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+
+
+def _f3(v):
+    return (C.c_float * 3)(*[float(x) for x in v])
+
+
+def make_scene_desc(sc: "scenes.Scene"):
+    """Fill a trhip_scene_desc from a Scene; returns (desc, keepalive)."""
+    verts = np.ascontiguousarray(sc.vertices, np.float32)
+    idx = np.ascontiguousarray(sc.indices, np.uint32)
+    mat = np.ascontiguousarray(sc.mat_type, np.uint8)
+    alb = np.ascontiguousarray(sc.albedo, np.float32)
+    rough = np.ascontiguousarray(sc.roughness, np.float32)
+    keep = [verts, idx, mat, alb, rough]
+    d = SceneDesc()
+    fp = C.POINTER(C.c_float)
+    d.vertices = verts.ctypes.data_as(fp)
+    d.n_vertices = verts.shape[0]
+    d.indices = idx.ctypes.data_as(C.POINTER(C.c_uint32))
+    d.n_triangles = idx.shape[0]
+    d.mat_type = mat.ctypes.data_as(C.POINTER(C.c_uint8))
+    d.albedo = alb.ctypes.data_as(fp)
+    d.roughness = rough.ctypes.data_as(fp)
+    d.light_pos = _f3(sc.light_pos)
+    d.light_intensity = sc.light_intensity
+    d.sensor = int(sc.sensor)
+    d.width = sc.width
+    d.height = sc.height
+    d.cam_origin = _f3(sc.cam_origin)
+    d.cam_right = _f3(sc.cam_right)
+    d.cam_up = _f3(sc.cam_up)
+    d.cam_fwd = _f3(sc.cam_fwd)
+    d.tan_x = sc.tan_x
+    d.tan_y = sc.tan_y
+    if sc.scan_points is not None:
+        scan = np.ascontiguousarray(sc.scan_points, np.float32)
+        keep.append(scan)
+        d.scan_points = scan.ctypes.data_as(fp)
+    d.wall_normal = _f3(sc.wall_normal)
+    d.wall_albedo = sc.wall_albedo
+    d.laser_power = sc.laser_power
+    d.sigma_t = sc.sigma_t
+    d.medium_albedo = sc.medium_albedo
+    d.n_bins = sc.n_bins
+    d.bin_width = sc.bin_width
+    d.bin_start = sc.bin_start
+    d.camera_unwarp = int(bool(sc.camera_unwarp))
+    return d, keep
+
+
+class DeviceScene:
+    """A scene uploaded to the GPU with its BVH (owns a trhip_scene*)."""
+
+    def __init__(self, sc: "scenes.Scene", stream=None):
+        self.scene = sc
+        desc, keep = make_scene_desc(sc)
+        h = C.c_void_p()
+        check(lib().trhip_scene_create(C.byref(desc), _stream_handle(stream), C.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise TrhipError(5, "scene destroyed")
+        return self._h
+
+    def info(self) -> dict:
+        inf = SceneInfo()
+        check(lib().trhip_scene_get_info(self.handle, C.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in SceneInfo._fields_}
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None:
+            check(lib().trhip_scene_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.destroy()
+
+
+def upload(sc: "scenes.Scene", stream=None) -> DeviceScene:
+    return DeviceScene(sc, stream)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def make_render_desc(dev: DeviceScene, spp=None, seed=None, max_depth=None, sample_offset=0, norm_spp=0,
+                     stream_id=0, pixel_centre=False, accumulate=False, frozen=False, albedo=None,
+                     roughness=None, tile_pixels=0, block_size=0) -> RenderDesc:
+    sc = dev.scene
+    r = RenderDesc()
+    r.spp = int(sc.spp if spp is None else spp)
+    r.sample_offset = int(sample_offset)
+    r.norm_spp = int(norm_spp)
+    r.max_depth = int(sc.max_depth if max_depth is None else max_depth)
+    r.seed = int(sc.seed if seed is None else seed)
+    r.stream_id = int(stream_id)
+    r.flags = ((FLAG_PIXEL_CENTRE if pixel_centre else 0) | (FLAG_ACCUMULATE if accumulate else 0)
+               | (FLAG_FROZEN_PROPOSAL if frozen else 0))
+    r.albedo_override = _ptr(albedo)
+    r.roughness_override = _ptr(roughness)
+    r.tile_pixels = int(tile_pixels)
+    r.block_size = int(block_size)
+    return r
+
+
+def _check_param(t, n, name):
+    torch = _torch()
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() == n):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor with {n} elements")
+    return t
+
+
+def render_transient(dev: DeviceScene, spp=None, seed=None, max_depth=None, film=None, steady=None, oow=None,
+                     stream=None, return_oow=False, **kw):
+    """Forward transient render.  Returns (steady [H, W], film [H, W, T])
+    (and oow [H, W] with return_oow) as float32 CUDA tensors."""
+    torch = _torch()
+    sc = dev.scene
+    shape = (sc.height, sc.width)
+    n = sc.n_tris
+    kw["albedo"] = _check_param(kw.get("albedo"), n, "albedo")
+    kw["roughness"] = _check_param(kw.get("roughness"), n, "roughness")
+    if film is None:
+        film = torch.empty(shape + (sc.n_bins,), device="cuda", dtype=torch.float32)
+    if steady is None:
+        steady = torch.empty(shape, device="cuda", dtype=torch.float32)
+    if oow is None and return_oow:
+        oow = torch.empty(shape, device="cuda", dtype=torch.float32)
+    r = make_render_desc(dev, spp, seed, max_depth, **kw)
+    check(lib().trhip_render_transient(dev.handle, C.byref(r), _ptr(film), _ptr(steady), _ptr(oow),
+                                       _stream_handle(stream)))
+    if return_oow:
+        return steady, film, oow
+    return steady, film
+
+
+def render_transient_counted(dev: DeviceScene, spp=None, seed=None, max_depth=None, stream=None, **kw):
+    """Same render as render_transient by the counting build of the kernel;
+    returns (steady, film, counts) with counts a dict of work counters
+    (BVH node visits, triangle tests, rays, shadow rays, vertices, Philox
+    draws, contributions).  Synchronous."""
+    torch = _torch()
+    from ._binding import COUNT_NAMES
+    sc = dev.scene
+    shape = (sc.height, sc.width)
+    kw["albedo"] = _check_param(kw.get("albedo"), sc.n_tris, "albedo")
+    kw["roughness"] = _check_param(kw.get("roughness"), sc.n_tris, "roughness")
+    film = torch.empty(shape + (sc.n_bins,), device="cuda", dtype=torch.float32)
+    steady = torch.empty(shape, device="cuda", dtype=torch.float32)
+    counts = (C.c_uint64 * len(COUNT_NAMES))()
+    r = make_render_desc(dev, spp, seed, max_depth, **kw)
+    check(lib().trhip_render_transient_counted(dev.handle, C.byref(r), _ptr(film), _ptr(steady), None, counts,
+                                               _stream_handle(stream)))
+    return steady, film, dict(zip(COUNT_NAMES, [int(c) for c in counts]))
+
+
+def render_transient_backward(dev: DeviceScene, grad_film, spp=None, seed=None, max_depth=None, primal=False,
+                              stream=None, **kw):
+    """Adjoint: returns (grad_albedo [nt], grad_roughness [nt]) (and the
+    replayed primal film when primal=True)."""
+    torch = _torch()
+    sc = dev.scene
+    n = sc.n_tris
+    kw["albedo"] = _check_param(kw.get("albedo"), n, "albedo")
+    kw["roughness"] = _check_param(kw.get("roughness"), n, "roughness")
+    g = grad_film.contiguous()
+    if g.numel() != sc.n_pixels * sc.n_bins or g.dtype != torch.float32 or not g.is_cuda:
+        raise ValueError("grad_film must be a float32 CUDA tensor of the film's shape")
+    ga = torch.empty(n, device="cuda", dtype=torch.float32)
+    gr = torch.empty(n, device="cuda", dtype=torch.float32)
+    pf = torch.empty((sc.height, sc.width, sc.n_bins), device="cuda", dtype=torch.float32) if primal else None
+    r = make_render_desc(dev, spp, seed, max_depth, **kw)
+    check(lib().trhip_render_transient_backward(dev.handle, C.byref(r), _ptr(g), _ptr(ga), _ptr(gr), _ptr(pf),
+                                                _stream_handle(stream)))
+    if primal:
+        return ga, gr, pf
+    return ga, gr
+
+
+class _TransientRenderFn:
+    pass
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class TransientRender(torch.autograd.Function):
+        """film = TransientRender.apply(albedo, roughness, dev, opts) with opts a
+        dict of render options (spp, seed, max_depth, ...).  The backward is
+        the library's path-replay adjoint at the same seed."""
+
+        @staticmethod
+        def forward(ctx, albedo, roughness, dev, opts):
+            opts = dict(opts or {})
+            _, film = render_transient(dev, albedo=albedo.contiguous(), roughness=roughness.contiguous(), **opts)
+            ctx.dev = dev
+            ctx.opts = opts
+            ctx.save_for_backward(albedo, roughness)
+            return film
+
+        @staticmethod
+        def backward(ctx, grad_film):
+            albedo, roughness = ctx.saved_tensors
+            ga, gr = render_transient_backward(ctx.dev, grad_film.contiguous(), albedo=albedo.contiguous(),
+                                               roughness=roughness.contiguous(), **ctx.opts)
+            return ga, gr, None, None
+
+    return TransientRender
+
+
+class _Lazy:
+    _fn = None
+
+    def __get__(self, obj, objtype=None):
+        if _Lazy._fn is None:
+            _Lazy._fn = _make_autograd()
+        return _Lazy._fn
+
+
+class _Namespace:
+    TransientRender = _Lazy()
+
+
+def __getattr__(name):
+    if name == "TransientRender":
+        return _Namespace.TransientRender
+    raise AttributeError(name)

@@ -1,0 +1,353 @@
+// bvh.hip -- linear BVH built on the device.
+//
+// Triangle boxes are padded by pad = (largest |coordinate|) * 2^-16 (exact
+// scaling), Morton codes of the box centres (10 bits per axis) are radix
+// sorted, the hierarchy over the sorted codes is emitted in parallel (one
+// thread per internal node, Karras, "Maximizing Parallelism in the
+// Construction of BVHs, Octrees, and k-d Trees", HPG 2012), boxes are
+// refitted bottom-up with one atomic arrival counter per node, and the
+// result is laid out as 64-byte two-child nodes plus 48-byte triangles in
+// Morton order.  Every box is a union of padded triangle boxes, so a box
+// always contains the padded boxes of all triangles below it.
+#include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
+
+#include "internal.h"
+#include "scene_view.h"
+
+namespace trhip {
+
+namespace {
+
+__device__ __forceinline__ uint32_t ordered_bits(float f)
+{
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float from_ordered(uint32_t u)
+{
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+// stats[0] = max |coordinate| bits, stats[1..3] centre min (ordered),
+// stats[4..6] centre max (ordered)
+__global__ void k_scene_stats(const float* __restrict__ tri9, uint32_t nt, uint32_t* __restrict__ stats)
+{
+    __shared__ uint32_t red[7];
+    if (threadIdx.x < 7) red[threadIdx.x] = (threadIdx.x == 0) ? 0u : (threadIdx.x < 4 ? 0xffffffffu : 0u);
+    __syncthreads();
+    uint32_t mabs = 0u;
+    uint32_t cmin[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, cmax[3] = {0u, 0u, 0u};
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nt; k += gridDim.x * blockDim.x) {
+        const float* t = tri9 + 9ull * k;
+        for (int a = 0; a < 3; ++a) {
+            const float x0 = t[a], x1 = t[3 + a], x2 = t[6 + a];
+            mabs = max(mabs, __float_as_uint(fmaxf(fmaxf(fabsf(x0), fabsf(x1)), fabsf(x2))));
+            const float lo = fminf(fminf(x0, x1), x2), hi = fmaxf(fmaxf(x0, x1), x2);
+            const uint32_t c = ordered_bits(0.5f * (lo + hi));
+            cmin[a] = min(cmin[a], c);
+            cmax[a] = max(cmax[a], c);
+        }
+    }
+    atomicMax(&red[0], mabs);
+    for (int a = 0; a < 3; ++a) {
+        atomicMin(&red[1 + a], cmin[a]);
+        atomicMax(&red[4 + a], cmax[a]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicMax(&stats[0], red[0]);
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(&stats[1 + a], red[1 + a]);
+            atomicMax(&stats[4 + a], red[4 + a]);
+        }
+    }
+}
+
+__global__ void k_init_stats(uint32_t* stats)
+{
+    if (threadIdx.x < 7) stats[threadIdx.x] = (threadIdx.x == 0) ? 0u : (threadIdx.x < 4 ? 0xffffffffu : 0u);
+}
+
+__device__ __forceinline__ uint32_t spread10(uint32_t v)
+{
+    v = (v * 0x00010001u) & 0xFF0000FFu;
+    v = (v * 0x00000101u) & 0x0F00F00Fu;
+    v = (v * 0x00000011u) & 0xC30C30C3u;
+    v = (v * 0x00000005u) & 0x49249249u;
+    return v;
+}
+
+// padded boxes (caller order) and Morton codes of the unpadded box centres
+__global__ void k_boxes_codes(const float* __restrict__ tri9, uint32_t nt, const uint32_t* __restrict__ stats,
+                              float* __restrict__ box, uint32_t* __restrict__ codes, uint32_t* __restrict__ ids)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nt) return;
+    const float pad = __uint_as_float(stats[0]) * 0x1p-16f;
+    const float* t = tri9 + 9ull * k;
+    uint32_t q[3];
+    for (int a = 0; a < 3; ++a) {
+        const float x0 = t[a], x1 = t[3 + a], x2 = t[6 + a];
+        const float lo = fminf(fminf(x0, x1), x2), hi = fmaxf(fmaxf(x0, x1), x2);
+        box[6ull * k + a] = lo - pad;
+        box[6ull * k + 3 + a] = hi + pad;
+        const float cmin = from_ordered(stats[1 + a]), cmax = from_ordered(stats[4 + a]);
+        const float ext = cmax - cmin;
+        const float rel = (ext > 0.0f) ? (0.5f * (lo + hi) - cmin) / ext : 0.5f;
+        q[a] = (uint32_t)fminf(fmaxf(rel * 1024.0f, 0.0f), 1023.0f);
+    }
+    codes[k] = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+    ids[k] = k;
+}
+
+// common-prefix length of sorted codes i and j (index tie-break for equal codes)
+__device__ __forceinline__ int prefix_len(const uint32_t* __restrict__ codes, int n, int i, int j)
+{
+    if (j < 0 || j >= n) return -1;
+    const uint32_t a = codes[i], b = codes[j];
+    if (a == b) return 32 + __clz((uint32_t)i ^ (uint32_t)j);
+    return __clz(a ^ b);
+}
+
+// internal node i spans a contiguous key range; children are internal
+// nodes (>= 0) or leaves (~sorted index)
+__global__ void k_hierarchy(const uint32_t* __restrict__ codes, int n, int32_t* __restrict__ child,
+                            int32_t* __restrict__ parent_int, int32_t* __restrict__ parent_leaf)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    const int d = (prefix_len(codes, n, i, i + 1) - prefix_len(codes, n, i, i - 1)) >= 0 ? 1 : -1;
+    const int dmin = prefix_len(codes, n, i, i - d);
+    long long lmax = 2;
+    while (prefix_len(codes, n, i, (int)(i + lmax * d)) > dmin) lmax *= 2;
+    long long l = 0;
+    for (long long t = lmax / 2; t >= 1; t /= 2)
+        if (prefix_len(codes, n, i, (int)(i + (l + t) * d)) > dmin) l += t;
+    const int j = (int)(i + l * d);
+    const int dnode = prefix_len(codes, n, i, j);
+    int s = 0;
+    long long step = l;
+    do {
+        step = (step + 1) / 2;
+        if (prefix_len(codes, n, i, (int)(i + (s + step) * d)) > dnode) s += (int)step;
+    } while (step > 1);
+    const int split = i + s * d + min(d, 0);
+    const int lo = min(i, j), hi = max(i, j);
+    const int c0 = (lo == split) ? ~split : split;
+    const int c1 = (hi == split + 1) ? ~(split + 1) : (split + 1);
+    child[2 * i] = c0;
+    child[2 * i + 1] = c1;
+    if (c0 < 0) parent_leaf[~c0] = i; else parent_int[c0] = i;
+    if (c1 < 0) parent_leaf[~c1] = i; else parent_int[c1] = i;
+}
+
+// internal-node boxes are read through volatile: during the refit they were
+// written by another wave, possibly on another compute unit
+__device__ __forceinline__ void child_box(const int32_t c, const float* __restrict__ tri_box,
+                                          const uint32_t* __restrict__ ids, const volatile float* node_box,
+                                          float lo[3], float hi[3])
+{
+    if (c < 0) {
+        const float* b = tri_box + 6ull * ids[~c];
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = b[a];
+            hi[a] = b[3 + a];
+        }
+    } else {
+        const volatile float* b = node_box + 6ull * c;
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = b[a];
+            hi[a] = b[3 + a];
+        }
+    }
+}
+
+// bottom-up refit: the second arrival at a node merges both children
+__global__ void k_refit(int n, const int32_t* __restrict__ child, const int32_t* __restrict__ parent_int,
+                        const int32_t* __restrict__ parent_leaf, const float* __restrict__ tri_box,
+                        const uint32_t* __restrict__ ids, float* node_box, uint32_t* arrivals)
+{
+    const int leaf = blockIdx.x * blockDim.x + threadIdx.x;
+    if (leaf >= n) return;
+    int node = parent_leaf[leaf];
+    for (int guard = 0; node >= 0 && guard < n; ++guard) {
+        __threadfence();
+        if (atomicAdd(&arrivals[node], 1u) == 0u) return;
+        __threadfence();
+        float l0[3], h0[3], l1[3], h1[3];
+        child_box(child[2 * node], tri_box, ids, node_box, l0, h0);
+        child_box(child[2 * node + 1], tri_box, ids, node_box, l1, h1);
+        volatile float* nb = node_box + 6ull * node;
+        for (int a = 0; a < 3; ++a) {
+            nb[a] = fminf(l0[a], l1[a]);
+            nb[3 + a] = fmaxf(h0[a], h1[a]);
+        }
+        node = parent_int[node];
+    }
+}
+
+__global__ void k_layout(int n, const int32_t* __restrict__ child, const float* __restrict__ tri_box,
+                         const uint32_t* __restrict__ ids, const float* __restrict__ node_box,
+                         BvhNode* __restrict__ nodes)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    float l0[3], h0[3], l1[3], h1[3];
+    const int32_t c0 = child[2 * i], c1 = child[2 * i + 1];
+    child_box(c0, tri_box, ids, node_box, l0, h0);
+    child_box(c1, tri_box, ids, node_box, l1, h1);
+    BvhNode nd;
+    nd.lo0x = l0[0]; nd.lo0y = l0[1]; nd.lo0z = l0[2]; nd.hi0x = h0[0];
+    nd.hi0y = h0[1]; nd.hi0z = h0[2]; nd.lo1x = l1[0]; nd.lo1y = l1[1];
+    nd.lo1z = l1[2]; nd.hi1x = h1[0]; nd.hi1y = h1[1]; nd.hi1z = h1[2];
+    nd.child0 = c0; nd.child1 = c1; nd.unused0 = 0; nd.unused1 = 0;
+    nodes[i] = nd;
+}
+
+__global__ void k_tris(int n, const float* __restrict__ tri9, const uint32_t* __restrict__ ids,
+                       TriRec* __restrict__ out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t k = ids[j];
+    const float* t = tri9 + 9ull * k;
+    TriRec r;
+    r.v0x = t[0]; r.v0y = t[1]; r.v0z = t[2];
+    r.prim = k;
+    r.e1x = t[3] - t[0]; r.e1y = t[4] - t[1]; r.e1z = t[5] - t[2];
+    r.e2x = t[6] - t[0]; r.e2y = t[7] - t[1]; r.e2z = t[8] - t[2];
+    r.unused0 = 0.0f; r.unused1 = 0.0f;
+    out[j] = r;
+}
+
+// depth (edges) of every leaf; max into *depth
+__global__ void k_depth(int n, const int32_t* __restrict__ parent_int, const int32_t* __restrict__ parent_leaf,
+                        uint32_t* depth)
+{
+    const int leaf = blockIdx.x * blockDim.x + threadIdx.x;
+    if (leaf >= n) return;
+    uint32_t d = 0;
+    int node = parent_leaf[leaf];
+    for (int guard = 0; node >= 0 && guard < n; ++guard) {
+        ++d;
+        node = parent_int[node];
+    }
+    atomicMax(depth, d);
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+#define TR_CHECK(expr)                   \
+    do {                                 \
+        hipError_t e_ = (expr);          \
+        if (e_ != hipSuccess) {          \
+            err = e_;                    \
+            goto done;                   \
+        }                                \
+    } while (0)
+
+hipError_t build_bvh(const float* d_tri9, uint32_t nt, hipStream_t stream, BvhBuild* out)
+{
+    hipError_t err = hipSuccess;
+    const int n = (int)nt;
+    uint32_t *stats = nullptr, *codes = nullptr, *codes_sorted = nullptr, *ids = nullptr, *ids_sorted = nullptr;
+    uint32_t *arrivals = nullptr, *depth = nullptr;
+    float *tri_box = nullptr, *node_box = nullptr;
+    int32_t *child = nullptr, *parent_int = nullptr, *parent_leaf = nullptr;
+    void* temp = nullptr;
+    size_t temp_bytes = 0;
+    uint32_t host_stats[7] = {0};
+    uint32_t host_depth = 0;
+    const int ni = n > 1 ? n - 1 : 1;
+    out->nodes = nullptr;
+    out->tris = nullptr;
+
+    TR_CHECK(hipMalloc(&stats, 7 * sizeof(uint32_t)));
+    TR_CHECK(hipMalloc(&codes, nt * sizeof(uint32_t)));
+    TR_CHECK(hipMalloc(&codes_sorted, nt * sizeof(uint32_t)));
+    TR_CHECK(hipMalloc(&ids, nt * sizeof(uint32_t)));
+    TR_CHECK(hipMalloc(&ids_sorted, nt * sizeof(uint32_t)));
+    TR_CHECK(hipMalloc(&tri_box, 6ull * nt * sizeof(float)));
+    TR_CHECK(hipMalloc(&node_box, 6ull * ni * sizeof(float)));
+    TR_CHECK(hipMalloc(&child, 2ull * ni * sizeof(int32_t)));
+    TR_CHECK(hipMalloc(&parent_int, (size_t)ni * sizeof(int32_t)));
+    TR_CHECK(hipMalloc(&parent_leaf, (size_t)nt * sizeof(int32_t)));
+    TR_CHECK(hipMalloc(&arrivals, (size_t)ni * sizeof(uint32_t)));
+    TR_CHECK(hipMalloc(&depth, sizeof(uint32_t)));
+    TR_CHECK(hipMalloc(&out->nodes, (size_t)ni * sizeof(BvhNode)));
+    TR_CHECK(hipMalloc(&out->tris, (size_t)nt * sizeof(TriRec)));
+
+    k_init_stats<<<1, 64, 0, stream>>>(stats);
+    {
+        const unsigned g = min(1024u, blocks_for(nt, 256));
+        k_scene_stats<<<g, 256, 0, stream>>>(d_tri9, nt, stats);
+    }
+    k_boxes_codes<<<blocks_for(nt, 256), 256, 0, stream>>>(d_tri9, nt, stats, tri_box, codes, ids);
+    TR_CHECK(hipGetLastError());
+    TR_CHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, codes, codes_sorted, ids, ids_sorted, n, 0,
+                                                30, stream));
+    TR_CHECK(hipMalloc(&temp, temp_bytes));
+    TR_CHECK(hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, codes, codes_sorted, ids, ids_sorted, n, 0, 30,
+                                                stream));
+    k_fill_i32<<<blocks_for(ni, 256), 256, 0, stream>>>(parent_int, -1, (size_t)ni);
+    k_fill_i32<<<blocks_for(nt, 256), 256, 0, stream>>>(parent_leaf, -1, (size_t)nt);
+    k_fill_u32<<<blocks_for(ni, 256), 256, 0, stream>>>(arrivals, 0u, (size_t)ni);
+    k_fill_u32<<<1, 64, 0, stream>>>(depth, 0u, 1);
+    if (n > 1) {
+        k_hierarchy<<<blocks_for(n - 1, 256), 256, 0, stream>>>(codes_sorted, n, child, parent_int, parent_leaf);
+        k_refit<<<blocks_for(n, 256), 256, 0, stream>>>(n, child, parent_int, parent_leaf, tri_box, ids_sorted,
+                                                        node_box, arrivals);
+        k_layout<<<blocks_for(n - 1, 256), 256, 0, stream>>>(n, child, tri_box, ids_sorted, node_box, out->nodes);
+        k_depth<<<blocks_for(n, 256), 256, 0, stream>>>(n, parent_int, parent_leaf, depth);
+    }
+    k_tris<<<blocks_for(n, 256), 256, 0, stream>>>(n, d_tri9, ids_sorted, out->tris);
+    TR_CHECK(hipGetLastError());
+    TR_CHECK(hipMemcpyAsync(host_stats, stats, sizeof(host_stats), hipMemcpyDeviceToHost, stream));
+    TR_CHECK(hipMemcpyAsync(&host_depth, depth, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+    if (n == 1) {
+        float b[6];
+        TR_CHECK(hipMemcpyAsync(b, tri_box, sizeof(b), hipMemcpyDeviceToHost, stream));
+        TR_CHECK(hipStreamSynchronize(stream));
+        for (int a = 0; a < 3; ++a) {
+            out->root_lo[a] = b[a];
+            out->root_hi[a] = b[3 + a];
+        }
+    }
+    TR_CHECK(hipStreamSynchronize(stream));
+    {
+        float mabs;
+        memcpy(&mabs, &host_stats[0], 4);
+        out->pad = mabs * 0x1p-16f;
+    }
+    out->root = (n > 1) ? 0 : ~0;
+    out->n_internal = (uint32_t)(n > 1 ? n - 1 : 0);
+    out->depth = host_depth;
+
+done:
+    hipFree(stats); hipFree(codes); hipFree(codes_sorted); hipFree(ids); hipFree(ids_sorted);
+    hipFree(tri_box); hipFree(node_box); hipFree(child); hipFree(parent_int); hipFree(parent_leaf);
+    hipFree(arrivals); hipFree(depth); hipFree(temp);
+    if (err != hipSuccess) {
+        hipFree(out->nodes);
+        hipFree(out->tris);
+        out->nodes = nullptr;
+        out->tris = nullptr;
+    }
+    return err;
+}
+
+}  // namespace trhip

@@ -1,0 +1,41 @@
+// internal.h -- declarations shared by the host library and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "scene_view.h"
+
+namespace trhip {
+
+struct BvhBuild {
+    BvhNode* nodes;
+    TriRec* tris;
+    int32_t root;
+    float root_lo[3], root_hi[3];
+    uint32_t n_internal;
+    uint32_t depth;
+    float pad;
+};
+
+// Builds the BVH of nt triangles given as a device float[nt][9] array;
+// synchronises `stream`.  On failure nothing stays allocated.
+hipError_t build_bvh(const float* d_tri9, uint32_t nt, hipStream_t stream, BvhBuild* out);
+
+// LDS bytes of one render / backward workgroup
+size_t render_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth);
+size_t backward_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth,
+                          bool primal);
+
+// counts: optional device uint64[7] receiving the work counters (node
+// visits, triangle tests, closest rays, shadow rays, vertices, Philox draws,
+// contributions); selects the counting build of the kernel
+hipError_t launch_render(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
+                         unsigned long long* counts = nullptr);
+hipError_t launch_backward(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream);
+hipError_t launch_zero_f64(double* p, size_t n, hipStream_t stream);
+hipError_t launch_f64_to_f32(const double* src, float* dst, size_t n, hipStream_t stream);
+hipError_t launch_scene_fill(const float* tri9, uint32_t nt, hipStream_t stream);
+
+}  // namespace trhip

@@ -1,0 +1,664 @@
+// render.hip -- transient path tracing kernels for gfx950.
+//
+// One workgroup owns a tile of consecutive pixels (all their time bins) and
+// traces every sample of those pixels, one path per lane at a time.  The
+// tile's film rows live in LDS, so contributions are LDS atomics and the
+// tile is written to HBM once, with coalesced stores, at the end: no film
+// zero-fill pass and no HBM atomics.  The BVH traversal stack of each lane
+// lives in LDS (stride = block size, so a wave's pushes hit 64 distinct
+// banks).
+//
+// Path construction (arXiv 2510.25660, Sec. 3): paths are traced from the
+// sensor (pinhole camera, or the scan point on the relay wall for the
+// confocal NLOS sensor of Sec. 4.5); at each scattering vertex the point
+// emitter is connected by next-event estimation (the G V terms of Eq. 8),
+// the contribution lands in bin floor((opl - b_start) / b_width) of the
+// path's pixel, where opl is the summed segment length (Eqs. 3-4) plus the
+// connection; the continuation is importance sampled (cosine for
+// Lambertian, visible normals for GGX; isotropic phase in a homogeneous
+// medium, Sec. 4.1).  The film is the estimator of Eq. 9 (divided by N).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device_math.h"
+#include "internal.h"
+#include "scene_view.h"
+
+namespace trhip {
+
+namespace {
+
+struct Ray {
+    vec3 o, d, inv, oi;
+};
+
+__device__ __forceinline__ float guard(float x) { return (fabsf(x) < 1e-30f) ? copysignf(1e-30f, x) : x; }
+
+__device__ __forceinline__ Ray make_ray(vec3 o, vec3 d)
+{
+    Ray r;
+    r.o = o;
+    r.d = d;
+    r.inv = v3(1.0f / guard(d.x), 1.0f / guard(d.y), 1.0f / guard(d.z));
+    r.oi = v3(o.x * r.inv.x, o.y * r.inv.y, o.z * r.inv.z);
+    return r;
+}
+
+// entry/exit of a box along the ray; planes at fma(bound, 1/d, -o/d)
+__device__ __forceinline__ void slab(const Ray& r, float lx, float ly, float lz, float hx, float hy, float hz,
+                                     float& tn, float& tf)
+{
+    const float ax = fmaf(lx, r.inv.x, -r.oi.x), bx = fmaf(hx, r.inv.x, -r.oi.x);
+    const float ay = fmaf(ly, r.inv.y, -r.oi.y), by = fmaf(hy, r.inv.y, -r.oi.y);
+    const float az = fmaf(lz, r.inv.z, -r.oi.z), bz = fmaf(hz, r.inv.z, -r.oi.z);
+    tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fminf(az, bz));
+    tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz));
+}
+
+// two-sided Moller-Trumbore on (v0, e1, e2)
+__device__ __forceinline__ bool intersect_tri(const Ray& r, const TriRec& tr, float& t)
+{
+    const vec3 e1 = v3(tr.e1x, tr.e1y, tr.e1z), e2 = v3(tr.e2x, tr.e2y, tr.e2z);
+    const vec3 p = cross(r.d, e2);
+    const float det = dot(e1, p);
+    if (det == 0.0f) return false;
+    const float inv = 1.0f / det;
+    const vec3 s = sub(r.o, v3(tr.v0x, tr.v0y, tr.v0z));
+    const float u = dot(s, p) * inv;
+    if (u < 0.0f || u > 1.0f) return false;
+    const vec3 q = cross(s, e1);
+    const float v = dot(r.d, q) * inv;
+    if (v < 0.0f || u + v > 1.0f) return false;
+    t = dot(e2, q) * inv;
+    return t > 0.0f;
+}
+
+__device__ __forceinline__ TriRec load_tri(const TriRec* __restrict__ tris, int j)
+{
+    const float4* p = reinterpret_cast<const float4*>(tris + j);
+    const float4 a = p[0], b = p[1], c = p[2];
+    TriRec t;
+    t.v0x = a.x; t.v0y = a.y; t.v0z = a.z; t.prim = __float_as_uint(a.w);
+    t.e1x = b.x; t.e1y = b.y; t.e1z = b.z; t.unused0 = 0.0f;
+    t.e2x = c.x; t.e2y = c.y; t.e2z = c.z; t.unused1 = 0.0f;
+    return t;
+}
+
+struct Hit {
+    float t;
+    int prim;    // caller index, -1 = miss
+    int sorted;  // BVH-order index
+};
+
+// Work counters of the profiling build (compiled out otherwise): node
+// visits, triangle tests, closest-hit rays, shadow rays, scattering
+// vertices, Philox draws, contributions.
+enum { kTallyNodes, kTallyTris, kTallyRays, kTallyShadow, kTallyVerts, kTallyDraws, kTallyContrib, kTallyN };
+
+template <bool kOn>
+struct Tally {
+    __device__ __forceinline__ void add(int, uint32_t = 1u) {}
+    __device__ __forceinline__ void flush(unsigned long long*) {}
+};
+template <>
+struct Tally<true> {
+    uint32_t n[kTallyN] = {0, 0, 0, 0, 0, 0, 0};
+    __device__ __forceinline__ void add(int i, uint32_t v = 1u) { n[i] += v; }
+    __device__ __forceinline__ void flush(unsigned long long* out)
+    {
+        for (int i = 0; i < kTallyN; ++i) atomicAdd(out + i, (unsigned long long)n[i]);
+    }
+};
+
+// Closest accepted triangle: smallest t, then smallest caller index.  A
+// triangle is accepted at t only if t is not before the entry of its own
+// padded box (the box stored for it in its parent), which makes the result
+// independent of the traversal order.
+template <class TallyT>
+__device__ __forceinline__ void leaf_closest(const SceneView& S, const Ray& r, int sorted, float tn, int exclude,
+                                             Hit& h, TallyT& tally)
+{
+    tally.add(kTallyTris);
+    const TriRec tr = load_tri(S.tris, sorted);
+    const int prim = (int)tr.prim;
+    if (prim == exclude) return;
+    float t;
+    if (!intersect_tri(r, tr, t) || tn > t) return;
+    if (t < h.t || (t == h.t && prim < h.prim)) {
+        h.t = t;
+        h.prim = prim;
+        h.sorted = sorted;
+    }
+}
+
+template <class TallyT>
+__device__ Hit closest_hit(const SceneView& S, const Ray& r, int exclude, uint32_t* stk, int stride, TallyT& tally)
+{
+    tally.add(kTallyRays);
+    Hit h;
+    h.t = __builtin_huge_valf();
+    h.prim = -1;
+    h.sorted = -1;
+    if (S.root < 0) {
+        float tn, tf;
+        slab(r, S.root_lo[0], S.root_lo[1], S.root_lo[2], S.root_hi[0], S.root_hi[1], S.root_hi[2], tn, tf);
+        if (tn <= tf && tf >= 0.0f) leaf_closest(S, r, ~S.root, tn, exclude, h, tally);
+        return h;
+    }
+    int node = S.root;
+    int sp = 0;
+    const float4* nodes = reinterpret_cast<const float4*>(S.nodes);
+    const int max_sp = (int)S.stack_depth;
+    // a tree visits each internal node at most once per ray
+    for (uint32_t visits = 0; visits < S.n_tris; ++visits) {
+        tally.add(kTallyNodes);
+        const float4 a = nodes[4 * node + 0];
+        const float4 b = nodes[4 * node + 1];
+        const float4 c = nodes[4 * node + 2];
+        const float4 l = nodes[4 * node + 3];
+        const int c0 = __float_as_int(l.x), c1 = __float_as_int(l.y);
+        float tn0, tf0, tn1, tf1;
+        slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tn0, tf0);
+        slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tn1, tf1);
+        bool h0 = tn0 <= tf0 && tf0 >= 0.0f && tn0 <= h.t;
+        bool h1 = tn1 <= tf1 && tf1 >= 0.0f && tn1 <= h.t;
+        if (h0 && c0 < 0) {
+            leaf_closest(S, r, ~c0, tn0, exclude, h, tally);
+            h0 = false;
+        }
+        if (h1 && c1 < 0) {
+            leaf_closest(S, r, ~c1, tn1, exclude, h, tally);
+            h1 = false;
+        }
+        h0 = h0 && tn0 <= h.t;
+        h1 = h1 && tn1 <= h.t;
+        if (h0 && h1 && sp < max_sp) {
+            const bool first0 = tn0 <= tn1;
+            stk[sp * stride] = (uint32_t)(first0 ? c1 : c0);
+            ++sp;
+            node = first0 ? c0 : c1;
+        } else if (h0) {
+            node = c0;
+        } else if (h1) {
+            node = c1;
+        } else {
+            if (sp == 0) break;
+            --sp;
+            node = (int)stk[sp * stride];
+        }
+    }
+    return h;
+}
+
+template <class TallyT>
+__device__ __forceinline__ bool leaf_blocks(const SceneView& S, const Ray& r, int sorted, float tn, int exclude,
+                                            float tmax, TallyT& tally)
+{
+    tally.add(kTallyTris);
+    const TriRec tr = load_tri(S.tris, sorted);
+    if ((int)tr.prim == exclude) return false;
+    float t;
+    return intersect_tri(r, tr, t) && !(tn > t) && t < tmax;
+}
+
+// any accepted triangle other than `exclude` with t < tmax
+template <class TallyT>
+__device__ bool occluded(const SceneView& S, const Ray& r, int exclude, float tmax, uint32_t* stk, int stride,
+                         TallyT& tally)
+{
+    tally.add(kTallyShadow);
+    if (S.root < 0) {
+        float tn, tf;
+        slab(r, S.root_lo[0], S.root_lo[1], S.root_lo[2], S.root_hi[0], S.root_hi[1], S.root_hi[2], tn, tf);
+        return tn <= tf && tf >= 0.0f && tn <= tmax && leaf_blocks(S, r, ~S.root, tn, exclude, tmax, tally);
+    }
+    int node = S.root;
+    int sp = 0;
+    const float4* nodes = reinterpret_cast<const float4*>(S.nodes);
+    const int max_sp = (int)S.stack_depth;
+    for (uint32_t visits = 0; visits < S.n_tris; ++visits) {
+        const float4 a = nodes[4 * node + 0];
+        const float4 b = nodes[4 * node + 1];
+        const float4 c = nodes[4 * node + 2];
+        const float4 l = nodes[4 * node + 3];
+        const int c0 = __float_as_int(l.x), c1 = __float_as_int(l.y);
+        float tn0, tf0, tn1, tf1;
+        slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tn0, tf0);
+        slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tn1, tf1);
+        tally.add(kTallyNodes);
+        bool h0 = tn0 <= tf0 && tf0 >= 0.0f && tn0 <= tmax;
+        bool h1 = tn1 <= tf1 && tf1 >= 0.0f && tn1 <= tmax;
+        if (h0 && c0 < 0) {
+            if (leaf_blocks(S, r, ~c0, tn0, exclude, tmax, tally)) return true;
+            h0 = false;
+        }
+        if (h1 && c1 < 0) {
+            if (leaf_blocks(S, r, ~c1, tn1, exclude, tmax, tally)) return true;
+            h1 = false;
+        }
+        if (h0 && h1 && sp < max_sp) {
+            stk[sp * stride] = (uint32_t)c1;
+            ++sp;
+            node = c0;
+        } else if (h0) {
+            node = c0;
+        } else if (h1) {
+            node = c1;
+        } else {
+            if (sp == 0) return false;
+            --sp;
+            node = (int)stk[sp * stride];
+        }
+    }
+    return false;
+}
+
+__device__ __forceinline__ vec3 ld3(const float* p) { return v3(p[0], p[1], p[2]); }
+
+constexpr float kShadowShrink = 1.0f - 0x1p-10f;
+
+// Traces one path and reports, through the sink, every next-event
+// contribution (vertex index, triangle, value, bin, d log f factors of the
+// connection) and every continuation (triangle, d log f factors of the
+// sampled direction).  Triangles are caller indices; -1 marks a medium
+// vertex.
+template <class Sink, class TallyT>
+__device__ void trace_path(const SceneView& S, const LaunchArgs& L, uint32_t pix, uint32_t sample, uint32_t* stk,
+                           int stride, Sink& sink, TallyT& tally)
+{
+    tally.add(kTallyDraws);
+    const bool confocal = S.sensor == 1;
+    const bool medium = S.sigma_t > 0.0f;
+    rand4 u = draw4(pix, sample, 0u, L.stream_id, L.key0, L.key1);
+    float u_ff = u.u2;
+    vec3 o, d, target;
+    float beta;
+    int vmax;
+    const vec3 wall_n = ld3(S.wall_n);
+    if (!confocal) {
+        const uint32_t ix = pix % S.width, iy = pix / S.width;
+        const bool centre = (L.flags & kFlagPixelCentre) != 0;
+        const float jx = centre ? 0.5f : u.u0, jy = centre ? 0.5f : u.u1;
+        const float fx = (float)ix + jx, fy = (float)iy + jy;
+        const float sx = ((fx * 2.0f) / (float)S.width - 1.0f) * S.tan_x;
+        const float sy = (1.0f - (fy * 2.0f) / (float)S.height) * S.tan_y;
+        d = normalize(v3(fmaf(S.cam_u[0], sy, fmaf(S.cam_r[0], sx, S.cam_f[0])),
+                         fmaf(S.cam_u[1], sy, fmaf(S.cam_r[1], sx, S.cam_f[1])),
+                         fmaf(S.cam_u[2], sy, fmaf(S.cam_r[2], sx, S.cam_f[2]))));
+        o = ld3(S.cam_o);
+        beta = 1.0f;
+        vmax = (int)L.max_depth - 1;
+        target = ld3(S.light);
+    } else {
+        // the path leaves the scan point of the relay wall, a Lambertian
+        // vertex whose cosine-sampling weight is its albedo
+        const vec3 xs = ld3(S.scan + 3ull * pix);
+        vec3 t, b;
+        basis(wall_n, t, b);
+        d = local_to_world(t, b, wall_n, cosine_dir(u.u0, u.u1));
+        o = nudge(xs, wall_n);
+        beta = S.wall_albedo;
+        vmax = (int)L.max_depth - 3;
+        target = xs;
+    }
+    int prev = -1;
+    float opl = 0.0f;
+    for (int v = 1; v <= vmax; ++v) {
+        const Ray ray = make_ray(o, d);
+        const Hit h = closest_hit(S, ray, prev, stk, stride, tally);
+        const bool hit = h.prim >= 0;
+        float t_hit = h.t;
+        bool med = false;
+        if (medium) {
+            const float t_ff = -log_one_minus(u_ff) / S.sigma_t;
+            if (!hit || t_ff < t_hit) {
+                med = true;
+                t_hit = t_ff;
+            }
+        }
+        if (!hit && !med) break;
+        tally.add(kTallyVerts);
+        const vec3 x = along(o, d, t_hit);
+        if (!(S.unwarp && !confocal && v == 1)) opl = opl + t_hit;
+        const vec3 wo = neg(d);
+        const vec3 dl = sub(target, x);
+        const float d2 = dot(dl, dl);
+        const float dist = sqrtf(d2);
+        const vec3 wl = scale(dl, 1.0f / dist);
+        float em;
+        if (confocal) {
+            const float cos_s = -dot(wall_n, wl);
+            em = (cos_s > 0.0f) ? ((S.wall_albedo * S.laser_power) * kInvPi) * cos_s : 0.0f;
+        } else {
+            em = S.intensity;
+        }
+        const float opl_c = opl + dist;
+        const float q = (opl_c - S.bin_start) / S.bin_width;
+        const int bin = (q >= 0.0f && q < (float)S.n_bins) ? (int)q : -1;
+        if (med) {
+            beta = beta * S.medium_albedo;
+            if (em > 0.0f) {
+                const Ray sh = make_ray(x, wl);
+                if (!occluded(S, sh, -1, dist * kShadowShrink, stk, stride, tally)) {
+                    tally.add(kTallyContrib);
+                    float c = ((beta * kInv4Pi) * em) / d2;
+                    c = c * expf(-(S.sigma_t * dist));
+                    sink.contribution(v, -1, c, bin, 0.0f, 0.0f);
+                }
+            }
+            if (v == vmax) break;
+            tally.add(kTallyDraws);
+            u = draw4(pix, sample, (uint32_t)v, L.stream_id, L.key0, L.key1);
+            const float z = 1.0f - (u.u0 + u.u0);
+            const float rr = sqrtf(fmaxf(0.0f, 1.0f - z * z));
+            float sn, cs;
+            sincos_2pi(u.u1, sn, cs);
+            d = v3(rr * cs, rr * sn, z);
+            o = x;
+            prev = -1;
+            u_ff = u.u3;
+            continue;
+        }
+        // surface vertex: two-sided, shading normal = geometric normal
+        // flipped toward wo
+        const TriRec tr = load_tri(S.tris, h.sorted);
+        const vec3 ng = normalize(cross(v3(tr.e1x, tr.e1y, tr.e1z), v3(tr.e2x, tr.e2y, tr.e2z)));
+        const vec3 n = (dot(ng, wo) < 0.0f) ? neg(ng) : ng;
+        if (!(dot(n, wo) > 0.0f)) break;
+        const int k = h.prim;
+        const bool ggx = S.mat[k] == 1;
+        const float albedo = L.albedo[k];
+        vec3 tb, bb;
+        basis(n, tb, bb);
+        const vec3 wol = v3(dot(wo, tb), dot(wo, bb), dot(wo, n));
+        float fcos = 0.0f, g_rough = 0.0f;
+        {
+            const float cos_l = dot(n, wl);
+            if (cos_l > 0.0f) {
+                if (ggx) {
+                    const float alpha = L.rough_eval[k];
+                    const vec3 wll = v3(dot(wl, tb), dot(wl, bb), dot(wl, n));
+                    const float f = ggx_eval(wol, wll, alpha, albedo);
+                    if (f > 0.0f) {
+                        fcos = f * wll.z;
+                        if (Sink::kWantsGradients) g_rough = ggx_dlog_dalpha(wol, wll, alpha);
+                    }
+                } else {
+                    fcos = (albedo * kInvPi) * cos_l;
+                }
+            }
+        }
+        if (fcos > 0.0f && em > 0.0f) {
+            const Ray sh = make_ray(nudge(x, n), wl);
+            if (!occluded(S, sh, k, dist * kShadowShrink, stk, stride, tally)) {
+                tally.add(kTallyContrib);
+                float c = ((beta * fcos) * em) / d2;
+                if (medium) c = c * expf(-(S.sigma_t * dist));
+                sink.contribution(v, k, c, bin, 1.0f / albedo, g_rough);
+            }
+        }
+        if (v == vmax) break;
+        tally.add(kTallyDraws);
+        u = draw4(pix, sample, (uint32_t)v, L.stream_id, L.key0, L.key1);
+        vec3 wi;
+        float w;
+        float gc_rough = 0.0f;
+        if (ggx) {
+            const float alpha = L.rough_eval[k];
+            const float alpha_s = L.rough_sample[k];
+            if (!(wol.z > 0.0f)) break;
+            const vec3 wil = ggx_vndf_sample(wol, alpha_s, u.u0, u.u1);
+            if (!(wil.z > 0.0f)) break;
+            if (L.flags & kFlagFrozen) {
+                const float pdf = ggx_vndf_pdf(wol, wil, alpha_s);
+                const float f = ggx_eval(wol, wil, alpha, albedo);
+                if (!(pdf > 0.0f)) break;
+                w = (f * wil.z) / pdf;
+            } else {
+                const float a2 = alpha * alpha;
+                const float lo = smith_lambda(wol, a2), li = smith_lambda(wil, a2);
+                w = albedo * ((1.0f + lo) / ((1.0f + lo) + li));
+            }
+            if (!(w > 0.0f)) break;
+            if (Sink::kWantsGradients) gc_rough = ggx_dlog_dalpha(wol, wil, alpha);
+            wi = local_to_world(tb, bb, n, wil);
+        } else {
+            wi = local_to_world(tb, bb, n, cosine_dir(u.u0, u.u1));
+            w = albedo;
+        }
+        sink.continuation(k, 1.0f / albedo, gc_rough);
+        beta = beta * w;
+        d = wi;
+        o = nudge(x, n);
+        prev = k;
+        u_ff = u.u3;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forward render
+// ---------------------------------------------------------------------------
+struct FilmSink {
+    static constexpr bool kWantsGradients = false;
+    float* row;     // LDS film row of the current pixel
+    float steady;   // register partial sums of the current pixel
+    float oow;
+    __device__ __forceinline__ void contribution(int, int, float c, int bin, float, float)
+    {
+        if (bin >= 0) atomicAdd(row + bin, c);
+        else oow += c;
+        steady += c;
+    }
+    __device__ __forceinline__ void continuation(int, float, float) {}
+};
+
+template <bool kCount>
+__global__ void __launch_bounds__(256) k_render(SceneView S, LaunchArgs L, unsigned long long* counts)
+{
+    Tally<kCount> tally;
+    extern __shared__ float lds[];
+    const uint32_t T = S.n_bins;
+    const uint32_t TP = L.tile_pixels;
+    float* tfilm = lds;
+    float* tsteady = lds + (size_t)TP * T;
+    float* toow = tsteady + TP;
+    uint32_t* stk = reinterpret_cast<uint32_t*>(toow + TP) + threadIdx.x;
+    const int stride = (int)blockDim.x;
+    const uint32_t p0 = blockIdx.x * TP;
+    const uint32_t npix = min(TP, L.n_pixels - p0);
+    for (uint32_t i = threadIdx.x; i < TP * T + 2 * TP; i += blockDim.x) lds[i] = 0.0f;
+    __syncthreads();
+
+    const uint32_t work = npix * L.spp;
+    uint32_t cur = 0xffffffffu;
+    FilmSink sink{nullptr, 0.0f, 0.0f};
+    for (uint32_t w = threadIdx.x; w < work; w += blockDim.x) {
+        const uint32_t pl = w / L.spp;
+        const uint32_t s = w - pl * L.spp;
+        if (pl != cur) {
+            if (cur != 0xffffffffu) {
+                atomicAdd(tsteady + cur, sink.steady);
+                atomicAdd(toow + cur, sink.oow);
+            }
+            cur = pl;
+            sink.row = tfilm + (size_t)pl * T;
+            sink.steady = 0.0f;
+            sink.oow = 0.0f;
+        }
+        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, sink, tally);
+    }
+    tally.flush(counts);
+    if (cur != 0xffffffffu) {
+        atomicAdd(tsteady + cur, sink.steady);
+        atomicAdd(toow + cur, sink.oow);
+    }
+    __syncthreads();
+
+    const bool acc = (L.flags & kFlagAccumulate) != 0;
+    const size_t base = (size_t)p0 * T;
+    const uint32_t nvals = npix * T;
+    for (uint32_t i = threadIdx.x; i < nvals; i += blockDim.x) {
+        const float v = tfilm[i] * L.norm;
+        L.film[base + i] = acc ? L.film[base + i] + v : v;
+    }
+    if (threadIdx.x < npix) {
+        const uint32_t p = p0 + threadIdx.x;
+        if (L.steady) {
+            const float v = tsteady[threadIdx.x] * L.norm;
+            L.steady[p] = acc ? L.steady[p] + v : v;
+        }
+        if (L.oow) {
+            const float v = toow[threadIdx.x] * L.norm;
+            L.oow[p] = acc ? L.oow[p] + v : v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// backward mode: path replay
+// ---------------------------------------------------------------------------
+// pass 1 sums a_j = delta[bin_j] c_j / N over the path; pass 2 replays the
+// same path and, at each vertex v, adds a_v d log f_nee + (A - sum_{j<=v} a_j)
+// d log f_cont to the vertex's triangle (contributions after v depend on the
+// direction sampled at v).
+struct AdjointSumSink {
+    static constexpr bool kWantsGradients = false;
+    const float* delta;  // LDS gradient row of the pixel
+    float norm;
+    double total;
+    __device__ __forceinline__ void contribution(int, int, float c, int bin, float, float)
+    {
+        if (bin >= 0) total += (double)delta[bin] * (double)c * (double)norm;
+    }
+    __device__ __forceinline__ void continuation(int, float, float) {}
+};
+
+struct AdjointScatterSink {
+    static constexpr bool kWantsGradients = true;
+    const float* delta;
+    float* primal_row;  // optional LDS primal film row
+    float norm;
+    double total;       // A from pass 1
+    double prefix;      // sum of a_j so far
+    double* g_alb;
+    double* g_rough;
+    __device__ __forceinline__ void contribution(int, int k, float c, int bin, float g_alb_nee, float g_rough_nee)
+    {
+        if (bin < 0) return;
+        if (primal_row) atomicAdd(primal_row + bin, c);
+        const double a = (double)delta[bin] * (double)c * (double)norm;
+        prefix += a;
+        if (k >= 0 && a != 0.0) {
+            unsafeAtomicAdd(g_alb + k, a * (double)g_alb_nee);
+            if (g_rough_nee != 0.0f) unsafeAtomicAdd(g_rough + k, a * (double)g_rough_nee);
+        }
+    }
+    __device__ __forceinline__ void continuation(int k, float g_alb_c, float g_rough_c)
+    {
+        const double rest = total - prefix;
+        if (rest != 0.0) {
+            unsafeAtomicAdd(g_alb + k, rest * (double)g_alb_c);
+            if (g_rough_c != 0.0f) unsafeAtomicAdd(g_rough + k, rest * (double)g_rough_c);
+        }
+    }
+};
+
+__global__ void __launch_bounds__(256) k_backward(SceneView S, LaunchArgs L)
+{
+    Tally<false> tally;
+    extern __shared__ float lds[];
+    const uint32_t T = S.n_bins;
+    const uint32_t TP = L.tile_pixels;
+    const bool want_primal = L.primal != nullptr;
+    float* tdelta = lds;
+    float* tprimal = lds + (size_t)TP * T;
+    uint32_t* stk = reinterpret_cast<uint32_t*>(tprimal + (want_primal ? (size_t)TP * T : 0)) + threadIdx.x;
+    const int stride = (int)blockDim.x;
+    const uint32_t p0 = blockIdx.x * TP;
+    const uint32_t npix = min(TP, L.n_pixels - p0);
+    const size_t base = (size_t)p0 * T;
+    for (uint32_t i = threadIdx.x; i < TP * T; i += blockDim.x) {
+        tdelta[i] = (i < npix * T) ? L.grad_film[base + i] : 0.0f;
+        if (want_primal) tprimal[i] = 0.0f;
+    }
+    __syncthreads();
+
+    const uint32_t work = npix * L.spp;
+    for (uint32_t w = threadIdx.x; w < work; w += blockDim.x) {
+        const uint32_t pl = w / L.spp;
+        const uint32_t s = w - pl * L.spp;
+        const float* drow = tdelta + (size_t)pl * T;
+        AdjointSumSink first{drow, L.norm, 0.0};
+        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, first, tally);
+        AdjointScatterSink second{drow, want_primal ? tprimal + (size_t)pl * T : nullptr, L.norm, first.total, 0.0,
+                                  L.g_alb, L.g_rough};
+        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, second, tally);
+    }
+    if (want_primal) {
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < npix * T; i += blockDim.x) L.primal[base + i] = tprimal[i] * L.norm;
+    }
+}
+
+__global__ void k_zero_f64(double* p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+__global__ void k_f64_to_f32(const double* __restrict__ s, float* __restrict__ d, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        d[i] = (float)s[i];
+}
+
+}  // namespace
+
+size_t render_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth)
+{
+    return ((size_t)tile_pixels * n_bins + 2ull * tile_pixels) * sizeof(float) +
+           (size_t)block * stack_depth * sizeof(uint32_t);
+}
+
+size_t backward_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth, bool primal)
+{
+    return (size_t)tile_pixels * n_bins * sizeof(float) * (primal ? 2 : 1) +
+           (size_t)block * stack_depth * sizeof(uint32_t);
+}
+
+hipError_t launch_render(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
+                         unsigned long long* counts)
+{
+    const uint32_t tiles = (L.n_pixels + L.tile_pixels - 1) / L.tile_pixels;
+    const size_t lds = render_lds_bytes(L.tile_pixels, S.n_bins, block, S.stack_depth);
+    if (counts)
+        hipLaunchKernelGGL(k_render<true>, dim3(tiles), dim3(block), lds, stream, S, L, counts);
+    else
+        hipLaunchKernelGGL(k_render<false>, dim3(tiles), dim3(block), lds, stream, S, L, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream)
+{
+    const uint32_t tiles = (L.n_pixels + L.tile_pixels - 1) / L.tile_pixels;
+    const size_t lds = backward_lds_bytes(L.tile_pixels, S.n_bins, block, S.stack_depth, L.primal != nullptr);
+    hipLaunchKernelGGL(k_backward, dim3(tiles), dim3(block), lds, stream, S, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(double* p, size_t n, hipStream_t stream)
+{
+    const unsigned g = (unsigned)std::min<size_t>(1024, (n + 255) / 256 + 1);
+    hipLaunchKernelGGL(k_zero_f64, dim3(g), dim3(256), 0, stream, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_f64_to_f32(const double* src, float* dst, size_t n, hipStream_t stream)
+{
+    const unsigned g = (unsigned)std::min<size_t>(1024, (n + 255) / 256 + 1);
+    hipLaunchKernelGGL(k_f64_to_f32, dim3(g), dim3(256), 0, stream, src, dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace trhip

@@ -1,0 +1,78 @@
+// scene_view.h -- device-side layout of an uploaded scene and of one launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace trhip {
+
+// One internal BVH node, 64 bytes = four 16-byte loads: the boxes of both
+// children (so one fetch decides both) and the two child links.  A link
+// >= 0 is an internal node; a link < 0 is ~(sorted triangle index) and the
+// box stored for it is exactly that triangle's padded box.
+struct alignas(16) BvhNode {
+    float lo0x, lo0y, lo0z, hi0x;
+    float hi0y, hi0z, lo1x, lo1y;
+    float lo1z, hi1x, hi1y, hi1z;
+    int32_t child0, child1, unused0, unused1;
+};
+static_assert(sizeof(BvhNode) == 64, "BvhNode must be 64 bytes");
+
+// One triangle in BVH (Morton) order, 48 bytes: v0, e1 = v1 - v0,
+// e2 = v2 - v0 and the caller's triangle index.
+struct alignas(16) TriRec {
+    float v0x, v0y, v0z;
+    uint32_t prim;
+    float e1x, e1y, e1z, unused0;
+    float e2x, e2y, e2z, unused1;
+};
+static_assert(sizeof(TriRec) == 48, "TriRec must be 48 bytes");
+
+struct SceneView {
+    const BvhNode* nodes;
+    const TriRec* tris;
+    const uint8_t* mat;      // caller order
+    const float* albedo;     // caller order
+    const float* rough;      // caller order
+    const float* scan;       // [n_pixels][3], confocal only
+    int32_t root;            // >= 0 internal node, < 0 leaf
+    float root_lo[3], root_hi[3];
+    uint32_t n_tris;
+    uint32_t stack_depth;    // longest root-to-leaf path (edges), >= 1
+
+    int32_t sensor;          // 0 pinhole, 1 confocal
+    uint32_t width, height;
+    float cam_o[3], cam_r[3], cam_u[3], cam_f[3];
+    float tan_x, tan_y;
+    float wall_n[3];
+    float wall_albedo, laser_power;
+    float light[3];
+    float intensity;
+    float sigma_t, medium_albedo;
+    uint32_t n_bins;
+    float bin_width, bin_start;
+    int32_t unwarp;
+};
+
+constexpr uint32_t kFlagPixelCentre = 1u << 0;
+constexpr uint32_t kFlagAccumulate = 1u << 1;
+constexpr uint32_t kFlagFrozen = 1u << 2;
+
+struct LaunchArgs {
+    uint32_t spp, sample_offset, max_depth, stream_id;
+    uint32_t key0, key1, flags;
+    uint32_t tile_pixels, n_pixels;
+    float norm;                 // 1 / norm_spp
+    const float* albedo;        // evaluation albedo (caller order)
+    const float* rough_eval;    // evaluation roughness
+    const float* rough_sample;  // sampling roughness (== rough_eval unless frozen)
+    float* film;
+    float* steady;
+    float* oow;
+    const float* grad_film;     // backward
+    double* g_alb;
+    double* g_rough;
+    float* primal;
+};
+
+}  // namespace trhip
