@@ -44,11 +44,36 @@ OPS_PER = {
 
 WORKLOADS = {
     "confocal": dict(desc="confocal NLOS 64x64 scan, 9,682 tris (9,680-tri blob + 2-tri wall), 512 bins x 2.4 mm "
-                          "from 0.9 m, 4096 spp, 3 bounces, FP32"),
+                          "from 0.9 m, 4096 spp, 3 bounces, FP32",
+                     traffic="k_render_confocal_nlos_64x64x512_4096spp_hbm_traffic.txt"),
     "box": dict(desc="box room 34 tris, 64x64 pinhole, 256 bins x 0.01 m from 0, 16 spp, max depth 4, FP32"),
     "large": dict(desc="terrain + 49 displaced spheres 998,608 tris, fog sigma_t 0.1, 512x512, 1024 bins x 5 mm "
                        "from 4.5 m, 64 spp, max depth 8, FP32"),
 }
+
+
+KERNEL_SOURCES = ["paper_2510_25660_amd/csrc/render.hip", "paper_2510_25660_amd/csrc/device_math.h",
+                  "paper_2510_25660_amd/csrc/scene_view.h", "paper_2510_25660_amd/csrc/bvh.hip"]
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the render kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when there is none or the kernel
+    sources changed after the counters were taken."""
+    import hashlib
+    name = WORKLOADS[workload].get("traffic")
+    if not name:
+        return None
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha1()
+    for p in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    fields = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line)
+    if fields.get("kernel_sources_sha1", "").strip() != h.hexdigest():
+        return None
+    return int(float(fields["traffic_bytes_per_launch"]))
 
 
 def make_scene(name):
@@ -107,9 +132,9 @@ def cpu_baseline(sc, max_threads=16):
     threads = max(1, min(max_threads, os.cpu_count() or 1))
     O = oracle.Oracle(sc)
     if sc.sensor == 1:
-        pix = np.arange(0, sc.n_pixels, 2, dtype=np.int32)
+        pix = np.arange(sc.n_pixels, dtype=np.int32)
         spp = sc.spp
-        sample = f"every other scan point ({len(pix)} of {sc.n_pixels}) at the full {spp} spp"
+        sample = f"the whole workload: all {sc.n_pixels} scan points at the full {spp} spp"
     else:
         pix = np.arange(0, sc.n_pixels, max(1, sc.n_pixels // 4096), dtype=np.int32)
         spp = min(sc.spp, 16)
@@ -131,6 +156,8 @@ def main():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--tile-pixels", type=int, default=0)
     ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="first run a device copy of this many MiB (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -140,6 +167,14 @@ def main():
     import torch
     import paper_2510_25660_amd as tr
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration_mb:
+        n = args.copy_calibration_mb * (1 << 20) // 4
+        src = torch.ones(n, device="cuda", dtype=torch.float32)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     sc = make_scene(args.workload)
     shape = dict(tile_pixels=args.tile_pixels, block_size=args.block_size)
     with tr.upload(sc) as dev:
@@ -171,7 +206,8 @@ def main():
         "config": {"workload": WORKLOADS[args.workload]["desc"], "paths_per_step": paths,
                    "triangles": info["n_triangles"], "bvh_depth": info["bvh_depth"]},
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(PEAK_VALU_LANE_OPS / 1e12, 2),
-                     "unit": "T lane-ops/s", "frac": round(achieved / PEAK_VALU_LANE_OPS, 4), "traffic": None,
+                     "unit": "T lane-ops/s", "frac": round(achieved / PEAK_VALU_LANE_OPS, 4),
+                     "traffic": measured_traffic(args.workload), "traffic_unit": "bytes/launch",
                      "kernel": "k_render", "launch_ms": round(launch_ms, 4),
                      "ops_per_launch": int(ops), "counts": counts},
     }
