@@ -49,6 +49,8 @@ WORKLOADS = {
     "box": dict(desc="box room 34 tris, 64x64 pinhole, 256 bins x 0.01 m from 0, 16 spp, max depth 4, FP32"),
     "large": dict(desc="terrain + 49 displaced spheres 998,608 tris, fog sigma_t 0.1, 512x512, 1024 bins x 5 mm "
                        "from 4.5 m, 64 spp, max depth 8, FP32"),
+    "batched": dict(desc="256 confocal NLOS scenes: blob triangles log-uniform 1k-50k, scan grids 16^2-64^2, "
+                         "256-1024 bins x 2.4 mm from 0.9 m, 256 spp, 3 bounces, one graph launch, FP32"),
 }
 
 
@@ -126,6 +128,41 @@ def backward_forward_ratio(tr, steps=5, warmup=1):
     return bwd_ms / fwd_ms, fwd_ms / steps, bwd_ms / steps
 
 
+def run_batched(args, tr):
+    """The batched workload: one graph launch renders all 256 scenes."""
+    import torch
+    from paper_2510_25660_amd import scenes
+    scs = scenes.batched_nlos()
+    devs = [tr.upload(s) for s in scs]
+    try:
+        b = tr.Batch(devs, autotune=True)
+        info = b.info()
+        total_ms, per = time_launches(b.render, args.steps, args.warmup)
+        seq = None
+        if args.compare_kernels:
+            films = b.films
+            seq_ms, _ = time_launches(lambda: [tr.render_transient(d, film=f) for d, f in zip(devs, films)],
+                                      max(1, args.steps // 4), 1)
+            seq = seq_ms / max(1, args.steps // 4)
+        b.destroy()
+    finally:
+        for d in devs:
+            d.destroy()
+    paths = sum(s.n_pixels * s.spp for s in scs)
+    ms = total_ms / args.steps
+    out = {
+        "metric": "Mpath-samples/s into transient film at 1 GPU; backward/forward time ratio",
+        "value": round(paths / (ms * 1e-3) / 1e6, 3), "unit": "Mpath-samples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded scene generators)",
+        "config": {"workload": WORKLOADS["batched"]["desc"], "paths_per_step": paths,
+                   "triangles": int(sum(s.n_tris for s in scs)), "batch": info},
+    }
+    if seq is not None:
+        out["sequential_single_scene_ms"] = round(seq, 3)
+    return out
+
+
 def cpu_baseline(sc, max_threads=16):
     """The oracle on the host cores over a bounded sample of the workload."""
     import oracle
@@ -156,6 +193,8 @@ def main():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--tile-pixels", type=int, default=0)
     ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--kernel", default="auto", choices=["auto", "path", "wavefront"])
+    ap.add_argument("--compare-kernels", action="store_true", help="also time each kernel form")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a device copy of this many MiB (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -175,8 +214,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload == "batched":
+        print(json.dumps(run_batched(args, tr)), flush=True)
+        return
     sc = make_scene(args.workload)
-    shape = dict(tile_pixels=args.tile_pixels, block_size=args.block_size)
+    shape = dict(tile_pixels=args.tile_pixels, block_size=args.block_size, kernel=args.kernel)
+    paths = sc.n_pixels * sc.spp
     with tr.upload(sc) as dev:
         info = dev.info()
         steady = torch.empty((sc.height, sc.width), device="cuda", dtype=torch.float32)
@@ -184,7 +227,13 @@ def main():
         step = lambda: tr.render_transient(dev, film=film, steady=steady, **shape)
         total_ms, per = time_launches(step, args.steps, args.warmup)
         _, _, counts = tr.render_transient_counted(dev, **shape)
-    paths = sc.n_pixels * sc.spp
+        forms = {}
+        if args.compare_kernels:
+            for form in ("path", "wavefront"):
+                sh = dict(shape, kernel=form)
+                ms, _ = time_launches(lambda: tr.render_transient(dev, film=film, steady=steady, **sh), args.steps,
+                                      args.warmup)
+                forms[form] = round(paths / (ms / args.steps * 1e-3) / 1e6, 3)
     ms_per_step = total_ms / args.steps
     value = paths / (ms_per_step * 1e-3) / 1e6
     launch_ms = float(np.mean(per))
@@ -211,6 +260,8 @@ def main():
                      "kernel": "k_render", "launch_ms": round(launch_ms, 4),
                      "ops_per_launch": int(ops), "counts": counts},
     }
+    if forms:
+        out["kernel_forms_mpaths_per_s"] = forms
     if not args.no_backward:
         ratio, f_ms, b_ms = backward_forward_ratio(tr)
         out["backward_forward_ratio"] = round(ratio, 3)

@@ -139,6 +139,10 @@ typedef struct {
  * albedo_override / roughness_override: optional DEVICE pointers to
  *   float[n_triangles] replacing the scene's values for this call.
  * tile_pixels / block_size: launch shape (0 = automatic choice).
+ * kernel: form of the forward render kernel, TRHIP_KERNEL_* (0 = automatic):
+ *   PATH traces one whole path per lane; WAVEFRONT runs the stages of a
+ *   workgroup's paths (generate, intersect, shade, shadow) over compacted
+ *   queues held in LDS.  Both produce the same film.  Ignored by backward.
  */
 typedef struct {
     uint32_t spp;
@@ -152,7 +156,10 @@ typedef struct {
     const float* roughness_override;
     uint32_t tile_pixels;
     uint32_t block_size;
+    uint32_t kernel;
 } trhip_render_desc;
+
+enum { TRHIP_KERNEL_AUTO = 0, TRHIP_KERNEL_PATH = 1, TRHIP_KERNEL_WAVEFRONT = 2 };
 
 typedef struct trhip_scene trhip_scene;
 
@@ -227,6 +234,55 @@ enum {
 };
 trhip_status trhip_render_transient_counted(trhip_scene* scene, const trhip_render_desc* render, float* film,
                                             float* steady, float* oow, uint64_t* counts, void* stream);
+
+/*
+ * Batched persistent rendering of many scenes (e.g. NLOS datasets, Sec. 4.5)
+ * in one launch.  Work items are (scene, pixel tile) pairs, ordered by
+ * estimated cost (largest first) and popped by persistent workgroups from a
+ * global cursor; the cursor reset and the persistent kernel are captured once
+ * into a hipGraph, so trhip_batch_render is one graph launch.
+ *
+ * scenes: HOST array of n_scenes live scene handles; renders: HOST array of
+ * n_scenes render descriptions (overrides must be NULL; flags may only hold
+ * TRHIP_FLAG_PIXEL_CENTRE; kernel/tile/block fields are ignored); films:
+ * HOST array of n_scenes DEVICE pointers, films[i] of scene i's film layout.
+ * Unlike every other entry point, the batch keeps the scene handles and
+ * the film pointers: the caller keeps them valid until trhip_batch_destroy.
+ * Each film receives exactly what trhip_render_transient would write for
+ * the same scene and render description.
+ */
+typedef struct trhip_batch trhip_batch;
+
+typedef struct {
+    uint32_t block_size;    /* workgroup size (multiple of 64, <= 256); 0 = choose */
+    uint32_t tile_pixels;   /* pixels per work item; 0 = choose */
+    uint32_t groups_per_cu; /* persistent workgroups per compute unit; 0 = choose */
+    int32_t autotune;       /* nonzero: time the candidate shapes for every field left 0 during
+                               trhip_batch_create (renders into the films) and keep the fastest;
+                               the choice is cached per process for the same batch shape */
+} trhip_batch_opts;
+
+typedef struct {
+    uint32_t n_scenes;
+    uint32_t n_items;       /* work items per render */
+    uint32_t block_size, tile_pixels, groups;
+    uint32_t stack_depth;   /* deepest BVH of the batch */
+    size_t lds_bytes;       /* dynamic LDS per workgroup */
+    uint32_t candidates;    /* shapes timed by the autotuner (0: none, or cached) */
+    float tune_ms;          /* wall time spent autotuning */
+    float best_ms;          /* measured render time of the chosen shape (0 if not timed) */
+} trhip_batch_info;
+
+/* Errors: INVALID_ARG, BAD_HANDLE (a scene), UNSUPPORTED (LDS), OOM, HIP.
+ * Synchronises `stream`. */
+trhip_status trhip_batch_create(trhip_scene* const* scenes, const trhip_render_desc* renders, uint32_t n_scenes,
+                                float* const* films, const trhip_batch_opts* opts, void* stream,
+                                trhip_batch** out);
+/* One graph launch on `stream`.  Errors: BAD_HANDLE, HIP. */
+trhip_status trhip_batch_render(trhip_batch* batch, void* stream);
+trhip_status trhip_batch_get_info(const trhip_batch* batch, trhip_batch_info* info);
+/* Waits for the device, frees the batch (not the scenes or films).  NULL is accepted. */
+trhip_status trhip_batch_destroy(trhip_batch* batch);
 
 /* Static strings; never NULL. */
 const char* trhip_status_string(trhip_status status);

@@ -20,12 +20,12 @@ from typing import Optional
 import numpy as np
 
 from . import scenes
-from ._binding import (FLAG_ACCUMULATE, FLAG_FROZEN_PROPOSAL, FLAG_PIXEL_CENTRE, RenderDesc, SceneDesc,
-                       SceneInfo, TrhipError, check, lib)
+from ._binding import (FLAG_ACCUMULATE, FLAG_FROZEN_PROPOSAL, FLAG_PIXEL_CENTRE, BatchInfo, BatchOpts, RenderDesc,
+                       SceneDesc, SceneInfo, TrhipError, check, lib)
 
 __all__ = [
     "scenes", "upload", "DeviceScene", "render_transient", "render_transient_backward", "render_transient_counted",
-    "TransientRender",
+    "TransientRender", "Batch",
     "TrhipError", "FLAG_PIXEL_CENTRE", "FLAG_ACCUMULATE", "FLAG_FROZEN_PROPOSAL", "version",
 ]
 
@@ -143,7 +143,7 @@ def _ptr(t) -> Optional[int]:
 
 def make_render_desc(dev: DeviceScene, spp=None, seed=None, max_depth=None, sample_offset=0, norm_spp=0,
                      stream_id=0, pixel_centre=False, accumulate=False, frozen=False, albedo=None,
-                     roughness=None, tile_pixels=0, block_size=0) -> RenderDesc:
+                     roughness=None, tile_pixels=0, block_size=0, kernel="auto") -> RenderDesc:
     sc = dev.scene
     r = RenderDesc()
     r.spp = int(sc.spp if spp is None else spp)
@@ -158,6 +158,8 @@ def make_render_desc(dev: DeviceScene, spp=None, seed=None, max_depth=None, samp
     r.roughness_override = _ptr(roughness)
     r.tile_pixels = int(tile_pixels)
     r.block_size = int(block_size)
+    from ._binding import KERNELS
+    r.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     return r
 
 
@@ -237,8 +239,57 @@ def render_transient_backward(dev: DeviceScene, grad_film, spp=None, seed=None, 
     return ga, gr
 
 
-class _TransientRenderFn:
-    pass
+class Batch:
+    """Many scenes rendered by one persistent, graph-captured launch
+    (trhip_batch_*).  films[i] (allocated here unless given) receives what
+    render_transient(devs[i], **renders[i]) would produce."""
+
+    def __init__(self, devs, renders=None, films=None, block_size=0, tile_pixels=0, groups_per_cu=0,
+                 autotune=True, stream=None):
+        torch = _torch()
+        self.devs = list(devs)
+        n = len(self.devs)
+        renders = renders or [{} for _ in range(n)]
+        if films is None:
+            films = [torch.empty((d.scene.height, d.scene.width, d.scene.n_bins), device="cuda",
+                                 dtype=torch.float32) for d in self.devs]
+        self.films = films
+        descs = (RenderDesc * n)()
+        for i, (d, kw) in enumerate(zip(self.devs, renders)):
+            descs[i] = make_render_desc(d, **kw)
+        handles = (C.c_void_p * n)(*[d.handle.value for d in self.devs])
+        fptrs = (C.c_void_p * n)(*[f.data_ptr() for f in films])
+        opts = BatchOpts(block_size, tile_pixels, groups_per_cu, 1 if autotune else 0)
+        h = C.c_void_p()
+        check(lib().trhip_batch_create(handles, descs, n, fptrs, C.byref(opts), _stream_handle(stream),
+                                       C.byref(h)))
+        self._h = h
+
+    def render(self, stream=None):
+        check(lib().trhip_batch_render(self._h, _stream_handle(stream)))
+        return self.films
+
+    def info(self) -> dict:
+        inf = BatchInfo()
+        check(lib().trhip_batch_get_info(self._h, C.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in BatchInfo._fields_}
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None:
+            check(lib().trhip_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.destroy()
 
 
 def _make_autograd():

@@ -20,10 +20,13 @@ FLAG_PIXEL_CENTRE = 1 << 0
 FLAG_ACCUMULATE = 1 << 1
 FLAG_FROZEN_PROPOSAL = 1 << 2
 
+KERNELS = {"auto": 0, "path": 1, "wavefront": 2}
+
 EXPORTED_SYMBOLS = (
     "trhip_scene_create", "trhip_scene_destroy", "trhip_scene_get_info", "trhip_render_transient",
     "trhip_render_transient_backward", "trhip_render_transient_counted", "trhip_status_string",
-    "trhip_last_error", "trhip_version",
+    "trhip_last_error", "trhip_version", "trhip_batch_create", "trhip_batch_render", "trhip_batch_get_info",
+    "trhip_batch_destroy",
 )
 
 COUNT_NAMES = ("nodes", "tris", "rays", "shadow_rays", "vertices", "draws", "contributions")
@@ -81,6 +84,7 @@ class RenderDesc(C.Structure):
         ("roughness_override", C.c_void_p),
         ("tile_pixels", C.c_uint32),
         ("block_size", C.c_uint32),
+        ("kernel", C.c_uint32),
     ]
 
 
@@ -93,6 +97,30 @@ class SceneInfo(C.Structure):
         ("bvh_depth", C.c_uint32),
         ("box_pad", C.c_float),
         ("device_bytes", C.c_size_t),
+    ]
+
+
+class BatchOpts(C.Structure):
+    _fields_ = [
+        ("block_size", C.c_uint32),
+        ("tile_pixels", C.c_uint32),
+        ("groups_per_cu", C.c_uint32),
+        ("autotune", C.c_int32),
+    ]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [
+        ("n_scenes", C.c_uint32),
+        ("n_items", C.c_uint32),
+        ("block_size", C.c_uint32),
+        ("tile_pixels", C.c_uint32),
+        ("groups", C.c_uint32),
+        ("stack_depth", C.c_uint32),
+        ("lds_bytes", C.c_size_t),
+        ("candidates", C.c_uint32),
+        ("tune_ms", C.c_float),
+        ("best_ms", C.c_float),
     ]
 
 
@@ -120,6 +148,15 @@ def lib():
         L.trhip_render_transient_counted.argtypes = [vp, C.POINTER(RenderDesc), vp, vp, vp,
                                                      C.POINTER(C.c_uint64), vp]
         L.trhip_render_transient_counted.restype = C.c_int
+        L.trhip_batch_create.argtypes = [C.POINTER(vp), C.POINTER(RenderDesc), C.c_uint32, C.POINTER(vp),
+                                         C.POINTER(BatchOpts), vp, C.POINTER(vp)]
+        L.trhip_batch_create.restype = C.c_int
+        L.trhip_batch_render.argtypes = [vp, vp]
+        L.trhip_batch_render.restype = C.c_int
+        L.trhip_batch_get_info.argtypes = [vp, C.POINTER(BatchInfo)]
+        L.trhip_batch_get_info.restype = C.c_int
+        L.trhip_batch_destroy.argtypes = [vp]
+        L.trhip_batch_destroy.restype = C.c_int
         L.trhip_status_string.argtypes = [C.c_int]
         L.trhip_status_string.restype = C.c_char_p
         L.trhip_last_error.argtypes = []

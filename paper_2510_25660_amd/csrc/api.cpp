@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -14,6 +16,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <unordered_set>
 #include <vector>
 
@@ -24,7 +27,7 @@
 namespace {
 
 constexpr uint32_t kSceneMagic = 0x54524850u;  // "TRHP"
-constexpr size_t kLdsBudget = 64 * 1024;       // bytes per workgroup
+constexpr size_t kLdsBudget = 63 * 1024;       // dynamic LDS bytes per workgroup
 constexpr uint32_t kMaxBlock = 256;
 
 thread_local std::string g_last_error;
@@ -215,41 +218,60 @@ trhip_status validate_render(const trhip_scene* s, const trhip_render_desc* r)
         return fail(TRHIP_ERR_INVALID_ARG, "block_size must be a multiple of 64 and <= %u", kMaxBlock);
     if (r->flags & ~(uint32_t)(TRHIP_FLAG_PIXEL_CENTRE | TRHIP_FLAG_ACCUMULATE | TRHIP_FLAG_FROZEN_PROPOSAL))
         return fail(TRHIP_ERR_INVALID_ARG, "unknown flag bits");
+    if (r->kernel > TRHIP_KERNEL_WAVEFRONT) return fail(TRHIP_ERR_INVALID_ARG, "unknown kernel %u", r->kernel);
     return TRHIP_OK;
 }
 
+enum class Kind { Path, Wavefront, Backward, BackwardPrimal };
+
+size_t lds_bytes(Kind kind, uint32_t tp, uint32_t T, uint32_t bs, uint32_t depth)
+{
+    switch (kind) {
+    case Kind::Path: return trhip::render_lds_bytes(tp, T, bs, depth);
+    case Kind::Wavefront: return trhip::wavefront_lds_bytes(tp, T, bs, depth);
+    case Kind::Backward: return trhip::backward_lds_bytes(tp, T, bs, depth, false);
+    default: return trhip::backward_lds_bytes(tp, T, bs, depth, true);
+    }
+}
+
 // Launch shape: enough pixels per tile that a workgroup has ~block samples
-// of work, capped by the LDS budget (tile film + traversal stacks).
-trhip_status choose_shape(const trhip_scene* s, const trhip_render_desc* r, bool backward, bool primal,
-                          uint32_t* tile, uint32_t* block)
+// of work, capped by the LDS budget (tile film + traversal stacks, plus the
+// path slots and queues of the wavefront form).
+trhip_status choose_shape(const trhip_scene* s, const trhip_render_desc* r, Kind kind, uint32_t* tile,
+                          uint32_t* block)
 {
     const uint32_t T = s->view.n_bins, depth = s->view.stack_depth;
     uint32_t bs = r->block_size ? r->block_size : kMaxBlock;
     if (!r->block_size) {
         // small per-tile work: narrower groups keep more of them in flight
         if ((uint64_t)s->n_pixels * r->spp < 256ull * 1024) bs = 64;
+        while (bs > 64 && lds_bytes(kind, 1, T, bs, depth) > kLdsBudget) bs /= 2;
     }
     uint32_t tp = r->tile_pixels;
     if (!tp) {
         tp = std::max<uint32_t>(1u, (bs + r->spp - 1) / r->spp);
         tp = std::min<uint32_t>(tp, s->n_pixels);
-        while (tp > 1) {
-            const size_t b = backward ? trhip::backward_lds_bytes(tp, T, bs, depth, primal)
-                                      : trhip::render_lds_bytes(tp, T, bs, depth);
-            if (b <= kLdsBudget) break;
-            tp /= 2;
-        }
+        while (tp > 1 && lds_bytes(kind, tp, T, bs, depth) > kLdsBudget) tp /= 2;
     }
     if ((uint64_t)tp * r->spp >= (1ull << 32))
         return fail(TRHIP_ERR_INVALID_ARG, "tile_pixels * spp must stay below 2^32");
-    const size_t need = backward ? trhip::backward_lds_bytes(tp, T, bs, depth, primal)
-                                 : trhip::render_lds_bytes(tp, T, bs, depth);
+    const size_t need = lds_bytes(kind, tp, T, bs, depth);
     if (need > kLdsBudget)
         return fail(TRHIP_ERR_UNSUPPORTED, "launch needs %zu bytes of LDS (tile %u x %u bins, block %u, stack %u)",
                     need, tp, T, bs, depth);
     *tile = tp;
     *block = bs;
     return TRHIP_OK;
+}
+
+// Forward kernel form: the wavefront form whenever its LDS fits.
+Kind forward_kind(const trhip_scene* s, const trhip_render_desc* r)
+{
+    if (r->kernel == TRHIP_KERNEL_PATH) return Kind::Path;
+    if (r->kernel == TRHIP_KERNEL_WAVEFRONT) return Kind::Wavefront;
+    const uint32_t bs = r->block_size ? r->block_size : 64;
+    return lds_bytes(Kind::Wavefront, 1, s->view.n_bins, bs, s->view.stack_depth) <= kLdsBudget ? Kind::Wavefront
+                                                                                                  : Kind::Path;
 }
 
 void fill_launch(const trhip_scene* s, const trhip_render_desc* r, uint32_t tile, trhip::LaunchArgs* L)
@@ -348,14 +370,16 @@ trhip_status trhip_render_transient(trhip_scene* scene, const trhip_render_desc*
     if (st != TRHIP_OK) return st;
     if ((st = validate_render(scene, render)) != TRHIP_OK) return st;
     if (!film) return fail(TRHIP_ERR_INVALID_ARG, "film is NULL");
+    const Kind kind = forward_kind(scene, render);
     uint32_t tile = 0, block = 0;
-    if ((st = choose_shape(scene, render, false, false, &tile, &block)) != TRHIP_OK) return st;
+    if ((st = choose_shape(scene, render, kind, &tile, &block)) != TRHIP_OK) return st;
     trhip::LaunchArgs L;
     fill_launch(scene, render, tile, &L);
     L.film = film;
     L.steady = steady;
     L.oow = oow;
-    hipError_t e = trhip::launch_render(scene->view, L, block, (hipStream_t)stream);
+    hipError_t e = (kind == Kind::Wavefront) ? trhip::launch_render_wavefront(scene->view, L, block, (hipStream_t)stream)
+                                             : trhip::launch_render(scene->view, L, block, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return TRHIP_OK;
 }
@@ -367,8 +391,9 @@ trhip_status trhip_render_transient_counted(trhip_scene* scene, const trhip_rend
     if (st != TRHIP_OK) return st;
     if ((st = validate_render(scene, render)) != TRHIP_OK) return st;
     if (!film || !counts) return fail(TRHIP_ERR_INVALID_ARG, "film and counts must be non-NULL");
+    const Kind kind = forward_kind(scene, render);
     uint32_t tile = 0, block = 0;
-    if ((st = choose_shape(scene, render, false, false, &tile, &block)) != TRHIP_OK) return st;
+    if ((st = choose_shape(scene, render, kind, &tile, &block)) != TRHIP_OK) return st;
     trhip::LaunchArgs L;
     fill_launch(scene, render, tile, &L);
     L.film = film;
@@ -378,7 +403,9 @@ trhip_status trhip_render_transient_counted(trhip_scene* scene, const trhip_rend
     unsigned long long* d_counts = nullptr;
     hipError_t e = hipMalloc(&d_counts, TRHIP_COUNT_N * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMemsetAsync(d_counts, 0, TRHIP_COUNT_N * sizeof(unsigned long long), s);
-    if (e == hipSuccess) e = trhip::launch_render(scene->view, L, block, s, d_counts);
+    if (e == hipSuccess)
+        e = (kind == Kind::Wavefront) ? trhip::launch_render_wavefront(scene->view, L, block, s, d_counts)
+                                      : trhip::launch_render(scene->view, L, block, s, d_counts);
     if (e == hipSuccess)
         e = hipMemcpyAsync(counts, d_counts, TRHIP_COUNT_N * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -399,7 +426,9 @@ trhip_status trhip_render_transient_backward(trhip_scene* scene, const trhip_ren
     if (render->flags & TRHIP_FLAG_ACCUMULATE)
         return fail(TRHIP_ERR_INVALID_ARG, "ACCUMULATE does not apply to the backward pass");
     uint32_t tile = 0, block = 0;
-    if ((st = choose_shape(scene, render, true, primal_film != nullptr, &tile, &block)) != TRHIP_OK) return st;
+    if ((st = choose_shape(scene, render, primal_film ? Kind::BackwardPrimal : Kind::Backward, &tile, &block)) !=
+        TRHIP_OK)
+        return st;
     hipStream_t s = (hipStream_t)stream;
     const size_t nt = scene->view.n_tris;
     trhip::LaunchArgs L;
@@ -415,6 +444,332 @@ trhip_status trhip_render_transient_backward(trhip_scene* scene, const trhip_ren
     if (e != hipSuccess) return hip_fail(e, "backward launch");
     return TRHIP_OK;
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched persistent rendering
+// ---------------------------------------------------------------------------
+constexpr uint32_t kBatchMagic = 0x54524842u;  // "TRHB"
+
+struct trhip_batch {
+    uint32_t magic;
+    std::vector<trhip_scene*> scenes;
+    std::vector<trhip::SceneView> views;
+    std::vector<trhip::LaunchArgs> args;   // tile_pixels filled per shape
+    std::vector<uint32_t> order;           // processing order (largest cost first)
+    trhip::SceneView* d_views;
+    trhip::LaunchArgs* d_args;
+    uint32_t* d_item_start;
+    uint32_t* d_order;
+    uint32_t* d_cursor;
+    trhip::BatchTables tables;
+    uint32_t block, tile, groups, depth;
+    size_t lds;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    trhip_batch_info info;
+};
+
+namespace {
+
+std::mutex g_batch_mutex;
+std::unordered_set<const trhip_batch*> g_live_batches;
+std::unordered_map<uint64_t, std::array<uint32_t, 3>> g_tune_cache;  // key -> block, tile, groups
+
+bool batch_live(const trhip_batch* b)
+{
+    std::lock_guard<std::mutex> lock(g_batch_mutex);
+    return b && g_live_batches.count(b) && b->magic == kBatchMagic;
+}
+
+void free_batch(trhip_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    (void)hipFree(b->d_views);
+    (void)hipFree(b->d_args);
+    (void)hipFree(b->d_item_start);
+    (void)hipFree(b->d_order);
+    (void)hipFree(b->d_cursor);
+    b->magic = 0;
+    delete b;
+}
+
+// shape -> tables on the device; returns false if the LDS does not fit
+hipError_t stage_shape(trhip_batch* b, uint32_t block, uint32_t tile, uint32_t groups, hipStream_t s, bool* fits)
+{
+    const uint32_t n = (uint32_t)b->scenes.size();
+    std::vector<uint32_t> start(n + 1, 0);
+    uint32_t film_words = 0;
+    for (uint32_t k = 0; k < n; ++k) {
+        const uint32_t i = b->order[k];
+        const uint32_t P = b->scenes[i]->n_pixels, T = b->views[i].n_bins;
+        start[k + 1] = start[k] + (P + tile - 1) / tile;
+        film_words = std::max<uint32_t>(film_words, tile * T + 2 * tile);
+    }
+    const size_t lds = trhip::batch_lds_bytes(film_words, block, b->depth);
+    *fits = lds <= kLdsBudget;
+    for (uint32_t i = 0; i < n; ++i) b->args[i].tile_pixels = tile;
+    for (uint32_t i = 0; i < n; ++i)
+        if ((uint64_t)tile * b->args[i].spp >= (1ull << 32)) *fits = false;
+    if (!*fits) return hipSuccess;
+    hipError_t e = hipMemcpyAsync(b->d_args, b->args.data(), n * sizeof(trhip::LaunchArgs), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_item_start, start.data(), (n + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    b->tables.views = b->d_views;
+    b->tables.args = b->d_args;
+    b->tables.item_start = b->d_item_start;
+    b->tables.order = b->d_order;
+    b->tables.n_scenes = n;
+    b->tables.n_items = start[n];
+    b->tables.film_words = film_words;
+    b->tables.cursor = b->d_cursor;
+    b->block = block;
+    b->tile = tile;
+    b->groups = groups;
+    b->lds = lds;
+    return e;
+}
+
+uint64_t tune_key(const trhip_batch* b, int device, const trhip_batch_opts& o)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) { h = (h ^ v) * 1099511628211ull; };
+    mix((uint64_t)device);
+    mix(o.block_size);
+    mix(o.tile_pixels);
+    mix(o.groups_per_cu);
+    for (size_t i = 0; i < b->scenes.size(); ++i) {
+        mix(b->scenes[i]->n_pixels);
+        mix(b->views[i].n_bins);
+        mix(b->views[i].n_tris);
+        mix(b->views[i].stack_depth);
+        mix(b->args[i].spp);
+        mix(b->args[i].max_depth);
+    }
+    return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+trhip_status trhip_batch_create(trhip_scene* const* scenes, const trhip_render_desc* renders, uint32_t n_scenes,
+                                float* const* films, const trhip_batch_opts* opts, void* stream,
+                                trhip_batch** out)
+{
+    if (!out) return fail(TRHIP_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!scenes || !renders || !films || n_scenes == 0)
+        return fail(TRHIP_ERR_INVALID_ARG, "scenes, renders and films must be non-empty arrays");
+    trhip_batch_opts o{};
+    if (opts) o = *opts;
+    if (o.block_size != 0 && (o.block_size % 64 != 0 || o.block_size > kMaxBlock))
+        return fail(TRHIP_ERR_INVALID_ARG, "block_size must be a multiple of 64 and <= %u", kMaxBlock);
+    if (o.groups_per_cu > 64) return fail(TRHIP_ERR_INVALID_ARG, "groups_per_cu must be <= 64");
+    for (uint32_t i = 0; i < n_scenes; ++i) {
+        trhip_status st = check_scene(scenes[i]);
+        if (st != TRHIP_OK) return fail(st, "scene %u: invalid handle", i);
+        if ((st = validate_render(scenes[i], &renders[i])) != TRHIP_OK) return st;
+        if (renders[i].albedo_override || renders[i].roughness_override)
+            return fail(TRHIP_ERR_INVALID_ARG, "scene %u: batched renders take no parameter overrides", i);
+        if (renders[i].flags & ~(uint32_t)TRHIP_FLAG_PIXEL_CENTRE)
+            return fail(TRHIP_ERR_INVALID_ARG, "scene %u: batched renders accept only TRHIP_FLAG_PIXEL_CENTRE", i);
+        if (!films[i]) return fail(TRHIP_ERR_INVALID_ARG, "scene %u: film is NULL", i);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    trhip_batch* b = new (std::nothrow) trhip_batch();
+    if (!b) return fail(TRHIP_ERR_OOM, "host allocation failed");
+    b->magic = 0;
+    b->scenes.assign(scenes, scenes + n_scenes);
+    b->views.resize(n_scenes);
+    b->args.resize(n_scenes);
+    b->depth = 1;
+    std::vector<double> cost(n_scenes);
+    for (uint32_t i = 0; i < n_scenes; ++i) {
+        b->views[i] = scenes[i]->view;
+        fill_launch(scenes[i], &renders[i], 1, &b->args[i]);
+        b->args[i].film = films[i];
+        b->depth = std::max(b->depth, scenes[i]->view.stack_depth);
+        cost[i] = (double)scenes[i]->n_pixels * renders[i].spp * (double)(scenes[i]->view.stack_depth + 4);
+    }
+    b->order.resize(n_scenes);
+    for (uint32_t i = 0; i < n_scenes; ++i) b->order[i] = i;
+    std::stable_sort(b->order.begin(), b->order.end(), [&](uint32_t a, uint32_t c) { return cost[a] > cost[c]; });
+    int device = 0, n_cu = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
+    if (e == hipSuccess) e = hipMalloc(&b->d_views, n_scenes * sizeof(trhip::SceneView));
+    if (e == hipSuccess) e = hipMalloc(&b->d_args, n_scenes * sizeof(trhip::LaunchArgs));
+    if (e == hipSuccess) e = hipMalloc(&b->d_item_start, (n_scenes + 1) * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&b->d_order, n_scenes * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc(&b->d_cursor, sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_views, b->views.data(), n_scenes * sizeof(trhip::SceneView), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_order, b->order.data(), n_scenes * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        free_batch(b);
+        return hip_fail(e, "batch tables");
+    }
+
+    // candidate shapes: the fields the caller left 0
+    const std::vector<uint32_t> blocks = o.block_size ? std::vector<uint32_t>{o.block_size}
+                                                      : std::vector<uint32_t>{64, 128, 256};
+    const std::vector<uint32_t> tiles = o.tile_pixels ? std::vector<uint32_t>{o.tile_pixels}
+                                                      : std::vector<uint32_t>{1, 2, 4};
+    const std::vector<uint32_t> gpcs = o.groups_per_cu ? std::vector<uint32_t>{o.groups_per_cu}
+                                                       : std::vector<uint32_t>{2, 4, 8};
+    std::array<uint32_t, 3> best{0, 0, 0};
+    float best_ms = 0.0f;
+    const uint64_t key = tune_key(b, device, o);
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lock(g_batch_mutex);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            best = it->second;
+            cached = true;
+        }
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    uint32_t timed = 0;
+    if (!cached && o.autotune) {
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        e = hipEventCreate(&ev0);
+        if (e == hipSuccess) e = hipEventCreate(&ev1);
+        float best_t = 0.0f;
+        for (uint32_t bs : blocks)
+            for (uint32_t tp : tiles)
+                for (uint32_t g : gpcs) {
+                    if (e != hipSuccess) break;
+                    bool fits = false;
+                    e = stage_shape(b, bs, tp, g, s, &fits);
+                    if (e != hipSuccess || !fits) continue;
+                    const uint32_t groups = std::max<uint32_t>(1u, (uint32_t)n_cu * g);
+                    e = trhip::launch_batch(b->tables, groups, bs, b->depth, s);  // warm-up
+                    if (e == hipSuccess) e = hipEventRecord(ev0, s);
+                    if (e == hipSuccess) e = trhip::launch_batch(b->tables, groups, bs, b->depth, s);
+                    if (e == hipSuccess) e = hipEventRecord(ev1, s);
+                    if (e == hipSuccess) e = hipEventSynchronize(ev1);
+                    float ms = 0.0f;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+                    if (e != hipSuccess) break;
+                    ++timed;
+                    if (best[0] == 0 || ms < best_t) {
+                        best_t = ms;
+                        best = {bs, tp, g};
+                    }
+                }
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (e != hipSuccess) {
+            free_batch(b);
+            return hip_fail(e, "batch autotune");
+        }
+        best_ms = best_t;
+        if (best[0]) {
+            std::lock_guard<std::mutex> lock(g_batch_mutex);
+            g_tune_cache[key] = best;
+        }
+    }
+    if (best[0] == 0) {
+        // untuned default: the largest block whose LDS fits, 1 pixel per item, 4 groups per CU
+        for (uint32_t bs : {256u, 128u, 64u}) {
+            if (o.block_size && bs != o.block_size) continue;
+            bool fits = false;
+            e = stage_shape(b, bs, o.tile_pixels ? o.tile_pixels : 1u, o.groups_per_cu ? o.groups_per_cu : 4u, s,
+                            &fits);
+            if (e != hipSuccess || fits) {
+                best = {bs, o.tile_pixels ? o.tile_pixels : 1u, o.groups_per_cu ? o.groups_per_cu : 4u};
+                break;
+            }
+        }
+    }
+    const float tune_ms =
+        std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    bool fits = false;
+    if (e == hipSuccess && best[0]) e = stage_shape(b, best[0], best[1], best[2], s, &fits);
+    if (e != hipSuccess) {
+        free_batch(b);
+        return hip_fail(e, "batch staging");
+    }
+    if (!best[0] || !fits) {
+        free_batch(b);
+        return fail(TRHIP_ERR_UNSUPPORTED, "no batch launch shape fits in %zu bytes of LDS", kLdsBudget);
+    }
+    // capture [cursor reset -> persistent kernel] once
+    const uint32_t groups = std::max<uint32_t>(1u, (uint32_t)n_cu * b->groups);
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = trhip::launch_batch(b->tables, groups, b->block, b->depth, cs);
+        e = hipStreamEndCapture(cs, &b->graph);
+        if (e == hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        free_batch(b);
+        return hip_fail(e, "batch graph capture");
+    }
+    b->groups = groups;
+    b->info.n_scenes = n_scenes;
+    b->info.n_items = b->tables.n_items;
+    b->info.block_size = b->block;
+    b->info.tile_pixels = b->tile;
+    b->info.groups = groups;
+    b->info.stack_depth = b->depth;
+    b->info.lds_bytes = b->lds;
+    b->info.candidates = timed;
+    b->info.tune_ms = timed ? tune_ms : 0.0f;
+    b->info.best_ms = best_ms;
+    b->magic = kBatchMagic;
+    {
+        std::lock_guard<std::mutex> lock(g_batch_mutex);
+        g_live_batches.insert(b);
+    }
+    *out = b;
+    return TRHIP_OK;
+}
+
+trhip_status trhip_batch_render(trhip_batch* batch, void* stream)
+{
+    if (!batch_live(batch)) return fail(TRHIP_ERR_BAD_HANDLE, "invalid batch handle");
+    for (trhip_scene* sc : batch->scenes)
+        if (!is_live(sc)) return fail(TRHIP_ERR_BAD_HANDLE, "a scene of the batch was destroyed");
+    hipError_t e = hipGraphLaunch(batch->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "batch graph launch");
+    return TRHIP_OK;
+}
+
+trhip_status trhip_batch_get_info(const trhip_batch* batch, trhip_batch_info* info)
+{
+    if (!batch_live(batch)) return fail(TRHIP_ERR_BAD_HANDLE, "invalid batch handle");
+    if (!info) return fail(TRHIP_ERR_INVALID_ARG, "info is NULL");
+    *info = batch->info;
+    return TRHIP_OK;
+}
+
+trhip_status trhip_batch_destroy(trhip_batch* batch)
+{
+    if (!batch) return TRHIP_OK;
+    {
+        std::lock_guard<std::mutex> lock(g_batch_mutex);
+        if (!g_live_batches.erase(batch)) return fail(TRHIP_ERR_BAD_HANDLE, "invalid batch handle");
+    }
+    (void)hipDeviceSynchronize();
+    free_batch(batch);
+    return TRHIP_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
 
 const char* trhip_status_string(trhip_status status)
 {

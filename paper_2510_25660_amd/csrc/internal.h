@@ -25,6 +25,7 @@ hipError_t build_bvh(const float* d_tri9, uint32_t nt, hipStream_t stream, BvhBu
 
 // LDS bytes of one render / backward workgroup
 size_t render_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth);
+size_t wavefront_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth);
 size_t backward_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth,
                           bool primal);
 
@@ -33,7 +34,13 @@ size_t backward_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block,
 // contributions); selects the counting build of the kernel
 hipError_t launch_render(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
                          unsigned long long* counts = nullptr);
+hipError_t launch_render_wavefront(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
+                                   unsigned long long* counts = nullptr);
 hipError_t launch_backward(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream);
+size_t batch_lds_bytes(uint32_t film_words, uint32_t block, uint32_t stack_depth);
+// resets the cursor and launches the persistent kernel (groups workgroups)
+hipError_t launch_batch(const BatchTables& B, uint32_t groups, uint32_t block, uint32_t stack_depth,
+                        hipStream_t stream);
 hipError_t launch_zero_f64(double* p, size_t n, hipStream_t stream);
 hipError_t launch_f64_to_f32(const double* src, float* dst, size_t n, hipStream_t stream);
 hipError_t launch_scene_fill(const float* tri9, uint32_t nt, hipStream_t stream);

@@ -258,6 +258,238 @@ __device__ __forceinline__ vec3 ld3(const float* p) { return v3(p[0], p[1], p[2]
 
 constexpr float kShadowShrink = 1.0f - 0x1p-10f;
 
+// State of one path between two closest-hit queries.
+struct PathState {
+    vec3 o, d;     // next ray
+    float beta;    // throughput
+    float opl;     // optical path length so far
+    float u_ff;    // uniform of the next free flight
+    int prev;      // caller index of the triangle the ray leaves (-1: none)
+    int v;         // index of the vertex the next ray creates (1-based)
+};
+
+// A next-event connection waiting for its shadow ray.
+struct Nee {
+    vec3 so, sd;   // shadow ray
+    float tmax;
+    int excl;      // triangle excluded from the shadow test
+    float c;       // contribution if unoccluded
+    int bin;       // -1: outside the film window
+    int k;         // triangle of the vertex (-1: medium vertex)
+    float g_alb, g_rough;  // d log f of the connection
+    bool valid;
+};
+
+// Outcome of the continuation at a vertex.
+struct Cont {
+    bool alive;    // the path continues with ps.o, ps.d
+    int k;         // triangle of the vertex (-1: medium)
+    float g_alb, g_rough;  // d log f of the sampled direction (surface only)
+};
+
+__device__ __forceinline__ int last_vertex(const SceneView& S, const LaunchArgs& L)
+{
+    return (S.sensor == 1) ? (int)L.max_depth - 3 : (int)L.max_depth - 1;
+}
+
+// Generation (Philox block 0): the camera ray through the jittered pixel, or
+// for the confocal sensor the cosine-sampled ray leaving the scan point of
+// the relay wall (a Lambertian vertex whose sampling weight is its albedo).
+__device__ __forceinline__ void begin_path(const SceneView& S, const LaunchArgs& L, uint32_t pix, uint32_t sample,
+                                           PathState& ps)
+{
+    const rand4 u = draw4(pix, sample, 0u, L.stream_id, L.key0, L.key1);
+    ps.u_ff = u.u2;
+    if (S.sensor != 1) {
+        const uint32_t ix = pix % S.width, iy = pix / S.width;
+        const bool centre = (L.flags & kFlagPixelCentre) != 0;
+        const float jx = centre ? 0.5f : u.u0, jy = centre ? 0.5f : u.u1;
+        const float fx = (float)ix + jx, fy = (float)iy + jy;
+        const float sx = ((fx * 2.0f) / (float)S.width - 1.0f) * S.tan_x;
+        const float sy = (1.0f - (fy * 2.0f) / (float)S.height) * S.tan_y;
+        ps.d = normalize(v3(fmaf(S.cam_u[0], sy, fmaf(S.cam_r[0], sx, S.cam_f[0])),
+                            fmaf(S.cam_u[1], sy, fmaf(S.cam_r[1], sx, S.cam_f[1])),
+                            fmaf(S.cam_u[2], sy, fmaf(S.cam_r[2], sx, S.cam_f[2]))));
+        ps.o = ld3(S.cam_o);
+        ps.beta = 1.0f;
+    } else {
+        const vec3 wall_n = ld3(S.wall_n);
+        const vec3 xs = ld3(S.scan + 3ull * pix);
+        vec3 t, b;
+        basis(wall_n, t, b);
+        ps.d = local_to_world(t, b, wall_n, cosine_dir(u.u0, u.u1));
+        ps.o = nudge(xs, wall_n);
+        ps.beta = S.wall_albedo;
+    }
+    ps.opl = 0.0f;
+    ps.prev = -1;
+    ps.v = 1;
+}
+
+// Free flight in the medium against the surface hit: returns whether a
+// vertex exists and sets its distance and kind.
+__device__ __forceinline__ bool resolve_event(const SceneView& S, const PathState& ps, const Hit& h, float& t_hit,
+                                              bool& med)
+{
+    const bool hit = h.prim >= 0;
+    t_hit = h.t;
+    med = false;
+    if (S.sigma_t > 0.0f) {
+        const float t_ff = -log_one_minus(ps.u_ff) / S.sigma_t;
+        if (!hit || t_ff < t_hit) {
+            med = true;
+            t_hit = t_ff;
+        }
+    }
+    return hit || med;
+}
+
+// Everything at one vertex except the two traversals: the next-event
+// connection (value, bin, shadow ray) and the continuation (Philox block v),
+// which updates ps in place.
+template <bool kGrad, class TallyT>
+__device__ __forceinline__ void shade_vertex(const SceneView& S, const LaunchArgs& L, uint32_t pix, uint32_t sample,
+                                             PathState& ps, const Hit& h, float t_hit, bool med, Nee& nee,
+                                             Cont& cont, TallyT& tally)
+{
+    const bool confocal = S.sensor == 1;
+    const bool medium = S.sigma_t > 0.0f;
+    const int vmax = last_vertex(S, L);
+    const int v = ps.v;
+    tally.add(kTallyVerts);
+    nee.valid = false;
+    cont.alive = false;
+    cont.k = med ? -1 : h.prim;
+    cont.g_alb = 0.0f;
+    cont.g_rough = 0.0f;
+    const vec3 target = confocal ? ld3(S.scan + 3ull * pix) : ld3(S.light);
+    const vec3 x = along(ps.o, ps.d, t_hit);
+    if (!(S.unwarp && !confocal && v == 1)) ps.opl = ps.opl + t_hit;
+    const vec3 wo = neg(ps.d);
+    const vec3 dl = sub(target, x);
+    const float d2 = dot(dl, dl);
+    const float dist = sqrtf(d2);
+    const vec3 wl = scale(dl, 1.0f / dist);
+    float em;
+    if (confocal) {
+        const float cos_s = -dot(ld3(S.wall_n), wl);
+        em = (cos_s > 0.0f) ? ((S.wall_albedo * S.laser_power) * kInvPi) * cos_s : 0.0f;
+    } else {
+        em = S.intensity;
+    }
+    const float opl_c = ps.opl + dist;
+    const float q = (opl_c - S.bin_start) / S.bin_width;
+    nee.bin = (q >= 0.0f && q < (float)S.n_bins) ? (int)q : -1;
+    nee.sd = wl;
+    nee.tmax = dist * kShadowShrink;
+    if (med) {
+        ps.beta = ps.beta * S.medium_albedo;
+        if (em > 0.0f) {
+            float c = ((ps.beta * kInv4Pi) * em) / d2;
+            c = c * expf(-(S.sigma_t * dist));
+            nee.valid = true;
+            nee.so = x;
+            nee.excl = -1;
+            nee.c = c;
+            nee.k = -1;
+            nee.g_alb = 0.0f;
+            nee.g_rough = 0.0f;
+        }
+        if (v == vmax) return;
+        tally.add(kTallyDraws);
+        const rand4 u = draw4(pix, sample, (uint32_t)v, L.stream_id, L.key0, L.key1);
+        const float z = 1.0f - (u.u0 + u.u0);
+        const float rr = sqrtf(fmaxf(0.0f, 1.0f - z * z));
+        float sn, cs;
+        sincos_2pi(u.u1, sn, cs);
+        ps.d = v3(rr * cs, rr * sn, z);
+        ps.o = x;
+        ps.prev = -1;
+        ps.u_ff = u.u3;
+        ps.v = v + 1;
+        cont.alive = true;
+        return;
+    }
+    // surface vertex: two-sided, shading normal = geometric normal flipped
+    // toward wo
+    const TriRec tr = load_tri(S.tris, h.sorted);
+    const vec3 ng = normalize(cross(v3(tr.e1x, tr.e1y, tr.e1z), v3(tr.e2x, tr.e2y, tr.e2z)));
+    const vec3 n = (dot(ng, wo) < 0.0f) ? neg(ng) : ng;
+    if (!(dot(n, wo) > 0.0f)) return;
+    const int k = h.prim;
+    const bool ggx = S.mat[k] == 1;
+    const float albedo = L.albedo[k];
+    vec3 tb, bb;
+    basis(n, tb, bb);
+    const vec3 wol = v3(dot(wo, tb), dot(wo, bb), dot(wo, n));
+    float fcos = 0.0f, g_rough = 0.0f;
+    {
+        const float cos_l = dot(n, wl);
+        if (cos_l > 0.0f) {
+            if (ggx) {
+                const float alpha = L.rough_eval[k];
+                const vec3 wll = v3(dot(wl, tb), dot(wl, bb), dot(wl, n));
+                const float f = ggx_eval(wol, wll, alpha, albedo);
+                if (f > 0.0f) {
+                    fcos = f * wll.z;
+                    if (kGrad) g_rough = ggx_dlog_dalpha(wol, wll, alpha);
+                }
+            } else {
+                fcos = (albedo * kInvPi) * cos_l;
+            }
+        }
+    }
+    if (fcos > 0.0f && em > 0.0f) {
+        float c = ((ps.beta * fcos) * em) / d2;
+        if (medium) c = c * expf(-(S.sigma_t * dist));
+        nee.valid = true;
+        nee.so = nudge(x, n);
+        nee.excl = k;
+        nee.c = c;
+        nee.k = k;
+        nee.g_alb = 1.0f / albedo;
+        nee.g_rough = g_rough;
+    }
+    if (v == vmax) return;
+    tally.add(kTallyDraws);
+    const rand4 u = draw4(pix, sample, (uint32_t)v, L.stream_id, L.key0, L.key1);
+    vec3 wi;
+    float w;
+    float gc_rough = 0.0f;
+    if (ggx) {
+        const float alpha = L.rough_eval[k];
+        const float alpha_s = L.rough_sample[k];
+        if (!(wol.z > 0.0f)) return;
+        const vec3 wil = ggx_vndf_sample(wol, alpha_s, u.u0, u.u1);
+        if (!(wil.z > 0.0f)) return;
+        if (L.flags & kFlagFrozen) {
+            const float pdf = ggx_vndf_pdf(wol, wil, alpha_s);
+            const float f = ggx_eval(wol, wil, alpha, albedo);
+            if (!(pdf > 0.0f)) return;
+            w = (f * wil.z) / pdf;
+        } else {
+            const float a2 = alpha * alpha;
+            const float lo = smith_lambda(wol, a2), li = smith_lambda(wil, a2);
+            w = albedo * ((1.0f + lo) / ((1.0f + lo) + li));
+        }
+        if (!(w > 0.0f)) return;
+        if (kGrad) gc_rough = ggx_dlog_dalpha(wol, wil, alpha);
+        wi = local_to_world(tb, bb, n, wil);
+    } else {
+        wi = local_to_world(tb, bb, n, cosine_dir(u.u0, u.u1));
+        w = albedo;
+    }
+    cont.alive = true;
+    cont.g_alb = 1.0f / albedo;
+    cont.g_rough = gc_rough;
+    ps.beta = ps.beta * w;
+    ps.d = wi;
+    ps.o = nudge(x, n);
+    ps.prev = k;
+    ps.u_ff = u.u3;
+    ps.v = v + 1;
+}
+
 // Traces one path and reports, through the sink, every next-event
 // contribution (vertex index, triangle, value, bin, d log f factors of the
 // connection) and every continuation (triangle, d log f factors of the
@@ -268,171 +500,24 @@ __device__ void trace_path(const SceneView& S, const LaunchArgs& L, uint32_t pix
                            int stride, Sink& sink, TallyT& tally)
 {
     tally.add(kTallyDraws);
-    const bool confocal = S.sensor == 1;
-    const bool medium = S.sigma_t > 0.0f;
-    rand4 u = draw4(pix, sample, 0u, L.stream_id, L.key0, L.key1);
-    float u_ff = u.u2;
-    vec3 o, d, target;
-    float beta;
-    int vmax;
-    const vec3 wall_n = ld3(S.wall_n);
-    if (!confocal) {
-        const uint32_t ix = pix % S.width, iy = pix / S.width;
-        const bool centre = (L.flags & kFlagPixelCentre) != 0;
-        const float jx = centre ? 0.5f : u.u0, jy = centre ? 0.5f : u.u1;
-        const float fx = (float)ix + jx, fy = (float)iy + jy;
-        const float sx = ((fx * 2.0f) / (float)S.width - 1.0f) * S.tan_x;
-        const float sy = (1.0f - (fy * 2.0f) / (float)S.height) * S.tan_y;
-        d = normalize(v3(fmaf(S.cam_u[0], sy, fmaf(S.cam_r[0], sx, S.cam_f[0])),
-                         fmaf(S.cam_u[1], sy, fmaf(S.cam_r[1], sx, S.cam_f[1])),
-                         fmaf(S.cam_u[2], sy, fmaf(S.cam_r[2], sx, S.cam_f[2]))));
-        o = ld3(S.cam_o);
-        beta = 1.0f;
-        vmax = (int)L.max_depth - 1;
-        target = ld3(S.light);
-    } else {
-        // the path leaves the scan point of the relay wall, a Lambertian
-        // vertex whose cosine-sampling weight is its albedo
-        const vec3 xs = ld3(S.scan + 3ull * pix);
-        vec3 t, b;
-        basis(wall_n, t, b);
-        d = local_to_world(t, b, wall_n, cosine_dir(u.u0, u.u1));
-        o = nudge(xs, wall_n);
-        beta = S.wall_albedo;
-        vmax = (int)L.max_depth - 3;
-        target = xs;
-    }
-    int prev = -1;
-    float opl = 0.0f;
-    for (int v = 1; v <= vmax; ++v) {
-        const Ray ray = make_ray(o, d);
-        const Hit h = closest_hit(S, ray, prev, stk, stride, tally);
-        const bool hit = h.prim >= 0;
-        float t_hit = h.t;
-        bool med = false;
-        if (medium) {
-            const float t_ff = -log_one_minus(u_ff) / S.sigma_t;
-            if (!hit || t_ff < t_hit) {
-                med = true;
-                t_hit = t_ff;
-            }
+    PathState ps;
+    begin_path(S, L, pix, sample, ps);
+    const int vmax = last_vertex(S, L);
+    while (ps.v <= vmax) {
+        const int v = ps.v;
+        const Hit h = closest_hit(S, make_ray(ps.o, ps.d), ps.prev, stk, stride, tally);
+        float t_hit;
+        bool med;
+        if (!resolve_event(S, ps, h, t_hit, med)) break;
+        Nee nee;
+        Cont cont;
+        shade_vertex<Sink::kWantsGradients>(S, L, pix, sample, ps, h, t_hit, med, nee, cont, tally);
+        if (nee.valid && !occluded(S, make_ray(nee.so, nee.sd), nee.excl, nee.tmax, stk, stride, tally)) {
+            tally.add(kTallyContrib);
+            sink.contribution(v, nee.k, nee.c, nee.bin, nee.g_alb, nee.g_rough);
         }
-        if (!hit && !med) break;
-        tally.add(kTallyVerts);
-        const vec3 x = along(o, d, t_hit);
-        if (!(S.unwarp && !confocal && v == 1)) opl = opl + t_hit;
-        const vec3 wo = neg(d);
-        const vec3 dl = sub(target, x);
-        const float d2 = dot(dl, dl);
-        const float dist = sqrtf(d2);
-        const vec3 wl = scale(dl, 1.0f / dist);
-        float em;
-        if (confocal) {
-            const float cos_s = -dot(wall_n, wl);
-            em = (cos_s > 0.0f) ? ((S.wall_albedo * S.laser_power) * kInvPi) * cos_s : 0.0f;
-        } else {
-            em = S.intensity;
-        }
-        const float opl_c = opl + dist;
-        const float q = (opl_c - S.bin_start) / S.bin_width;
-        const int bin = (q >= 0.0f && q < (float)S.n_bins) ? (int)q : -1;
-        if (med) {
-            beta = beta * S.medium_albedo;
-            if (em > 0.0f) {
-                const Ray sh = make_ray(x, wl);
-                if (!occluded(S, sh, -1, dist * kShadowShrink, stk, stride, tally)) {
-                    tally.add(kTallyContrib);
-                    float c = ((beta * kInv4Pi) * em) / d2;
-                    c = c * expf(-(S.sigma_t * dist));
-                    sink.contribution(v, -1, c, bin, 0.0f, 0.0f);
-                }
-            }
-            if (v == vmax) break;
-            tally.add(kTallyDraws);
-            u = draw4(pix, sample, (uint32_t)v, L.stream_id, L.key0, L.key1);
-            const float z = 1.0f - (u.u0 + u.u0);
-            const float rr = sqrtf(fmaxf(0.0f, 1.0f - z * z));
-            float sn, cs;
-            sincos_2pi(u.u1, sn, cs);
-            d = v3(rr * cs, rr * sn, z);
-            o = x;
-            prev = -1;
-            u_ff = u.u3;
-            continue;
-        }
-        // surface vertex: two-sided, shading normal = geometric normal
-        // flipped toward wo
-        const TriRec tr = load_tri(S.tris, h.sorted);
-        const vec3 ng = normalize(cross(v3(tr.e1x, tr.e1y, tr.e1z), v3(tr.e2x, tr.e2y, tr.e2z)));
-        const vec3 n = (dot(ng, wo) < 0.0f) ? neg(ng) : ng;
-        if (!(dot(n, wo) > 0.0f)) break;
-        const int k = h.prim;
-        const bool ggx = S.mat[k] == 1;
-        const float albedo = L.albedo[k];
-        vec3 tb, bb;
-        basis(n, tb, bb);
-        const vec3 wol = v3(dot(wo, tb), dot(wo, bb), dot(wo, n));
-        float fcos = 0.0f, g_rough = 0.0f;
-        {
-            const float cos_l = dot(n, wl);
-            if (cos_l > 0.0f) {
-                if (ggx) {
-                    const float alpha = L.rough_eval[k];
-                    const vec3 wll = v3(dot(wl, tb), dot(wl, bb), dot(wl, n));
-                    const float f = ggx_eval(wol, wll, alpha, albedo);
-                    if (f > 0.0f) {
-                        fcos = f * wll.z;
-                        if (Sink::kWantsGradients) g_rough = ggx_dlog_dalpha(wol, wll, alpha);
-                    }
-                } else {
-                    fcos = (albedo * kInvPi) * cos_l;
-                }
-            }
-        }
-        if (fcos > 0.0f && em > 0.0f) {
-            const Ray sh = make_ray(nudge(x, n), wl);
-            if (!occluded(S, sh, k, dist * kShadowShrink, stk, stride, tally)) {
-                tally.add(kTallyContrib);
-                float c = ((beta * fcos) * em) / d2;
-                if (medium) c = c * expf(-(S.sigma_t * dist));
-                sink.contribution(v, k, c, bin, 1.0f / albedo, g_rough);
-            }
-        }
-        if (v == vmax) break;
-        tally.add(kTallyDraws);
-        u = draw4(pix, sample, (uint32_t)v, L.stream_id, L.key0, L.key1);
-        vec3 wi;
-        float w;
-        float gc_rough = 0.0f;
-        if (ggx) {
-            const float alpha = L.rough_eval[k];
-            const float alpha_s = L.rough_sample[k];
-            if (!(wol.z > 0.0f)) break;
-            const vec3 wil = ggx_vndf_sample(wol, alpha_s, u.u0, u.u1);
-            if (!(wil.z > 0.0f)) break;
-            if (L.flags & kFlagFrozen) {
-                const float pdf = ggx_vndf_pdf(wol, wil, alpha_s);
-                const float f = ggx_eval(wol, wil, alpha, albedo);
-                if (!(pdf > 0.0f)) break;
-                w = (f * wil.z) / pdf;
-            } else {
-                const float a2 = alpha * alpha;
-                const float lo = smith_lambda(wol, a2), li = smith_lambda(wil, a2);
-                w = albedo * ((1.0f + lo) / ((1.0f + lo) + li));
-            }
-            if (!(w > 0.0f)) break;
-            if (Sink::kWantsGradients) gc_rough = ggx_dlog_dalpha(wol, wil, alpha);
-            wi = local_to_world(tb, bb, n, wil);
-        } else {
-            wi = local_to_world(tb, bb, n, cosine_dir(u.u0, u.u1));
-            w = albedo;
-        }
-        sink.continuation(k, 1.0f / albedo, gc_rough);
-        beta = beta * w;
-        d = wi;
-        o = nudge(x, n);
-        prev = k;
-        u_ff = u.u3;
+        if (!cont.alive) break;
+        if (cont.k >= 0) sink.continuation(cont.k, cont.g_alb, cont.g_rough);
     }
 }
 
@@ -453,21 +538,21 @@ struct FilmSink {
     __device__ __forceinline__ void continuation(int, float, float) {}
 };
 
-template <bool kCount>
-__global__ void __launch_bounds__(256) k_render(SceneView S, LaunchArgs L, unsigned long long* counts)
+// Renders one tile of pixels [p0, p0 + tile_pixels) with all their samples:
+// LDS film rows (zeroed here), paths traced one per lane, then one
+// coalesced write (or accumulate) of the tile to HBM.  lds_film holds
+// tile_pixels * n_bins + 2 * tile_pixels floats; stk is the lane's stack.
+template <class TallyT>
+__device__ __forceinline__ void render_tile(const SceneView& S, const LaunchArgs& L, uint32_t p0, float* lds_film,
+                                            uint32_t* stk, int stride, TallyT& tally)
 {
-    Tally<kCount> tally;
-    extern __shared__ float lds[];
     const uint32_t T = S.n_bins;
     const uint32_t TP = L.tile_pixels;
-    float* tfilm = lds;
-    float* tsteady = lds + (size_t)TP * T;
+    float* tfilm = lds_film;
+    float* tsteady = lds_film + (size_t)TP * T;
     float* toow = tsteady + TP;
-    uint32_t* stk = reinterpret_cast<uint32_t*>(toow + TP) + threadIdx.x;
-    const int stride = (int)blockDim.x;
-    const uint32_t p0 = blockIdx.x * TP;
     const uint32_t npix = min(TP, L.n_pixels - p0);
-    for (uint32_t i = threadIdx.x; i < TP * T + 2 * TP; i += blockDim.x) lds[i] = 0.0f;
+    for (uint32_t i = threadIdx.x; i < TP * T + 2 * TP; i += blockDim.x) lds_film[i] = 0.0f;
     __syncthreads();
 
     const uint32_t work = npix * L.spp;
@@ -488,7 +573,6 @@ __global__ void __launch_bounds__(256) k_render(SceneView S, LaunchArgs L, unsig
         }
         trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, sink, tally);
     }
-    tally.flush(counts);
     if (cur != 0xffffffffu) {
         atomicAdd(tsteady + cur, sink.steady);
         atomicAdd(toow + cur, sink.oow);
@@ -510,6 +594,253 @@ __global__ void __launch_bounds__(256) k_render(SceneView S, LaunchArgs L, unsig
         }
         if (L.oow) {
             const float v = toow[threadIdx.x] * L.norm;
+            L.oow[p] = acc ? L.oow[p] + v : v;
+        }
+    }
+}
+
+template <bool kCount>
+__global__ void __launch_bounds__(256) k_render(SceneView S, LaunchArgs L, unsigned long long* counts)
+{
+    Tally<kCount> tally;
+    extern __shared__ float lds[];
+    const uint32_t TP = L.tile_pixels;
+    uint32_t* stk = reinterpret_cast<uint32_t*>(lds + (size_t)TP * S.n_bins + 2 * TP) + threadIdx.x;
+    render_tile(S, L, blockIdx.x * TP, lds, stk, (int)blockDim.x, tally);
+    tally.flush(counts);
+}
+
+// ---------------------------------------------------------------------------
+// batched persistent form: many scenes, one launch
+// ---------------------------------------------------------------------------
+// Work items are (scene, pixel tile) pairs numbered scene by scene in the
+// processing order; a workgroup pops items from a global cursor until they
+// run out, so scenes of very different cost balance themselves.
+__global__ void __launch_bounds__(256) k_batch(BatchTables B)
+{
+    extern __shared__ float lds[];
+    __shared__ uint32_t s_item;
+    Tally<false> tally;
+    uint32_t* stk = reinterpret_cast<uint32_t*>(lds + B.film_words) + threadIdx.x;
+    while (true) {
+        if (threadIdx.x == 0) s_item = atomicAdd(B.cursor, 1u);
+        __syncthreads();
+        const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
+        if (item >= B.n_items) break;
+        uint32_t lo = 0, hi = B.n_scenes;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (B.item_start[mid] <= item) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t scene = __builtin_amdgcn_readfirstlane(B.order[lo]);
+        const uint32_t tile = item - B.item_start[lo];
+        const SceneView* __restrict__ views = B.views;
+        const LaunchArgs* __restrict__ args = B.args;
+        render_tile(views[scene], args[scene], tile * args[scene].tile_pixels, lds, stk, (int)blockDim.x, tally);
+        __syncthreads();
+    }
+}
+
+__global__ void k_reset_cursor(uint32_t* cursor)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *cursor = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// forward render, wavefront form: one workgroup runs the stages of its
+// tile's paths over queues kept in LDS
+// ---------------------------------------------------------------------------
+// Each lane owns one path slot (SoA arrays in LDS).  A round is
+//   GEN       dead slots take the next (pixel, sample) of the tile,
+//   INTERSECT closest hit + free flight for every live ray (ray queue),
+//   SHADE     next-event geometry and continuation for every vertex (hit
+//             queue), producing shadow records (shadow queue) and the
+//             continuing rays (ray queue of the next round),
+//   SHADOW    any-hit for every shadow record, accumulation into the tile
+//             film in LDS,
+// with a barrier between stages.  Compaction into queues keeps the costly
+// stages dense: a wave that has no entry in a queue skips that stage and
+// leaves its SIMD to other waves.
+constexpr int kWfWords = 31;  // 32-bit words of LDS per slot
+
+struct WfSlots {
+    float *ox, *oy, *oz, *dx, *dy, *dz, *beta, *opl, *uff;
+    int *prev, *v, *pl, *live;
+    uint32_t* sample;
+    float* ht;
+    int *hprim, *hsorted, *hmed;
+    float *sox, *soy, *soz, *sdx, *sdy, *sdz, *stmax, *sc;
+    int *sexcl, *sbin;
+    int *ray_q, *hit_q, *sh_q;
+};
+
+__device__ __forceinline__ WfSlots carve_slots(float* base, int ns)
+{
+    WfSlots w;
+    float* f = base;
+    auto take_f = [&]() { float* r = f; f += ns; return r; };
+    auto take_i = [&]() { int* r = reinterpret_cast<int*>(f); f += ns; return r; };
+    w.ox = take_f(); w.oy = take_f(); w.oz = take_f();
+    w.dx = take_f(); w.dy = take_f(); w.dz = take_f();
+    w.beta = take_f(); w.opl = take_f(); w.uff = take_f();
+    w.prev = take_i(); w.v = take_i(); w.pl = take_i(); w.live = take_i();
+    w.sample = reinterpret_cast<uint32_t*>(take_i());
+    w.ht = take_f(); w.hprim = take_i(); w.hsorted = take_i(); w.hmed = take_i();
+    w.sox = take_f(); w.soy = take_f(); w.soz = take_f();
+    w.sdx = take_f(); w.sdy = take_f(); w.sdz = take_f();
+    w.stmax = take_f(); w.sc = take_f();
+    w.sexcl = take_i(); w.sbin = take_i();
+    w.ray_q = take_i(); w.hit_q = take_i(); w.sh_q = take_i();
+    return w;
+}
+
+__device__ __forceinline__ void store_state(const WfSlots& w, int i, const PathState& ps)
+{
+    w.ox[i] = ps.o.x; w.oy[i] = ps.o.y; w.oz[i] = ps.o.z;
+    w.dx[i] = ps.d.x; w.dy[i] = ps.d.y; w.dz[i] = ps.d.z;
+    w.beta[i] = ps.beta; w.opl[i] = ps.opl; w.uff[i] = ps.u_ff;
+    w.prev[i] = ps.prev; w.v[i] = ps.v;
+}
+
+__device__ __forceinline__ PathState load_state(const WfSlots& w, int i)
+{
+    PathState ps;
+    ps.o = v3(w.ox[i], w.oy[i], w.oz[i]);
+    ps.d = v3(w.dx[i], w.dy[i], w.dz[i]);
+    ps.beta = w.beta[i]; ps.opl = w.opl[i]; ps.u_ff = w.uff[i];
+    ps.prev = w.prev[i]; ps.v = w.v[i];
+    return ps;
+}
+
+template <bool kCount>
+__global__ void __launch_bounds__(256) k_render_wf(SceneView S, LaunchArgs L, unsigned long long* counts)
+{
+    extern __shared__ float lds[];
+    __shared__ uint32_t ctr[4];  // ray queue, hit queue, shadow queue, next work item
+    Tally<kCount> tally;
+    const uint32_t T = S.n_bins;
+    const uint32_t TP = L.tile_pixels;
+    const int nb = (int)blockDim.x;
+    const int tid = (int)threadIdx.x;
+    float* tfilm = lds;
+    float* tsteady = lds + (size_t)TP * T;
+    float* toow = tsteady + TP;
+    const WfSlots w = carve_slots(toow + TP, nb);
+    uint32_t* stk = reinterpret_cast<uint32_t*>(toow + TP + (size_t)kWfWords * nb) + tid;
+    const uint32_t p0 = blockIdx.x * TP;
+    const uint32_t npix = min(TP, L.n_pixels - p0);
+    for (uint32_t i = tid; i < TP * T + 2 * TP; i += nb) lds[i] = 0.0f;
+    w.live[tid] = 0;
+    if (tid < 4) ctr[tid] = 0u;
+    __syncthreads();
+    const uint32_t work = npix * L.spp;
+
+    while (true) {
+        // GEN: dead slots take new samples
+        if (!w.live[tid] && ctr[3] < work) {
+            const uint32_t item = atomicAdd(&ctr[3], 1u);
+            if (item < work) {
+                const uint32_t pl = item / L.spp;
+                const uint32_t s = L.sample_offset + (item - pl * L.spp);
+                tally.add(kTallyDraws);
+                PathState ps;
+                begin_path(S, L, p0 + pl, s, ps);
+                store_state(w, tid, ps);
+                w.pl[tid] = (int)pl;
+                w.sample[tid] = s;
+                w.live[tid] = 1;
+                w.ray_q[atomicAdd(&ctr[0], 1u)] = tid;
+            }
+        }
+        __syncthreads();
+        const int nr = (int)ctr[0];
+        if (nr == 0) break;
+        // INTERSECT
+        for (int j = tid; j < nr; j += nb) {
+            const int i = w.ray_q[j];
+            const PathState ps = load_state(w, i);
+            const Hit h = closest_hit(S, make_ray(ps.o, ps.d), ps.prev, stk, nb, tally);
+            float t_hit;
+            bool med;
+            if (resolve_event(S, ps, h, t_hit, med)) {
+                w.ht[i] = t_hit;
+                w.hprim[i] = h.prim;
+                w.hsorted[i] = h.sorted;
+                w.hmed[i] = med ? 1 : 0;
+                w.hit_q[atomicAdd(&ctr[1], 1u)] = i;
+            } else {
+                w.live[i] = 0;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) ctr[0] = 0u;
+        const int nh = (int)ctr[1];
+        __syncthreads();
+        // SHADE
+        for (int j = tid; j < nh; j += nb) {
+            const int i = w.hit_q[j];
+            PathState ps = load_state(w, i);
+            Hit h;
+            h.t = w.ht[i];
+            h.prim = w.hprim[i];
+            h.sorted = w.hsorted[i];
+            Nee nee;
+            Cont cont;
+            shade_vertex<false>(S, L, p0 + (uint32_t)w.pl[i], w.sample[i], ps, h, h.t, w.hmed[i] != 0, nee, cont,
+                                tally);
+            if (nee.valid) {
+                w.sox[i] = nee.so.x; w.soy[i] = nee.so.y; w.soz[i] = nee.so.z;
+                w.sdx[i] = nee.sd.x; w.sdy[i] = nee.sd.y; w.sdz[i] = nee.sd.z;
+                w.stmax[i] = nee.tmax; w.sc[i] = nee.c; w.sexcl[i] = nee.excl; w.sbin[i] = nee.bin;
+                w.sh_q[atomicAdd(&ctr[2], 1u)] = i;
+            }
+            if (cont.alive) {
+                store_state(w, i, ps);
+                w.ray_q[atomicAdd(&ctr[0], 1u)] = i;
+            } else {
+                w.live[i] = 0;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) ctr[1] = 0u;
+        const int ns = (int)ctr[2];
+        __syncthreads();
+        // SHADOW + accumulate into the tile film
+        for (int j = tid; j < ns; j += nb) {
+            const int i = w.sh_q[j];
+            const Ray sh = make_ray(v3(w.sox[i], w.soy[i], w.soz[i]), v3(w.sdx[i], w.sdy[i], w.sdz[i]));
+            if (!occluded(S, sh, w.sexcl[i], w.stmax[i], stk, nb, tally)) {
+                tally.add(kTallyContrib);
+                const float c = w.sc[i];
+                const int bin = w.sbin[i];
+                const int pl = w.pl[i];
+                if (bin >= 0) atomicAdd(tfilm + (size_t)pl * T + bin, c);
+                else atomicAdd(toow + pl, c);
+                atomicAdd(tsteady + pl, c);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) ctr[2] = 0u;
+    }
+    tally.flush(counts);
+    __syncthreads();
+
+    const bool acc = (L.flags & kFlagAccumulate) != 0;
+    const size_t base = (size_t)p0 * T;
+    const uint32_t nvals = npix * T;
+    for (uint32_t i = tid; i < nvals; i += nb) {
+        const float v = tfilm[i] * L.norm;
+        L.film[base + i] = acc ? L.film[base + i] + v : v;
+    }
+    if ((uint32_t)tid < npix) {
+        const uint32_t p = p0 + tid;
+        if (L.steady) {
+            const float v = tsteady[tid] * L.norm;
+            L.steady[p] = acc ? L.steady[p] + v : v;
+        }
+        if (L.oow) {
+            const float v = toow[tid] * L.norm;
             L.oow[p] = acc ? L.oow[p] + v : v;
         }
     }
@@ -621,10 +952,28 @@ size_t render_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, u
            (size_t)block * stack_depth * sizeof(uint32_t);
 }
 
+size_t wavefront_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth)
+{
+    return ((size_t)tile_pixels * n_bins + 2ull * tile_pixels) * sizeof(float) +
+           (size_t)kWfWords * block * sizeof(float) + (size_t)block * stack_depth * sizeof(uint32_t);
+}
+
 size_t backward_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth, bool primal)
 {
     return (size_t)tile_pixels * n_bins * sizeof(float) * (primal ? 2 : 1) +
            (size_t)block * stack_depth * sizeof(uint32_t);
+}
+
+hipError_t launch_render_wavefront(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
+                                   unsigned long long* counts)
+{
+    const uint32_t tiles = (L.n_pixels + L.tile_pixels - 1) / L.tile_pixels;
+    const size_t lds = wavefront_lds_bytes(L.tile_pixels, S.n_bins, block, S.stack_depth);
+    if (counts)
+        hipLaunchKernelGGL(k_render_wf<true>, dim3(tiles), dim3(block), lds, stream, S, L, counts);
+    else
+        hipLaunchKernelGGL(k_render_wf<false>, dim3(tiles), dim3(block), lds, stream, S, L, counts);
+    return hipGetLastError();
 }
 
 hipError_t launch_render(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
@@ -644,6 +993,20 @@ hipError_t launch_backward(const SceneView& S, const LaunchArgs& L, uint32_t blo
     const uint32_t tiles = (L.n_pixels + L.tile_pixels - 1) / L.tile_pixels;
     const size_t lds = backward_lds_bytes(L.tile_pixels, S.n_bins, block, S.stack_depth, L.primal != nullptr);
     hipLaunchKernelGGL(k_backward, dim3(tiles), dim3(block), lds, stream, S, L);
+    return hipGetLastError();
+}
+
+size_t batch_lds_bytes(uint32_t film_words, uint32_t block, uint32_t stack_depth)
+{
+    return (size_t)film_words * sizeof(float) + (size_t)block * stack_depth * sizeof(uint32_t);
+}
+
+hipError_t launch_batch(const BatchTables& B, uint32_t groups, uint32_t block, uint32_t stack_depth,
+                        hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_reset_cursor, dim3(1), dim3(64), 0, stream, B.cursor);
+    hipLaunchKernelGGL(k_batch, dim3(groups), dim3(block), batch_lds_bytes(B.film_words, block, stack_depth), stream,
+                       B);
     return hipGetLastError();
 }
 

@@ -75,4 +75,16 @@ struct LaunchArgs {
     float* primal;
 };
 
+// Tables of the batched persistent kernel (device memory).
+struct BatchTables {
+    const SceneView* views;      // [n_scenes]
+    const LaunchArgs* args;      // [n_scenes]
+    const uint32_t* item_start;  // [n_scenes + 1]: first work item of the k-th scene in processing order
+    const uint32_t* order;       // [n_scenes]: scene index of the k-th scene in processing order
+    uint32_t n_scenes;
+    uint32_t n_items;
+    uint32_t film_words;         // LDS floats reserved for the largest tile film
+    uint32_t* cursor;            // next work item
+};
+
 }  // namespace trhip

@@ -1,0 +1,114 @@
+"""Batched persistent rendering (one graph launch for many confocal scenes of
+uneven size) against the single-scene forward render and the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2510_25660_amd import scenes
+from tests.parity import compare_films
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tr():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs an MI355X"
+    import paper_2510_25660_amd as tr
+    return tr
+
+
+def _small_batch(n=10, spp=64):
+    return scenes.batched_nlos(n_scenes=n, spp=spp, tri_range=(300, 6000), grid_range=(4, 12),
+                               bins_range=(256, 1024))
+
+
+@pytest.mark.parametrize("autotune", [False, True])
+def test_batch_matches_single_renders(tr, autotune):
+    import torch
+    scs = _small_batch()
+    _announce(f"batch of {len(scs)} autotune={autotune}")
+    devs = [tr.upload(s) for s in scs]
+    try:
+        with tr.Batch(devs, autotune=autotune) as b:
+            info = b.info()
+            assert info["n_scenes"] == len(scs)
+            assert info["n_items"] >= sum(s.n_pixels for s in scs) // max(1, info["tile_pixels"])
+            films = [f.clone() for f in b.render()]
+            torch.cuda.synchronize()
+        for d, f in zip(devs, films):
+            _, ref = tr.render_transient(d)
+            torch.cuda.synchronize()
+            a, r = f.cpu().numpy(), ref.cpu().numpy()
+            assert ((a != 0) == (r != 0)).all()
+            np.testing.assert_allclose(a, r, rtol=1e-5, atol=0)
+    finally:
+        for d in devs:
+            d.destroy()
+
+
+def test_batch_matches_oracle(tr, oracle_mod):
+    import torch
+    scs = _small_batch(n=4, spp=128)
+    _announce("batch vs oracle")
+    devs = [tr.upload(s) for s in scs]
+    try:
+        with tr.Batch(devs, autotune=False) as b:
+            films = [f.cpu().numpy() for f in b.render()]
+            torch.cuda.synchronize()
+        for s, f in zip(scs, films):
+            o_film, _, _ = oracle_mod.Oracle(s).render()
+            compare_films(f.reshape(s.n_pixels, s.n_bins), o_film)
+    finally:
+        for d in devs:
+            d.destroy()
+
+
+def test_batch_graph_replays(tr):
+    """Replays of the captured graph, with eager work in between, each equal
+    the first replay."""
+    import torch
+    scs = _small_batch(n=6, spp=32)
+    _announce("batch graph replays")
+    devs = [tr.upload(s) for s in scs]
+    try:
+        with tr.Batch(devs, autotune=False) as b:
+            first = [f.clone() for f in b.render()]
+            torch.cuda.synchronize()
+            for rep in range(3):
+                junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+                for f in b.films:
+                    f.fill_(-1.0)
+                torch.cuda.synchronize()
+                out = b.render()
+                torch.cuda.synchronize()
+                for a, c in zip(first, out):
+                    np.testing.assert_allclose(c.cpu().numpy(), a.cpu().numpy(), rtol=1e-5, atol=0)
+                del junk
+    finally:
+        for d in devs:
+            d.destroy()
+
+
+def test_batch_rejects_bad_input(tr):
+    import ctypes as C
+    from paper_2510_25660_amd import _binding as B
+    sc = scenes.confocal_nlos(grid=4, n_tris=200, spp=8)
+    dev = tr.upload(sc)
+    try:
+        L = B.lib()
+        h = C.c_void_p()
+        descs = (B.RenderDesc * 1)(tr.make_render_desc(dev, frozen=True))
+        handles = (C.c_void_p * 1)(dev.handle.value)
+        films = (C.c_void_p * 1)(None)
+        assert L.trhip_batch_create(handles, descs, 1, films, None, None, C.byref(h)) == 1
+        assert L.trhip_batch_render(C.c_void_p(1234), None) == 5
+        assert L.trhip_batch_destroy(C.c_void_p(1234)) == 5
+    finally:
+        dev.destroy()

@@ -11,6 +11,8 @@ from tests.parity import compare_films, compare_vec
 
 pytestmark = pytest.mark.gpu
 
+KERNELS = ["path", "wavefront"]
+
 
 def _announce(msg):
     print(f"[gpu-case] {msg}", flush=True)
@@ -50,80 +52,90 @@ def _check(tr, oracle_mod, sc, pixels=None, **kw):
     return err, info
 
 
-def test_box_scene_full(tr, oracle_mod):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_box_scene_full(tr, oracle_mod, kernel):
     """The 34-triangle box room at its full size: 64x64, 256 bins, 16 spp, depth 4."""
     sc = scenes.box_scene()
-    _announce("box 64x64x256 spp16 d4")
-    err, info = _check(tr, oracle_mod, sc)
+    _announce(f"box 64x64x256 spp16 d4 {kernel}")
+    err, info = _check(tr, oracle_mod, sc, kernel=kernel)
     assert info["n_triangles"] == 34
 
 
-def test_box_scene_ragged_unwarp(tr, oracle_mod):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_box_scene_ragged_unwarp(tr, oracle_mod, kernel):
     """Odd film size (ragged last tile), camera unwarping, 5 spp, depth 6."""
     sc = scenes.box_scene(width=37, height=23, n_bins=300, bin_width=0.007, bin_start=0.3)
     sc.camera_unwarp = True
     _announce("box 37x23 unwarp")
-    _check(tr, oracle_mod, sc, spp=5, max_depth=6, seed=99)
+    _check(tr, oracle_mod, sc, spp=5, max_depth=6, seed=99, kernel=kernel)
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("tile,block", [(1, 64), (3, 128), (7, 256)])
-def test_launch_shapes(tr, oracle_mod, tile, block):
+def test_launch_shapes(tr, oracle_mod, tile, block, kernel):
     sc = scenes.box_scene(width=20, height=13)
-    _announce(f"box launch shape tile={tile} block={block}")
-    _check(tr, oracle_mod, sc, spp=11, tile_pixels=tile, block_size=block)
+    _announce(f"box launch shape tile={tile} block={block} {kernel}")
+    _check(tr, oracle_mod, sc, spp=11, tile_pixels=tile, block_size=block, kernel=kernel)
 
 
-def test_pixel_centre_plane(tr, oracle_mod):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_pixel_centre_plane(tr, oracle_mod, kernel):
     sc = scenes.plane_scene()
     _announce("plane pixel centre")
-    _check(tr, oracle_mod, sc, spp=1, max_depth=2, pixel_centre=True)
+    _check(tr, oracle_mod, sc, spp=1, max_depth=2, pixel_centre=True, kernel=kernel)
 
 
-def test_confocal_reduced(tr, oracle_mod):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_confocal_reduced(tr, oracle_mod, kernel):
     """Confocal NLOS, 9,682 triangles, 16x16 scan grid, 256 spp."""
     sc = scenes.confocal_nlos(grid=16, spp=256)
     _announce("confocal 16x16 spp256")
-    err, info = _check(tr, oracle_mod, sc)
+    err, info = _check(tr, oracle_mod, sc, kernel=kernel)
     assert info["n_triangles"] == 9682
 
 
-def test_confocal_full_size_sampled(tr, oracle_mod):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_confocal_full_size_sampled(tr, oracle_mod, kernel):
     """Confocal NLOS at its full size (64x64 scan points, 4096 spp, 512 bins),
     the launch the benchmark times; the oracle recomputes 24 sampled rows."""
     sc = scenes.confocal_nlos()
     rng = np.random.default_rng(4)
     pix = np.sort(rng.choice(sc.n_pixels, 24, replace=False)).astype(np.int32)
-    _announce("confocal 64x64 spp4096 sampled")
-    _check(tr, oracle_mod, sc, pixels=pix)
+    _announce(f"confocal 64x64 spp4096 sampled {kernel}")
+    _check(tr, oracle_mod, sc, pixels=pix, kernel=kernel)
 
 
-def test_ggx_fog_scene(tr, oracle_mod):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_ggx_fog_scene(tr, oracle_mod, kernel):
     """Terrain + spheres with GGX and Lambertian triangles in fog, depth 8."""
     sc = scenes.large_scene(cells=24, sphere_freq=4, grid=3, width=40, height=30, n_bins=256, bin_width=0.02,
                             spp=4)
     _announce(f"terrain+spheres fog ggx nt={sc.n_tris}")
-    _check(tr, oracle_mod, sc)
+    _check(tr, oracle_mod, sc, kernel=kernel)
 
 
-def test_large_scene_full_size_sampled(tr, oracle_mod):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_large_scene_full_size_sampled(tr, oracle_mod, kernel):
     """~1M triangles, 512x512 pixels, 1024 bins, 64 spp, depth 8, fog: the
     oracle recomputes 12 sampled pixels."""
     sc = scenes.large_scene()
     rng = np.random.default_rng(5)
     pix = np.sort(rng.choice(sc.n_pixels, 12, replace=False)).astype(np.int32)
-    _announce(f"large nt={sc.n_tris} 512x512x1024 spp64 sampled")
-    err, info = _check(tr, oracle_mod, sc, pixels=pix)
+    _announce(f"large nt={sc.n_tris} 512x512x1024 spp64 sampled {kernel}")
+    err, info = _check(tr, oracle_mod, sc, pixels=pix, kernel=kernel)
     assert info["n_triangles"] == sc.n_tris
 
 
-def test_sphere_furnace(tr, oracle_mod):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_sphere_furnace(tr, oracle_mod, kernel):
     sc = scenes.sphere_furnace(radius=1.003, freq=40, width=16, height=16)
     _announce("sphere furnace")
-    _check(tr, oracle_mod, sc, spp=16)
+    _check(tr, oracle_mod, sc, spp=16, kernel=kernel)
 
 
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("n_tris", [1, 2, 3])
-def test_tiny_bvh(tr, oracle_mod, n_tris):
+def test_tiny_bvh(tr, oracle_mod, n_tris, kernel):
     """Root-is-a-leaf and one/two internal-node BVHs."""
     sc = scenes.plane_scene(half=2.0)
     if n_tris == 1:
@@ -137,13 +149,14 @@ def test_tiny_bvh(tr, oracle_mod, n_tris):
     sc.albedo = sc.albedo[:1].repeat(nt)
     sc.roughness = sc.roughness[:1].repeat(nt)
     _announce(f"tiny bvh nt={nt}")
-    _check(tr, oracle_mod, sc, spp=8, max_depth=3)
+    _check(tr, oracle_mod, sc, spp=8, max_depth=3, kernel=kernel)
 
 
-def test_time_sum_equals_steady_gpu(tr):
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_time_sum_equals_steady_gpu(tr, kernel):
     sc = scenes.box_scene()
-    _announce("sum over time")
-    film, st, oow, _ = _gpu_render(tr, sc)
+    _announce(f"sum over time {kernel}")
+    film, st, oow, _ = _gpu_render(tr, sc, kernel=kernel)
     np.testing.assert_allclose(film.sum(1, dtype=np.float64) + oow, st, rtol=1e-5)
 
 
@@ -159,6 +172,18 @@ def test_accumulate_split_ranges(tr):
         torch.cuda.synchronize()
         np.testing.assert_allclose(film2.cpu().numpy(), film.cpu().numpy(), rtol=2e-6, atol=1e-9)
         np.testing.assert_allclose(st2.cpu().numpy(), st.cpu().numpy(), rtol=2e-6)
+
+
+def test_kernel_forms_agree(tr):
+    """Path-per-lane and wavefront forms give the same film (same paths,
+    FP32 sums in a different order) with identical non-zero bins."""
+    sc = scenes.large_scene(cells=32, sphere_freq=5, grid=3, width=48, height=40, n_bins=512, bin_width=0.01,
+                            spp=8)
+    _announce("path vs wavefront")
+    a = _gpu_render(tr, sc, kernel="path")[0]
+    b = _gpu_render(tr, sc, kernel="wavefront")[0]
+    assert ((a != 0) == (b != 0)).all()
+    np.testing.assert_allclose(a, b, rtol=1e-5, atol=0)
 
 
 def test_repeatable(tr):
