@@ -193,7 +193,7 @@ def main():
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--tile-pixels", type=int, default=0)
     ap.add_argument("--block-size", type=int, default=0)
-    ap.add_argument("--kernel", default="auto", choices=["auto", "path", "wavefront"])
+    ap.add_argument("--kernel", default="auto", choices=["auto", "path", "deferred", "wavefront"])
     ap.add_argument("--compare-kernels", action="store_true", help="also time each kernel form")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a device copy of this many MiB (reference kernel for HBM byte counters)")
@@ -229,7 +229,7 @@ def main():
         _, _, counts = tr.render_transient_counted(dev, **shape)
         forms = {}
         if args.compare_kernels:
-            for form in ("path", "wavefront"):
+            for form in ("path", "deferred", "wavefront"):
                 sh = dict(shape, kernel=form)
                 ms, _ = time_launches(lambda: tr.render_transient(dev, film=film, steady=steady, **sh), args.steps,
                                       args.warmup)

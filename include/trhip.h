@@ -140,9 +140,12 @@ typedef struct {
  *   float[n_triangles] replacing the scene's values for this call.
  * tile_pixels / block_size: launch shape (0 = automatic choice).
  * kernel: form of the forward render kernel, TRHIP_KERNEL_* (0 = automatic):
- *   PATH traces one whole path per lane; WAVEFRONT runs the stages of a
- *   workgroup's paths (generate, intersect, shade, shadow) over compacted
- *   queues held in LDS.  Both produce the same film.  Ignored by backward.
+ *   PATH traces one whole path per lane; DEFERRED traces the first ray of
+ *   one sample per lane, buffers the first vertices in LDS and follows the
+ *   rest of those paths on densely packed lanes; WAVEFRONT runs the stages
+ *   of a workgroup's paths (generate, intersect, shade, shadow) over
+ *   compacted queues held in LDS.  All produce the same film.  Ignored by
+ *   the backward pass.
  */
 typedef struct {
     uint32_t spp;
@@ -159,7 +162,7 @@ typedef struct {
     uint32_t kernel;
 } trhip_render_desc;
 
-enum { TRHIP_KERNEL_AUTO = 0, TRHIP_KERNEL_PATH = 1, TRHIP_KERNEL_WAVEFRONT = 2 };
+enum { TRHIP_KERNEL_AUTO = 0, TRHIP_KERNEL_PATH = 1, TRHIP_KERNEL_WAVEFRONT = 2, TRHIP_KERNEL_DEFERRED = 3 };
 
 typedef struct trhip_scene trhip_scene;
 
@@ -257,6 +260,7 @@ typedef struct {
     uint32_t block_size;    /* workgroup size (multiple of 64, <= 256); 0 = choose */
     uint32_t tile_pixels;   /* pixels per work item; 0 = choose */
     uint32_t groups_per_cu; /* persistent workgroups per compute unit; 0 = choose */
+    uint32_t kernel;        /* TRHIP_KERNEL_PATH or TRHIP_KERNEL_DEFERRED per work item; 0 = choose */
     int32_t autotune;       /* nonzero: time the candidate shapes for every field left 0 during
                                trhip_batch_create (renders into the films) and keep the fastest;
                                the choice is cached per process for the same batch shape */
@@ -266,6 +270,7 @@ typedef struct {
     uint32_t n_scenes;
     uint32_t n_items;       /* work items per render */
     uint32_t block_size, tile_pixels, groups;
+    uint32_t kernel;        /* TRHIP_KERNEL_PATH or TRHIP_KERNEL_DEFERRED */
     uint32_t stack_depth;   /* deepest BVH of the batch */
     size_t lds_bytes;       /* dynamic LDS per workgroup */
     uint32_t candidates;    /* shapes timed by the autotuner (0: none, or cached) */

@@ -245,7 +245,7 @@ class Batch:
     render_transient(devs[i], **renders[i]) would produce."""
 
     def __init__(self, devs, renders=None, films=None, block_size=0, tile_pixels=0, groups_per_cu=0,
-                 autotune=True, stream=None):
+                 kernel="auto", autotune=True, stream=None):
         torch = _torch()
         self.devs = list(devs)
         n = len(self.devs)
@@ -259,7 +259,9 @@ class Batch:
             descs[i] = make_render_desc(d, **kw)
         handles = (C.c_void_p * n)(*[d.handle.value for d in self.devs])
         fptrs = (C.c_void_p * n)(*[f.data_ptr() for f in films])
-        opts = BatchOpts(block_size, tile_pixels, groups_per_cu, 1 if autotune else 0)
+        from ._binding import KERNELS
+        opts = BatchOpts(block_size, tile_pixels, groups_per_cu, KERNELS[kernel] if isinstance(kernel, str) else kernel,
+                         1 if autotune else 0)
         h = C.c_void_p()
         check(lib().trhip_batch_create(handles, descs, n, fptrs, C.byref(opts), _stream_handle(stream),
                                        C.byref(h)))

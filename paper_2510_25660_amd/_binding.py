@@ -20,7 +20,7 @@ FLAG_PIXEL_CENTRE = 1 << 0
 FLAG_ACCUMULATE = 1 << 1
 FLAG_FROZEN_PROPOSAL = 1 << 2
 
-KERNELS = {"auto": 0, "path": 1, "wavefront": 2}
+KERNELS = {"auto": 0, "path": 1, "wavefront": 2, "deferred": 3}
 
 EXPORTED_SYMBOLS = (
     "trhip_scene_create", "trhip_scene_destroy", "trhip_scene_get_info", "trhip_render_transient",
@@ -105,6 +105,7 @@ class BatchOpts(C.Structure):
         ("block_size", C.c_uint32),
         ("tile_pixels", C.c_uint32),
         ("groups_per_cu", C.c_uint32),
+        ("kernel", C.c_uint32),
         ("autotune", C.c_int32),
     ]
 
@@ -116,6 +117,7 @@ class BatchInfo(C.Structure):
         ("block_size", C.c_uint32),
         ("tile_pixels", C.c_uint32),
         ("groups", C.c_uint32),
+        ("kernel", C.c_uint32),
         ("stack_depth", C.c_uint32),
         ("lds_bytes", C.c_size_t),
         ("candidates", C.c_uint32),

@@ -218,17 +218,18 @@ trhip_status validate_render(const trhip_scene* s, const trhip_render_desc* r)
         return fail(TRHIP_ERR_INVALID_ARG, "block_size must be a multiple of 64 and <= %u", kMaxBlock);
     if (r->flags & ~(uint32_t)(TRHIP_FLAG_PIXEL_CENTRE | TRHIP_FLAG_ACCUMULATE | TRHIP_FLAG_FROZEN_PROPOSAL))
         return fail(TRHIP_ERR_INVALID_ARG, "unknown flag bits");
-    if (r->kernel > TRHIP_KERNEL_WAVEFRONT) return fail(TRHIP_ERR_INVALID_ARG, "unknown kernel %u", r->kernel);
+    if (r->kernel > TRHIP_KERNEL_DEFERRED) return fail(TRHIP_ERR_INVALID_ARG, "unknown kernel %u", r->kernel);
     return TRHIP_OK;
 }
 
-enum class Kind { Path, Wavefront, Backward, BackwardPrimal };
+enum class Kind { Path, Wavefront, Deferred, Backward, BackwardPrimal };
 
 size_t lds_bytes(Kind kind, uint32_t tp, uint32_t T, uint32_t bs, uint32_t depth)
 {
     switch (kind) {
     case Kind::Path: return trhip::render_lds_bytes(tp, T, bs, depth);
     case Kind::Wavefront: return trhip::wavefront_lds_bytes(tp, T, bs, depth);
+    case Kind::Deferred: return trhip::deferred_lds_bytes(tp, T, bs, depth);
     case Kind::Backward: return trhip::backward_lds_bytes(tp, T, bs, depth, false);
     default: return trhip::backward_lds_bytes(tp, T, bs, depth, true);
     }
@@ -264,14 +265,29 @@ trhip_status choose_shape(const trhip_scene* s, const trhip_render_desc* r, Kind
     return TRHIP_OK;
 }
 
-// Forward kernel form: the wavefront form whenever its LDS fits.
+// Forward kernel form.  Measured on MI355X: deferring first hits pays when
+// most first rays leave the scene (confocal NLOS: +25%) and costs when
+// nearly all of them hit (closed pinhole scenes: -28%), so the automatic
+// choice follows the sensor; the wavefront form is never faster here.
 Kind forward_kind(const trhip_scene* s, const trhip_render_desc* r)
 {
     if (r->kernel == TRHIP_KERNEL_PATH) return Kind::Path;
     if (r->kernel == TRHIP_KERNEL_WAVEFRONT) return Kind::Wavefront;
+    if (r->kernel == TRHIP_KERNEL_DEFERRED) return Kind::Deferred;
+    if (s->view.sensor != TRHIP_SENSOR_CONFOCAL) return Kind::Path;
     const uint32_t bs = r->block_size ? r->block_size : 64;
-    return lds_bytes(Kind::Wavefront, 1, s->view.n_bins, bs, s->view.stack_depth) <= kLdsBudget ? Kind::Wavefront
-                                                                                                  : Kind::Path;
+    return lds_bytes(Kind::Deferred, 1, s->view.n_bins, bs, s->view.stack_depth) <= kLdsBudget ? Kind::Deferred
+                                                                                                 : Kind::Path;
+}
+
+hipError_t launch_forward(Kind kind, const trhip::SceneView& S, const trhip::LaunchArgs& L, uint32_t block,
+                          hipStream_t stream, unsigned long long* counts)
+{
+    switch (kind) {
+    case Kind::Wavefront: return trhip::launch_render_wavefront(S, L, block, stream, counts);
+    case Kind::Deferred: return trhip::launch_render_deferred(S, L, block, stream, counts);
+    default: return trhip::launch_render(S, L, block, stream, counts);
+    }
 }
 
 void fill_launch(const trhip_scene* s, const trhip_render_desc* r, uint32_t tile, trhip::LaunchArgs* L)
@@ -378,8 +394,7 @@ trhip_status trhip_render_transient(trhip_scene* scene, const trhip_render_desc*
     L.film = film;
     L.steady = steady;
     L.oow = oow;
-    hipError_t e = (kind == Kind::Wavefront) ? trhip::launch_render_wavefront(scene->view, L, block, (hipStream_t)stream)
-                                             : trhip::launch_render(scene->view, L, block, (hipStream_t)stream);
+    hipError_t e = launch_forward(kind, scene->view, L, block, (hipStream_t)stream, nullptr);
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return TRHIP_OK;
 }
@@ -403,9 +418,7 @@ trhip_status trhip_render_transient_counted(trhip_scene* scene, const trhip_rend
     unsigned long long* d_counts = nullptr;
     hipError_t e = hipMalloc(&d_counts, TRHIP_COUNT_N * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMemsetAsync(d_counts, 0, TRHIP_COUNT_N * sizeof(unsigned long long), s);
-    if (e == hipSuccess)
-        e = (kind == Kind::Wavefront) ? trhip::launch_render_wavefront(scene->view, L, block, s, d_counts)
-                                      : trhip::launch_render(scene->view, L, block, s, d_counts);
+    if (e == hipSuccess) e = launch_forward(kind, scene->view, L, block, s, d_counts);
     if (e == hipSuccess)
         e = hipMemcpyAsync(counts, d_counts, TRHIP_COUNT_N * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -465,6 +478,7 @@ struct trhip_batch {
     uint32_t* d_cursor;
     trhip::BatchTables tables;
     uint32_t block, tile, groups, depth;
+    bool deferred;
     size_t lds;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -475,7 +489,7 @@ namespace {
 
 std::mutex g_batch_mutex;
 std::unordered_set<const trhip_batch*> g_live_batches;
-std::unordered_map<uint64_t, std::array<uint32_t, 3>> g_tune_cache;  // key -> block, tile, groups
+std::unordered_map<uint64_t, std::array<uint32_t, 4>> g_tune_cache;  // key -> block, tile, groups, deferred
 
 bool batch_live(const trhip_batch* b)
 {
@@ -497,7 +511,8 @@ void free_batch(trhip_batch* b)
 }
 
 // shape -> tables on the device; returns false if the LDS does not fit
-hipError_t stage_shape(trhip_batch* b, uint32_t block, uint32_t tile, uint32_t groups, hipStream_t s, bool* fits)
+hipError_t stage_shape(trhip_batch* b, uint32_t block, uint32_t tile, uint32_t groups, bool deferred, hipStream_t s,
+                       bool* fits)
 {
     const uint32_t n = (uint32_t)b->scenes.size();
     std::vector<uint32_t> start(n + 1, 0);
@@ -508,7 +523,7 @@ hipError_t stage_shape(trhip_batch* b, uint32_t block, uint32_t tile, uint32_t g
         start[k + 1] = start[k] + (P + tile - 1) / tile;
         film_words = std::max<uint32_t>(film_words, tile * T + 2 * tile);
     }
-    const size_t lds = trhip::batch_lds_bytes(film_words, block, b->depth);
+    const size_t lds = trhip::batch_lds_bytes(film_words, block, b->depth, deferred);
     *fits = lds <= kLdsBudget;
     for (uint32_t i = 0; i < n; ++i) b->args[i].tile_pixels = tile;
     for (uint32_t i = 0; i < n; ++i)
@@ -529,6 +544,7 @@ hipError_t stage_shape(trhip_batch* b, uint32_t block, uint32_t tile, uint32_t g
     b->block = block;
     b->tile = tile;
     b->groups = groups;
+    b->deferred = deferred;
     b->lds = lds;
     return e;
 }
@@ -541,6 +557,7 @@ uint64_t tune_key(const trhip_batch* b, int device, const trhip_batch_opts& o)
     mix(o.block_size);
     mix(o.tile_pixels);
     mix(o.groups_per_cu);
+    mix(o.kernel);
     for (size_t i = 0; i < b->scenes.size(); ++i) {
         mix(b->scenes[i]->n_pixels);
         mix(b->views[i].n_bins);
@@ -569,6 +586,8 @@ trhip_status trhip_batch_create(trhip_scene* const* scenes, const trhip_render_d
     if (o.block_size != 0 && (o.block_size % 64 != 0 || o.block_size > kMaxBlock))
         return fail(TRHIP_ERR_INVALID_ARG, "block_size must be a multiple of 64 and <= %u", kMaxBlock);
     if (o.groups_per_cu > 64) return fail(TRHIP_ERR_INVALID_ARG, "groups_per_cu must be <= 64");
+    if (o.kernel != 0 && o.kernel != TRHIP_KERNEL_PATH && o.kernel != TRHIP_KERNEL_DEFERRED)
+        return fail(TRHIP_ERR_INVALID_ARG, "batch kernel must be PATH or DEFERRED");
     for (uint32_t i = 0; i < n_scenes; ++i) {
         trhip_status st = check_scene(scenes[i]);
         if (st != TRHIP_OK) return fail(st, "scene %u: invalid handle", i);
@@ -622,8 +641,10 @@ trhip_status trhip_batch_create(trhip_scene* const* scenes, const trhip_render_d
     const std::vector<uint32_t> tiles = o.tile_pixels ? std::vector<uint32_t>{o.tile_pixels}
                                                       : std::vector<uint32_t>{1, 2, 4};
     const std::vector<uint32_t> gpcs = o.groups_per_cu ? std::vector<uint32_t>{o.groups_per_cu}
-                                                       : std::vector<uint32_t>{2, 4, 8};
-    std::array<uint32_t, 3> best{0, 0, 0};
+                                                       : std::vector<uint32_t>{4, 8};
+    const std::vector<uint32_t> forms = o.kernel ? std::vector<uint32_t>{o.kernel}
+                                                 : std::vector<uint32_t>{TRHIP_KERNEL_PATH, TRHIP_KERNEL_DEFERRED};
+    std::array<uint32_t, 4> best{0, 0, 0, 0};
     float best_ms = 0.0f;
     const uint64_t key = tune_key(b, device, o);
     bool cached = false;
@@ -642,17 +663,19 @@ trhip_status trhip_batch_create(trhip_scene* const* scenes, const trhip_render_d
         e = hipEventCreate(&ev0);
         if (e == hipSuccess) e = hipEventCreate(&ev1);
         float best_t = 0.0f;
+        for (uint32_t form : forms)
         for (uint32_t bs : blocks)
             for (uint32_t tp : tiles)
                 for (uint32_t g : gpcs) {
                     if (e != hipSuccess) break;
                     bool fits = false;
-                    e = stage_shape(b, bs, tp, g, s, &fits);
+                    const bool dfr = form == TRHIP_KERNEL_DEFERRED;
+                    e = stage_shape(b, bs, tp, g, dfr, s, &fits);
                     if (e != hipSuccess || !fits) continue;
                     const uint32_t groups = std::max<uint32_t>(1u, (uint32_t)n_cu * g);
-                    e = trhip::launch_batch(b->tables, groups, bs, b->depth, s);  // warm-up
+                    e = trhip::launch_batch(b->tables, groups, bs, b->depth, dfr, s);  // warm-up
                     if (e == hipSuccess) e = hipEventRecord(ev0, s);
-                    if (e == hipSuccess) e = trhip::launch_batch(b->tables, groups, bs, b->depth, s);
+                    if (e == hipSuccess) e = trhip::launch_batch(b->tables, groups, bs, b->depth, dfr, s);
                     if (e == hipSuccess) e = hipEventRecord(ev1, s);
                     if (e == hipSuccess) e = hipEventSynchronize(ev1);
                     float ms = 0.0f;
@@ -661,7 +684,7 @@ trhip_status trhip_batch_create(trhip_scene* const* scenes, const trhip_render_d
                     ++timed;
                     if (best[0] == 0 || ms < best_t) {
                         best_t = ms;
-                        best = {bs, tp, g};
+                        best = {bs, tp, g, dfr ? 1u : 0u};
                     }
                 }
         if (ev0) (void)hipEventDestroy(ev0);
@@ -677,14 +700,16 @@ trhip_status trhip_batch_create(trhip_scene* const* scenes, const trhip_render_d
         }
     }
     if (best[0] == 0) {
-        // untuned default: the largest block whose LDS fits, 1 pixel per item, 4 groups per CU
+        // untuned default: deferred form, the largest block whose LDS fits,
+        // 1 pixel per item, 8 groups per CU
+        const bool dfr = o.kernel != TRHIP_KERNEL_PATH;
         for (uint32_t bs : {256u, 128u, 64u}) {
             if (o.block_size && bs != o.block_size) continue;
             bool fits = false;
-            e = stage_shape(b, bs, o.tile_pixels ? o.tile_pixels : 1u, o.groups_per_cu ? o.groups_per_cu : 4u, s,
+            e = stage_shape(b, bs, o.tile_pixels ? o.tile_pixels : 1u, o.groups_per_cu ? o.groups_per_cu : 8u, dfr, s,
                             &fits);
             if (e != hipSuccess || fits) {
-                best = {bs, o.tile_pixels ? o.tile_pixels : 1u, o.groups_per_cu ? o.groups_per_cu : 4u};
+                best = {bs, o.tile_pixels ? o.tile_pixels : 1u, o.groups_per_cu ? o.groups_per_cu : 8u, dfr ? 1u : 0u};
                 break;
             }
         }
@@ -692,7 +717,7 @@ trhip_status trhip_batch_create(trhip_scene* const* scenes, const trhip_render_d
     const float tune_ms =
         std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
     bool fits = false;
-    if (e == hipSuccess && best[0]) e = stage_shape(b, best[0], best[1], best[2], s, &fits);
+    if (e == hipSuccess && best[0]) e = stage_shape(b, best[0], best[1], best[2], best[3] != 0, s, &fits);
     if (e != hipSuccess) {
         free_batch(b);
         return hip_fail(e, "batch staging");
@@ -707,7 +732,7 @@ trhip_status trhip_batch_create(trhip_scene* const* scenes, const trhip_render_d
     e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = trhip::launch_batch(b->tables, groups, b->block, b->depth, cs);
+        hipError_t le = trhip::launch_batch(b->tables, groups, b->block, b->depth, b->deferred, cs);
         e = hipStreamEndCapture(cs, &b->graph);
         if (e == hipSuccess) e = le;
     }
@@ -723,6 +748,7 @@ trhip_status trhip_batch_create(trhip_scene* const* scenes, const trhip_render_d
     b->info.block_size = b->block;
     b->info.tile_pixels = b->tile;
     b->info.groups = groups;
+    b->info.kernel = b->deferred ? TRHIP_KERNEL_DEFERRED : TRHIP_KERNEL_PATH;
     b->info.stack_depth = b->depth;
     b->info.lds_bytes = b->lds;
     b->info.candidates = timed;

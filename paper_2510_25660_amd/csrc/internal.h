@@ -37,10 +37,13 @@ hipError_t launch_render(const SceneView& S, const LaunchArgs& L, uint32_t block
 hipError_t launch_render_wavefront(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
                                    unsigned long long* counts = nullptr);
 hipError_t launch_backward(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream);
-size_t batch_lds_bytes(uint32_t film_words, uint32_t block, uint32_t stack_depth);
+size_t deferred_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth);
+size_t batch_lds_bytes(uint32_t film_words, uint32_t block, uint32_t stack_depth, bool deferred);
 // resets the cursor and launches the persistent kernel (groups workgroups)
-hipError_t launch_batch(const BatchTables& B, uint32_t groups, uint32_t block, uint32_t stack_depth,
+hipError_t launch_batch(const BatchTables& B, uint32_t groups, uint32_t block, uint32_t stack_depth, bool deferred,
                         hipStream_t stream);
+hipError_t launch_render_deferred(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
+                                  unsigned long long* counts = nullptr);
 hipError_t launch_zero_f64(double* p, size_t n, hipStream_t stream);
 hipError_t launch_f64_to_f32(const double* src, float* dst, size_t n, hipStream_t stream);
 hipError_t launch_scene_fill(const float* tri9, uint32_t nt, hipStream_t stream);

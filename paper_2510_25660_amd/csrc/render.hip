@@ -490,22 +490,18 @@ __device__ __forceinline__ void shade_vertex(const SceneView& S, const LaunchArg
     ps.v = v + 1;
 }
 
-// Traces one path and reports, through the sink, every next-event
-// contribution (vertex index, triangle, value, bin, d log f factors of the
-// connection) and every continuation (triangle, d log f factors of the
-// sampled direction).  Triangles are caller indices; -1 marks a medium
-// vertex.
+// Continues a path whose next closest hit h is known, and reports through
+// the sink every next-event contribution (vertex index, triangle, value,
+// bin, d log f factors of the connection) and every continuation (triangle,
+// d log f factors of the sampled direction).  Triangles are caller indices;
+// -1 marks a medium vertex.
 template <class Sink, class TallyT>
-__device__ void trace_path(const SceneView& S, const LaunchArgs& L, uint32_t pix, uint32_t sample, uint32_t* stk,
-                           int stride, Sink& sink, TallyT& tally)
+__device__ void continue_path(const SceneView& S, const LaunchArgs& L, uint32_t pix, uint32_t sample, PathState& ps,
+                              Hit h, uint32_t* stk, int stride, Sink& sink, TallyT& tally)
 {
-    tally.add(kTallyDraws);
-    PathState ps;
-    begin_path(S, L, pix, sample, ps);
     const int vmax = last_vertex(S, L);
-    while (ps.v <= vmax) {
+    while (true) {
         const int v = ps.v;
-        const Hit h = closest_hit(S, make_ray(ps.o, ps.d), ps.prev, stk, stride, tally);
         float t_hit;
         bool med;
         if (!resolve_event(S, ps, h, t_hit, med)) break;
@@ -518,7 +514,22 @@ __device__ void trace_path(const SceneView& S, const LaunchArgs& L, uint32_t pix
         }
         if (!cont.alive) break;
         if (cont.k >= 0) sink.continuation(cont.k, cont.g_alb, cont.g_rough);
+        if (ps.v > vmax) break;
+        h = closest_hit(S, make_ray(ps.o, ps.d), ps.prev, stk, stride, tally);
     }
+}
+
+// Traces one whole path (Philox block 0 generation, then vertex by vertex).
+template <class Sink, class TallyT>
+__device__ void trace_path(const SceneView& S, const LaunchArgs& L, uint32_t pix, uint32_t sample, uint32_t* stk,
+                           int stride, Sink& sink, TallyT& tally)
+{
+    tally.add(kTallyDraws);
+    PathState ps;
+    begin_path(S, L, pix, sample, ps);
+    if (last_vertex(S, L) < 1) return;
+    const Hit h = closest_hit(S, make_ray(ps.o, ps.d), ps.prev, stk, stride, tally);
+    continue_path(S, L, pix, sample, ps, h, stk, stride, sink, tally);
 }
 
 // ---------------------------------------------------------------------------
@@ -599,6 +610,141 @@ __device__ __forceinline__ void render_tile(const SceneView& S, const LaunchArgs
     }
 }
 
+// Same tile, deferred form.  Phase 1 traces only the first ray of each
+// sample (one sample per lane) and appends every first vertex (work index,
+// t, triangle) to an LDS buffer; once the buffer holds a block's worth,
+// phase 2 drains it: each lane regenerates its entry's ray (Philox block 0,
+// a few hundred operations), then shades, tests the shadow ray and follows
+// the rest of the path.  Lanes whose first ray leaves the scene finish in
+// phase 1, so the costly vertex work runs on densely packed lanes.  The
+// buffer holds 2 * block entries (phase 1 adds at most one per lane).
+struct FirstHits {
+    uint32_t* work;
+    float* t;
+    int* prim;
+    int* sorted;
+    uint32_t* count;
+};
+
+__device__ __forceinline__ FirstHits carve_first_hits(float* base, uint32_t cap)
+{
+    FirstHits f;
+    f.work = reinterpret_cast<uint32_t*>(base);
+    f.t = base + cap;
+    f.prim = reinterpret_cast<int*>(base + 2 * cap);
+    f.sorted = reinterpret_cast<int*>(base + 3 * cap);
+    f.count = reinterpret_cast<uint32_t*>(base + 4 * cap);
+    return f;
+}
+
+template <class TallyT>
+__device__ __forceinline__ void render_tile_deferred(const SceneView& S, const LaunchArgs& L, uint32_t p0,
+                                                     float* lds_film, const FirstHits& fh, uint32_t* stk,
+                                                     int stride, TallyT& tally)
+{
+    const uint32_t T = S.n_bins;
+    const uint32_t TP = L.tile_pixels;
+    float* tfilm = lds_film;
+    float* tsteady = lds_film + (size_t)TP * T;
+    float* toow = tsteady + TP;
+    const uint32_t npix = min(TP, L.n_pixels - p0);
+    const uint32_t nb = blockDim.x;
+    for (uint32_t i = threadIdx.x; i < TP * T + 2 * TP; i += nb) lds_film[i] = 0.0f;
+    if (threadIdx.x == 0) *fh.count = 0u;
+    __syncthreads();
+
+    const uint32_t work = npix * L.spp;
+    const bool has_vertex = last_vertex(S, L) >= 1;
+    uint32_t cur = 0xffffffffu;
+    FilmSink sink{nullptr, 0.0f, 0.0f};
+    for (uint32_t base = 0; base < work; base += nb) {
+        const uint32_t w = base + threadIdx.x;
+        if (w < work && has_vertex) {
+            const uint32_t pl = w / L.spp;
+            tally.add(kTallyDraws);
+            PathState ps;
+            begin_path(S, L, p0 + pl, L.sample_offset + (w - pl * L.spp), ps);
+            const Hit h = closest_hit(S, make_ray(ps.o, ps.d), ps.prev, stk, stride, tally);
+            float t_hit;
+            bool med;
+            if (resolve_event(S, ps, h, t_hit, med)) {
+                const uint32_t j = atomicAdd(fh.count, 1u);
+                fh.work[j] = w;
+                fh.t[j] = h.t;
+                fh.prim[j] = h.prim;
+                fh.sorted[j] = h.sorted;
+            }
+        }
+        __syncthreads();
+        const uint32_t n = *fh.count;
+        if (n >= nb || base + nb >= work) {
+            for (uint32_t j = threadIdx.x; j < n; j += nb) {
+                const uint32_t wj = fh.work[j];
+                const uint32_t pl = wj / L.spp;
+                const uint32_t sample = L.sample_offset + (wj - pl * L.spp);
+                if (pl != cur) {
+                    if (cur != 0xffffffffu) {
+                        atomicAdd(tsteady + cur, sink.steady);
+                        atomicAdd(toow + cur, sink.oow);
+                    }
+                    cur = pl;
+                    sink.row = tfilm + (size_t)pl * T;
+                    sink.steady = 0.0f;
+                    sink.oow = 0.0f;
+                }
+                PathState ps;
+                begin_path(S, L, p0 + pl, sample, ps);
+                Hit h;
+                h.t = fh.t[j];
+                h.prim = fh.prim[j];
+                h.sorted = fh.sorted[j];
+                continue_path(S, L, p0 + pl, sample, ps, h, stk, stride, sink, tally);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) *fh.count = 0u;
+            __syncthreads();
+        }
+    }
+    if (cur != 0xffffffffu) {
+        atomicAdd(tsteady + cur, sink.steady);
+        atomicAdd(toow + cur, sink.oow);
+    }
+    __syncthreads();
+
+    const bool acc = (L.flags & kFlagAccumulate) != 0;
+    const size_t base = (size_t)p0 * T;
+    const uint32_t nvals = npix * T;
+    for (uint32_t i = threadIdx.x; i < nvals; i += nb) {
+        const float v = tfilm[i] * L.norm;
+        L.film[base + i] = acc ? L.film[base + i] + v : v;
+    }
+    if (threadIdx.x < npix) {
+        const uint32_t p = p0 + threadIdx.x;
+        if (L.steady) {
+            const float v = tsteady[threadIdx.x] * L.norm;
+            L.steady[p] = acc ? L.steady[p] + v : v;
+        }
+        if (L.oow) {
+            const float v = toow[threadIdx.x] * L.norm;
+            L.oow[p] = acc ? L.oow[p] + v : v;
+        }
+    }
+}
+
+template <bool kCount>
+__global__ void __launch_bounds__(256) k_render_deferred(SceneView S, LaunchArgs L, unsigned long long* counts)
+{
+    Tally<kCount> tally;
+    extern __shared__ float lds[];
+    const uint32_t TP = L.tile_pixels;
+    const uint32_t cap = 2 * blockDim.x;
+    float* after_film = lds + (size_t)TP * S.n_bins + 2 * TP;
+    const FirstHits fh = carve_first_hits(after_film, cap);
+    uint32_t* stk = reinterpret_cast<uint32_t*>(after_film + 4 * cap + 1) + threadIdx.x;
+    render_tile_deferred(S, L, blockIdx.x * TP, lds, fh, stk, (int)blockDim.x, tally);
+    tally.flush(counts);
+}
+
 template <bool kCount>
 __global__ void __launch_bounds__(256) k_render(SceneView S, LaunchArgs L, unsigned long long* counts)
 {
@@ -616,12 +762,15 @@ __global__ void __launch_bounds__(256) k_render(SceneView S, LaunchArgs L, unsig
 // Work items are (scene, pixel tile) pairs numbered scene by scene in the
 // processing order; a workgroup pops items from a global cursor until they
 // run out, so scenes of very different cost balance themselves.
+template <bool kDeferred>
 __global__ void __launch_bounds__(256) k_batch(BatchTables B)
 {
     extern __shared__ float lds[];
     __shared__ uint32_t s_item;
     Tally<false> tally;
-    uint32_t* stk = reinterpret_cast<uint32_t*>(lds + B.film_words) + threadIdx.x;
+    const uint32_t cap = 2 * blockDim.x;
+    const FirstHits fh = carve_first_hits(lds + B.film_words, cap);
+    uint32_t* stk = reinterpret_cast<uint32_t*>(lds + B.film_words + (kDeferred ? 4 * cap + 1 : 0)) + threadIdx.x;
     while (true) {
         if (threadIdx.x == 0) s_item = atomicAdd(B.cursor, 1u);
         __syncthreads();
@@ -637,7 +786,11 @@ __global__ void __launch_bounds__(256) k_batch(BatchTables B)
         const uint32_t tile = item - B.item_start[lo];
         const SceneView* __restrict__ views = B.views;
         const LaunchArgs* __restrict__ args = B.args;
-        render_tile(views[scene], args[scene], tile * args[scene].tile_pixels, lds, stk, (int)blockDim.x, tally);
+        if (kDeferred)
+            render_tile_deferred(views[scene], args[scene], tile * args[scene].tile_pixels, lds, fh, stk,
+                                 (int)blockDim.x, tally);
+        else
+            render_tile(views[scene], args[scene], tile * args[scene].tile_pixels, lds, stk, (int)blockDim.x, tally);
         __syncthreads();
     }
 }
@@ -996,17 +1149,39 @@ hipError_t launch_backward(const SceneView& S, const LaunchArgs& L, uint32_t blo
     return hipGetLastError();
 }
 
-size_t batch_lds_bytes(uint32_t film_words, uint32_t block, uint32_t stack_depth)
+size_t deferred_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth)
 {
-    return (size_t)film_words * sizeof(float) + (size_t)block * stack_depth * sizeof(uint32_t);
+    return ((size_t)tile_pixels * n_bins + 2ull * tile_pixels + 8ull * block + 1) * sizeof(float) +
+           (size_t)block * stack_depth * sizeof(uint32_t);
 }
 
-hipError_t launch_batch(const BatchTables& B, uint32_t groups, uint32_t block, uint32_t stack_depth,
+size_t batch_lds_bytes(uint32_t film_words, uint32_t block, uint32_t stack_depth, bool deferred)
+{
+    return ((size_t)film_words + (deferred ? 8ull * block + 1 : 0)) * sizeof(float) +
+           (size_t)block * stack_depth * sizeof(uint32_t);
+}
+
+hipError_t launch_batch(const BatchTables& B, uint32_t groups, uint32_t block, uint32_t stack_depth, bool deferred,
                         hipStream_t stream)
 {
     hipLaunchKernelGGL(k_reset_cursor, dim3(1), dim3(64), 0, stream, B.cursor);
-    hipLaunchKernelGGL(k_batch, dim3(groups), dim3(block), batch_lds_bytes(B.film_words, block, stack_depth), stream,
-                       B);
+    const size_t lds = batch_lds_bytes(B.film_words, block, stack_depth, deferred);
+    if (deferred)
+        hipLaunchKernelGGL(k_batch<true>, dim3(groups), dim3(block), lds, stream, B);
+    else
+        hipLaunchKernelGGL(k_batch<false>, dim3(groups), dim3(block), lds, stream, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_render_deferred(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
+                                  unsigned long long* counts)
+{
+    const uint32_t tiles = (L.n_pixels + L.tile_pixels - 1) / L.tile_pixels;
+    const size_t lds = deferred_lds_bytes(L.tile_pixels, S.n_bins, block, S.stack_depth);
+    if (counts)
+        hipLaunchKernelGGL(k_render_deferred<true>, dim3(tiles), dim3(block), lds, stream, S, L, counts);
+    else
+        hipLaunchKernelGGL(k_render_deferred<false>, dim3(tiles), dim3(block), lds, stream, S, L, counts);
     return hipGetLastError();
 }
 

@@ -29,14 +29,14 @@ def _small_batch(n=10, spp=64):
                                bins_range=(256, 1024))
 
 
-@pytest.mark.parametrize("autotune", [False, True])
-def test_batch_matches_single_renders(tr, autotune):
+@pytest.mark.parametrize("autotune,kernel", [(False, "path"), (False, "deferred"), (True, "auto")])
+def test_batch_matches_single_renders(tr, autotune, kernel):
     import torch
     scs = _small_batch()
-    _announce(f"batch of {len(scs)} autotune={autotune}")
+    _announce(f"batch of {len(scs)} autotune={autotune} kernel={kernel}")
     devs = [tr.upload(s) for s in scs]
     try:
-        with tr.Batch(devs, autotune=autotune) as b:
+        with tr.Batch(devs, autotune=autotune, kernel=kernel) as b:
             info = b.info()
             assert info["n_scenes"] == len(scs)
             assert info["n_items"] >= sum(s.n_pixels for s in scs) // max(1, info["tile_pixels"])

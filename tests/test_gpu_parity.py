@@ -11,7 +11,7 @@ from tests.parity import compare_films, compare_vec
 
 pytestmark = pytest.mark.gpu
 
-KERNELS = ["path", "wavefront"]
+KERNELS = ["path", "deferred", "wavefront"]
 
 
 def _announce(msg):
@@ -179,11 +179,12 @@ def test_kernel_forms_agree(tr):
     FP32 sums in a different order) with identical non-zero bins."""
     sc = scenes.large_scene(cells=32, sphere_freq=5, grid=3, width=48, height=40, n_bins=512, bin_width=0.01,
                             spp=8)
-    _announce("path vs wavefront")
+    _announce("path vs deferred vs wavefront")
     a = _gpu_render(tr, sc, kernel="path")[0]
-    b = _gpu_render(tr, sc, kernel="wavefront")[0]
-    assert ((a != 0) == (b != 0)).all()
-    np.testing.assert_allclose(a, b, rtol=1e-5, atol=0)
+    for form in ("deferred", "wavefront"):
+        b = _gpu_render(tr, sc, kernel=form)[0]
+        assert ((a != 0) == (b != 0)).all()
+        np.testing.assert_allclose(a, b, rtol=1e-5, atol=0)
 
 
 def test_repeatable(tr):
