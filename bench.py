@@ -195,6 +195,7 @@ def main():
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--kernel", default="auto", choices=["auto", "path", "deferred", "wavefront"])
     ap.add_argument("--compare-kernels", action="store_true", help="also time each kernel form")
+    ap.add_argument("--builder", default="ploc", choices=["ploc", "lbvh"])
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a device copy of this many MiB (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -220,7 +221,7 @@ def main():
     sc = make_scene(args.workload)
     shape = dict(tile_pixels=args.tile_pixels, block_size=args.block_size, kernel=args.kernel)
     paths = sc.n_pixels * sc.spp
-    with tr.upload(sc) as dev:
+    with tr.upload(sc, builder=args.builder) as dev:
         info = dev.info()
         steady = torch.empty((sc.height, sc.width), device="cuda", dtype=torch.float32)
         film = torch.empty((sc.height, sc.width, sc.n_bins), device="cuda", dtype=torch.float32)

@@ -92,6 +92,11 @@ enum {
  * bin_start (the sensor window of Eq. 6, half-open at its end).
  * camera_unwarp != 0 omits the camera segment (Sec. 3, "Camera warp and
  * unwarping"); pinhole only.
+ *
+ * bvh_builder: TRHIP_BVH_PLOC (0, default: locally-ordered clustering over
+ * the Morton order) or TRHIP_BVH_LBVH (Karras hierarchy over the Morton
+ * order).  Any builder yields the same renders (see trhip_render_transient);
+ * they differ in traversal cost.
  */
 typedef struct {
     const float* vertices;
@@ -121,7 +126,10 @@ typedef struct {
     float bin_width;
     float bin_start;
     int32_t camera_unwarp;
+    int32_t bvh_builder;
 } trhip_scene_desc;
+
+enum { TRHIP_BVH_PLOC = 0, TRHIP_BVH_LBVH = 1 };
 
 /*
  * Render description.
@@ -178,8 +186,9 @@ typedef struct {
 } trhip_scene_info;
 
 /*
- * Upload a scene and build its BVH (a linear BVH over 30-bit Morton codes,
- * built on the device) on `stream`; blocks until the build has finished.
+ * Upload a scene and build its BVH on the device (30-bit Morton codes, radix
+ * sort, then the hierarchy of desc->bvh_builder) on `stream`; blocks until
+ * the build has finished.
  * On success *out owns all scene memory until trhip_scene_destroy.
  * Errors: INVALID_ARG (NULL desc/out, bad sizes or values, degenerate or
  * non-finite triangles, index out of range), OOM, HIP.

@@ -50,7 +50,7 @@ def _f3(v):
     return (C.c_float * 3)(*[float(x) for x in v])
 
 
-def make_scene_desc(sc: "scenes.Scene"):
+def make_scene_desc(sc: "scenes.Scene", builder="ploc"):
     """Fill a trhip_scene_desc from a Scene; returns (desc, keepalive)."""
     verts = np.ascontiguousarray(sc.vertices, np.float32)
     idx = np.ascontiguousarray(sc.indices, np.uint32)
@@ -91,15 +91,17 @@ def make_scene_desc(sc: "scenes.Scene"):
     d.bin_width = sc.bin_width
     d.bin_start = sc.bin_start
     d.camera_unwarp = int(bool(sc.camera_unwarp))
+    from ._binding import BUILDERS
+    d.bvh_builder = BUILDERS[builder] if isinstance(builder, str) else int(builder)
     return d, keep
 
 
 class DeviceScene:
     """A scene uploaded to the GPU with its BVH (owns a trhip_scene*)."""
 
-    def __init__(self, sc: "scenes.Scene", stream=None):
+    def __init__(self, sc: "scenes.Scene", stream=None, builder="ploc"):
         self.scene = sc
-        desc, keep = make_scene_desc(sc)
+        desc, keep = make_scene_desc(sc, builder)
         h = C.c_void_p()
         check(lib().trhip_scene_create(C.byref(desc), _stream_handle(stream), C.byref(h)))
         self._h = h
@@ -133,8 +135,9 @@ class DeviceScene:
         self.destroy()
 
 
-def upload(sc: "scenes.Scene", stream=None) -> DeviceScene:
-    return DeviceScene(sc, stream)
+def upload(sc: "scenes.Scene", stream=None, builder="ploc") -> DeviceScene:
+    """Upload a scene and build its BVH on the device (builder "ploc" or "lbvh")."""
+    return DeviceScene(sc, stream, builder)
 
 
 def _ptr(t) -> Optional[int]:

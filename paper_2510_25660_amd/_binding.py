@@ -20,6 +20,8 @@ FLAG_PIXEL_CENTRE = 1 << 0
 FLAG_ACCUMULATE = 1 << 1
 FLAG_FROZEN_PROPOSAL = 1 << 2
 
+BUILDERS = {"ploc": 0, "lbvh": 1}
+
 KERNELS = {"auto": 0, "path": 1, "wavefront": 2, "deferred": 3}
 
 EXPORTED_SYMBOLS = (
@@ -68,6 +70,7 @@ class SceneDesc(C.Structure):
         ("bin_width", C.c_float),
         ("bin_start", C.c_float),
         ("camera_unwarp", C.c_int32),
+        ("bvh_builder", C.c_int32),
     ]
 
 

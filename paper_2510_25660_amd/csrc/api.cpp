@@ -115,6 +115,8 @@ trhip_status validate_desc(const trhip_scene_desc* d, std::vector<float>& tri9)
     if (d->n_bins == 0 || d->n_bins > (1u << 24)) return fail(TRHIP_ERR_INVALID_ARG, "n_bins out of range");
     if (!(d->bin_width > 0.0f) || !std::isfinite(d->bin_width) || !std::isfinite(d->bin_start))
         return fail(TRHIP_ERR_INVALID_ARG, "bin_width must be > 0 and finite");
+    if (d->bvh_builder != TRHIP_BVH_PLOC && d->bvh_builder != TRHIP_BVH_LBVH)
+        return fail(TRHIP_ERR_INVALID_ARG, "unknown bvh_builder %d", d->bvh_builder);
     if (!(d->sigma_t >= 0.0f) || !std::isfinite(d->sigma_t))
         return fail(TRHIP_ERR_INVALID_ARG, "sigma_t must be >= 0");
     if (d->sigma_t > 0.0f && !(d->medium_albedo >= 0.0f && d->medium_albedo <= 1.0f))
@@ -334,7 +336,9 @@ trhip_status trhip_scene_create(const trhip_scene_desc* desc, void* stream, trhi
     if (e == hipSuccess && desc->sensor == TRHIP_SENSOR_CONFOCAL)
         e = upload(&sc->d_scan, desc->scan_points, 3ull * sc->n_pixels, s);
     if (e == hipSuccess) e = hipMalloc(&sc->d_grad, 2ull * nt * sizeof(double));
-    if (e == hipSuccess) e = trhip::build_bvh(d_tri9, nt, s, &sc->bvh);
+    if (e == hipSuccess)
+        e = trhip::build_bvh(d_tri9, nt, desc->bvh_builder == TRHIP_BVH_LBVH ? trhip::kBuilderLbvh : trhip::kBuilderPloc,
+                             s, &sc->bvh);
     (void)hipFree(d_tri9);
     if (e != hipSuccess) {
         free_scene(sc);

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>
 
+#include <utility>
+
 #include "internal.h"
 #include "scene_view.h"
 
@@ -247,6 +249,126 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n)
     if (i < n) p[i] = v;
 }
 
+// ---------------------------------------------------------------------------
+// Locally-ordered clustering over the Morton order (Meister and Bittner,
+// "Parallel Locally-Ordered Clustering for Bounding Volume Hierarchy
+// Construction", IEEE TVCG 2018): every cluster picks, among its kPlocRadius
+// neighbours on each side in the current order, the one whose union box has
+// the smallest surface area; mutual nearest neighbours merge into a new
+// internal node; survivors are compacted in order; repeat until one cluster.
+// ---------------------------------------------------------------------------
+constexpr int kPlocRadius = 16;
+
+__device__ __forceinline__ float half_area(float lx, float ly, float lz, float hx, float hy, float hz)
+{
+    const float dx = hx - lx, dy = hy - ly, dz = hz - lz;
+    return dx * dy + dy * dz + dz * dx;
+}
+
+__global__ void k_ploc_init(int n, const float* __restrict__ tri_box, const uint32_t* __restrict__ ids,
+                            int32_t* __restrict__ c_node, float* __restrict__ c_box)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    c_node[j] = ~j;
+    const float* b = tri_box + 6ull * ids[j];
+    for (int a = 0; a < 6; ++a) c_box[6ull * j + a] = b[a];
+}
+
+// nearest neighbour in the window; boxes of the block and its halo in LDS
+__global__ void __launch_bounds__(256) k_ploc_nn(int nc, const float* __restrict__ c_box, int32_t* __restrict__ nn)
+{
+    __shared__ float sb[(256 + 2 * kPlocRadius) * 6];
+    const int first = blockIdx.x * 256 - kPlocRadius;
+    for (int k = threadIdx.x; k < (256 + 2 * kPlocRadius) * 6; k += 256) {
+        const int c = first + k / 6;
+        sb[k] = (c >= 0 && c < nc) ? c_box[6ll * c + k % 6] : 0.0f;
+    }
+    __syncthreads();
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= nc) return;
+    const float* bi = sb + 6 * (threadIdx.x + kPlocRadius);
+    float best = __builtin_huge_valf();
+    int arg = -1;
+    const int lo = max(0, i - kPlocRadius), hi = min(nc - 1, i + kPlocRadius);
+    for (int j = lo; j <= hi; ++j) {
+        if (j == i) continue;
+        const float* bj = sb + 6 * (j - first);
+        const float a = half_area(fminf(bi[0], bj[0]), fminf(bi[1], bj[1]), fminf(bi[2], bj[2]), fmaxf(bi[3], bj[3]),
+                                  fmaxf(bi[4], bj[4]), fmaxf(bi[5], bj[5]));
+        if (a < best) {  // ties keep the smaller index (scanned first)
+            best = a;
+            arg = j;
+        }
+    }
+    nn[i] = arg;
+}
+
+// merge flags: 1 where cluster i starts a new node (mutual pair, i < partner);
+// keep flags: 1 where cluster i survives (merged-into or unpaired)
+__global__ void k_ploc_flags(int nc, const int32_t* __restrict__ nn, int force_pairs, uint32_t* __restrict__ mflag,
+                             uint32_t* __restrict__ keep)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nc) return;
+    int j = nn[i];
+    bool mutual = j >= 0 && nn[j] == i;
+    if (force_pairs) {  // progress guarantee: pair neighbours (2k, 2k+1)
+        j = (i & 1) ? i - 1 : (i + 1 < nc ? i + 1 : -1);
+        mutual = j >= 0;
+    }
+    mflag[i] = (mutual && i < j) ? 1u : 0u;
+    keep[i] = (mutual && i > j) ? 0u : 1u;
+}
+
+__global__ void k_ploc_merge(int nc, const int32_t* __restrict__ nn, int force_pairs, const uint32_t* __restrict__ mflag,
+                             const uint32_t* __restrict__ moff, const uint32_t* __restrict__ koff,
+                             const int32_t* __restrict__ c_node, const float* __restrict__ c_box, int node_base,
+                             int32_t* __restrict__ child, float* __restrict__ node_box, int32_t* __restrict__ c_node2,
+                             float* __restrict__ c_box2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nc) return;
+    int j = nn[i];
+    bool mutual = j >= 0 && nn[j] == i;
+    if (force_pairs) {
+        j = (i & 1) ? i - 1 : (i + 1 < nc ? i + 1 : -1);
+        mutual = j >= 0;
+    }
+    if (mutual && i > j) return;  // absorbed by its partner
+    const int out = (int)koff[i];
+    if (mflag[i]) {
+        const int idx = node_base + (int)moff[i];
+        child[2 * idx] = c_node[i];
+        child[2 * idx + 1] = c_node[j];
+        float b[6];
+        for (int a = 0; a < 3; ++a) {
+            b[a] = fminf(c_box[6ll * i + a], c_box[6ll * j + a]);
+            b[3 + a] = fmaxf(c_box[6ll * i + 3 + a], c_box[6ll * j + 3 + a]);
+        }
+        for (int a = 0; a < 6; ++a) {
+            node_box[6ll * idx + a] = b[a];
+            c_box2[6ll * out + a] = b[a];
+        }
+        c_node2[out] = idx;
+    } else {
+        c_node2[out] = c_node[i];
+        for (int a = 0; a < 6; ++a) c_box2[6ll * out + a] = c_box[6ll * i + a];
+    }
+}
+
+__global__ void k_parents(int ni, const int32_t* __restrict__ child, int32_t* __restrict__ parent_int,
+                          int32_t* __restrict__ parent_leaf)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ni) return;
+    for (int s = 0; s < 2; ++s) {
+        const int c = child[2 * i + s];
+        if (c < 0) parent_leaf[~c] = i;
+        else parent_int[c] = i;
+    }
+}
+
 inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -260,12 +382,17 @@ inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 
         }                                \
     } while (0)
 
-hipError_t build_bvh(const float* d_tri9, uint32_t nt, hipStream_t stream, BvhBuild* out)
+hipError_t build_bvh(const float* d_tri9, uint32_t nt, int builder, hipStream_t stream, BvhBuild* out)
 {
     hipError_t err = hipSuccess;
     const int n = (int)nt;
     uint32_t *stats = nullptr, *codes = nullptr, *codes_sorted = nullptr, *ids = nullptr, *ids_sorted = nullptr;
     uint32_t *arrivals = nullptr, *depth = nullptr;
+    int32_t *c_node = nullptr, *c_node2 = nullptr, *nn = nullptr;
+    float *c_box = nullptr, *c_box2 = nullptr;
+    uint32_t *mflag = nullptr, *keep = nullptr, *moff = nullptr, *koff = nullptr;
+    void* scan_temp = nullptr;
+    size_t scan_bytes = 0;
     float *tri_box = nullptr, *node_box = nullptr;
     int32_t *child = nullptr, *parent_int = nullptr, *parent_leaf = nullptr;
     void* temp = nullptr;
@@ -307,10 +434,57 @@ hipError_t build_bvh(const float* d_tri9, uint32_t nt, hipStream_t stream, BvhBu
     k_fill_i32<<<blocks_for(nt, 256), 256, 0, stream>>>(parent_leaf, -1, (size_t)nt);
     k_fill_u32<<<blocks_for(ni, 256), 256, 0, stream>>>(arrivals, 0u, (size_t)ni);
     k_fill_u32<<<1, 64, 0, stream>>>(depth, 0u, 1);
-    if (n > 1) {
+    out->root = (n > 1) ? 0 : ~0;
+    if (n > 1 && builder == kBuilderLbvh) {
         k_hierarchy<<<blocks_for(n - 1, 256), 256, 0, stream>>>(codes_sorted, n, child, parent_int, parent_leaf);
         k_refit<<<blocks_for(n, 256), 256, 0, stream>>>(n, child, parent_int, parent_leaf, tri_box, ids_sorted,
                                                         node_box, arrivals);
+    } else if (n > 1) {
+        TR_CHECK(hipMalloc(&c_node, (size_t)n * sizeof(int32_t)));
+        TR_CHECK(hipMalloc(&c_node2, (size_t)n * sizeof(int32_t)));
+        TR_CHECK(hipMalloc(&nn, (size_t)n * sizeof(int32_t)));
+        TR_CHECK(hipMalloc(&c_box, 6ull * n * sizeof(float)));
+        TR_CHECK(hipMalloc(&c_box2, 6ull * n * sizeof(float)));
+        TR_CHECK(hipMalloc(&mflag, ((size_t)n + 1) * sizeof(uint32_t)));
+        TR_CHECK(hipMalloc(&keep, ((size_t)n + 1) * sizeof(uint32_t)));
+        TR_CHECK(hipMalloc(&moff, ((size_t)n + 1) * sizeof(uint32_t)));
+        TR_CHECK(hipMalloc(&koff, ((size_t)n + 1) * sizeof(uint32_t)));
+        TR_CHECK(hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, mflag, moff, n + 1, stream));
+        TR_CHECK(hipMalloc(&scan_temp, scan_bytes));
+        k_ploc_init<<<blocks_for(n, 256), 256, 0, stream>>>(n, tri_box, ids_sorted, c_node, c_box);
+        int nc = n;
+        int made = 0;  // internal nodes so far; node indices grow in creation order
+        int stall = 0;
+        while (nc > 1) {
+            const int force = stall ? 1 : 0;
+            k_ploc_nn<<<blocks_for(nc, 256), 256, 0, stream>>>(nc, c_box, nn);
+            k_ploc_flags<<<blocks_for(nc, 256), 256, 0, stream>>>(nc, nn, force, mflag, keep);
+            // exclusive scans over nc + 1 entries give the totals in the last slot
+            k_fill_u32<<<1, 64, 0, stream>>>(mflag + nc, 0u, 1);
+            k_fill_u32<<<1, 64, 0, stream>>>(keep + nc, 0u, 1);
+            TR_CHECK(hipcub::DeviceScan::ExclusiveSum(scan_temp, scan_bytes, mflag, moff, nc + 1, stream));
+            TR_CHECK(hipcub::DeviceScan::ExclusiveSum(scan_temp, scan_bytes, keep, koff, nc + 1, stream));
+            k_ploc_merge<<<blocks_for(nc, 256), 256, 0, stream>>>(nc, nn, force, mflag, moff, koff, c_node, c_box,
+                                                                  made, child, node_box, c_node2, c_box2);
+            TR_CHECK(hipGetLastError());
+            uint32_t counts[2];
+            TR_CHECK(hipMemcpyAsync(&counts[0], moff + nc, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+            TR_CHECK(hipMemcpyAsync(&counts[1], koff + nc, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+            TR_CHECK(hipStreamSynchronize(stream));
+            made += (int)counts[0];
+            stall = (counts[0] == 0) ? 1 : 0;
+            nc = (int)counts[1];
+            std::swap(c_node, c_node2);
+            std::swap(c_box, c_box2);
+            if (made > n - 1) {
+                err = hipErrorUnknown;
+                goto done;
+            }
+        }
+        out->root = made - 1;
+        k_parents<<<blocks_for(n - 1, 256), 256, 0, stream>>>(n - 1, child, parent_int, parent_leaf);
+    }
+    if (n > 1) {
         k_layout<<<blocks_for(n - 1, 256), 256, 0, stream>>>(n, child, tri_box, ids_sorted, node_box, out->nodes);
         k_depth<<<blocks_for(n, 256), 256, 0, stream>>>(n, parent_int, parent_leaf, depth);
     }
@@ -333,7 +507,6 @@ hipError_t build_bvh(const float* d_tri9, uint32_t nt, hipStream_t stream, BvhBu
         memcpy(&mabs, &host_stats[0], 4);
         out->pad = mabs * 0x1p-16f;
     }
-    out->root = (n > 1) ? 0 : ~0;
     out->n_internal = (uint32_t)(n > 1 ? n - 1 : 0);
     out->depth = host_depth;
 
@@ -341,6 +514,8 @@ done:
     hipFree(stats); hipFree(codes); hipFree(codes_sorted); hipFree(ids); hipFree(ids_sorted);
     hipFree(tri_box); hipFree(node_box); hipFree(child); hipFree(parent_int); hipFree(parent_leaf);
     hipFree(arrivals); hipFree(depth); hipFree(temp);
+    hipFree(c_node); hipFree(c_node2); hipFree(nn); hipFree(c_box); hipFree(c_box2);
+    hipFree(mflag); hipFree(keep); hipFree(moff); hipFree(koff); hipFree(scan_temp);
     if (err != hipSuccess) {
         hipFree(out->nodes);
         hipFree(out->tris);

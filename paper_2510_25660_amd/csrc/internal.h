@@ -19,9 +19,12 @@ struct BvhBuild {
     float pad;
 };
 
+constexpr int kBuilderPloc = 0;
+constexpr int kBuilderLbvh = 1;
+
 // Builds the BVH of nt triangles given as a device float[nt][9] array;
 // synchronises `stream`.  On failure nothing stays allocated.
-hipError_t build_bvh(const float* d_tri9, uint32_t nt, hipStream_t stream, BvhBuild* out);
+hipError_t build_bvh(const float* d_tri9, uint32_t nt, int builder, hipStream_t stream, BvhBuild* out);
 
 // LDS bytes of one render / backward workgroup
 size_t render_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth);

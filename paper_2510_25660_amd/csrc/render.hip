@@ -610,36 +610,73 @@ __device__ __forceinline__ void render_tile(const SceneView& S, const LaunchArgs
     }
 }
 
-// Same tile, deferred form.  Phase 1 traces only the first ray of each
-// sample (one sample per lane) and appends every first vertex (work index,
-// t, triangle) to an LDS buffer; once the buffer holds a block's worth,
-// phase 2 drains it: each lane regenerates its entry's ray (Philox block 0,
-// a few hundred operations), then shades, tests the shadow ray and follows
-// the rest of the path.  Lanes whose first ray leaves the scene finish in
-// phase 1, so the costly vertex work runs on densely packed lanes.  The
-// buffer holds 2 * block entries (phase 1 adds at most one per lane).
-struct FirstHits {
-    uint32_t* work;
+// Same tile, deferred form.  Phase 1 takes the tile's samples in batches
+// of kSortPerLane * block: every lane generates the first rays of its
+// samples, the batch is counting-sorted in LDS by an octahedral direction
+// key (64 cells, Morton order), and the lanes then trace the first rays in
+// sorted order, appending every first vertex (work index, t, triangle) to
+// an LDS buffer.  Rays of similar direction share waves, so the rays that
+// reach the scene (and traverse deep) are packed together and waves of
+// escaping rays finish early.  Once the buffer holds at least a block's
+// worth, phase 2 drains it: each lane regenerates its entry's ray (Philox
+// block 0), then shades, tests the shadow ray and follows the rest of the
+// path, on densely packed lanes.
+constexpr uint32_t kSortPerLane = 2;
+constexpr uint32_t kDirCells = 64;
+
+struct DeferredLds {
+    uint32_t* work;    // first-hit buffer, capacity block * (kSortPerLane + 1)
     float* t;
     int* prim;
     int* sorted;
-    uint32_t* count;
+    uint32_t* count;   // [0] buffer fill, [1] batch size
+    uint32_t* order;   // [block * kSortPerLane] work indices in key order
+    uint32_t* start;   // [kDirCells] first slot of each key
+    uint32_t* fill;    // [kDirCells]
 };
 
-__device__ __forceinline__ FirstHits carve_first_hits(float* base, uint32_t cap)
+// 32-bit words of LDS the deferred form adds per block of nb lanes
+__host__ __device__ constexpr size_t deferred_words(uint32_t nb)
 {
-    FirstHits f;
-    f.work = reinterpret_cast<uint32_t*>(base);
-    f.t = base + cap;
-    f.prim = reinterpret_cast<int*>(base + 2 * cap);
-    f.sorted = reinterpret_cast<int*>(base + 3 * cap);
-    f.count = reinterpret_cast<uint32_t*>(base + 4 * cap);
+    return 4ull * nb * (kSortPerLane + 1) + 2 + (size_t)nb * kSortPerLane + 2ull * kDirCells;
+}
+
+__device__ __forceinline__ DeferredLds carve_deferred(float* base, uint32_t nb)
+{
+    const uint32_t cap = nb * (kSortPerLane + 1);
+    DeferredLds f;
+    uint32_t* u = reinterpret_cast<uint32_t*>(base);
+    f.work = u;
+    f.t = reinterpret_cast<float*>(u + cap);
+    f.prim = reinterpret_cast<int*>(u + 2 * cap);
+    f.sorted = reinterpret_cast<int*>(u + 3 * cap);
+    f.count = u + 4 * cap;
+    f.order = u + 4 * cap + 2;
+    f.start = f.order + nb * kSortPerLane;
+    f.fill = f.start + kDirCells;
     return f;
+}
+
+__device__ __forceinline__ uint32_t spread3(uint32_t b) { return (b & 1u) | ((b & 2u) << 1) | ((b & 4u) << 2); }
+
+// octahedral cell of a direction (8 x 8), Morton-ordered
+__device__ __forceinline__ uint32_t direction_cell(vec3 d)
+{
+    const float s = fabsf(d.x) + fabsf(d.y) + fabsf(d.z);
+    float u = d.x / s, v = d.y / s;
+    if (d.z < 0.0f) {
+        const float fu = (1.0f - fabsf(v)) * copysignf(1.0f, u);
+        v = (1.0f - fabsf(u)) * copysignf(1.0f, v);
+        u = fu;
+    }
+    const uint32_t qx = min((uint32_t)fmaxf((u * 0.5f + 0.5f) * 8.0f, 0.0f), 7u);
+    const uint32_t qy = min((uint32_t)fmaxf((v * 0.5f + 0.5f) * 8.0f, 0.0f), 7u);
+    return spread3(qx) | (spread3(qy) << 1);
 }
 
 template <class TallyT>
 __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const LaunchArgs& L, uint32_t p0,
-                                                     float* lds_film, const FirstHits& fh, uint32_t* stk,
+                                                     float* lds_film, const DeferredLds& fh, uint32_t* stk,
                                                      int stride, TallyT& tally)
 {
     const uint32_t T = S.n_bins;
@@ -649,17 +686,57 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
     float* toow = tsteady + TP;
     const uint32_t npix = min(TP, L.n_pixels - p0);
     const uint32_t nb = blockDim.x;
-    for (uint32_t i = threadIdx.x; i < TP * T + 2 * TP; i += nb) lds_film[i] = 0.0f;
-    if (threadIdx.x == 0) *fh.count = 0u;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t i = tid; i < TP * T + 2 * TP; i += nb) lds_film[i] = 0.0f;
+    if (tid == 0) fh.count[0] = 0u;
     __syncthreads();
 
     const uint32_t work = npix * L.spp;
     const bool has_vertex = last_vertex(S, L) >= 1;
+    const uint32_t batch = nb * kSortPerLane;
     uint32_t cur = 0xffffffffu;
     FilmSink sink{nullptr, 0.0f, 0.0f};
-    for (uint32_t base = 0; base < work; base += nb) {
-        const uint32_t w = base + threadIdx.x;
-        if (w < work && has_vertex) {
+    for (uint32_t base = 0; base < work; base += batch) {
+        // phase 1a: direction cells of the batch, counting sort
+        if (tid < kDirCells) {
+            fh.start[tid] = 0u;
+            fh.fill[tid] = 0u;
+        }
+        __syncthreads();
+        uint32_t cell[kSortPerLane];
+#pragma unroll
+        for (uint32_t k = 0; k < kSortPerLane; ++k) {
+            const uint32_t w = base + k * nb + tid;
+            cell[k] = 0xffffffffu;
+            if (w < work && has_vertex) {
+                const uint32_t pl = w / L.spp;
+                PathState ps;
+                begin_path(S, L, p0 + pl, L.sample_offset + (w - pl * L.spp), ps);
+                cell[k] = direction_cell(ps.d);
+                atomicAdd(fh.start + cell[k], 1u);
+            }
+        }
+        __syncthreads();
+        if (tid < kDirCells) {  // exclusive scan of the cell counts by the first wave
+            const uint32_t c = fh.start[tid];
+            uint32_t x = c;
+            for (int off = 1; off < (int)kDirCells; off <<= 1) {
+                const uint32_t y = __shfl_up(x, off, kDirCells);
+                if ((int)tid >= off) x += y;
+            }
+            fh.start[tid] = x - c;
+            if (tid == kDirCells - 1) fh.count[1] = x;
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t k = 0; k < kSortPerLane; ++k)
+            if (cell[k] != 0xffffffffu)
+                fh.order[fh.start[cell[k]] + atomicAdd(fh.fill + cell[k], 1u)] = base + k * nb + tid;
+        __syncthreads();
+        // phase 1b: first rays in direction order
+        const uint32_t nvalid = fh.count[1];
+        for (uint32_t j = tid; j < nvalid; j += nb) {
+            const uint32_t w = fh.order[j];
             const uint32_t pl = w / L.spp;
             tally.add(kTallyDraws);
             PathState ps;
@@ -668,17 +745,18 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
             float t_hit;
             bool med;
             if (resolve_event(S, ps, h, t_hit, med)) {
-                const uint32_t j = atomicAdd(fh.count, 1u);
-                fh.work[j] = w;
-                fh.t[j] = h.t;
-                fh.prim[j] = h.prim;
-                fh.sorted[j] = h.sorted;
+                const uint32_t q = atomicAdd(fh.count, 1u);
+                fh.work[q] = w;
+                fh.t[q] = h.t;
+                fh.prim[q] = h.prim;
+                fh.sorted[q] = h.sorted;
             }
         }
         __syncthreads();
-        const uint32_t n = *fh.count;
-        if (n >= nb || base + nb >= work) {
-            for (uint32_t j = threadIdx.x; j < n; j += nb) {
+        // phase 2: the rest of the buffered paths on packed lanes
+        const uint32_t n = fh.count[0];
+        if (n >= nb || base + batch >= work) {
+            for (uint32_t j = tid; j < n; j += nb) {
                 const uint32_t wj = fh.work[j];
                 const uint32_t pl = wj / L.spp;
                 const uint32_t sample = L.sample_offset + (wj - pl * L.spp);
@@ -701,7 +779,7 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
                 continue_path(S, L, p0 + pl, sample, ps, h, stk, stride, sink, tally);
             }
             __syncthreads();
-            if (threadIdx.x == 0) *fh.count = 0u;
+            if (tid == 0) fh.count[0] = 0u;
             __syncthreads();
         }
     }
@@ -712,20 +790,20 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
     __syncthreads();
 
     const bool acc = (L.flags & kFlagAccumulate) != 0;
-    const size_t base = (size_t)p0 * T;
+    const size_t fbase = (size_t)p0 * T;
     const uint32_t nvals = npix * T;
-    for (uint32_t i = threadIdx.x; i < nvals; i += nb) {
+    for (uint32_t i = tid; i < nvals; i += nb) {
         const float v = tfilm[i] * L.norm;
-        L.film[base + i] = acc ? L.film[base + i] + v : v;
+        L.film[fbase + i] = acc ? L.film[fbase + i] + v : v;
     }
-    if (threadIdx.x < npix) {
-        const uint32_t p = p0 + threadIdx.x;
+    if (tid < npix) {
+        const uint32_t p = p0 + tid;
         if (L.steady) {
-            const float v = tsteady[threadIdx.x] * L.norm;
+            const float v = tsteady[tid] * L.norm;
             L.steady[p] = acc ? L.steady[p] + v : v;
         }
         if (L.oow) {
-            const float v = toow[threadIdx.x] * L.norm;
+            const float v = toow[tid] * L.norm;
             L.oow[p] = acc ? L.oow[p] + v : v;
         }
     }
@@ -737,10 +815,9 @@ __global__ void __launch_bounds__(256) k_render_deferred(SceneView S, LaunchArgs
     Tally<kCount> tally;
     extern __shared__ float lds[];
     const uint32_t TP = L.tile_pixels;
-    const uint32_t cap = 2 * blockDim.x;
     float* after_film = lds + (size_t)TP * S.n_bins + 2 * TP;
-    const FirstHits fh = carve_first_hits(after_film, cap);
-    uint32_t* stk = reinterpret_cast<uint32_t*>(after_film + 4 * cap + 1) + threadIdx.x;
+    const DeferredLds fh = carve_deferred(after_film, blockDim.x);
+    uint32_t* stk = reinterpret_cast<uint32_t*>(after_film + deferred_words(blockDim.x)) + threadIdx.x;
     render_tile_deferred(S, L, blockIdx.x * TP, lds, fh, stk, (int)blockDim.x, tally);
     tally.flush(counts);
 }
@@ -768,9 +845,9 @@ __global__ void __launch_bounds__(256) k_batch(BatchTables B)
     extern __shared__ float lds[];
     __shared__ uint32_t s_item;
     Tally<false> tally;
-    const uint32_t cap = 2 * blockDim.x;
-    const FirstHits fh = carve_first_hits(lds + B.film_words, cap);
-    uint32_t* stk = reinterpret_cast<uint32_t*>(lds + B.film_words + (kDeferred ? 4 * cap + 1 : 0)) + threadIdx.x;
+    const DeferredLds fh = carve_deferred(lds + B.film_words, blockDim.x);
+    uint32_t* stk =
+        reinterpret_cast<uint32_t*>(lds + B.film_words + (kDeferred ? deferred_words(blockDim.x) : 0)) + threadIdx.x;
     while (true) {
         if (threadIdx.x == 0) s_item = atomicAdd(B.cursor, 1u);
         __syncthreads();
@@ -1151,13 +1228,13 @@ hipError_t launch_backward(const SceneView& S, const LaunchArgs& L, uint32_t blo
 
 size_t deferred_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth)
 {
-    return ((size_t)tile_pixels * n_bins + 2ull * tile_pixels + 8ull * block + 1) * sizeof(float) +
+    return ((size_t)tile_pixels * n_bins + 2ull * tile_pixels + deferred_words(block)) * sizeof(float) +
            (size_t)block * stack_depth * sizeof(uint32_t);
 }
 
 size_t batch_lds_bytes(uint32_t film_words, uint32_t block, uint32_t stack_depth, bool deferred)
 {
-    return ((size_t)film_words + (deferred ? 8ull * block + 1 : 0)) * sizeof(float) +
+    return ((size_t)film_words + (deferred ? deferred_words(block) : 0)) * sizeof(float) +
            (size_t)block * stack_depth * sizeof(uint32_t);
 }
 

@@ -198,3 +198,27 @@ def test_repeatable(tr):
         torch.cuda.synchronize()
     assert ((a != 0) == (b != 0)).all()
     np.testing.assert_allclose(a, b, rtol=1e-5, atol=0)
+
+
+@pytest.mark.parametrize("make", ["confocal", "large_small", "furnace"])
+def test_bvh_builders_agree(tr, make):
+    """LBVH and PLOC trees give the same film: the closest hit is a function
+    of the triangle set alone."""
+    import torch
+    if make == "confocal":
+        sc = scenes.confocal_nlos(grid=16, spp=256)
+    elif make == "large_small":
+        sc = scenes.large_scene(cells=64, sphere_freq=8, grid=3, width=48, height=40, n_bins=256, spp=4)
+    else:
+        sc = scenes.sphere_furnace(radius=1.003, freq=40, width=16, height=16)
+    _announce(f"builders {make}")
+    out = {}
+    for b in ("lbvh", "ploc"):
+        with tr.upload(sc, builder=b) as dev:
+            info = dev.info()
+            assert info["bvh_internal_nodes"] == sc.n_tris - 1
+            out[b] = tr.render_transient(dev)[1].cpu().numpy()
+            torch.cuda.synchronize()
+    a, c = out["lbvh"], out["ploc"]
+    assert ((a != 0) == (c != 0)).all()
+    np.testing.assert_allclose(a, c, rtol=1e-5, atol=0)
