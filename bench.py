@@ -125,7 +125,9 @@ def backward_forward_ratio(tr, steps=5, warmup=1):
         fwd_ms, _ = time_launches(lambda: tr.render_transient(dev, film=film, albedo=a, roughness=r), steps, warmup)
         bwd_ms, _ = time_launches(lambda: tr.render_transient_backward(dev, delta, albedo=a, roughness=r), steps,
                                   warmup)
-    return bwd_ms / fwd_ms, fwd_ms / steps, bwd_ms / steps
+        rep_ms, _ = time_launches(lambda: tr.render_transient_backward(dev, delta, albedo=a, roughness=r,
+                                                                       kernel="path"), steps, warmup)
+    return bwd_ms / fwd_ms, fwd_ms / steps, bwd_ms / steps, rep_ms / steps
 
 
 def run_batched(args, tr):
@@ -264,9 +266,10 @@ def main():
     if forms:
         out["kernel_forms_mpaths_per_s"] = forms
     if not args.no_backward:
-        ratio, f_ms, b_ms = backward_forward_ratio(tr)
+        ratio, f_ms, b_ms, rep_ms = backward_forward_ratio(tr)
         out["backward_forward_ratio"] = round(ratio, 3)
         out["backward_forward_ms"] = [round(f_ms, 3), round(b_ms, 3)]
+        out["backward_replay_ms"] = round(rep_ms, 3)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc)
     print(json.dumps(out), flush=True)

@@ -152,8 +152,11 @@ enum { TRHIP_BVH_PLOC = 0, TRHIP_BVH_LBVH = 1 };
  *   one sample per lane, buffers the first vertices in LDS and follows the
  *   rest of those paths on densely packed lanes; WAVEFRONT runs the stages
  *   of a workgroup's paths (generate, intersect, shade, shadow) over
- *   compacted queues held in LDS.  All produce the same film.  Ignored by
- *   the backward pass.
+ *   compacted queues held in LDS.  All produce the same film.  For the
+ *   backward pass, TRHIP_KERNEL_PATH selects path replay (every path traced
+ *   twice) and any other value the automatic choice (one trace per path with
+ *   a per-path register stash when a path has at most 8 vertices, else
+ *   replay); both give the same gradients up to rounding.
  */
 typedef struct {
     uint32_t spp;
@@ -217,8 +220,9 @@ trhip_status trhip_render_transient(trhip_scene* scene, const trhip_render_desc*
  * same layout as the film), writes dL/d(albedo) and dL/d(roughness) per
  * triangle (DEVICE float[n_triangles], overwritten; roughness gradients of
  * Lambertian triangles are 0).  The gradient is that of the estimator at
- * the given seed with the sampling pdf held fixed (path replay: each path
- * is traced twice with the same random numbers).  primal_film (optional,
+ * the given seed with the sampling pdf held fixed, from the same paths as
+ * the forward render (see render->kernel for the two evaluation orders).
+ * primal_film (optional,
  * DEVICE, film layout) receives the film of the replayed paths.
  * Errors: BAD_HANDLE, INVALID_ARG, UNSUPPORTED, OOM, HIP.
  */

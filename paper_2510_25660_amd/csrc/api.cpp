@@ -454,8 +454,14 @@ trhip_status trhip_render_transient_backward(trhip_scene* scene, const trhip_ren
     L.g_alb = scene->d_grad;
     L.g_rough = scene->d_grad + nt;
     L.primal = primal_film;
+    // single trace with a register stash when a path has few continuations,
+    // path replay otherwise (or when asked for with TRHIP_KERNEL_PATH)
+    const int vmax = (scene->view.sensor == TRHIP_SENSOR_CONFOCAL) ? (int)render->max_depth - 3
+                                                                    : (int)render->max_depth - 1;
+    int max_cont = 0;
+    if (render->kernel != TRHIP_KERNEL_PATH) max_cont = (vmax - 1 <= 2) ? 2 : (vmax - 1 <= 7 ? 7 : 0);
     hipError_t e = trhip::launch_zero_f64(scene->d_grad, 2 * nt, s);
-    if (e == hipSuccess) e = trhip::launch_backward(scene->view, L, block, s);
+    if (e == hipSuccess) e = trhip::launch_backward(scene->view, L, block, max_cont, s);
     if (e == hipSuccess) e = trhip::launch_f64_to_f32(scene->d_grad, grad_albedo, nt, s);
     if (e == hipSuccess) e = trhip::launch_f64_to_f32(scene->d_grad + nt, grad_roughness, nt, s);
     if (e != hipSuccess) return hip_fail(e, "backward launch");

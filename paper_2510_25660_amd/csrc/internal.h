@@ -39,7 +39,9 @@ hipError_t launch_render(const SceneView& S, const LaunchArgs& L, uint32_t block
                          unsigned long long* counts = nullptr);
 hipError_t launch_render_wavefront(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
                                    unsigned long long* counts = nullptr);
-hipError_t launch_backward(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream);
+// max_cont 2 or 7: single-trace adjoint with a per-path stash of that many
+// continuation vertices; anything else: path replay (two traces per path)
+hipError_t launch_backward(const SceneView& S, const LaunchArgs& L, uint32_t block, int max_cont, hipStream_t stream);
 size_t deferred_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth);
 size_t batch_lds_bytes(uint32_t film_words, uint32_t block, uint32_t stack_depth, bool deferred);
 // resets the cursor and launches the persistent kernel (groups workgroups)

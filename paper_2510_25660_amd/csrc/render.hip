@@ -513,7 +513,7 @@ __device__ void continue_path(const SceneView& S, const LaunchArgs& L, uint32_t 
             sink.contribution(v, nee.k, nee.c, nee.bin, nee.g_alb, nee.g_rough);
         }
         if (!cont.alive) break;
-        if (cont.k >= 0) sink.continuation(cont.k, cont.g_alb, cont.g_rough);
+        if (cont.k >= 0) sink.continuation(v, cont.k, cont.g_alb, cont.g_rough);
         if (ps.v > vmax) break;
         h = closest_hit(S, make_ray(ps.o, ps.d), ps.prev, stk, stride, tally);
     }
@@ -546,7 +546,7 @@ struct FilmSink {
         else oow += c;
         steady += c;
     }
-    __device__ __forceinline__ void continuation(int, float, float) {}
+    __device__ __forceinline__ void continuation(int, int, float, float) {}
 };
 
 // Renders one tile of pixels [p0, p0 + tile_pixels) with all their samples:
@@ -1092,7 +1092,7 @@ struct AdjointSumSink {
     {
         if (bin >= 0) total += (double)delta[bin] * (double)c * (double)norm;
     }
-    __device__ __forceinline__ void continuation(int, float, float) {}
+    __device__ __forceinline__ void continuation(int, int, float, float) {}
 };
 
 struct AdjointScatterSink {
@@ -1115,7 +1115,7 @@ struct AdjointScatterSink {
             if (g_rough_nee != 0.0f) unsafeAtomicAdd(g_rough + k, a * (double)g_rough_nee);
         }
     }
-    __device__ __forceinline__ void continuation(int k, float g_alb_c, float g_rough_c)
+    __device__ __forceinline__ void continuation(int, int k, float g_alb_c, float g_rough_c)
     {
         const double rest = total - prefix;
         if (rest != 0.0) {
@@ -1155,6 +1155,115 @@ __global__ void __launch_bounds__(256) k_backward(SceneView S, LaunchArgs L)
         AdjointScatterSink second{drow, want_primal ? tprimal + (size_t)pl * T : nullptr, L.norm, first.total, 0.0,
                                   L.g_alb, L.g_rough};
         trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, second, tally);
+    }
+    if (want_primal) {
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < npix * T; i += blockDim.x) L.primal[base + i] = tprimal[i] * L.norm;
+    }
+}
+
+// Single-trace adjoint for paths of at most kMaxCont continuations.  The
+// sink keeps, per continuation vertex v, its triangle, d log f of the
+// sampled direction, a_v times d log f of its connection, and R_v, the sum
+// of a_j over the contributions after v (each contribution adds its a_j to
+// every stashed vertex).  At the end of the path every stashed vertex adds
+// a_v dlogf_nee + R_v dlogf_cont to its triangle: the same gradient as path
+// replay, from one trace.  The stash lives in registers (static indices).
+template <int kMaxCont>
+struct AdjointStashSink {
+    static constexpr bool kWantsGradients = true;
+    const float* delta;
+    float* primal_row;
+    float norm;
+    double* g_alb;
+    double* g_rough;
+    int nv = 0;
+    int k[kMaxCont];
+    float ca[kMaxCont], cr[kMaxCont], na[kMaxCont], nr[kMaxCont], R[kMaxCont];
+    bool pending = false;  // connection term of the current vertex
+    int pk = -1;
+    float pa = 0.0f, pr = 0.0f;
+
+    __device__ __forceinline__ void contribution(int, int kv, float c, int bin, float g_alb_nee, float g_rough_nee)
+    {
+        if (bin < 0) return;
+        if (primal_row) atomicAdd(primal_row + bin, c);
+        const float a = (delta[bin] * c) * norm;
+#pragma unroll
+        for (int i = 0; i < kMaxCont; ++i)
+            if (i < nv) R[i] += a;
+        if (kv >= 0) {
+            pending = true;
+            pk = kv;
+            pa = a * g_alb_nee;
+            pr = a * g_rough_nee;
+        }
+    }
+    __device__ __forceinline__ void continuation(int, int kv, float g_alb_c, float g_rough_c)
+    {
+        const bool mine = pending && pk == kv;
+#pragma unroll
+        for (int i = 0; i < kMaxCont; ++i)
+            if (i == nv) {
+                k[i] = kv;
+                ca[i] = g_alb_c;
+                cr[i] = g_rough_c;
+                na[i] = mine ? pa : 0.0f;
+                nr[i] = mine ? pr : 0.0f;
+                R[i] = 0.0f;
+            }
+        ++nv;
+        pending = false;
+    }
+    __device__ __forceinline__ void finish()
+    {
+        if (pending) {
+            if (pa != 0.0f) unsafeAtomicAdd(g_alb + pk, (double)pa);
+            if (pr != 0.0f) unsafeAtomicAdd(g_rough + pk, (double)pr);
+        }
+#pragma unroll
+        for (int i = 0; i < kMaxCont; ++i)
+            if (i < nv) {
+                const double ga = (double)na[i] + (double)R[i] * (double)ca[i];
+                const double gr = (double)nr[i] + (double)R[i] * (double)cr[i];
+                if (ga != 0.0) unsafeAtomicAdd(g_alb + k[i], ga);
+                if (gr != 0.0) unsafeAtomicAdd(g_rough + k[i], gr);
+            }
+    }
+};
+
+template <int kMaxCont>
+__global__ void __launch_bounds__(256) k_backward_stash(SceneView S, LaunchArgs L)
+{
+    Tally<false> tally;
+    extern __shared__ float lds[];
+    const uint32_t T = S.n_bins;
+    const uint32_t TP = L.tile_pixels;
+    const bool want_primal = L.primal != nullptr;
+    float* tdelta = lds;
+    float* tprimal = lds + (size_t)TP * T;
+    uint32_t* stk = reinterpret_cast<uint32_t*>(tprimal + (want_primal ? (size_t)TP * T : 0)) + threadIdx.x;
+    const int stride = (int)blockDim.x;
+    const uint32_t p0 = blockIdx.x * TP;
+    const uint32_t npix = min(TP, L.n_pixels - p0);
+    const size_t base = (size_t)p0 * T;
+    for (uint32_t i = threadIdx.x; i < TP * T; i += blockDim.x) {
+        tdelta[i] = (i < npix * T) ? L.grad_film[base + i] : 0.0f;
+        if (want_primal) tprimal[i] = 0.0f;
+    }
+    __syncthreads();
+    const uint32_t work = npix * L.spp;
+    for (uint32_t w = threadIdx.x; w < work; w += blockDim.x) {
+        const uint32_t pl = w / L.spp;
+        const uint32_t s = w - pl * L.spp;
+        AdjointStashSink<kMaxCont> sink;
+        sink.delta = tdelta + (size_t)pl * T;
+        sink.primal_row = want_primal ? tprimal + (size_t)pl * T : nullptr;
+        sink.norm = L.norm;
+        sink.g_alb = L.g_alb;
+        sink.g_rough = L.g_rough;
+        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, sink, tally);
+        sink.finish();
     }
     if (want_primal) {
         __syncthreads();
@@ -1218,11 +1327,16 @@ hipError_t launch_render(const SceneView& S, const LaunchArgs& L, uint32_t block
     return hipGetLastError();
 }
 
-hipError_t launch_backward(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream)
+hipError_t launch_backward(const SceneView& S, const LaunchArgs& L, uint32_t block, int max_cont, hipStream_t stream)
 {
     const uint32_t tiles = (L.n_pixels + L.tile_pixels - 1) / L.tile_pixels;
     const size_t lds = backward_lds_bytes(L.tile_pixels, S.n_bins, block, S.stack_depth, L.primal != nullptr);
-    hipLaunchKernelGGL(k_backward, dim3(tiles), dim3(block), lds, stream, S, L);
+    if (max_cont == 2)
+        hipLaunchKernelGGL(k_backward_stash<2>, dim3(tiles), dim3(block), lds, stream, S, L);
+    else if (max_cont == 7)
+        hipLaunchKernelGGL(k_backward_stash<7>, dim3(tiles), dim3(block), lds, stream, S, L);
+    else
+        hipLaunchKernelGGL(k_backward, dim3(tiles), dim3(block), lds, stream, S, L);
     return hipGetLastError();
 }
 

@@ -31,20 +31,26 @@ def _setup(sub=2, res=16, spp=64):
     return sc, ta, trough
 
 
-def test_adjoint_matches_oracle(tr, oracle_mod):
+@pytest.mark.parametrize("mode", ["replay", "stash"])
+@pytest.mark.parametrize("depth", [4, 6])
+def test_adjoint_matches_oracle(tr, oracle_mod, mode, depth):
+    """Single-trace (register stash) and path-replay adjoints against the
+    oracle's adjoint, at 3 and 5 vertices per path."""
     import torch
     sc, ta, trough = _setup()
     spp, seed = 64, 77
-    _announce("adjoint vs oracle")
+    _announce(f"adjoint vs oracle {mode} depth {depth}")
     O = oracle_mod.Oracle(sc)
-    target, _, _ = O.render(spp=spp, seed=seed, stream_id=1, albedo=ta, roughness=trough)
-    film_o, _, _ = O.render(spp=spp, seed=seed)
+    target, _, _ = O.render(spp=spp, seed=seed, max_depth=depth, stream_id=1, albedo=ta, roughness=trough)
+    film_o, _, _ = O.render(spp=spp, seed=seed, max_depth=depth)
     delta = (2.0 * (film_o - target)).astype(np.float32)
-    ga_o, gr_o = O.backward(delta, spp=spp, seed=seed)
+    ga_o, gr_o = O.backward(delta, spp=spp, seed=seed, max_depth=depth)
+    kernel = "path" if mode == "replay" else "auto"
     with tr.upload(sc) as dev:
         d = torch.from_numpy(delta.reshape(sc.height, sc.width, sc.n_bins)).cuda()
-        ga, gr, primal = tr.render_transient_backward(dev, d, spp=spp, seed=seed, primal=True)
-        _, film = tr.render_transient(dev, spp=spp, seed=seed)
+        ga, gr, primal = tr.render_transient_backward(dev, d, spp=spp, seed=seed, max_depth=depth, primal=True,
+                                                      kernel=kernel)
+        _, film = tr.render_transient(dev, spp=spp, seed=seed, max_depth=depth)
         torch.cuda.synchronize()
         ga, gr = ga.cpu().numpy().astype(np.float64), gr.cpu().numpy().astype(np.float64)
         primal = primal.cpu().numpy()
@@ -121,3 +127,72 @@ def test_autograd_function(tr):
         torch.cuda.synchronize()
         np.testing.assert_allclose(a.grad.cpu().numpy(), ga.cpu().numpy(), rtol=1e-5, atol=1e-12)
         np.testing.assert_allclose(r.grad.cpu().numpy(), gr.cpu().numpy(), rtol=1e-5, atol=1e-12)
+
+
+def test_adjoint_full_size_sampled_pixels(tr, oracle_mod):
+    """The differentiable workload at full size (9,826 triangles, 64x64, 256
+    bins, 1024 spp, depth 4) in the launch the benchmark times, with
+    dL/dfilm non-zero on 64 sampled pixels only, so that the oracle's adjoint
+    over exactly those pixels is the reference."""
+    import torch
+    sc = scenes.diff_scene()
+    ta, trough = scenes.perturbed_params(sc, seed=5)
+    rng = np.random.default_rng(31)
+    pix = np.sort(rng.choice(sc.n_pixels, 64, replace=False)).astype(np.int32)
+    _announce("adjoint full size, sampled pixels")
+    O = oracle_mod.Oracle(sc)
+    tgt, _, _ = O.render(pixels=pix, stream_id=1, albedo=ta, roughness=trough)
+    cur, _, _ = O.render(pixels=pix)
+    delta = np.zeros((sc.n_pixels, sc.n_bins), np.float32)
+    delta[pix] = 2.0 * (cur - tgt)
+    ga_o, gr_o = O.backward(delta, pixels=pix)
+    with tr.upload(sc) as dev:
+        d = torch.from_numpy(delta.reshape(sc.height, sc.width, sc.n_bins)).cuda()
+        ga, gr = tr.render_transient_backward(dev, d)
+        torch.cuda.synchronize()
+        ga, gr = ga.cpu().numpy().astype(np.float64), gr.cpu().numpy().astype(np.float64)
+    assert np.abs(ga - ga_o).max() <= 1e-4 * np.abs(ga_o).max()
+    assert np.abs(gr - gr_o).max() <= 1e-4 * np.abs(gr_o).max()
+    assert (np.abs(ga_o) > 0).sum() > 100
+
+
+def test_adjoint_full_size_finite_differences(tr):
+    """Full-size differentiable workload: GPU adjoint against central
+    differences (eps 1e-3) of GPU renders on 32 seeded parameters with
+    |g| >= 1e-3 max|g| (16 albedo, 16 GGX roughness, frozen proposal)."""
+    import torch
+    sc = scenes.diff_scene()
+    ta, trough = scenes.perturbed_params(sc, seed=5)
+    eps = 1e-3
+    _announce("adjoint full size vs finite differences")
+    with tr.upload(sc) as dev:
+        a0 = torch.from_numpy(sc.albedo).cuda()
+        r0 = torch.from_numpy(sc.roughness).cuda()
+        _, target = tr.render_transient(dev, stream_id=1, albedo=torch.from_numpy(ta).cuda(),
+                                        roughness=torch.from_numpy(trough).cuda())
+        _, film = tr.render_transient(dev, frozen=True, albedo=a0, roughness=r0)
+        ga, gr = tr.render_transient_backward(dev, 2.0 * (film - target), frozen=True, albedo=a0, roughness=r0)
+        torch.cuda.synchronize()
+        ga_n, gr_n = ga.cpu().numpy().astype(np.float64), gr.cpu().numpy().astype(np.float64)
+        tgt = target.double()
+
+        def fd(which, k):
+            out = []
+            for sgn in (1, -1):
+                a = a0.clone()
+                r = r0.clone()
+                (a if which == "a" else r)[k] += sgn * eps
+                out.append(tr.render_transient(dev, frozen=True, albedo=a, roughness=r)[1].double())
+            return float(((out[0] - out[1]) * (out[0] + out[1] - 2 * tgt)).sum().item() / (2 * eps))
+
+        rng = np.random.default_rng(32)
+        ggx = np.flatnonzero(sc.mat_type == scenes.MAT_GGX)
+        cand_a = np.flatnonzero(np.abs(ga_n) >= 1e-3 * np.abs(ga_n).max())
+        cand_r = ggx[np.abs(gr_n[ggx]) >= 1e-3 * np.abs(gr_n[ggx]).max()]
+        worst = 0.0
+        for k in rng.choice(cand_a, 16, replace=False):
+            worst = max(worst, abs(fd("a", int(k)) - ga_n[k]) / np.abs(ga_n).max())
+        for k in rng.choice(cand_r, 16, replace=False):
+            worst = max(worst, abs(fd("r", int(k)) - gr_n[k]) / np.abs(gr_n).max())
+    print(f"full-size worst FD deviation / max|g| = {worst:.2e}")
+    assert worst <= 5e-3
