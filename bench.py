@@ -45,7 +45,7 @@ OPS_PER = {
 WORKLOADS = {
     "confocal": dict(desc="confocal NLOS 64x64 scan, 9,682 tris (9,680-tri blob + 2-tri wall), 512 bins x 2.4 mm "
                           "from 0.9 m, 4096 spp, 3 bounces, FP32",
-                     traffic="k_render_confocal_nlos_64x64x512_4096spp_hbm_traffic.txt"),
+                     traffic="k_render_deferred_confocal_nlos_64x64x512_4096spp_hbm_traffic.txt"),
     "box": dict(desc="box room 34 tris, 64x64 pinhole, 256 bins x 0.01 m from 0, 16 spp, max depth 4, FP32"),
     "large": dict(desc="terrain + 49 displaced spheres 998,608 tris, fog sigma_t 0.1, 512x512, 1024 bins x 5 mm "
                        "from 4.5 m, 64 spp, max depth 8, FP32"),
@@ -241,6 +241,9 @@ def main():
     value = paths / (ms_per_step * 1e-3) / 1e6
     launch_ms = float(np.mean(per))
     ops = sum(OPS_PER[k] * v for k, v in counts.items())
+    # the kernel the automatic choice runs: the deferred form for the confocal sensor
+    form = args.kernel if args.kernel != "auto" else ("deferred" if sc.sensor == 1 else "path")
+    kernel_name = {"path": "k_render", "deferred": "k_render_deferred", "wavefront": "k_render_wf"}[form]
     achieved = ops / (launch_ms * 1e-3)
     out = {
         "metric": "Mpath-samples/s into transient film at 1 GPU; backward/forward time ratio",
@@ -260,7 +263,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(PEAK_VALU_LANE_OPS / 1e12, 2),
                      "unit": "T lane-ops/s", "frac": round(achieved / PEAK_VALU_LANE_OPS, 4),
                      "traffic": measured_traffic(args.workload), "traffic_unit": "bytes/launch",
-                     "kernel": "k_render", "launch_ms": round(launch_ms, 4),
+                     "kernel": kernel_name, "launch_ms": round(launch_ms, 4),
                      "ops_per_launch": int(ops), "counts": counts},
     }
     if forms:
