@@ -226,16 +226,19 @@ trhip_status validate_render(const trhip_scene* s, const trhip_render_desc* r)
 
 enum class Kind { Path, Wavefront, Deferred, Backward, BackwardPrimal };
 
-size_t lds_bytes(Kind kind, uint32_t tp, uint32_t T, uint32_t bs, uint32_t depth)
+// stack: LDS bytes of one lane's traversal stack
+size_t lds_bytes(Kind kind, uint32_t tp, uint32_t T, uint32_t bs, uint32_t stack)
 {
     switch (kind) {
-    case Kind::Path: return trhip::render_lds_bytes(tp, T, bs, depth);
-    case Kind::Wavefront: return trhip::wavefront_lds_bytes(tp, T, bs, depth);
-    case Kind::Deferred: return trhip::deferred_lds_bytes(tp, T, bs, depth);
-    case Kind::Backward: return trhip::backward_lds_bytes(tp, T, bs, depth, false);
-    default: return trhip::backward_lds_bytes(tp, T, bs, depth, true);
+    case Kind::Path: return trhip::render_lds_bytes(tp, T, bs, stack);
+    case Kind::Wavefront: return trhip::wavefront_lds_bytes(tp, T, bs, stack);
+    case Kind::Deferred: return trhip::deferred_lds_bytes(tp, T, bs, stack);
+    case Kind::Backward: return trhip::backward_lds_bytes(tp, T, bs, stack, false);
+    default: return trhip::backward_lds_bytes(tp, T, bs, stack, true);
     }
 }
+
+uint32_t lane_stack_bytes(const trhip_scene* s) { return trhip::stack_lane_bytes(s->view.n_tris, s->view.stack_depth); }
 
 // Launch shape: enough pixels per tile that a workgroup has ~block samples
 // of work, capped by the LDS budget (tile film + traversal stacks, plus the
@@ -243,7 +246,7 @@ size_t lds_bytes(Kind kind, uint32_t tp, uint32_t T, uint32_t bs, uint32_t depth
 trhip_status choose_shape(const trhip_scene* s, const trhip_render_desc* r, Kind kind, uint32_t* tile,
                           uint32_t* block)
 {
-    const uint32_t T = s->view.n_bins, depth = s->view.stack_depth;
+    const uint32_t T = s->view.n_bins, depth = lane_stack_bytes(s);
     uint32_t bs = r->block_size ? r->block_size : kMaxBlock;
     if (!r->block_size) {
         // small per-tile work: narrower groups keep more of them in flight
@@ -260,7 +263,8 @@ trhip_status choose_shape(const trhip_scene* s, const trhip_render_desc* r, Kind
         return fail(TRHIP_ERR_INVALID_ARG, "tile_pixels * spp must stay below 2^32");
     const size_t need = lds_bytes(kind, tp, T, bs, depth);
     if (need > kLdsBudget)
-        return fail(TRHIP_ERR_UNSUPPORTED, "launch needs %zu bytes of LDS (tile %u x %u bins, block %u, stack %u)",
+        return fail(TRHIP_ERR_UNSUPPORTED,
+                    "launch needs %zu bytes of LDS (tile %u x %u bins, block %u, stack %u bytes per lane)",
                     need, tp, T, bs, depth);
     *tile = tp;
     *block = bs;
@@ -278,7 +282,7 @@ Kind forward_kind(const trhip_scene* s, const trhip_render_desc* r)
     if (r->kernel == TRHIP_KERNEL_DEFERRED) return Kind::Deferred;
     if (s->view.sensor != TRHIP_SENSOR_CONFOCAL) return Kind::Path;
     const uint32_t bs = r->block_size ? r->block_size : 64;
-    return lds_bytes(Kind::Deferred, 1, s->view.n_bins, bs, s->view.stack_depth) <= kLdsBudget ? Kind::Deferred
+    return lds_bytes(Kind::Deferred, 1, s->view.n_bins, bs, lane_stack_bytes(s)) <= kLdsBudget ? Kind::Deferred
                                                                                                  : Kind::Path;
 }
 
@@ -488,6 +492,7 @@ struct trhip_batch {
     uint32_t* d_cursor;
     trhip::BatchTables tables;
     uint32_t block, tile, groups, depth;
+    bool short_links;  // every scene's stack links fit 16 bits
     bool deferred;
     size_t lds;
     hipGraph_t graph;
@@ -533,7 +538,7 @@ hipError_t stage_shape(trhip_batch* b, uint32_t block, uint32_t tile, uint32_t g
         start[k + 1] = start[k] + (P + tile - 1) / tile;
         film_words = std::max<uint32_t>(film_words, tile * T + 2 * tile);
     }
-    const size_t lds = trhip::batch_lds_bytes(film_words, block, b->depth, deferred);
+    const size_t lds = trhip::batch_lds_bytes(film_words, block, b->depth * (b->short_links ? 2u : 4u), deferred);
     *fits = lds <= kLdsBudget;
     for (uint32_t i = 0; i < n; ++i) b->args[i].tile_pixels = tile;
     for (uint32_t i = 0; i < n; ++i)
@@ -616,12 +621,14 @@ trhip_status trhip_batch_create(trhip_scene* const* scenes, const trhip_render_d
     b->views.resize(n_scenes);
     b->args.resize(n_scenes);
     b->depth = 1;
+    b->short_links = true;
     std::vector<double> cost(n_scenes);
     for (uint32_t i = 0; i < n_scenes; ++i) {
         b->views[i] = scenes[i]->view;
         fill_launch(scenes[i], &renders[i], 1, &b->args[i]);
         b->args[i].film = films[i];
         b->depth = std::max(b->depth, scenes[i]->view.stack_depth);
+        b->short_links = b->short_links && trhip::short_stack(scenes[i]->view.n_tris);
         cost[i] = (double)scenes[i]->n_pixels * renders[i].spp * (double)(scenes[i]->view.stack_depth + 4);
     }
     b->order.resize(n_scenes);
@@ -683,9 +690,9 @@ trhip_status trhip_batch_create(trhip_scene* const* scenes, const trhip_render_d
                     e = stage_shape(b, bs, tp, g, dfr, s, &fits);
                     if (e != hipSuccess || !fits) continue;
                     const uint32_t groups = std::max<uint32_t>(1u, (uint32_t)n_cu * g);
-                    e = trhip::launch_batch(b->tables, groups, bs, b->depth, dfr, s);  // warm-up
+                    e = trhip::launch_batch(b->tables, groups, bs, b->depth, b->short_links, dfr, s);  // warm-up
                     if (e == hipSuccess) e = hipEventRecord(ev0, s);
-                    if (e == hipSuccess) e = trhip::launch_batch(b->tables, groups, bs, b->depth, dfr, s);
+                    if (e == hipSuccess) e = trhip::launch_batch(b->tables, groups, bs, b->depth, b->short_links, dfr, s);
                     if (e == hipSuccess) e = hipEventRecord(ev1, s);
                     if (e == hipSuccess) e = hipEventSynchronize(ev1);
                     float ms = 0.0f;
@@ -742,7 +749,7 @@ trhip_status trhip_batch_create(trhip_scene* const* scenes, const trhip_render_d
     e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = trhip::launch_batch(b->tables, groups, b->block, b->depth, b->deferred, cs);
+        hipError_t le = trhip::launch_batch(b->tables, groups, b->block, b->depth, b->short_links, b->deferred, cs);
         e = hipStreamEndCapture(cs, &b->graph);
         if (e == hipSuccess) e = le;
     }

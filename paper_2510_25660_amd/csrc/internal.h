@@ -26,10 +26,21 @@ constexpr int kBuilderLbvh = 1;
 // synchronises `stream`.  On failure nothing stays allocated.
 hipError_t build_bvh(const float* d_tri9, uint32_t nt, int builder, hipStream_t stream, BvhBuild* out);
 
-// LDS bytes of one render / backward workgroup
-size_t render_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth);
-size_t wavefront_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth);
-size_t backward_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth,
+// Traversal stacks hold one BVH link per level.  With at most 32,768
+// triangles every link (internal node index, or ~sorted triangle index)
+// fits in 16 bits, which halves the stacks' LDS; larger scenes use 32 bits.
+constexpr uint32_t kShortStackMaxTris = 32768;
+inline bool short_stack(uint32_t n_tris) { return n_tris <= kShortStackMaxTris; }
+// LDS bytes of one lane's stack
+inline uint32_t stack_lane_bytes(uint32_t n_tris, uint32_t stack_depth)
+{
+    return stack_depth * (short_stack(n_tris) ? 2u : 4u);
+}
+
+// LDS bytes of one render / backward workgroup (stack_bytes per lane)
+size_t render_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes);
+size_t wavefront_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes);
+size_t backward_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes,
                           bool primal);
 
 // counts: optional device uint64[7] receiving the work counters (node
@@ -42,11 +53,12 @@ hipError_t launch_render_wavefront(const SceneView& S, const LaunchArgs& L, uint
 // max_cont 2 or 7: single-trace adjoint with a per-path stash of that many
 // continuation vertices; anything else: path replay (two traces per path)
 hipError_t launch_backward(const SceneView& S, const LaunchArgs& L, uint32_t block, int max_cont, hipStream_t stream);
-size_t deferred_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth);
-size_t batch_lds_bytes(uint32_t film_words, uint32_t block, uint32_t stack_depth, bool deferred);
-// resets the cursor and launches the persistent kernel (groups workgroups)
-hipError_t launch_batch(const BatchTables& B, uint32_t groups, uint32_t block, uint32_t stack_depth, bool deferred,
-                        hipStream_t stream);
+size_t deferred_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes);
+size_t batch_lds_bytes(uint32_t film_words, uint32_t block, uint32_t stack_bytes, bool deferred);
+// resets the cursor and launches the persistent kernel (groups workgroups);
+// short_links: every scene of the batch has 16-bit stack links
+hipError_t launch_batch(const BatchTables& B, uint32_t groups, uint32_t block, uint32_t stack_depth,
+                        bool short_links, bool deferred, hipStream_t stream);
 hipError_t launch_render_deferred(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
                                   unsigned long long* counts = nullptr);
 hipError_t launch_zero_f64(double* p, size_t n, hipStream_t stream);

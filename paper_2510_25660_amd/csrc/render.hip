@@ -5,8 +5,8 @@
 // tile's film rows live in LDS, so contributions are LDS atomics and the
 // tile is written to HBM once, with coalesced stores, at the end: no film
 // zero-fill pass and no HBM atomics.  The BVH traversal stack of each lane
-// lives in LDS (stride = block size, so a wave's pushes hit 64 distinct
-// banks).
+// lives in LDS (stride = block size, so a wave's pushes are contiguous),
+// with 16-bit links when the scene is small enough, 32-bit otherwise.
 //
 // Path construction (arXiv 2510.25660, Sec. 3): paths are traced from the
 // sensor (pinhole camera, or the scan point on the relay wall for the
@@ -22,6 +22,7 @@
 #include <algorithm>
 
 #include "device_math.h"
+
 #include "internal.h"
 #include "scene_view.h"
 
@@ -111,6 +112,12 @@ struct Tally<true> {
     }
 };
 
+// A BVH link read back from a traversal stack: 32-bit words hold it as is,
+// 16-bit words (scenes of at most 32,768 triangles, where every internal
+// node index and every ~triangle index fits in an int16) are sign-extended.
+__device__ __forceinline__ int link_of(uint32_t w) { return (int)w; }
+__device__ __forceinline__ int link_of(uint16_t w) { return (int)(int16_t)w; }
+
 // Closest accepted triangle: smallest t, then smallest caller index.  A
 // triangle is accepted at t only if t is not before the entry of its own
 // padded box (the box stored for it in its parent), which makes the result
@@ -132,8 +139,8 @@ __device__ __forceinline__ void leaf_closest(const SceneView& S, const Ray& r, i
     }
 }
 
-template <class TallyT>
-__device__ Hit closest_hit(const SceneView& S, const Ray& r, int exclude, uint32_t* stk, int stride, TallyT& tally)
+template <class W, class TallyT>
+__device__ Hit closest_hit(const SceneView& S, const Ray& r, int exclude, W* stk, int stride, TallyT& tally)
 {
     tally.add(kTallyRays);
     Hit h;
@@ -175,7 +182,7 @@ __device__ Hit closest_hit(const SceneView& S, const Ray& r, int exclude, uint32
         h1 = h1 && tn1 <= h.t;
         if (h0 && h1 && sp < max_sp) {
             const bool first0 = tn0 <= tn1;
-            stk[sp * stride] = (uint32_t)(first0 ? c1 : c0);
+            stk[sp * stride] = (W)(first0 ? c1 : c0);
             ++sp;
             node = first0 ? c0 : c1;
         } else if (h0) {
@@ -185,7 +192,7 @@ __device__ Hit closest_hit(const SceneView& S, const Ray& r, int exclude, uint32
         } else {
             if (sp == 0) break;
             --sp;
-            node = (int)stk[sp * stride];
+            node = link_of(stk[sp * stride]);
         }
     }
     return h;
@@ -203,8 +210,8 @@ __device__ __forceinline__ bool leaf_blocks(const SceneView& S, const Ray& r, in
 }
 
 // any accepted triangle other than `exclude` with t < tmax
-template <class TallyT>
-__device__ bool occluded(const SceneView& S, const Ray& r, int exclude, float tmax, uint32_t* stk, int stride,
+template <class W, class TallyT>
+__device__ bool occluded(const SceneView& S, const Ray& r, int exclude, float tmax, W* stk, int stride,
                          TallyT& tally)
 {
     tally.add(kTallyShadow);
@@ -238,7 +245,7 @@ __device__ bool occluded(const SceneView& S, const Ray& r, int exclude, float tm
             h1 = false;
         }
         if (h0 && h1 && sp < max_sp) {
-            stk[sp * stride] = (uint32_t)c1;
+            stk[sp * stride] = (W)c1;
             ++sp;
             node = c0;
         } else if (h0) {
@@ -248,7 +255,7 @@ __device__ bool occluded(const SceneView& S, const Ray& r, int exclude, float tm
         } else {
             if (sp == 0) return false;
             --sp;
-            node = (int)stk[sp * stride];
+            node = link_of(stk[sp * stride]);
         }
     }
     return false;
@@ -495,9 +502,9 @@ __device__ __forceinline__ void shade_vertex(const SceneView& S, const LaunchArg
 // bin, d log f factors of the connection) and every continuation (triangle,
 // d log f factors of the sampled direction).  Triangles are caller indices;
 // -1 marks a medium vertex.
-template <class Sink, class TallyT>
+template <class Sink, class W, class TallyT>
 __device__ void continue_path(const SceneView& S, const LaunchArgs& L, uint32_t pix, uint32_t sample, PathState& ps,
-                              Hit h, uint32_t* stk, int stride, Sink& sink, TallyT& tally)
+                              Hit h, W* stk, int stride, Sink& sink, TallyT& tally)
 {
     const int vmax = last_vertex(S, L);
     while (true) {
@@ -520,8 +527,8 @@ __device__ void continue_path(const SceneView& S, const LaunchArgs& L, uint32_t 
 }
 
 // Traces one whole path (Philox block 0 generation, then vertex by vertex).
-template <class Sink, class TallyT>
-__device__ void trace_path(const SceneView& S, const LaunchArgs& L, uint32_t pix, uint32_t sample, uint32_t* stk,
+template <class Sink, class W, class TallyT>
+__device__ void trace_path(const SceneView& S, const LaunchArgs& L, uint32_t pix, uint32_t sample, W* stk,
                            int stride, Sink& sink, TallyT& tally)
 {
     tally.add(kTallyDraws);
@@ -553,9 +560,9 @@ struct FilmSink {
 // LDS film rows (zeroed here), paths traced one per lane, then one
 // coalesced write (or accumulate) of the tile to HBM.  lds_film holds
 // tile_pixels * n_bins + 2 * tile_pixels floats; stk is the lane's stack.
-template <class TallyT>
+template <class W, class TallyT>
 __device__ __forceinline__ void render_tile(const SceneView& S, const LaunchArgs& L, uint32_t p0, float* lds_film,
-                                            uint32_t* stk, int stride, TallyT& tally)
+                                            W* stk, int stride, TallyT& tally)
 {
     const uint32_t T = S.n_bins;
     const uint32_t TP = L.tile_pixels;
@@ -613,37 +620,39 @@ __device__ __forceinline__ void render_tile(const SceneView& S, const LaunchArgs
 // Same tile, deferred form.  Phase 1 takes the tile's samples in batches
 // of kSortPerLane * block: every lane generates the first rays of its
 // samples, the batch is counting-sorted in LDS by an octahedral direction
-// key (64 cells, Morton order), and the lanes then trace the first rays in
-// sorted order, appending every first vertex (work index, t, triangle) to
-// an LDS buffer.  Rays of similar direction share waves, so the rays that
-// reach the scene (and traverse deep) are packed together and waves of
-// escaping rays finish early.  Once the buffer holds at least a block's
-// worth, phase 2 drains it: each lane regenerates its entry's ray (Philox
-// block 0), then shades, tests the shadow ray and follows the rest of the
-// path, on densely packed lanes.
-constexpr uint32_t kSortPerLane = 2;
+// cell (64 cells, Morton order), and the lanes then trace the first rays in
+// sorted order, a block at a time, appending every first vertex (work
+// index, t, triangle) to an LDS buffer.  Rays of similar direction share
+// waves, so the rays that reach the scene (and traverse deep) are packed
+// together and waves of escaping rays finish early.  Whenever the buffer
+// holds a block's worth, phase 2 drains it: each lane regenerates its
+// entry's path state (Philox block 0), then shades, tests the shadow ray
+// and follows the rest of the path, on densely packed lanes.  Redrawing a
+// first ray costs less than keeping it: four LDS words per sample would
+// cost the kernel a workgroup per CU.
+constexpr uint32_t kSortPerLane = 8;
 constexpr uint32_t kDirCells = 64;
 
 struct DeferredLds {
-    uint32_t* work;    // first-hit buffer, capacity block * (kSortPerLane + 1)
+    uint32_t* work;    // first-hit buffer, capacity 2 * block
     float* t;
     int* prim;
     int* sorted;
-    uint32_t* count;   // [0] buffer fill, [1] batch size
-    uint32_t* order;   // [block * kSortPerLane] work indices in key order
-    uint32_t* start;   // [kDirCells] first slot of each key
+    uint32_t* count;   // [0] buffer fill, [1] sorted batch size
+    uint32_t* order;   // [block * kSortPerLane] work indices in cell order
+    uint32_t* start;   // [kDirCells] first slot of each cell
     uint32_t* fill;    // [kDirCells]
 };
 
 // 32-bit words of LDS the deferred form adds per block of nb lanes
 __host__ __device__ constexpr size_t deferred_words(uint32_t nb)
 {
-    return 4ull * nb * (kSortPerLane + 1) + 2 + (size_t)nb * kSortPerLane + 2ull * kDirCells;
+    return 8ull * nb + 2 + (size_t)nb * kSortPerLane + 2ull * kDirCells;
 }
 
 __device__ __forceinline__ DeferredLds carve_deferred(float* base, uint32_t nb)
 {
-    const uint32_t cap = nb * (kSortPerLane + 1);
+    const uint32_t cap = 2 * nb;
     DeferredLds f;
     uint32_t* u = reinterpret_cast<uint32_t*>(base);
     f.work = u;
@@ -674,9 +683,9 @@ __device__ __forceinline__ uint32_t direction_cell(vec3 d)
     return spread3(qx) | (spread3(qy) << 1);
 }
 
-template <class TallyT>
+template <class W, class TallyT>
 __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const LaunchArgs& L, uint32_t p0,
-                                                     float* lds_film, const DeferredLds& fh, uint32_t* stk,
+                                                     float* lds_film, const DeferredLds& fh, W* stk,
                                                      int stride, TallyT& tally)
 {
     const uint32_t T = S.n_bins;
@@ -697,7 +706,7 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
     uint32_t cur = 0xffffffffu;
     FilmSink sink{nullptr, 0.0f, 0.0f};
     for (uint32_t base = 0; base < work; base += batch) {
-        // phase 1a: direction cells of the batch, counting sort
+        // phase 1a: first rays of the batch, counting sort by direction cell
         if (tid < kDirCells) {
             fh.start[tid] = 0u;
             fh.fill[tid] = 0u;
@@ -710,6 +719,7 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
             cell[k] = 0xffffffffu;
             if (w < work && has_vertex) {
                 const uint32_t pl = w / L.spp;
+                tally.add(kTallyDraws);
                 PathState ps;
                 begin_path(S, L, p0 + pl, L.sample_offset + (w - pl * L.spp), ps);
                 cell[k] = direction_cell(ps.d);
@@ -733,54 +743,57 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
             if (cell[k] != 0xffffffffu)
                 fh.order[fh.start[cell[k]] + atomicAdd(fh.fill + cell[k], 1u)] = base + k * nb + tid;
         __syncthreads();
-        // phase 1b: first rays in direction order
+        // phase 1b: first rays in cell order, a block at a time
         const uint32_t nvalid = fh.count[1];
-        for (uint32_t j = tid; j < nvalid; j += nb) {
-            const uint32_t w = fh.order[j];
-            const uint32_t pl = w / L.spp;
-            tally.add(kTallyDraws);
-            PathState ps;
-            begin_path(S, L, p0 + pl, L.sample_offset + (w - pl * L.spp), ps);
-            const Hit h = closest_hit(S, make_ray(ps.o, ps.d), ps.prev, stk, stride, tally);
-            float t_hit;
-            bool med;
-            if (resolve_event(S, ps, h, t_hit, med)) {
-                const uint32_t q = atomicAdd(fh.count, 1u);
-                fh.work[q] = w;
-                fh.t[q] = h.t;
-                fh.prim[q] = h.prim;
-                fh.sorted[q] = h.sorted;
-            }
-        }
-        __syncthreads();
-        // phase 2: the rest of the buffered paths on packed lanes
-        const uint32_t n = fh.count[0];
-        if (n >= nb || base + batch >= work) {
-            for (uint32_t j = tid; j < n; j += nb) {
-                const uint32_t wj = fh.work[j];
-                const uint32_t pl = wj / L.spp;
-                const uint32_t sample = L.sample_offset + (wj - pl * L.spp);
-                if (pl != cur) {
-                    if (cur != 0xffffffffu) {
-                        atomicAdd(tsteady + cur, sink.steady);
-                        atomicAdd(toow + cur, sink.oow);
-                    }
-                    cur = pl;
-                    sink.row = tfilm + (size_t)pl * T;
-                    sink.steady = 0.0f;
-                    sink.oow = 0.0f;
-                }
+        const bool last_batch = base + batch >= work;
+        for (uint32_t c0 = 0; c0 < nvalid || (c0 == 0 && last_batch); c0 += nb) {
+            const uint32_t j = c0 + tid;
+            if (j < nvalid) {
+                const uint32_t w = fh.order[j];
+                const uint32_t pl = w / L.spp;
                 PathState ps;
-                begin_path(S, L, p0 + pl, sample, ps);
-                Hit h;
-                h.t = fh.t[j];
-                h.prim = fh.prim[j];
-                h.sorted = fh.sorted[j];
-                continue_path(S, L, p0 + pl, sample, ps, h, stk, stride, sink, tally);
+                begin_path(S, L, p0 + pl, L.sample_offset + (w - pl * L.spp), ps);
+                const Hit h = closest_hit(S, make_ray(ps.o, ps.d), ps.prev, stk, stride, tally);
+                float t_hit;
+                bool med;
+                if (resolve_event(S, ps, h, t_hit, med)) {
+                    const uint32_t q = atomicAdd(fh.count, 1u);
+                    fh.work[q] = w;
+                    fh.t[q] = h.t;
+                    fh.prim[q] = h.prim;
+                    fh.sorted[q] = h.sorted;
+                }
             }
             __syncthreads();
-            if (tid == 0) fh.count[0] = 0u;
-            __syncthreads();
+            // phase 2: the rest of the buffered paths on packed lanes
+            const uint32_t n = fh.count[0];
+            if (n >= nb || (last_batch && c0 + nb >= nvalid)) {
+                for (uint32_t jj = tid; jj < n; jj += nb) {
+                    const uint32_t wj = fh.work[jj];
+                    const uint32_t pl = wj / L.spp;
+                    const uint32_t sample = L.sample_offset + (wj - pl * L.spp);
+                    if (pl != cur) {
+                        if (cur != 0xffffffffu) {
+                            atomicAdd(tsteady + cur, sink.steady);
+                            atomicAdd(toow + cur, sink.oow);
+                        }
+                        cur = pl;
+                        sink.row = tfilm + (size_t)pl * T;
+                        sink.steady = 0.0f;
+                        sink.oow = 0.0f;
+                    }
+                    PathState ps;
+                    begin_path(S, L, p0 + pl, sample, ps);
+                    Hit h;
+                    h.t = fh.t[jj];
+                    h.prim = fh.prim[jj];
+                    h.sorted = fh.sorted[jj];
+                    continue_path(S, L, p0 + pl, sample, ps, h, stk, stride, sink, tally);
+                }
+                __syncthreads();
+                if (tid == 0) fh.count[0] = 0u;
+                __syncthreads();
+            }
         }
     }
     if (cur != 0xffffffffu) {
@@ -809,26 +822,29 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
     }
 }
 
-template <bool kCount>
-__global__ void __launch_bounds__(256) k_render_deferred(SceneView S, LaunchArgs L, unsigned long long* counts)
+// Five waves per SIMD (at most 96 VGPRs, a few spilled outside the
+// traversal loops) beat four without spills by 15% on confocal scans.
+template <bool kCount, class W>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+k_render_deferred(SceneView S, LaunchArgs L, unsigned long long* counts)
 {
     Tally<kCount> tally;
     extern __shared__ float lds[];
     const uint32_t TP = L.tile_pixels;
     float* after_film = lds + (size_t)TP * S.n_bins + 2 * TP;
     const DeferredLds fh = carve_deferred(after_film, blockDim.x);
-    uint32_t* stk = reinterpret_cast<uint32_t*>(after_film + deferred_words(blockDim.x)) + threadIdx.x;
+    W* stk = reinterpret_cast<W*>(after_film + deferred_words(blockDim.x)) + threadIdx.x;
     render_tile_deferred(S, L, blockIdx.x * TP, lds, fh, stk, (int)blockDim.x, tally);
     tally.flush(counts);
 }
 
-template <bool kCount>
+template <bool kCount, class W>
 __global__ void __launch_bounds__(256) k_render(SceneView S, LaunchArgs L, unsigned long long* counts)
 {
     Tally<kCount> tally;
     extern __shared__ float lds[];
     const uint32_t TP = L.tile_pixels;
-    uint32_t* stk = reinterpret_cast<uint32_t*>(lds + (size_t)TP * S.n_bins + 2 * TP) + threadIdx.x;
+    W* stk = reinterpret_cast<W*>(lds + (size_t)TP * S.n_bins + 2 * TP) + threadIdx.x;
     render_tile(S, L, blockIdx.x * TP, lds, stk, (int)blockDim.x, tally);
     tally.flush(counts);
 }
@@ -839,15 +855,16 @@ __global__ void __launch_bounds__(256) k_render(SceneView S, LaunchArgs L, unsig
 // Work items are (scene, pixel tile) pairs numbered scene by scene in the
 // processing order; a workgroup pops items from a global cursor until they
 // run out, so scenes of very different cost balance themselves.
-template <bool kDeferred>
+template <bool kDeferred, class W>
 __global__ void __launch_bounds__(256) k_batch(BatchTables B)
 {
     extern __shared__ float lds[];
     __shared__ uint32_t s_item;
     Tally<false> tally;
     const DeferredLds fh = carve_deferred(lds + B.film_words, blockDim.x);
-    uint32_t* stk =
-        reinterpret_cast<uint32_t*>(lds + B.film_words + (kDeferred ? deferred_words(blockDim.x) : 0)) + threadIdx.x;
+    W* stk = reinterpret_cast<W*>(
+                        lds + B.film_words + (kDeferred ? deferred_words(blockDim.x) : 0)) +
+                    threadIdx.x;
     while (true) {
         if (threadIdx.x == 0) s_item = atomicAdd(B.cursor, 1u);
         __syncthreads();
@@ -864,8 +881,8 @@ __global__ void __launch_bounds__(256) k_batch(BatchTables B)
         const SceneView* __restrict__ views = B.views;
         const LaunchArgs* __restrict__ args = B.args;
         if (kDeferred)
-            render_tile_deferred(views[scene], args[scene], tile * args[scene].tile_pixels, lds, fh, stk,
-                                 (int)blockDim.x, tally);
+            render_tile_deferred(views[scene], args[scene], tile * args[scene].tile_pixels,
+                                                         lds, fh, stk, (int)blockDim.x, tally);
         else
             render_tile(views[scene], args[scene], tile * args[scene].tile_pixels, lds, stk, (int)blockDim.x, tally);
         __syncthreads();
@@ -943,7 +960,7 @@ __device__ __forceinline__ PathState load_state(const WfSlots& w, int i)
     return ps;
 }
 
-template <bool kCount>
+template <bool kCount, class W>
 __global__ void __launch_bounds__(256) k_render_wf(SceneView S, LaunchArgs L, unsigned long long* counts)
 {
     extern __shared__ float lds[];
@@ -957,7 +974,7 @@ __global__ void __launch_bounds__(256) k_render_wf(SceneView S, LaunchArgs L, un
     float* tsteady = lds + (size_t)TP * T;
     float* toow = tsteady + TP;
     const WfSlots w = carve_slots(toow + TP, nb);
-    uint32_t* stk = reinterpret_cast<uint32_t*>(toow + TP + (size_t)kWfWords * nb) + tid;
+    W* stk = reinterpret_cast<W*>(toow + TP + (size_t)kWfWords * nb) + tid;
     const uint32_t p0 = blockIdx.x * TP;
     const uint32_t npix = min(TP, L.n_pixels - p0);
     for (uint32_t i = tid; i < TP * T + 2 * TP; i += nb) lds[i] = 0.0f;
@@ -1125,6 +1142,7 @@ struct AdjointScatterSink {
     }
 };
 
+template <class W>
 __global__ void __launch_bounds__(256) k_backward(SceneView S, LaunchArgs L)
 {
     Tally<false> tally;
@@ -1134,7 +1152,7 @@ __global__ void __launch_bounds__(256) k_backward(SceneView S, LaunchArgs L)
     const bool want_primal = L.primal != nullptr;
     float* tdelta = lds;
     float* tprimal = lds + (size_t)TP * T;
-    uint32_t* stk = reinterpret_cast<uint32_t*>(tprimal + (want_primal ? (size_t)TP * T : 0)) + threadIdx.x;
+    W* stk = reinterpret_cast<W*>(tprimal + (want_primal ? (size_t)TP * T : 0)) + threadIdx.x;
     const int stride = (int)blockDim.x;
     const uint32_t p0 = blockIdx.x * TP;
     const uint32_t npix = min(TP, L.n_pixels - p0);
@@ -1232,8 +1250,10 @@ struct AdjointStashSink {
     }
 };
 
-template <int kMaxCont>
-__global__ void __launch_bounds__(256) k_backward_stash(SceneView S, LaunchArgs L)
+// Four waves per SIMD (at most 128 VGPRs) instead of three.
+template <int kMaxCont, class W>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_backward_stash(SceneView S, LaunchArgs L)
 {
     Tally<false> tally;
     extern __shared__ float lds[];
@@ -1242,7 +1262,7 @@ __global__ void __launch_bounds__(256) k_backward_stash(SceneView S, LaunchArgs 
     const bool want_primal = L.primal != nullptr;
     float* tdelta = lds;
     float* tprimal = lds + (size_t)TP * T;
-    uint32_t* stk = reinterpret_cast<uint32_t*>(tprimal + (want_primal ? (size_t)TP * T : 0)) + threadIdx.x;
+    W* stk = reinterpret_cast<W*>(tprimal + (want_primal ? (size_t)TP * T : 0)) + threadIdx.x;
     const int stride = (int)blockDim.x;
     const uint32_t p0 = blockIdx.x * TP;
     const uint32_t npix = min(TP, L.n_pixels - p0);
@@ -1285,94 +1305,150 @@ __global__ void k_f64_to_f32(const double* __restrict__ s, float* __restrict__ d
 
 }  // namespace
 
-size_t render_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth)
+size_t render_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes)
 {
-    return ((size_t)tile_pixels * n_bins + 2ull * tile_pixels) * sizeof(float) +
-           (size_t)block * stack_depth * sizeof(uint32_t);
+    return ((size_t)tile_pixels * n_bins + 2ull * tile_pixels) * sizeof(float) + (size_t)block * stack_bytes;
 }
 
-size_t wavefront_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth)
+size_t wavefront_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes)
 {
     return ((size_t)tile_pixels * n_bins + 2ull * tile_pixels) * sizeof(float) +
-           (size_t)kWfWords * block * sizeof(float) + (size_t)block * stack_depth * sizeof(uint32_t);
+           (size_t)kWfWords * block * sizeof(float) + (size_t)block * stack_bytes;
 }
 
-size_t backward_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth, bool primal)
+size_t backward_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes, bool primal)
 {
-    return (size_t)tile_pixels * n_bins * sizeof(float) * (primal ? 2 : 1) +
-           (size_t)block * stack_depth * sizeof(uint32_t);
+    return (size_t)tile_pixels * n_bins * sizeof(float) * (primal ? 2 : 1) + (size_t)block * stack_bytes;
+}
+
+size_t deferred_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes)
+{
+    return ((size_t)tile_pixels * n_bins + 2ull * tile_pixels + deferred_words(block)) *
+               sizeof(float) +
+           (size_t)block * stack_bytes;
+}
+
+size_t batch_lds_bytes(uint32_t film_words, uint32_t block, uint32_t stack_bytes, bool deferred)
+{
+    return ((size_t)film_words + (deferred ? deferred_words(block) : 0)) * sizeof(float) +
+           (size_t)block * stack_bytes;
+}
+
+namespace {
+
+uint32_t tiles_of(const LaunchArgs& L) { return (L.n_pixels + L.tile_pixels - 1) / L.tile_pixels; }
+
+template <class W>
+void launch_render_w(const SceneView& S, const LaunchArgs& L, uint32_t block, size_t lds, hipStream_t stream,
+                     unsigned long long* counts)
+{
+    if (counts)
+        hipLaunchKernelGGL((k_render<true, W>), dim3(tiles_of(L)), dim3(block), lds, stream, S, L, counts);
+    else
+        hipLaunchKernelGGL((k_render<false, W>), dim3(tiles_of(L)), dim3(block), lds, stream, S, L, counts);
+}
+
+template <class W>
+void launch_wavefront_w(const SceneView& S, const LaunchArgs& L, uint32_t block, size_t lds, hipStream_t stream,
+                        unsigned long long* counts)
+{
+    if (counts)
+        hipLaunchKernelGGL((k_render_wf<true, W>), dim3(tiles_of(L)), dim3(block), lds, stream, S, L, counts);
+    else
+        hipLaunchKernelGGL((k_render_wf<false, W>), dim3(tiles_of(L)), dim3(block), lds, stream, S, L, counts);
+}
+
+template <class W>
+void launch_deferred_w(const SceneView& S, const LaunchArgs& L, uint32_t block, size_t lds, hipStream_t stream,
+                       unsigned long long* counts)
+{
+    if (counts)
+        hipLaunchKernelGGL((k_render_deferred<true, W>), dim3(tiles_of(L)), dim3(block), lds,
+                           stream, S, L, counts);
+    else
+        hipLaunchKernelGGL((k_render_deferred<false, W>), dim3(tiles_of(L)), dim3(block), lds,
+                           stream, S, L, counts);
+}
+
+template <class W>
+void launch_backward_w(const SceneView& S, const LaunchArgs& L, uint32_t block, int max_cont, size_t lds,
+                       hipStream_t stream)
+{
+    if (max_cont == 2)
+        hipLaunchKernelGGL((k_backward_stash<2, W>), dim3(tiles_of(L)), dim3(block), lds, stream, S, L);
+    else if (max_cont == 7)
+        hipLaunchKernelGGL((k_backward_stash<7, W>), dim3(tiles_of(L)), dim3(block), lds, stream, S, L);
+    else
+        hipLaunchKernelGGL((k_backward<W>), dim3(tiles_of(L)), dim3(block), lds, stream, S, L);
+}
+
+template <class W>
+void launch_batch_w(const BatchTables& B, uint32_t groups, uint32_t block, size_t lds, bool deferred,
+                    hipStream_t stream)
+{
+    if (deferred)
+        hipLaunchKernelGGL((k_batch<true, W>), dim3(groups), dim3(block), lds, stream, B);
+    else
+        hipLaunchKernelGGL((k_batch<false, W>), dim3(groups), dim3(block), lds, stream, B);
+}
+
+}  // namespace
+
+hipError_t launch_render(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
+                         unsigned long long* counts)
+{
+    const size_t lds = render_lds_bytes(L.tile_pixels, S.n_bins, block, stack_lane_bytes(S.n_tris, S.stack_depth));
+    if (short_stack(S.n_tris))
+        launch_render_w<uint16_t>(S, L, block, lds, stream, counts);
+    else
+        launch_render_w<uint32_t>(S, L, block, lds, stream, counts);
+    return hipGetLastError();
 }
 
 hipError_t launch_render_wavefront(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
                                    unsigned long long* counts)
 {
-    const uint32_t tiles = (L.n_pixels + L.tile_pixels - 1) / L.tile_pixels;
-    const size_t lds = wavefront_lds_bytes(L.tile_pixels, S.n_bins, block, S.stack_depth);
-    if (counts)
-        hipLaunchKernelGGL(k_render_wf<true>, dim3(tiles), dim3(block), lds, stream, S, L, counts);
+    const size_t lds =
+        wavefront_lds_bytes(L.tile_pixels, S.n_bins, block, stack_lane_bytes(S.n_tris, S.stack_depth));
+    if (short_stack(S.n_tris))
+        launch_wavefront_w<uint16_t>(S, L, block, lds, stream, counts);
     else
-        hipLaunchKernelGGL(k_render_wf<false>, dim3(tiles), dim3(block), lds, stream, S, L, counts);
-    return hipGetLastError();
-}
-
-hipError_t launch_render(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
-                         unsigned long long* counts)
-{
-    const uint32_t tiles = (L.n_pixels + L.tile_pixels - 1) / L.tile_pixels;
-    const size_t lds = render_lds_bytes(L.tile_pixels, S.n_bins, block, S.stack_depth);
-    if (counts)
-        hipLaunchKernelGGL(k_render<true>, dim3(tiles), dim3(block), lds, stream, S, L, counts);
-    else
-        hipLaunchKernelGGL(k_render<false>, dim3(tiles), dim3(block), lds, stream, S, L, counts);
-    return hipGetLastError();
-}
-
-hipError_t launch_backward(const SceneView& S, const LaunchArgs& L, uint32_t block, int max_cont, hipStream_t stream)
-{
-    const uint32_t tiles = (L.n_pixels + L.tile_pixels - 1) / L.tile_pixels;
-    const size_t lds = backward_lds_bytes(L.tile_pixels, S.n_bins, block, S.stack_depth, L.primal != nullptr);
-    if (max_cont == 2)
-        hipLaunchKernelGGL(k_backward_stash<2>, dim3(tiles), dim3(block), lds, stream, S, L);
-    else if (max_cont == 7)
-        hipLaunchKernelGGL(k_backward_stash<7>, dim3(tiles), dim3(block), lds, stream, S, L);
-    else
-        hipLaunchKernelGGL(k_backward, dim3(tiles), dim3(block), lds, stream, S, L);
-    return hipGetLastError();
-}
-
-size_t deferred_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_depth)
-{
-    return ((size_t)tile_pixels * n_bins + 2ull * tile_pixels + deferred_words(block)) * sizeof(float) +
-           (size_t)block * stack_depth * sizeof(uint32_t);
-}
-
-size_t batch_lds_bytes(uint32_t film_words, uint32_t block, uint32_t stack_depth, bool deferred)
-{
-    return ((size_t)film_words + (deferred ? deferred_words(block) : 0)) * sizeof(float) +
-           (size_t)block * stack_depth * sizeof(uint32_t);
-}
-
-hipError_t launch_batch(const BatchTables& B, uint32_t groups, uint32_t block, uint32_t stack_depth, bool deferred,
-                        hipStream_t stream)
-{
-    hipLaunchKernelGGL(k_reset_cursor, dim3(1), dim3(64), 0, stream, B.cursor);
-    const size_t lds = batch_lds_bytes(B.film_words, block, stack_depth, deferred);
-    if (deferred)
-        hipLaunchKernelGGL(k_batch<true>, dim3(groups), dim3(block), lds, stream, B);
-    else
-        hipLaunchKernelGGL(k_batch<false>, dim3(groups), dim3(block), lds, stream, B);
+        launch_wavefront_w<uint32_t>(S, L, block, lds, stream, counts);
     return hipGetLastError();
 }
 
 hipError_t launch_render_deferred(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
                                   unsigned long long* counts)
 {
-    const uint32_t tiles = (L.n_pixels + L.tile_pixels - 1) / L.tile_pixels;
-    const size_t lds = deferred_lds_bytes(L.tile_pixels, S.n_bins, block, S.stack_depth);
-    if (counts)
-        hipLaunchKernelGGL(k_render_deferred<true>, dim3(tiles), dim3(block), lds, stream, S, L, counts);
+    const size_t lds =
+        deferred_lds_bytes(L.tile_pixels, S.n_bins, block, stack_lane_bytes(S.n_tris, S.stack_depth));
+    if (short_stack(S.n_tris))
+        launch_deferred_w<uint16_t>(S, L, block, lds, stream, counts);
     else
-        hipLaunchKernelGGL(k_render_deferred<false>, dim3(tiles), dim3(block), lds, stream, S, L, counts);
+        launch_deferred_w<uint32_t>(S, L, block, lds, stream, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_backward(const SceneView& S, const LaunchArgs& L, uint32_t block, int max_cont, hipStream_t stream)
+{
+    const size_t lds = backward_lds_bytes(L.tile_pixels, S.n_bins, block, stack_lane_bytes(S.n_tris, S.stack_depth),
+                                          L.primal != nullptr);
+    if (short_stack(S.n_tris))
+        launch_backward_w<uint16_t>(S, L, block, max_cont, lds, stream);
+    else
+        launch_backward_w<uint32_t>(S, L, block, max_cont, lds, stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchTables& B, uint32_t groups, uint32_t block, uint32_t stack_depth,
+                        bool short_links, bool deferred, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_reset_cursor, dim3(1), dim3(64), 0, stream, B.cursor);
+    const size_t lds = batch_lds_bytes(B.film_words, block, stack_depth * (short_links ? 2u : 4u), deferred);
+    if (short_links)
+        launch_batch_w<uint16_t>(B, groups, block, lds, deferred, stream);
+    else
+        launch_batch_w<uint32_t>(B, groups, block, lds, deferred, stream);
     return hipGetLastError();
 }
 

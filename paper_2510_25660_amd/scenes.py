@@ -248,6 +248,30 @@ def box_scene(seed: int = BASE_SEED + 1, width=64, height=64, n_bins=256, bin_wi
                    light_intensity=1.0, spp=spp, max_depth=max_depth, seed=seed, name="box", **cam)
 
 
+def cluttered_box(n_tris: int, seed: int = BASE_SEED + 11, width=24, height=16, n_bins=128, bin_width=0.02,
+                  spp=8, max_depth=4) -> Scene:
+    """The box room filled up to exactly n_tris triangles with small random
+    triangles (edge ~0.01) uniform in the room; every other one GGX with
+    roughness U[0.1, 0.7].  Sizes either side of a power of two probe the
+    traversal's index widths."""
+    rng = np.random.default_rng(seed)
+    v, f = merge(_box_room_parts())
+    k = n_tris - len(f)
+    assert k >= 0
+    c = rng.uniform(0.02, 0.98, size=(k, 1, 3))
+    cv = (c + rng.normal(scale=0.005, size=(k, 3, 3))).reshape(-1, 3)
+    verts = np.concatenate([v, cv])
+    faces = np.concatenate([f, len(v) + np.arange(3 * k).reshape(-1, 3)])
+    mat = np.zeros(n_tris)
+    mat[len(f) + 1::2] = MAT_GGX
+    albedo = rng.uniform(0.3, 0.9, n_tris)
+    rough = rng.uniform(0.1, 0.7, n_tris)
+    cam = look_at([0.5, 0.5, 1.5], [0.5, 0.5, 0.0], [0, 1, 0], 40.0, width, height)
+    return _finish(verts, faces, mat, albedo, rough, n_bins=n_bins, bin_width=bin_width, bin_start=0.0,
+                   width=width, height=height, light_pos=(0.5, 0.9, 0.5), light_intensity=1.0, spp=spp,
+                   max_depth=max_depth, seed=seed, name=f"cluttered_box_{n_tris}", **cam)
+
+
 def subdivide(verts, faces, k: int):
     """Split every triangle into k^2 congruent sub-triangles (same geometry)."""
     ii, jj = [], []

@@ -196,3 +196,27 @@ def test_adjoint_full_size_finite_differences(tr):
             worst = max(worst, abs(fd("r", int(k)) - gr_n[k]) / np.abs(gr_n).max())
     print(f"full-size worst FD deviation / max|g| = {worst:.2e}")
     assert worst <= 5e-3
+
+
+@pytest.mark.parametrize("kernel", ["path", "auto"])
+@pytest.mark.parametrize("n_tris", [32768, 32769])
+def test_adjoint_stack_link_widths(tr, oracle_mod, n_tris, kernel):
+    """Adjoint (replay and stash) on scenes either side of the 16-bit stack
+    link limit, against the oracle's adjoint."""
+    import torch
+    sc = scenes.cluttered_box(n_tris)
+    ta, trough = scenes.perturbed_params(sc, seed=6)
+    _announce(f"adjoint cluttered box nt={n_tris} {kernel}")
+    O = oracle_mod.Oracle(sc)
+    target, _, _ = O.render(stream_id=1, albedo=ta, roughness=trough)
+    film_o, _, _ = O.render()
+    delta = (2.0 * (film_o - target)).astype(np.float32)
+    ga_o, gr_o = O.backward(delta)
+    with tr.upload(sc) as dev:
+        d = torch.from_numpy(delta.reshape(sc.height, sc.width, sc.n_bins)).cuda()
+        ga, gr = tr.render_transient_backward(dev, d, kernel=kernel)
+        torch.cuda.synchronize()
+        ga, gr = ga.cpu().numpy().astype(np.float64), gr.cpu().numpy().astype(np.float64)
+    assert np.abs(ga_o).max() > 0 and np.abs(gr_o).max() > 0
+    assert np.abs(ga - ga_o).max() <= 1e-4 * np.abs(ga_o).max()
+    assert np.abs(gr - gr_o).max() <= 1e-4 * np.abs(gr_o).max()

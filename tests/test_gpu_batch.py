@@ -112,3 +112,27 @@ def test_batch_rejects_bad_input(tr):
         assert L.trhip_batch_destroy(C.c_void_p(1234)) == 5
     finally:
         dev.destroy()
+
+
+@pytest.mark.parametrize("big", [32768, 32769])
+def test_batch_mixed_link_widths(tr, big):
+    """A batch holding a scene at or above the 16-bit stack link limit next to
+    small scenes (the whole batch then takes the wider links) against the
+    single-scene renders."""
+    import torch
+    scs = _small_batch(n=3, spp=32) + [scenes.cluttered_box(big)]
+    _announce(f"batch with cluttered box nt={big}")
+    devs = [tr.upload(s) for s in scs]
+    try:
+        with tr.Batch(devs, autotune=False) as b:
+            films = [f.clone() for f in b.render()]
+            torch.cuda.synchronize()
+        for d, f in zip(devs, films):
+            _, ref = tr.render_transient(d)
+            torch.cuda.synchronize()
+            a, r = f.cpu().numpy(), ref.cpu().numpy()
+            assert ((a != 0) == (r != 0)).all()
+            np.testing.assert_allclose(a, r, rtol=1e-5, atol=0)
+    finally:
+        for d in devs:
+            d.destroy()

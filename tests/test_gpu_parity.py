@@ -222,3 +222,14 @@ def test_bvh_builders_agree(tr, make):
     a, c = out["lbvh"], out["ploc"]
     assert ((a != 0) == (c != 0)).all()
     np.testing.assert_allclose(a, c, rtol=1e-5, atol=0)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("n_tris", [32768, 32769])
+def test_stack_link_widths(tr, oracle_mod, n_tris, kernel):
+    """Either side of the largest scene whose traversal stacks hold 16-bit
+    links (32,768 triangles): both stack widths against the oracle."""
+    sc = scenes.cluttered_box(n_tris)
+    _announce(f"cluttered box nt={n_tris} {kernel}")
+    err, info = _check(tr, oracle_mod, sc, kernel=kernel)
+    assert info["n_triangles"] == n_tris
