@@ -139,63 +139,88 @@ __device__ __forceinline__ void leaf_closest(const SceneView& S, const Ray& r, i
     }
 }
 
+// Closest-hit traversal as a resumable state machine: the state between
+// two internal-node visits.
+struct ClosestTrav {
+    Hit h;
+    int node;         // next internal node
+    int sp;           // stack entries in use
+    uint32_t visits;  // a tree visits each internal node at most once per ray
+};
+
+template <class TallyT>
+__device__ __forceinline__ void closest_begin(const SceneView& S, const Ray& r, int exclude, ClosestTrav& c,
+                                              TallyT& tally)
+{
+    tally.add(kTallyRays);
+    c.h.t = __builtin_huge_valf();
+    c.h.prim = -1;
+    c.h.sorted = -1;
+    c.node = S.root;
+    c.sp = 0;
+    c.visits = 0;
+    if (S.root < 0) {  // a single triangle: no internal node to visit
+        float tn, tf;
+        slab(r, S.root_lo[0], S.root_lo[1], S.root_lo[2], S.root_hi[0], S.root_hi[1], S.root_hi[2], tn, tf);
+        if (tn <= tf && tf >= 0.0f) leaf_closest(S, r, ~S.root, tn, exclude, c.h, tally);
+        c.visits = S.n_tris;
+    }
+}
+
+// Visits one internal node; returns true once the traversal has finished.
+template <class W, class TallyT>
+__device__ __forceinline__ bool closest_step(const SceneView& S, const Ray& r, int exclude, W* stk, int stride,
+                                             ClosestTrav& c, TallyT& tally)
+{
+    if (c.visits >= S.n_tris) return true;
+    ++c.visits;
+    tally.add(kTallyNodes);
+    const float4* nodes = reinterpret_cast<const float4*>(S.nodes);
+    const float4 a = nodes[4 * c.node + 0];
+    const float4 b = nodes[4 * c.node + 1];
+    const float4 d = nodes[4 * c.node + 2];
+    const float4 l = nodes[4 * c.node + 3];
+    const int c0 = __float_as_int(l.x), c1 = __float_as_int(l.y);
+    float tn0, tf0, tn1, tf1;
+    slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tn0, tf0);
+    slab(r, b.z, b.w, d.x, d.y, d.z, d.w, tn1, tf1);
+    bool h0 = tn0 <= tf0 && tf0 >= 0.0f && tn0 <= c.h.t;
+    bool h1 = tn1 <= tf1 && tf1 >= 0.0f && tn1 <= c.h.t;
+    if (h0 && c0 < 0) {
+        leaf_closest(S, r, ~c0, tn0, exclude, c.h, tally);
+        h0 = false;
+    }
+    if (h1 && c1 < 0) {
+        leaf_closest(S, r, ~c1, tn1, exclude, c.h, tally);
+        h1 = false;
+    }
+    h0 = h0 && tn0 <= c.h.t;
+    h1 = h1 && tn1 <= c.h.t;
+    if (h0 && h1 && c.sp < (int)S.stack_depth) {
+        const bool first0 = tn0 <= tn1;
+        stk[c.sp * stride] = (W)(first0 ? c1 : c0);
+        ++c.sp;
+        c.node = first0 ? c0 : c1;
+    } else if (h0) {
+        c.node = c0;
+    } else if (h1) {
+        c.node = c1;
+    } else {
+        if (c.sp == 0) return true;
+        --c.sp;
+        c.node = link_of(stk[c.sp * stride]);
+    }
+    return false;
+}
+
 template <class W, class TallyT>
 __device__ Hit closest_hit(const SceneView& S, const Ray& r, int exclude, W* stk, int stride, TallyT& tally)
 {
-    tally.add(kTallyRays);
-    Hit h;
-    h.t = __builtin_huge_valf();
-    h.prim = -1;
-    h.sorted = -1;
-    if (S.root < 0) {
-        float tn, tf;
-        slab(r, S.root_lo[0], S.root_lo[1], S.root_lo[2], S.root_hi[0], S.root_hi[1], S.root_hi[2], tn, tf);
-        if (tn <= tf && tf >= 0.0f) leaf_closest(S, r, ~S.root, tn, exclude, h, tally);
-        return h;
+    ClosestTrav c;
+    closest_begin(S, r, exclude, c, tally);
+    while (!closest_step(S, r, exclude, stk, stride, c, tally)) {
     }
-    int node = S.root;
-    int sp = 0;
-    const float4* nodes = reinterpret_cast<const float4*>(S.nodes);
-    const int max_sp = (int)S.stack_depth;
-    // a tree visits each internal node at most once per ray
-    for (uint32_t visits = 0; visits < S.n_tris; ++visits) {
-        tally.add(kTallyNodes);
-        const float4 a = nodes[4 * node + 0];
-        const float4 b = nodes[4 * node + 1];
-        const float4 c = nodes[4 * node + 2];
-        const float4 l = nodes[4 * node + 3];
-        const int c0 = __float_as_int(l.x), c1 = __float_as_int(l.y);
-        float tn0, tf0, tn1, tf1;
-        slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tn0, tf0);
-        slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tn1, tf1);
-        bool h0 = tn0 <= tf0 && tf0 >= 0.0f && tn0 <= h.t;
-        bool h1 = tn1 <= tf1 && tf1 >= 0.0f && tn1 <= h.t;
-        if (h0 && c0 < 0) {
-            leaf_closest(S, r, ~c0, tn0, exclude, h, tally);
-            h0 = false;
-        }
-        if (h1 && c1 < 0) {
-            leaf_closest(S, r, ~c1, tn1, exclude, h, tally);
-            h1 = false;
-        }
-        h0 = h0 && tn0 <= h.t;
-        h1 = h1 && tn1 <= h.t;
-        if (h0 && h1 && sp < max_sp) {
-            const bool first0 = tn0 <= tn1;
-            stk[sp * stride] = (W)(first0 ? c1 : c0);
-            ++sp;
-            node = first0 ? c0 : c1;
-        } else if (h0) {
-            node = c0;
-        } else if (h1) {
-            node = c1;
-        } else {
-            if (sp == 0) break;
-            --sp;
-            node = link_of(stk[sp * stride]);
-        }
-    }
-    return h;
+    return c.h;
 }
 
 template <class TallyT>
@@ -618,27 +643,36 @@ __device__ __forceinline__ void render_tile(const SceneView& S, const LaunchArgs
 }
 
 // Same tile, deferred form.  Phase 1 takes the tile's samples in batches
-// of kSortPerLane * block: every lane generates the first rays of its
-// samples, the batch is counting-sorted in LDS by an octahedral direction
-// cell (64 cells, Morton order), and the lanes then trace the first rays in
-// sorted order, a block at a time, appending every first vertex (work
-// index, t, triangle) to an LDS buffer.  Rays of similar direction share
-// waves, so the rays that reach the scene (and traverse deep) are packed
-// together and waves of escaping rays finish early.  Whenever the buffer
-// holds a block's worth, phase 2 drains it: each lane regenerates its
-// entry's path state (Philox block 0), then shades, tests the shadow ray
-// and follows the rest of the path, on densely packed lanes.  Redrawing a
-// first ray costs less than keeping it: four LDS words per sample would
-// cost the kernel a workgroup per CU.
+// of kSortPerLane * block: the batch is counting-sorted in LDS by a cell of
+// its first rays' directions, and the waves then trace the first rays in
+// sorted order, each lane taking the next ray of the order as soon as its
+// own has finished (in groups, see trace_first_hits), and append every
+// first vertex (work index, t, triangle) to an LDS buffer.  Sorting keeps
+// rays of similar direction (similar traversals) in the same wave; the
+// refill keeps the waves full while the few rays that reach the scene
+// traverse deep.  Whenever the buffer holds a block's worth, phase 2
+// drains it: each lane regenerates its entry's path state (Philox block
+// 0), then shades, tests the shadow ray and follows the rest of the path,
+// on densely packed lanes.  Redrawing a first ray costs less than keeping
+// it: four LDS words per sample would cost the kernel a workgroup per CU.
+//
+// The sort cell needs no direction: for a given pixel the first ray's
+// direction is a continuous function of the two uniforms (u0, u1) of
+// Philox block 0 (the cosine map in the relay wall's frame, which is the
+// same for every scan point, or the jitter inside a pinhole pixel), so a
+// Morton-ordered cell of the (u0, u1) square is a compact cell of
+// directions, and equally probable.
 constexpr uint32_t kSortPerLane = 8;
-constexpr uint32_t kDirCells = 64;
+constexpr uint32_t kCellBits = 4;  // per axis: 256 cells
+constexpr uint32_t kDirCells = 1u << (2 * kCellBits);
+static_assert(kDirCells % 64 == 0, "one wave scans the cell counts");
 
 struct DeferredLds {
     uint32_t* work;    // first-hit buffer, capacity 2 * block
     float* t;
     int* prim;
     int* sorted;
-    uint32_t* count;   // [0] buffer fill, [1] sorted batch size
+    uint32_t* count;   // [0] buffer fill, [1] sorted batch size, [2] next sorted ray, [3] reserved slots
     uint32_t* order;   // [block * kSortPerLane] work indices in cell order
     uint32_t* start;   // [kDirCells] first slot of each cell
     uint32_t* fill;    // [kDirCells]
@@ -647,7 +681,7 @@ struct DeferredLds {
 // 32-bit words of LDS the deferred form adds per block of nb lanes
 __host__ __device__ constexpr size_t deferred_words(uint32_t nb)
 {
-    return 8ull * nb + 2 + (size_t)nb * kSortPerLane + 2ull * kDirCells;
+    return 8ull * nb + 4 + (size_t)nb * kSortPerLane + 2ull * kDirCells;
 }
 
 __device__ __forceinline__ DeferredLds carve_deferred(float* base, uint32_t nb)
@@ -660,27 +694,86 @@ __device__ __forceinline__ DeferredLds carve_deferred(float* base, uint32_t nb)
     f.prim = reinterpret_cast<int*>(u + 2 * cap);
     f.sorted = reinterpret_cast<int*>(u + 3 * cap);
     f.count = u + 4 * cap;
-    f.order = u + 4 * cap + 2;
+    f.order = u + 4 * cap + 4;
     f.start = f.order + nb * kSortPerLane;
     f.fill = f.start + kDirCells;
     return f;
 }
 
-__device__ __forceinline__ uint32_t spread3(uint32_t b) { return (b & 1u) | ((b & 2u) << 1) | ((b & 4u) << 2); }
-
-// octahedral cell of a direction (8 x 8), Morton-ordered
-__device__ __forceinline__ uint32_t direction_cell(vec3 d)
+// sort cell of a sample's first ray: Morton index of (u0, u1) on a
+// 2^kCellBits square grid
+__device__ __forceinline__ uint32_t first_ray_cell(const LaunchArgs& L, uint32_t pix, uint32_t sample)
 {
-    const float s = fabsf(d.x) + fabsf(d.y) + fabsf(d.z);
-    float u = d.x / s, v = d.y / s;
-    if (d.z < 0.0f) {
-        const float fu = (1.0f - fabsf(v)) * copysignf(1.0f, u);
-        v = (1.0f - fabsf(u)) * copysignf(1.0f, v);
-        u = fu;
+    const rand4 u = draw4(pix, sample, 0u, L.stream_id, L.key0, L.key1);
+    constexpr float kRes = (float)(1u << kCellBits);
+    uint32_t qx = (uint32_t)(u.u0 * kRes), qy = (uint32_t)(u.u1 * kRes);
+    uint32_t m = 0;
+#pragma unroll
+    for (uint32_t b = 0; b < kCellBits; ++b) m |= (((qx >> b) & 1u) << (2 * b)) | (((qy >> b) & 1u) << (2 * b + 1));
+    return m;
+}
+
+constexpr int kRefill = 32;
+
+// Closest hits of the sorted first rays [0, nvalid) of a batch, appended
+// to the first-hit buffer.  Each wave keeps its lanes busy: once kRefill
+// of its lanes have finished their rays, those lanes take the next rays of
+// the order, so the long traversals of rays that reach the scene run side
+// by side instead of each holding a mostly idle wave.  A ray starts only
+// with a reserved buffer slot (released if it leaves the scene), so the
+// buffer never overflows; a wave returns once it can start no ray and has
+// none in flight.  No barrier inside.
+template <class W, class TallyT>
+__device__ __forceinline__ void trace_first_hits(const SceneView& S, const LaunchArgs& L, uint32_t p0,
+                                                 const DeferredLds& fh, uint32_t nvalid, W* stk, int stride,
+                                                 TallyT& tally)
+{
+    const uint32_t cap = 2 * blockDim.x;
+    bool active = false;
+    bool fetch = true;  // wave-uniform
+    uint32_t w = 0;
+    PathState ps;
+    Ray r;
+    ClosestTrav c;
+    for (;;) {
+        if (fetch && __popcll(__ballot(!active)) >= kRefill) {
+            bool failed = false;
+            if (!active) {
+                const uint32_t rs = atomicAdd(fh.count + 3, 1u);
+                const uint32_t j = rs < cap ? atomicAdd(fh.count + 2, 1u) : 0xffffffffu;
+                if (j < nvalid) {
+                    w = fh.order[j];
+                    const uint32_t pl = w / L.spp;
+                    begin_path(S, L, p0 + pl, L.sample_offset + (w - pl * L.spp), ps);
+                    r = make_ray(ps.o, ps.d);
+                    closest_begin(S, r, ps.prev, c, tally);
+                    active = true;
+                } else {
+                    atomicSub(fh.count + 3, 1u);
+                    failed = true;
+                }
+            }
+            if (__any(failed)) fetch = false;
+        }
+        if (!__any(active)) break;
+        while (active) {
+            if (closest_step(S, r, ps.prev, stk, stride, c, tally)) {
+                float t_hit;
+                bool med;
+                if (resolve_event(S, ps, c.h, t_hit, med)) {
+                    const uint32_t q = atomicAdd(fh.count, 1u);
+                    fh.work[q] = w;
+                    fh.t[q] = c.h.t;
+                    fh.prim[q] = c.h.prim;
+                    fh.sorted[q] = c.h.sorted;
+                } else {
+                    atomicSub(fh.count + 3, 1u);
+                }
+                active = false;
+            }
+            if (fetch && __popcll(__ballot(active)) <= 64 - kRefill) break;
+        }
     }
-    const uint32_t qx = min((uint32_t)fmaxf((u * 0.5f + 0.5f) * 8.0f, 0.0f), 7u);
-    const uint32_t qy = min((uint32_t)fmaxf((v * 0.5f + 0.5f) * 8.0f, 0.0f), 7u);
-    return spread3(qx) | (spread3(qy) << 1);
 }
 
 template <class W, class TallyT>
@@ -697,7 +790,10 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
     const uint32_t nb = blockDim.x;
     const uint32_t tid = threadIdx.x;
     for (uint32_t i = tid; i < TP * T + 2 * TP; i += nb) lds_film[i] = 0.0f;
-    if (tid == 0) fh.count[0] = 0u;
+    if (tid == 0) {
+        fh.count[0] = 0u;
+        fh.count[3] = 0u;
+    }
     __syncthreads();
 
     const uint32_t work = npix * L.spp;
@@ -706,10 +802,10 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
     uint32_t cur = 0xffffffffu;
     FilmSink sink{nullptr, 0.0f, 0.0f};
     for (uint32_t base = 0; base < work; base += batch) {
-        // phase 1a: first rays of the batch, counting sort by direction cell
-        if (tid < kDirCells) {
-            fh.start[tid] = 0u;
-            fh.fill[tid] = 0u;
+        // phase 1a: counting sort of the batch by first-ray cell
+        for (uint32_t i = tid; i < kDirCells; i += nb) {
+            fh.start[i] = 0u;
+            fh.fill[i] = 0u;
         }
         __syncthreads();
         uint32_t cell[kSortPerLane];
@@ -720,22 +816,35 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
             if (w < work && has_vertex) {
                 const uint32_t pl = w / L.spp;
                 tally.add(kTallyDraws);
-                PathState ps;
-                begin_path(S, L, p0 + pl, L.sample_offset + (w - pl * L.spp), ps);
-                cell[k] = direction_cell(ps.d);
+                cell[k] = first_ray_cell(L, p0 + pl, L.sample_offset + (w - pl * L.spp));
                 atomicAdd(fh.start + cell[k], 1u);
             }
         }
         __syncthreads();
-        if (tid < kDirCells) {  // exclusive scan of the cell counts by the first wave
-            const uint32_t c = fh.start[tid];
-            uint32_t x = c;
-            for (int off = 1; off < (int)kDirCells; off <<= 1) {
-                const uint32_t y = __shfl_up(x, off, kDirCells);
+        if (tid < 64) {  // exclusive scan of the cell counts by the first wave
+            constexpr uint32_t kPerLane = kDirCells / 64;
+            uint32_t c[kPerLane];
+            uint32_t sum = 0;
+#pragma unroll
+            for (uint32_t i = 0; i < kPerLane; ++i) {
+                c[i] = fh.start[tid * kPerLane + i];
+                sum += c[i];
+            }
+            uint32_t x = sum;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(x, off, 64);
                 if ((int)tid >= off) x += y;
             }
-            fh.start[tid] = x - c;
-            if (tid == kDirCells - 1) fh.count[1] = x;
+            uint32_t run = x - sum;
+#pragma unroll
+            for (uint32_t i = 0; i < kPerLane; ++i) {
+                fh.start[tid * kPerLane + i] = run;
+                run += c[i];
+            }
+            if (tid == 63) {
+                fh.count[1] = x;
+                fh.count[2] = 0u;
+            }
         }
         __syncthreads();
 #pragma unroll
@@ -743,31 +852,16 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
             if (cell[k] != 0xffffffffu)
                 fh.order[fh.start[cell[k]] + atomicAdd(fh.fill + cell[k], 1u)] = base + k * nb + tid;
         __syncthreads();
-        // phase 1b: first rays in cell order, a block at a time
+        // phase 1b: first rays in cell order; phase 2 whenever the buffer
+        // holds a block's worth (or at the end of the tile)
         const uint32_t nvalid = fh.count[1];
         const bool last_batch = base + batch >= work;
-        for (uint32_t c0 = 0; c0 < nvalid || (c0 == 0 && last_batch); c0 += nb) {
-            const uint32_t j = c0 + tid;
-            if (j < nvalid) {
-                const uint32_t w = fh.order[j];
-                const uint32_t pl = w / L.spp;
-                PathState ps;
-                begin_path(S, L, p0 + pl, L.sample_offset + (w - pl * L.spp), ps);
-                const Hit h = closest_hit(S, make_ray(ps.o, ps.d), ps.prev, stk, stride, tally);
-                float t_hit;
-                bool med;
-                if (resolve_event(S, ps, h, t_hit, med)) {
-                    const uint32_t q = atomicAdd(fh.count, 1u);
-                    fh.work[q] = w;
-                    fh.t[q] = h.t;
-                    fh.prim[q] = h.prim;
-                    fh.sorted[q] = h.sorted;
-                }
-            }
+        for (;;) {
+            trace_first_hits(S, L, p0, fh, nvalid, stk, stride, tally);
             __syncthreads();
-            // phase 2: the rest of the buffered paths on packed lanes
             const uint32_t n = fh.count[0];
-            if (n >= nb || (last_batch && c0 + nb >= nvalid)) {
+            const bool exhausted = fh.count[2] >= nvalid;
+            if (n >= nb || (last_batch && exhausted)) {
                 for (uint32_t jj = tid; jj < n; jj += nb) {
                     const uint32_t wj = fh.work[jj];
                     const uint32_t pl = wj / L.spp;
@@ -791,9 +885,13 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
                     continue_path(S, L, p0 + pl, sample, ps, h, stk, stride, sink, tally);
                 }
                 __syncthreads();
-                if (tid == 0) fh.count[0] = 0u;
+                if (tid == 0) {
+                    fh.count[0] = 0u;
+                    fh.count[3] = 0u;
+                }
                 __syncthreads();
             }
+            if (exhausted) break;
         }
     }
     if (cur != 0xffffffffu) {
