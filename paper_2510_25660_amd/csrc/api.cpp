@@ -308,6 +308,8 @@ void fill_launch(const trhip_scene* s, const trhip_render_desc* r, uint32_t tile
     L->flags = r->flags;
     L->tile_pixels = tile;
     L->n_pixels = s->n_pixels;
+    L->chunks = 1;
+    L->chunk_spp = r->spp;
     L->norm = 1.0f / (float)(r->norm_spp ? r->norm_spp : r->spp);
     L->albedo = r->albedo_override ? r->albedo_override : s->d_albedo;
     L->rough_eval = r->roughness_override ? r->roughness_override : s->d_rough;

@@ -900,9 +900,21 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
     }
     __syncthreads();
 
-    const bool acc = (L.flags & kFlagAccumulate) != 0;
     const size_t fbase = (size_t)p0 * T;
     const uint32_t nvals = npix * T;
+    if (L.chunks > 1) {  // other workgroups hold other samples of these pixels
+        for (uint32_t i = tid; i < nvals; i += nb) {
+            const float v = tfilm[i] * L.norm;
+            if (v != 0.0f) unsafeAtomicAdd(L.film + fbase + i, v);
+        }
+        if (tid < npix) {
+            const uint32_t p = p0 + tid;
+            if (L.steady) unsafeAtomicAdd(L.steady + p, tsteady[tid] * L.norm);
+            if (L.oow) unsafeAtomicAdd(L.oow + p, toow[tid] * L.norm);
+        }
+        return;
+    }
+    const bool acc = (L.flags & kFlagAccumulate) != 0;
     for (uint32_t i = tid; i < nvals; i += nb) {
         const float v = tfilm[i] * L.norm;
         L.film[fbase + i] = acc ? L.film[fbase + i] + v : v;
@@ -929,10 +941,15 @@ k_render_deferred(SceneView S, LaunchArgs L, unsigned long long* counts)
     Tally<kCount> tally;
     extern __shared__ float lds[];
     const uint32_t TP = L.tile_pixels;
+    // workgroup -> (tile, chunk of the tile's samples)
+    const uint32_t tile = blockIdx.x / L.chunks, chunk = blockIdx.x - tile * L.chunks;
+    LaunchArgs Lc = L;
+    Lc.sample_offset = L.sample_offset + chunk * L.chunk_spp;
+    Lc.spp = min(L.chunk_spp, L.spp - chunk * L.chunk_spp);
     float* after_film = lds + (size_t)TP * S.n_bins + 2 * TP;
     const DeferredLds fh = carve_deferred(after_film, blockDim.x);
     W* stk = reinterpret_cast<W*>(after_film + deferred_words(blockDim.x)) + threadIdx.x;
-    render_tile_deferred(S, L, blockIdx.x * TP, lds, fh, stk, (int)blockDim.x, tally);
+    render_tile_deferred(S, Lc, tile * TP, lds, fh, stk, (int)blockDim.x, tally);
     tally.flush(counts);
 }
 
@@ -1389,6 +1406,12 @@ k_backward_stash(SceneView S, LaunchArgs L)
     }
 }
 
+__global__ void k_zero_f32(float* p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
 __global__ void k_zero_f64(double* p, size_t n)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -1460,12 +1483,17 @@ template <class W>
 void launch_deferred_w(const SceneView& S, const LaunchArgs& L, uint32_t block, size_t lds, hipStream_t stream,
                        unsigned long long* counts)
 {
+    const dim3 grid(tiles_of(L) * L.chunks);
     if (counts)
-        hipLaunchKernelGGL((k_render_deferred<true, W>), dim3(tiles_of(L)), dim3(block), lds,
-                           stream, S, L, counts);
+        hipLaunchKernelGGL((k_render_deferred<true, W>), grid, dim3(block), lds, stream, S, L, counts);
     else
-        hipLaunchKernelGGL((k_render_deferred<false, W>), dim3(tiles_of(L)), dim3(block), lds,
-                           stream, S, L, counts);
+        hipLaunchKernelGGL((k_render_deferred<false, W>), grid, dim3(block), lds, stream, S, L, counts);
+}
+
+void launch_zero_f32(float* p, size_t n, hipStream_t stream)
+{
+    const unsigned g = (unsigned)std::min<size_t>(1024, (n + 255) / 256 + 1);
+    hipLaunchKernelGGL(k_zero_f32, dim3(g), dim3(256), 0, stream, p, n);
 }
 
 template <class W>
@@ -1515,9 +1543,25 @@ hipError_t launch_render_wavefront(const SceneView& S, const LaunchArgs& L, uint
     return hipGetLastError();
 }
 
-hipError_t launch_render_deferred(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
+// The deferred form splits a tile's samples into chunks of one sort batch
+// when there are more: shorter workgroups shrink the tail of the launch
+// (measured on the confocal workload, 4096 samples per pixel: +4.5%; one
+// workgroup per half batch loses more to per-workgroup work than it gains).
+// Chunks of one tile add their partial films atomically.
+hipError_t launch_render_deferred(const SceneView& S, const LaunchArgs& L0, uint32_t block, hipStream_t stream,
                                   unsigned long long* counts)
 {
+    LaunchArgs L = L0;
+    const uint32_t c = kSortPerLane * block;
+    if (L.spp > c) {
+        L.chunk_spp = c;
+        L.chunks = (L.spp + c - 1) / c;
+        if ((L.flags & kFlagAccumulate) == 0) {
+            launch_zero_f32(L.film, (size_t)L.n_pixels * S.n_bins, stream);
+            if (L.steady) launch_zero_f32(L.steady, L.n_pixels, stream);
+            if (L.oow) launch_zero_f32(L.oow, L.n_pixels, stream);
+        }
+    }
     const size_t lds =
         deferred_lds_bytes(L.tile_pixels, S.n_bins, block, stack_lane_bytes(S.n_tris, S.stack_depth));
     if (short_stack(S.n_tris))

@@ -62,6 +62,8 @@ struct LaunchArgs {
     uint32_t spp, sample_offset, max_depth, stream_id;
     uint32_t key0, key1, flags;
     uint32_t tile_pixels, n_pixels;
+    uint32_t chunks;            // sample chunks per tile (deferred form): > 1 adds partial films atomically
+    uint32_t chunk_spp;         // samples per chunk
     float norm;                 // 1 / norm_spp
     const float* albedo;        // evaluation albedo (caller order)
     const float* rough_eval;    // evaluation roughness

@@ -233,3 +233,23 @@ def test_stack_link_widths(tr, oracle_mod, n_tris, kernel):
     _announce(f"cluttered box nt={n_tris} {kernel}")
     err, info = _check(tr, oracle_mod, sc, kernel=kernel)
     assert info["n_triangles"] == n_tris
+
+
+def test_deferred_sample_chunks(tr, oracle_mod):
+    """More samples per pixel than one sort batch: the deferred form splits
+    each pixel's samples over several workgroups that add their partial
+    films atomically (fresh film, then accumulated onto an existing one)."""
+    import torch
+    sc = scenes.confocal_nlos(grid=8, spp=8192)
+    _announce("deferred sample chunks 8x8 spp 8192")
+    _check(tr, oracle_mod, sc, kernel="deferred")
+    with tr.upload(sc) as dev:
+        st, film = tr.render_transient(dev, kernel="deferred")
+        st2, film2 = tr.render_transient(dev, kernel="deferred", spp=4096, norm_spp=8192)
+        tr.render_transient(dev, kernel="deferred", spp=4096, sample_offset=4096, norm_spp=8192, accumulate=True,
+                            film=film2, steady=st2)
+        torch.cuda.synchronize()
+        a, b = film.cpu().numpy(), film2.cpu().numpy()
+    assert ((a != 0) == (b != 0)).all()
+    np.testing.assert_allclose(b, a, rtol=1e-5, atol=0)
+    np.testing.assert_allclose(st2.cpu().numpy(), st.cpu().numpy(), rtol=1e-5)
