@@ -302,6 +302,20 @@ trhip_status trhip_batch_get_info(const trhip_batch* batch, trhip_batch_info* in
 /* Waits for the device, frees the batch (not the scenes or films).  NULL is accepted. */
 trhip_status trhip_batch_destroy(trhip_batch* batch);
 
+/*
+ * Photon-count (shot) noise for synthetic captures, a measurement-free
+ * stand-in for the device noise that Sec. 4.5 ("Realistic hardware noise")
+ * adds to simulated NLOS captures.  Reads film[i] as the expected count
+ * scale * film[i] and writes one draw of it: out[i] = N_i / scale with
+ * N_i ~ Poisson(scale * film[i]) (exact inversion in FP64 up to a mean of
+ * 2^16, the normal approximation above; non-positive values give 0).
+ * film, out: DEVICE float[n] (out may equal film); scale > 0 and finite;
+ * the draws depend only on (seed, i, film[i], scale).
+ * Errors: INVALID_ARG (NULL pointer with n > 0, bad scale), HIP.
+ */
+trhip_status trhip_poisson_noise(const float* film, float* out, uint64_t n, float scale, uint64_t seed,
+                                 void* stream);
+
 /* Static strings; never NULL. */
 const char* trhip_status_string(trhip_status status);
 const char* trhip_last_error(void);

@@ -219,6 +219,25 @@ def render_transient_counted(dev: DeviceScene, spp=None, seed=None, max_depth=No
     return steady, film, dict(zip(COUNT_NAMES, [int(c) for c in counts]))
 
 
+def poisson_noise(film, scale=None, peak_count=1000.0, seed=0, out=None, stream=None):
+    """One photon-count capture of a film: out = Poisson(scale * film) / scale
+    (trhip_poisson_noise).  scale defaults to peak_count / max(film), so the
+    brightest bin expects peak_count photons.  Returns (out, scale)."""
+    torch = _torch()
+    if not (film.is_cuda and film.dtype == torch.float32 and film.is_contiguous()):
+        raise ValueError("film must be a contiguous float32 CUDA tensor")
+    if scale is None:
+        peak = float(film.max().item())
+        if not peak > 0.0:
+            raise ValueError("film has no positive bin; pass scale explicitly")
+        scale = float(peak_count) / peak
+    if out is None:
+        out = torch.empty_like(film)
+    check(lib().trhip_poisson_noise(_ptr(film), _ptr(out), film.numel(), float(scale), int(seed),
+                                    _stream_handle(stream)))
+    return out, scale
+
+
 def render_transient_backward(dev: DeviceScene, grad_film, spp=None, seed=None, max_depth=None, primal=False,
                               stream=None, **kw):
     """Adjoint: returns (grad_albedo [nt], grad_roughness [nt]) (and the

@@ -816,6 +816,16 @@ trhip_status trhip_batch_destroy(trhip_batch* batch)
 
 extern "C" {
 
+trhip_status trhip_poisson_noise(const float* film, float* out, uint64_t n, float scale, uint64_t seed, void* stream)
+{
+    if (n == 0) return TRHIP_OK;
+    if (!film || !out) return fail(TRHIP_ERR_INVALID_ARG, "film and out must be non-NULL");
+    if (!(scale > 0.0f) || !std::isfinite(scale)) return fail(TRHIP_ERR_INVALID_ARG, "scale must be positive and finite");
+    hipError_t e = trhip::launch_poisson(film, out, n, scale, seed, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "noise launch");
+    return TRHIP_OK;
+}
+
 const char* trhip_status_string(trhip_status status)
 {
     switch (status) {

@@ -62,6 +62,8 @@ hipError_t launch_batch(const BatchTables& B, uint32_t groups, uint32_t block, u
 hipError_t launch_render_deferred(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
                                   unsigned long long* counts = nullptr);
 hipError_t launch_zero_f64(double* p, size_t n, hipStream_t stream);
+// out[i] = Poisson(scale * film[i]) / scale (noise.hip)
+hipError_t launch_poisson(const float* film, float* out, uint64_t n, float scale, uint64_t seed, hipStream_t stream);
 hipError_t launch_f64_to_f32(const double* src, float* dst, size_t n, hipStream_t stream);
 hipError_t launch_scene_fill(const float* tri9, uint32_t nt, hipStream_t stream);
 

@@ -120,6 +120,17 @@ def test_bad_handles(B):
     assert L.trhip_scene_get_info(fake, C.byref(info)) == 5
 
 
+def test_poisson_noise_validation(B):
+    """Invalid noise arguments are rejected on the host, before any HIP call."""
+    L = B.lib()
+    assert L.trhip_poisson_noise(None, None, 0, 1.0, 0, None) == 0
+    assert L.trhip_poisson_noise(None, C.c_void_p(16), 4, 1.0, 0, None) == 1
+    assert L.trhip_poisson_noise(C.c_void_p(16), None, 4, 1.0, 0, None) == 1
+    for bad in (0.0, -1.0, float("inf"), float("nan")):
+        assert L.trhip_poisson_noise(C.c_void_p(16), C.c_void_p(16), 4, bad, 0, None) == 1
+    assert b"scale" in L.trhip_last_error()
+
+
 def test_product_path_has_no_oracle_or_fallback():
     """The package never imports the oracle and has no CPU rendering path."""
     pkg = os.path.join(ROOT, "paper_2510_25660_amd")
