@@ -198,6 +198,8 @@ def main():
     ap.add_argument("--kernel", default="auto", choices=["auto", "path", "deferred", "wavefront"])
     ap.add_argument("--compare-kernels", action="store_true", help="also time each kernel form")
     ap.add_argument("--builder", default="ploc", choices=["ploc", "lbvh"])
+    ap.add_argument("--phasor-freqs", type=int, default=16,
+                    help="also time the frequency-space film with this many frequencies (0: skip)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a device copy of this many MiB (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -237,6 +239,15 @@ def main():
                 ms, _ = time_launches(lambda: tr.render_transient(dev, film=film, steady=steady, **sh), args.steps,
                                       args.warmup)
                 forms[form] = round(paths / (ms / args.steps * 1e-3) / 1e6, 3)
+        phasor = None
+        if args.phasor_freqs:
+            # the same paths into a phasor film (Sec. 4.3) instead of the histogram
+            freqs = list(np.linspace(0.5, 16.6, args.phasor_freqs))
+            ph = torch.empty((sc.height, sc.width, len(freqs), 2), device="cuda", dtype=torch.float32)
+            ms, _ = time_launches(lambda: tr.render_phasor(dev, freqs, phasor=ph, steady=steady, **shape),
+                                  args.steps, args.warmup)
+            phasor = {"n_freq": len(freqs), "freq_range_per_m": [0.5, 16.6], "ms_per_step": round(ms / args.steps, 4),
+                      "mpaths_per_s": round(paths / (ms / args.steps * 1e-3) / 1e6, 3)}
     ms_per_step = total_ms / args.steps
     value = paths / (ms_per_step * 1e-3) / 1e6
     launch_ms = float(np.mean(per))
@@ -268,6 +279,8 @@ def main():
     }
     if forms:
         out["kernel_forms_mpaths_per_s"] = forms
+    if phasor:
+        out["phasor_film"] = phasor
     if not args.no_backward:
         ratio, f_ms, b_ms, rep_ms = backward_forward_ratio(tr)
         out["backward_forward_ratio"] = round(ratio, 3)

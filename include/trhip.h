@@ -303,6 +303,31 @@ trhip_status trhip_batch_get_info(const trhip_batch* batch, trhip_batch_info* in
 trhip_status trhip_batch_destroy(trhip_batch* batch);
 
 /*
+ * Frequency-space (phasor) film, Sec. 4.3: per pixel and frequency f_j
+ * (cycles per metre of optical path, i.e. Omega_j = 2 pi f_j in the
+ * exp(-i Omega t) of Eq. 13 with t in metres), the Monte Carlo estimate of
+ * Eq. 14: (1/N) sum over the contributions c of the pixel's N paths of
+ * c exp(-2 pi i f_j tof), accumulated per sample during rendering with no
+ * time histogram and no window (every contribution counts, so the
+ * transform covers all t).  tof is the optical path length that the time
+ * histogram bins (camera unwarping and the confocal convention apply).
+ * The phase is reduced exactly to one cycle of FP32 f_j * tof, so it is
+ * accurate while f_j * tof stays far below 2^23 cycles.
+ *
+ * render: as for trhip_render_transient (kernel WAVEFRONT is UNSUPPORTED;
+ * ACCUMULATE adds into phasor and steady).  freqs: HOST float[n_freq],
+ * 1 <= n_freq <= TRHIP_MAX_FREQS, finite (0 gives the steady image as a
+ * real number).  phasor: DEVICE float[n_pixels][n_freq][2] (re, im), the
+ * layout of a complex64 array [H][W][n_freq]; steady: DEVICE float[n_pixels]
+ * or NULL.  The same paths as trhip_render_transient with the same render
+ * description.
+ * Errors: INVALID_ARG, BAD_HANDLE, UNSUPPORTED, HIP.
+ */
+#define TRHIP_MAX_FREQS 32
+trhip_status trhip_render_phasor(trhip_scene* scene, const trhip_render_desc* render, const float* freqs,
+                                 uint32_t n_freq, float* phasor, float* steady, void* stream);
+
+/*
  * Photon-count (shot) noise for synthetic captures, a measurement-free
  * stand-in for the device noise that Sec. 4.5 ("Realistic hardware noise")
  * adds to simulated NLOS captures.  Reads film[i] as the expected count

@@ -108,6 +108,7 @@ def lib():
         L.orc_pad.argtypes = [C.c_void_p]
         L.orc_trace_path.argtypes = [C.c_void_p, C.POINTER(_Render), C.c_uint32, C.c_uint32, C.POINTER(_Path)]
         L.orc_render_film.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, dp, dp, dp, C.c_int]
+        L.orc_render_phasor.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, dp, C.c_int, dp, dp, C.c_int]
         L.orc_backward.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, fp, dp, dp, dp, C.c_int]
         L.orc_closest_hit.argtypes = [C.c_void_p, fp, fp, C.c_int, C.c_int, fp, ip]
         L.orc_philox_n.argtypes = [C.c_int64, up, up, up]
@@ -333,6 +334,32 @@ class Oracle:
         if rc != 0:
             raise ValueError("oracle render failed")
         return film, steady, oow
+
+    def render_phasor(self, freqs, spp=None, seed=None, max_depth=None, pixels: Optional[Sequence[int]] = None,
+                      threads: int = 0, **kw):
+        """Returns (phasor [n_pix, K] complex128, steady [n_pix]) for the
+        frequencies `freqs` (cycles per metre of optical path)."""
+        sc = self.scene
+        spp = sc.spp if spp is None else spp
+        seed = sc.seed if seed is None else seed
+        max_depth = sc.max_depth if max_depth is None else max_depth
+        if pixels is None:
+            pixels = np.arange(sc.n_pixels, dtype=np.int32)
+        pixels = np.ascontiguousarray(pixels, np.int32)
+        f = np.ascontiguousarray(np.asarray(freqs, np.float64).ravel())
+        n = len(pixels)
+        out = np.zeros((n, f.size, 2), np.float64)
+        steady = np.zeros(n, np.float64)
+        r, keep = self._render_desc(spp, seed, max_depth, **kw)
+        if threads <= 0:
+            threads = os.cpu_count() or 1
+        D = C.POINTER(C.c_double)
+        rc = lib().orc_render_phasor(self._h, C.byref(r), pixels.ctypes.data_as(C.POINTER(C.c_int32)), n,
+                                     f.ctypes.data_as(D), int(f.size), out.ctypes.data_as(D),
+                                     steady.ctypes.data_as(D), int(threads))
+        if rc != 0:
+            raise ValueError("oracle phasor render failed")
+        return out[..., 0] + 1j * out[..., 1], steady
 
     def backward(self, grad_film: np.ndarray, spp=None, seed=None, max_depth=None, pixels=None,
                  threads: int = 0, want_primal=False, **kw):

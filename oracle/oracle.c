@@ -904,6 +904,10 @@ typedef struct {
     double* film;  /* [n_pix][T] */
     double* steady;
     double* oow;
+    /* phasor film */
+    const double* freqs;
+    int n_freq;
+    double* phasor; /* [n_pix][n_freq][2] */
     /* adjoint */
     const float* grad_film; /* full film layout [P][T] */
     double* g_alb;
@@ -929,6 +933,39 @@ static void* render_worker(void* arg)
                 if (!vx->has_c) continue;
                 if (vx->bin >= 0) row[vx->bin] += (double)vx->c;
                 else if (J->oow) J->oow[i] += (double)vx->c;
+                if (J->steady) J->steady[i] += (double)vx->c;
+            }
+        }
+    }
+    free(rec);
+    return NULL;
+}
+
+/* Sec. 4.3, Eq. 14: every contribution c of the pixel's paths adds
+ * c exp(-2 pi i f tof) for each frequency f (cycles per metre of optical
+ * path), with tof the optical path length of the connected path; there is
+ * no window, the transform covers all times. */
+static void* phasor_worker(void* arg)
+{
+    job_t* J = (job_t*)arg;
+    orc_path* rec = (orc_path*)malloc(sizeof(orc_path));
+    const double two_pi = 6.283185307179586476925286766559;
+    int i, j;
+    uint32_t s;
+    for (i = J->tid; i < J->n_pix; i += J->nthreads) {
+        uint32_t pix = (uint32_t)J->pixels[i];
+        double* row = J->phasor + (size_t)i * (size_t)J->n_freq * 2;
+        for (s = 0; s < (uint32_t)J->R->spp; ++s) {
+            int v;
+            orc_trace_path(J->P, J->R, pix, J->R->sample_offset + s, rec);
+            for (v = 0; v < rec->n_vert; ++v) {
+                const orc_vertex* vx = &rec->v[v];
+                if (!vx->has_c) continue;
+                for (j = 0; j < J->n_freq; ++j) {
+                    const double ang = two_pi * J->freqs[j] * (double)vx->opl_c;
+                    row[2 * j] += (double)vx->c * cos(ang);
+                    row[2 * j + 1] -= (double)vx->c * sin(ang);
+                }
                 if (J->steady) J->steady[i] += (double)vx->c;
             }
         }
@@ -1027,6 +1064,28 @@ int orc_render_film(const orc_prepared* P, const orc_render* R, const int32_t* p
         for (b = 0; b < T; ++b) film[(size_t)i * T + b] *= inv_n;
         if (steady) steady[i] *= inv_n;
         if (oow) oow[i] *= inv_n;
+    }
+    return 0;
+}
+
+int orc_render_phasor(const orc_prepared* P, const orc_render* R, const int32_t* pixels, int n_pix,
+                      const double* freqs, int n_freq, double* phasor, double* steady, int nthreads)
+{
+    job_t J;
+    int i;
+    size_t k, n2 = 2 * (size_t)n_freq;
+    double inv_n;
+    if (!P || !R || R->spp <= 0 || R->max_depth < 1 || n_freq < 1 || !freqs || !phasor) return -1;
+    memset(&J, 0, sizeof(J));
+    J.P = P; J.R = R; J.pixels = pixels; J.n_pix = n_pix;
+    J.freqs = freqs; J.n_freq = n_freq; J.phasor = phasor; J.steady = steady;
+    memset(phasor, 0, sizeof(double) * n2 * (size_t)n_pix);
+    if (steady) memset(steady, 0, sizeof(double) * (size_t)n_pix);
+    run_jobs(&J, nthreads, phasor_worker);
+    inv_n = 1.0 / (double)R->spp;
+    for (i = 0; i < n_pix; ++i) {
+        for (k = 0; k < n2; ++k) phasor[(size_t)i * n2 + k] *= inv_n;
+        if (steady) steady[i] *= inv_n;
     }
     return 0;
 }

@@ -71,6 +71,10 @@ float orc_pad(const orc_prepared* p);
 int orc_trace_path(const orc_prepared* p, const orc_render* r, uint32_t pix, uint32_t sample, orc_path* rec);
 int orc_render_film(const orc_prepared* p, const orc_render* r, const int32_t* pixels, int n_pix,
                     double* film, double* steady, double* oow, int nthreads);
+/* phasor film of Sec. 4.3 (Eq. 14): phasor[n_pix][n_freq][2] = (re, im) of
+ * (1/N) sum c exp(-2 pi i f tof), f in cycles per metre of optical path */
+int orc_render_phasor(const orc_prepared* p, const orc_render* r, const int32_t* pixels, int n_pix,
+                      const double* freqs, int n_freq, double* phasor, double* steady, int nthreads);
 int orc_backward(const orc_prepared* p, const orc_render* r, const int32_t* pixels, int n_pix,
                  const float* grad_film, double* g_alb, double* g_rough, double* primal_film, int nthreads);
 

@@ -199,6 +199,28 @@ def render_transient(dev: DeviceScene, spp=None, seed=None, max_depth=None, film
     return steady, film
 
 
+def render_phasor(dev: DeviceScene, freqs, spp=None, seed=None, max_depth=None, phasor=None, steady=None,
+                  stream=None, **kw):
+    """Frequency-space film (trhip_render_phasor): returns (steady [H, W],
+    phasor [H, W, K] complex64) for the K frequencies `freqs` (cycles per
+    metre of optical path): the mean over samples of c exp(-2 pi i f tof)."""
+    torch = _torch()
+    sc = dev.scene
+    shape = (sc.height, sc.width)
+    f = np.ascontiguousarray(np.asarray(freqs, dtype=np.float32).ravel())
+    k = int(f.size)
+    kw["albedo"] = _check_param(kw.get("albedo"), sc.n_tris, "albedo")
+    kw["roughness"] = _check_param(kw.get("roughness"), sc.n_tris, "roughness")
+    if phasor is None:
+        phasor = torch.empty(shape + (k, 2), device="cuda", dtype=torch.float32)
+    if steady is None:
+        steady = torch.empty(shape, device="cuda", dtype=torch.float32)
+    r = make_render_desc(dev, spp, seed, max_depth, **kw)
+    check(lib().trhip_render_phasor(dev.handle, C.byref(r), f.ctypes.data_as(C.POINTER(C.c_float)), k,
+                                    _ptr(phasor), _ptr(steady), _stream_handle(stream)))
+    return steady, torch.view_as_complex(phasor)
+
+
 def render_transient_counted(dev: DeviceScene, spp=None, seed=None, max_depth=None, stream=None, **kw):
     """Same render as render_transient by the counting build of the kernel;
     returns (steady, film, counts) with counts a dict of work counters

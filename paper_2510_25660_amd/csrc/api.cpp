@@ -243,10 +243,11 @@ uint32_t lane_stack_bytes(const trhip_scene* s) { return trhip::stack_lane_bytes
 // Launch shape: enough pixels per tile that a workgroup has ~block samples
 // of work, capped by the LDS budget (tile film + traversal stacks, plus the
 // path slots and queues of the wavefront form).
+// words: floats of one pixel's film (0: the time bins)
 trhip_status choose_shape(const trhip_scene* s, const trhip_render_desc* r, Kind kind, uint32_t* tile,
-                          uint32_t* block)
+                          uint32_t* block, uint32_t words = 0)
 {
-    const uint32_t T = s->view.n_bins, depth = lane_stack_bytes(s);
+    const uint32_t T = words ? words : s->view.n_bins, depth = lane_stack_bytes(s);
     uint32_t bs = r->block_size ? r->block_size : kMaxBlock;
     if (!r->block_size) {
         // small per-tile work: narrower groups keep more of them in flight
@@ -406,6 +407,36 @@ trhip_status trhip_render_transient(trhip_scene* scene, const trhip_render_desc*
     L.oow = oow;
     hipError_t e = launch_forward(kind, scene->view, L, block, (hipStream_t)stream, nullptr);
     if (e != hipSuccess) return hip_fail(e, "render launch");
+    return TRHIP_OK;
+}
+
+static_assert(TRHIP_MAX_FREQS == trhip::kMaxFreq, "phasor frequency limit");
+
+trhip_status trhip_render_phasor(trhip_scene* scene, const trhip_render_desc* render, const float* freqs,
+                                 uint32_t n_freq, float* phasor, float* steady, void* stream)
+{
+    trhip_status st = check_scene(scene);
+    if (st != TRHIP_OK) return st;
+    if ((st = validate_render(scene, render)) != TRHIP_OK) return st;
+    if (!phasor) return fail(TRHIP_ERR_INVALID_ARG, "phasor is NULL");
+    if (!freqs || n_freq == 0 || n_freq > trhip::kMaxFreq)
+        return fail(TRHIP_ERR_INVALID_ARG, "freqs must hold 1..%u frequencies", trhip::kMaxFreq);
+    for (uint32_t j = 0; j < n_freq; ++j)
+        if (!std::isfinite(freqs[j])) return fail(TRHIP_ERR_INVALID_ARG, "freqs[%u] is not finite", j);
+    if (render->kernel == TRHIP_KERNEL_WAVEFRONT)
+        return fail(TRHIP_ERR_UNSUPPORTED, "the wavefront form has no phasor film");
+    const Kind kind = forward_kind(scene, render);
+    uint32_t tile = 0, block = 0;
+    if ((st = choose_shape(scene, render, kind, &tile, &block, 2 * n_freq)) != TRHIP_OK) return st;
+    trhip::LaunchArgs L;
+    fill_launch(scene, render, tile, &L);
+    L.film = phasor;
+    L.steady = steady;
+    L.oow = nullptr;
+    L.n_freq = n_freq;
+    for (uint32_t j = 0; j < n_freq; ++j) L.freq[j] = freqs[j];
+    hipError_t e = launch_forward(kind, scene->view, L, block, (hipStream_t)stream, nullptr);
+    if (e != hipSuccess) return hip_fail(e, "phasor launch");
     return TRHIP_OK;
 }
 

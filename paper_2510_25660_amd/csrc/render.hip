@@ -307,6 +307,7 @@ struct Nee {
     int excl;      // triangle excluded from the shadow test
     float c;       // contribution if unoccluded
     int bin;       // -1: outside the film window
+    float tof;     // optical path length of the connected path
     int k;         // triangle of the vertex (-1: medium vertex)
     float g_alb, g_rough;  // d log f of the connection
     bool valid;
@@ -412,6 +413,7 @@ __device__ __forceinline__ void shade_vertex(const SceneView& S, const LaunchArg
     const float opl_c = ps.opl + dist;
     const float q = (opl_c - S.bin_start) / S.bin_width;
     nee.bin = (q >= 0.0f && q < (float)S.n_bins) ? (int)q : -1;
+    nee.tof = opl_c;
     nee.sd = wl;
     nee.tmax = dist * kShadowShrink;
     if (med) {
@@ -542,7 +544,7 @@ __device__ void continue_path(const SceneView& S, const LaunchArgs& L, uint32_t 
         shade_vertex<Sink::kWantsGradients>(S, L, pix, sample, ps, h, t_hit, med, nee, cont, tally);
         if (nee.valid && !occluded(S, make_ray(nee.so, nee.sd), nee.excl, nee.tmax, stk, stride, tally)) {
             tally.add(kTallyContrib);
-            sink.contribution(v, nee.k, nee.c, nee.bin, nee.g_alb, nee.g_rough);
+            sink.contribution(v, nee.k, nee.c, nee.bin, nee.tof, nee.g_alb, nee.g_rough);
         }
         if (!cont.alive) break;
         if (cont.k >= 0) sink.continuation(v, cont.k, cont.g_alb, cont.g_rough);
@@ -567,15 +569,48 @@ __device__ void trace_path(const SceneView& S, const LaunchArgs& L, uint32_t pix
 // ---------------------------------------------------------------------------
 // forward render
 // ---------------------------------------------------------------------------
+// floats of one pixel's film: the time bins, or (re, im) per frequency
+__device__ __forceinline__ uint32_t film_words(const SceneView& S, const LaunchArgs& L)
+{
+    return L.n_freq ? 2 * L.n_freq : S.n_bins;
+}
+
+// the frequencies of a phasor film into LDS (constant indices only, so
+// the kernel argument array stays in registers / the argument segment)
+__device__ __forceinline__ void load_freqs(const LaunchArgs& L, float* s_freq)
+{
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (uint32_t j = 0; j < kMaxFreq; ++j) s_freq[j] = L.freq[j];
+    }
+}
+
 struct FilmSink {
     static constexpr bool kWantsGradients = false;
     float* row;     // LDS film row of the current pixel
     float steady;   // register partial sums of the current pixel
     float oow;
-    __device__ __forceinline__ void contribution(int, int, float c, int bin, float, float)
+    const float* freq;  // LDS frequencies of a phasor film
+    uint32_t n_freq;    // 0: time histogram
+    __device__ __forceinline__ void contribution(int, int, float c, int bin, float tof, float, float)
     {
-        if (bin >= 0) atomicAdd(row + bin, c);
-        else oow += c;
+        if (n_freq) {
+            // Sec. 4.3, Eq. 14: the contribution times exp(-2 pi i f tof);
+            // the phase in cycles is reduced to [0, 1) exactly
+            for (uint32_t j = 0; j < n_freq; ++j) {
+                const float cyc = freq[j] * tof;
+                float fr = cyc - floorf(cyc);
+                if (fr >= 1.0f) fr = 0.0f;
+                float sn, cs;
+                sincos_2pi(fr, sn, cs);
+                atomicAdd(row + 2 * j, c * cs);
+                atomicAdd(row + 2 * j + 1, -(c * sn));
+            }
+        } else if (bin >= 0) {
+            atomicAdd(row + bin, c);
+        } else {
+            oow += c;
+        }
         steady += c;
     }
     __device__ __forceinline__ void continuation(int, int, float, float) {}
@@ -587,9 +622,9 @@ struct FilmSink {
 // tile_pixels * n_bins + 2 * tile_pixels floats; stk is the lane's stack.
 template <class W, class TallyT>
 __device__ __forceinline__ void render_tile(const SceneView& S, const LaunchArgs& L, uint32_t p0, float* lds_film,
-                                            W* stk, int stride, TallyT& tally)
+                                            const float* freq, W* stk, int stride, TallyT& tally)
 {
-    const uint32_t T = S.n_bins;
+    const uint32_t T = film_words(S, L);
     const uint32_t TP = L.tile_pixels;
     float* tfilm = lds_film;
     float* tsteady = lds_film + (size_t)TP * T;
@@ -600,7 +635,7 @@ __device__ __forceinline__ void render_tile(const SceneView& S, const LaunchArgs
 
     const uint32_t work = npix * L.spp;
     uint32_t cur = 0xffffffffu;
-    FilmSink sink{nullptr, 0.0f, 0.0f};
+    FilmSink sink{nullptr, 0.0f, 0.0f, freq, L.n_freq};
     for (uint32_t w = threadIdx.x; w < work; w += blockDim.x) {
         const uint32_t pl = w / L.spp;
         const uint32_t s = w - pl * L.spp;
@@ -778,10 +813,10 @@ __device__ __forceinline__ void trace_first_hits(const SceneView& S, const Launc
 
 template <class W, class TallyT>
 __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const LaunchArgs& L, uint32_t p0,
-                                                     float* lds_film, const DeferredLds& fh, W* stk,
-                                                     int stride, TallyT& tally)
+                                                     float* lds_film, const float* freq, const DeferredLds& fh,
+                                                     W* stk, int stride, TallyT& tally)
 {
-    const uint32_t T = S.n_bins;
+    const uint32_t T = film_words(S, L);
     const uint32_t TP = L.tile_pixels;
     float* tfilm = lds_film;
     float* tsteady = lds_film + (size_t)TP * T;
@@ -800,7 +835,7 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
     const bool has_vertex = last_vertex(S, L) >= 1;
     const uint32_t batch = nb * kSortPerLane;
     uint32_t cur = 0xffffffffu;
-    FilmSink sink{nullptr, 0.0f, 0.0f};
+    FilmSink sink{nullptr, 0.0f, 0.0f, freq, L.n_freq};
     for (uint32_t base = 0; base < work; base += batch) {
         // phase 1a: counting sort of the batch by first-ray cell
         for (uint32_t i = tid; i < kDirCells; i += nb) {
@@ -946,10 +981,12 @@ k_render_deferred(SceneView S, LaunchArgs L, unsigned long long* counts)
     LaunchArgs Lc = L;
     Lc.sample_offset = L.sample_offset + chunk * L.chunk_spp;
     Lc.spp = min(L.chunk_spp, L.spp - chunk * L.chunk_spp);
-    float* after_film = lds + (size_t)TP * S.n_bins + 2 * TP;
+    __shared__ float s_freq[kMaxFreq];
+    load_freqs(L, s_freq);
+    float* after_film = lds + (size_t)TP * film_words(S, L) + 2 * TP;
     const DeferredLds fh = carve_deferred(after_film, blockDim.x);
     W* stk = reinterpret_cast<W*>(after_film + deferred_words(blockDim.x)) + threadIdx.x;
-    render_tile_deferred(S, Lc, tile * TP, lds, fh, stk, (int)blockDim.x, tally);
+    render_tile_deferred(S, Lc, tile * TP, lds, s_freq, fh, stk, (int)blockDim.x, tally);
     tally.flush(counts);
 }
 
@@ -959,8 +996,10 @@ __global__ void __launch_bounds__(256) k_render(SceneView S, LaunchArgs L, unsig
     Tally<kCount> tally;
     extern __shared__ float lds[];
     const uint32_t TP = L.tile_pixels;
-    W* stk = reinterpret_cast<W*>(lds + (size_t)TP * S.n_bins + 2 * TP) + threadIdx.x;
-    render_tile(S, L, blockIdx.x * TP, lds, stk, (int)blockDim.x, tally);
+    __shared__ float s_freq[kMaxFreq];
+    load_freqs(L, s_freq);
+    W* stk = reinterpret_cast<W*>(lds + (size_t)TP * film_words(S, L) + 2 * TP) + threadIdx.x;
+    render_tile(S, L, blockIdx.x * TP, lds, s_freq, stk, (int)blockDim.x, tally);
     tally.flush(counts);
 }
 
@@ -977,9 +1016,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchTables B)
     __shared__ uint32_t s_item;
     Tally<false> tally;
     const DeferredLds fh = carve_deferred(lds + B.film_words, blockDim.x);
-    W* stk = reinterpret_cast<W*>(
-                        lds + B.film_words + (kDeferred ? deferred_words(blockDim.x) : 0)) +
-                    threadIdx.x;
+    W* stk = reinterpret_cast<W*>(lds + B.film_words + (kDeferred ? deferred_words(blockDim.x) : 0)) + threadIdx.x;
     while (true) {
         if (threadIdx.x == 0) s_item = atomicAdd(B.cursor, 1u);
         __syncthreads();
@@ -996,10 +1033,11 @@ __global__ void __launch_bounds__(256) k_batch(BatchTables B)
         const SceneView* __restrict__ views = B.views;
         const LaunchArgs* __restrict__ args = B.args;
         if (kDeferred)
-            render_tile_deferred(views[scene], args[scene], tile * args[scene].tile_pixels,
-                                                         lds, fh, stk, (int)blockDim.x, tally);
+            render_tile_deferred(views[scene], args[scene], tile * args[scene].tile_pixels, lds, nullptr, fh, stk,
+                                 (int)blockDim.x, tally);
         else
-            render_tile(views[scene], args[scene], tile * args[scene].tile_pixels, lds, stk, (int)blockDim.x, tally);
+            render_tile(views[scene], args[scene], tile * args[scene].tile_pixels, lds, nullptr, stk,
+                        (int)blockDim.x, tally);
         __syncthreads();
     }
 }
@@ -1220,7 +1258,7 @@ struct AdjointSumSink {
     const float* delta;  // LDS gradient row of the pixel
     float norm;
     double total;
-    __device__ __forceinline__ void contribution(int, int, float c, int bin, float, float)
+    __device__ __forceinline__ void contribution(int, int, float c, int bin, float, float, float)
     {
         if (bin >= 0) total += (double)delta[bin] * (double)c * (double)norm;
     }
@@ -1236,7 +1274,8 @@ struct AdjointScatterSink {
     double prefix;      // sum of a_j so far
     double* g_alb;
     double* g_rough;
-    __device__ __forceinline__ void contribution(int, int k, float c, int bin, float g_alb_nee, float g_rough_nee)
+    __device__ __forceinline__ void contribution(int, int k, float c, int bin, float, float g_alb_nee,
+                                                 float g_rough_nee)
     {
         if (bin < 0) return;
         if (primal_row) atomicAdd(primal_row + bin, c);
@@ -1317,7 +1356,8 @@ struct AdjointStashSink {
     int pk = -1;
     float pa = 0.0f, pr = 0.0f;
 
-    __device__ __forceinline__ void contribution(int, int kv, float c, int bin, float g_alb_nee, float g_rough_nee)
+    __device__ __forceinline__ void contribution(int, int kv, float c, int bin, float, float g_alb_nee,
+                                                 float g_rough_nee)
     {
         if (bin < 0) return;
         if (primal_row) atomicAdd(primal_row + bin, c);
@@ -1523,7 +1563,8 @@ void launch_batch_w(const BatchTables& B, uint32_t groups, uint32_t block, size_
 hipError_t launch_render(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
                          unsigned long long* counts)
 {
-    const size_t lds = render_lds_bytes(L.tile_pixels, S.n_bins, block, stack_lane_bytes(S.n_tris, S.stack_depth));
+    const uint32_t words = L.n_freq ? 2 * L.n_freq : S.n_bins;
+    const size_t lds = render_lds_bytes(L.tile_pixels, words, block, stack_lane_bytes(S.n_tris, S.stack_depth));
     if (short_stack(S.n_tris))
         launch_render_w<uint16_t>(S, L, block, lds, stream, counts);
     else
@@ -1557,13 +1598,13 @@ hipError_t launch_render_deferred(const SceneView& S, const LaunchArgs& L0, uint
         L.chunk_spp = c;
         L.chunks = (L.spp + c - 1) / c;
         if ((L.flags & kFlagAccumulate) == 0) {
-            launch_zero_f32(L.film, (size_t)L.n_pixels * S.n_bins, stream);
+            launch_zero_f32(L.film, (size_t)L.n_pixels * (L.n_freq ? 2 * L.n_freq : S.n_bins), stream);
             if (L.steady) launch_zero_f32(L.steady, L.n_pixels, stream);
             if (L.oow) launch_zero_f32(L.oow, L.n_pixels, stream);
         }
     }
-    const size_t lds =
-        deferred_lds_bytes(L.tile_pixels, S.n_bins, block, stack_lane_bytes(S.n_tris, S.stack_depth));
+    const uint32_t words = L.n_freq ? 2 * L.n_freq : S.n_bins;
+    const size_t lds = deferred_lds_bytes(L.tile_pixels, words, block, stack_lane_bytes(S.n_tris, S.stack_depth));
     if (short_stack(S.n_tris))
         launch_deferred_w<uint16_t>(S, L, block, lds, stream, counts);
     else

@@ -54,6 +54,8 @@ struct SceneView {
     int32_t unwarp;
 };
 
+constexpr uint32_t kMaxFreq = 32;  // frequencies of one phasor film
+
 constexpr uint32_t kFlagPixelCentre = 1u << 0;
 constexpr uint32_t kFlagAccumulate = 1u << 1;
 constexpr uint32_t kFlagFrozen = 1u << 2;
@@ -75,6 +77,11 @@ struct LaunchArgs {
     double* g_alb;
     double* g_rough;
     float* primal;
+    // phasor film (n_freq > 0): film is [n_pixels][n_freq][2] (re, im) of
+    // sum c exp(-2 pi i f tof) over all contributions, f = freq[j] in cycles
+    // per metre of optical path; n_freq = 0: the time histogram
+    uint32_t n_freq;
+    float freq[kMaxFreq];
 };
 
 // Tables of the batched persistent kernel (device memory).
