@@ -127,7 +127,12 @@ def backward_forward_ratio(tr, steps=5, warmup=1):
                                   warmup)
         rep_ms, _ = time_launches(lambda: tr.render_transient_backward(dev, delta, albedo=a, roughness=r,
                                                                        kernel="path"), steps, warmup)
-    return bwd_ms / fwd_ms, fwd_ms / steps, bwd_ms / steps, rep_ms / steps
+        # forward mode along one parameter: the roughness of the two boxes
+        v = (torch.from_numpy(sc.mat_type) == scenes.MAT_GGX).float().cuda()
+        dfilm = torch.empty_like(film)
+        tan_ms, _ = time_launches(lambda: tr.render_transient_tangent(dev, None, v, film=film, dfilm=dfilm, albedo=a,
+                                                                      roughness=r), steps, warmup)
+    return bwd_ms / fwd_ms, fwd_ms / steps, bwd_ms / steps, rep_ms / steps, tan_ms / steps
 
 
 def run_batched(args, tr):
@@ -282,10 +287,11 @@ def main():
     if phasor:
         out["phasor_film"] = phasor
     if not args.no_backward:
-        ratio, f_ms, b_ms, rep_ms = backward_forward_ratio(tr)
+        ratio, f_ms, b_ms, rep_ms, t_ms = backward_forward_ratio(tr)
         out["backward_forward_ratio"] = round(ratio, 3)
         out["backward_forward_ms"] = [round(f_ms, 3), round(b_ms, 3)]
         out["backward_replay_ms"] = round(rep_ms, 3)
+        out["forward_mode_ms"] = round(t_ms, 3)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc)
     print(json.dumps(out), flush=True)

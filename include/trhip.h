@@ -303,6 +303,30 @@ trhip_status trhip_batch_get_info(const trhip_batch* batch, trhip_batch_info* in
 trhip_status trhip_batch_destroy(trhip_batch* batch);
 
 /*
+ * Forward-mode derivative (Sec. 4.4, "forward mode differentiation"): the
+ * film of trhip_render_transient and, in the same pass, its derivative
+ * along a direction of the per-triangle parameters,
+ *   dfilm = sum_k (dfilm/dalbedo_k) tangent_albedo[k]
+ *         + (dfilm/droughness_k) tangent_roughness[k],
+ * for the estimator at the render's seed with the sampling held fixed (the
+ * gradient that trhip_render_transient_backward transposes: for any dL/dfilm
+ * the two satisfy <dL/dfilm, dfilm> = <grad_albedo, tangent_albedo> +
+ * <grad_roughness, tangent_roughness>).  One parameter pi_i is the
+ * indicator direction of the triangles it controls.
+ *
+ * render: as for trhip_render_transient (kernel, tile and block fields:
+ * path per lane; TRHIP_FLAG_FROZEN_PROPOSAL for roughness directions that
+ * finite differences at a fixed seed can check).  tangent_albedo,
+ * tangent_roughness: DEVICE float[n_triangles] (caller order) or NULL for a
+ * zero component.  film, dfilm: DEVICE float[n_pixels][n_bins]; steady:
+ * DEVICE float[n_pixels] or NULL.
+ * Errors: INVALID_ARG, BAD_HANDLE, UNSUPPORTED (LDS), HIP.
+ */
+trhip_status trhip_render_transient_tangent(trhip_scene* scene, const trhip_render_desc* render,
+                                            const float* tangent_albedo, const float* tangent_roughness, float* film,
+                                            float* dfilm, float* steady, void* stream);
+
+/*
  * Frequency-space (phasor) film, Sec. 4.3: per pixel and frequency f_j
  * (cycles per metre of optical path, i.e. Omega_j = 2 pi f_j in the
  * exp(-i Omega t) of Eq. 13 with t in metres), the Monte Carlo estimate of

@@ -108,6 +108,7 @@ def lib():
         L.orc_pad.argtypes = [C.c_void_p]
         L.orc_trace_path.argtypes = [C.c_void_p, C.POINTER(_Render), C.c_uint32, C.c_uint32, C.POINTER(_Path)]
         L.orc_render_film.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, dp, dp, dp, C.c_int]
+        L.orc_render_tangent.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, dp, dp, dp, dp, dp, C.c_int]
         L.orc_render_phasor.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, dp, C.c_int, dp, dp, C.c_int]
         L.orc_backward.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, fp, dp, dp, dp, C.c_int]
         L.orc_closest_hit.argtypes = [C.c_void_p, fp, fp, C.c_int, C.c_int, fp, ip]
@@ -334,6 +335,35 @@ class Oracle:
         if rc != 0:
             raise ValueError("oracle render failed")
         return film, steady, oow
+
+    def render_tangent(self, v_albedo=None, v_roughness=None, spp=None, seed=None, max_depth=None,
+                       pixels: Optional[Sequence[int]] = None, threads: int = 0, **kw):
+        """Returns (film [n_pix, T], dfilm [n_pix, T], steady [n_pix]): the film
+        and its derivative along (v_albedo, v_roughness) at a fixed seed."""
+        sc = self.scene
+        spp = sc.spp if spp is None else spp
+        seed = sc.seed if seed is None else seed
+        max_depth = sc.max_depth if max_depth is None else max_depth
+        if pixels is None:
+            pixels = np.arange(sc.n_pixels, dtype=np.int32)
+        pixels = np.ascontiguousarray(pixels, np.int32)
+        n = len(pixels)
+        D = C.POINTER(C.c_double)
+        va = None if v_albedo is None else np.ascontiguousarray(v_albedo, np.float64)
+        vr = None if v_roughness is None else np.ascontiguousarray(v_roughness, np.float64)
+        film = np.zeros((n, sc.n_bins), np.float64)
+        dfilm = np.zeros((n, sc.n_bins), np.float64)
+        steady = np.zeros(n, np.float64)
+        r, keep = self._render_desc(spp, seed, max_depth, **kw)
+        if threads <= 0:
+            threads = os.cpu_count() or 1
+        rc = lib().orc_render_tangent(self._h, C.byref(r), pixels.ctypes.data_as(C.POINTER(C.c_int32)), n,
+                                      None if va is None else va.ctypes.data_as(D),
+                                      None if vr is None else vr.ctypes.data_as(D), film.ctypes.data_as(D),
+                                      dfilm.ctypes.data_as(D), steady.ctypes.data_as(D), int(threads))
+        if rc != 0:
+            raise ValueError("oracle tangent render failed")
+        return film, dfilm, steady
 
     def render_phasor(self, freqs, spp=None, seed=None, max_depth=None, pixels: Optional[Sequence[int]] = None,
                       threads: int = 0, **kw):

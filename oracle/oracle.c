@@ -904,6 +904,10 @@ typedef struct {
     double* film;  /* [n_pix][T] */
     double* steady;
     double* oow;
+    /* forward-mode derivative */
+    const double* v_alb;
+    const double* v_rough;
+    double* dfilm; /* [n_pix][T] */
     /* phasor film */
     const double* freqs;
     int n_freq;
@@ -967,6 +971,53 @@ static void* phasor_worker(void* arg)
                     row[2 * j + 1] -= (double)vx->c * sin(ang);
                 }
                 if (J->steady) J->steady[i] += (double)vx->c;
+            }
+        }
+    }
+    free(rec);
+    return NULL;
+}
+
+/* Sec. 4.4, forward mode: at a fixed seed with the sampling held fixed, a
+ * contribution c_j carries the product of the continuation weights of the
+ * vertices before it and the connection factor at its own vertex, so its
+ * derivative along the direction v is c_j times (the sum over earlier
+ * vertices of d log w . v plus d log f_nee . v of its vertex). */
+static double along(const job_t* J, int tri, double d_alb, double d_rough)
+{
+    double d = 0.0;
+    if (tri < 0) return 0.0;
+    if (J->v_alb) d += J->v_alb[tri] * d_alb;
+    if (J->v_rough) d += J->v_rough[tri] * d_rough;
+    return d;
+}
+
+static void* tangent_worker(void* arg)
+{
+    job_t* J = (job_t*)arg;
+    const orc_scene* sc = &J->P->sc;
+    orc_path* rec = (orc_path*)malloc(sizeof(orc_path));
+    int i;
+    uint32_t s;
+    int T = sc->n_bins;
+    for (i = J->tid; i < J->n_pix; i += J->nthreads) {
+        uint32_t pix = (uint32_t)J->pixels[i];
+        double* row = J->film + (size_t)i * (size_t)T;
+        double* drow = J->dfilm + (size_t)i * (size_t)T;
+        for (s = 0; s < (uint32_t)J->R->spp; ++s) {
+            int v;
+            double tang = 0.0;
+            orc_trace_path(J->P, J->R, pix, J->R->sample_offset + s, rec);
+            for (v = 0; v < rec->n_vert; ++v) {
+                const orc_vertex* vx = &rec->v[v];
+                if (vx->has_c) {
+                    if (J->steady) J->steady[i] += (double)vx->c;
+                    if (vx->bin >= 0) {
+                        row[vx->bin] += (double)vx->c;
+                        drow[vx->bin] += (double)vx->c * (tang + along(J, vx->tri, vx->dn_alb, vx->dn_rough));
+                    }
+                }
+                if (vx->has_cont) tang += along(J, vx->tri, vx->dc_alb, vx->dc_rough);
             }
         }
     }
@@ -1064,6 +1115,33 @@ int orc_render_film(const orc_prepared* P, const orc_render* R, const int32_t* p
         for (b = 0; b < T; ++b) film[(size_t)i * T + b] *= inv_n;
         if (steady) steady[i] *= inv_n;
         if (oow) oow[i] *= inv_n;
+    }
+    return 0;
+}
+
+int orc_render_tangent(const orc_prepared* P, const orc_render* R, const int32_t* pixels, int n_pix,
+                       const double* v_alb, const double* v_rough, double* film, double* dfilm, double* steady,
+                       int nthreads)
+{
+    job_t J;
+    int i;
+    size_t b, T = (size_t)P->sc.n_bins;
+    double inv_n;
+    if (!P || !R || R->spp <= 0 || R->max_depth < 1 || !film || !dfilm) return -1;
+    memset(&J, 0, sizeof(J));
+    J.P = P; J.R = R; J.pixels = pixels; J.n_pix = n_pix;
+    J.v_alb = v_alb; J.v_rough = v_rough; J.film = film; J.dfilm = dfilm; J.steady = steady;
+    memset(film, 0, sizeof(double) * T * (size_t)n_pix);
+    memset(dfilm, 0, sizeof(double) * T * (size_t)n_pix);
+    if (steady) memset(steady, 0, sizeof(double) * (size_t)n_pix);
+    run_jobs(&J, nthreads, tangent_worker);
+    inv_n = 1.0 / (double)R->spp;
+    for (i = 0; i < n_pix; ++i) {
+        for (b = 0; b < T; ++b) {
+            film[(size_t)i * T + b] *= inv_n;
+            dfilm[(size_t)i * T + b] *= inv_n;
+        }
+        if (steady) steady[i] *= inv_n;
     }
     return 0;
 }

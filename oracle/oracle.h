@@ -71,6 +71,11 @@ float orc_pad(const orc_prepared* p);
 int orc_trace_path(const orc_prepared* p, const orc_render* r, uint32_t pix, uint32_t sample, orc_path* rec);
 int orc_render_film(const orc_prepared* p, const orc_render* r, const int32_t* pixels, int n_pix,
                     double* film, double* steady, double* oow, int nthreads);
+/* forward-mode derivative (Sec. 4.4): film and dfilm [n_pix][T], dfilm the
+ * derivative along (v_alb, v_rough) (either may be NULL) */
+int orc_render_tangent(const orc_prepared* p, const orc_render* r, const int32_t* pixels, int n_pix,
+                       const double* v_alb, const double* v_rough, double* film, double* dfilm, double* steady,
+                       int nthreads);
 /* phasor film of Sec. 4.3 (Eq. 14): phasor[n_pix][n_freq][2] = (re, im) of
  * (1/N) sum c exp(-2 pi i f tof), f in cycles per metre of optical path */
 int orc_render_phasor(const orc_prepared* p, const orc_render* r, const int32_t* pixels, int n_pix,

@@ -25,6 +25,7 @@ from ._binding import (FLAG_ACCUMULATE, FLAG_FROZEN_PROPOSAL, FLAG_PIXEL_CENTRE,
 
 __all__ = [
     "scenes", "upload", "DeviceScene", "render_transient", "render_transient_backward", "render_transient_counted",
+    "render_transient_tangent", "render_phasor", "poisson_noise",
     "TransientRender", "Batch",
     "TrhipError", "FLAG_PIXEL_CENTRE", "FLAG_ACCUMULATE", "FLAG_FROZEN_PROPOSAL", "version",
 ]
@@ -221,6 +222,31 @@ def render_phasor(dev: DeviceScene, freqs, spp=None, seed=None, max_depth=None, 
     return steady, torch.view_as_complex(phasor)
 
 
+def render_transient_tangent(dev: DeviceScene, tangent_albedo=None, tangent_roughness=None, spp=None, seed=None,
+                             max_depth=None, film=None, dfilm=None, steady=None, stream=None, **kw):
+    """Forward-mode derivative (trhip_render_transient_tangent): returns
+    (steady [H, W], film [H, W, T], dfilm [H, W, T]) where dfilm is the
+    derivative of the film along (tangent_albedo, tangent_roughness)."""
+    torch = _torch()
+    sc = dev.scene
+    shape = (sc.height, sc.width)
+    n = sc.n_tris
+    kw["albedo"] = _check_param(kw.get("albedo"), n, "albedo")
+    kw["roughness"] = _check_param(kw.get("roughness"), n, "roughness")
+    ta = _check_param(tangent_albedo, n, "tangent_albedo")
+    trr = _check_param(tangent_roughness, n, "tangent_roughness")
+    if film is None:
+        film = torch.empty(shape + (sc.n_bins,), device="cuda", dtype=torch.float32)
+    if dfilm is None:
+        dfilm = torch.empty(shape + (sc.n_bins,), device="cuda", dtype=torch.float32)
+    if steady is None:
+        steady = torch.empty(shape, device="cuda", dtype=torch.float32)
+    r = make_render_desc(dev, spp, seed, max_depth, **kw)
+    check(lib().trhip_render_transient_tangent(dev.handle, C.byref(r), _ptr(ta), _ptr(trr), _ptr(film), _ptr(dfilm),
+                                               _ptr(steady), _stream_handle(stream)))
+    return steady, film, dfilm
+
+
 def render_transient_counted(dev: DeviceScene, spp=None, seed=None, max_depth=None, stream=None, **kw):
     """Same render as render_transient by the counting build of the kernel;
     returns (steady, film, counts) with counts a dict of work counters
@@ -344,16 +370,31 @@ def _make_autograd():
     class TransientRender(torch.autograd.Function):
         """film = TransientRender.apply(albedo, roughness, dev, opts) with opts a
         dict of render options (spp, seed, max_depth, ...).  The backward is
-        the library's path-replay adjoint at the same seed."""
+        the library's adjoint at the same seed; its forward-mode derivative
+        (torch.autograd.forward_ad) is the library's tangent render."""
 
         @staticmethod
-        def forward(ctx, albedo, roughness, dev, opts):
-            opts = dict(opts or {})
-            _, film = render_transient(dev, albedo=albedo.contiguous(), roughness=roughness.contiguous(), **opts)
-            ctx.dev = dev
-            ctx.opts = opts
-            ctx.save_for_backward(albedo, roughness)
+        def forward(albedo, roughness, dev, opts):
+            _, film = render_transient(dev, albedo=albedo.contiguous(), roughness=roughness.contiguous(),
+                                       **dict(opts or {}))
             return film
+
+        @staticmethod
+        def setup_context(ctx, inputs, output):
+            albedo, roughness, dev, opts = inputs
+            ctx.dev = dev
+            ctx.opts = dict(opts or {})
+            ctx.save_for_backward(albedo, roughness)
+            ctx.save_for_forward(albedo, roughness)
+
+        @staticmethod
+        def jvp(ctx, d_albedo, d_roughness, _dev, _opts):
+            albedo, roughness = ctx.saved_tensors
+            ta = d_albedo.contiguous() if d_albedo is not None else None
+            trr = d_roughness.contiguous() if d_roughness is not None else None
+            _, _, dfilm = render_transient_tangent(ctx.dev, ta, trr, albedo=albedo.contiguous(),
+                                                   roughness=roughness.contiguous(), **ctx.opts)
+            return dfilm
 
         @staticmethod
         def backward(ctx, grad_film):

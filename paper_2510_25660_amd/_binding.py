@@ -28,7 +28,7 @@ EXPORTED_SYMBOLS = (
     "trhip_scene_create", "trhip_scene_destroy", "trhip_scene_get_info", "trhip_render_transient",
     "trhip_render_transient_backward", "trhip_render_transient_counted", "trhip_status_string",
     "trhip_last_error", "trhip_version", "trhip_batch_create", "trhip_batch_render", "trhip_batch_get_info",
-    "trhip_batch_destroy", "trhip_poisson_noise", "trhip_render_phasor",
+    "trhip_batch_destroy", "trhip_poisson_noise", "trhip_render_phasor", "trhip_render_transient_tangent",
 )
 
 COUNT_NAMES = ("nodes", "tris", "rays", "shadow_rays", "vertices", "draws", "contributions")
@@ -164,6 +164,8 @@ def lib():
         L.trhip_batch_destroy.restype = C.c_int
         L.trhip_render_phasor.argtypes = [vp, C.POINTER(RenderDesc), C.POINTER(C.c_float), C.c_uint32, vp, vp, vp]
         L.trhip_render_phasor.restype = C.c_int
+        L.trhip_render_transient_tangent.argtypes = [vp, C.POINTER(RenderDesc), vp, vp, vp, vp, vp, vp]
+        L.trhip_render_transient_tangent.restype = C.c_int
         L.trhip_poisson_noise.argtypes = [vp, vp, C.c_uint64, C.c_float, C.c_uint64, vp]
         L.trhip_poisson_noise.restype = C.c_int
         L.trhip_status_string.argtypes = [C.c_int]

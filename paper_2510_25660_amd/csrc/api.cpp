@@ -224,7 +224,7 @@ trhip_status validate_render(const trhip_scene* s, const trhip_render_desc* r)
     return TRHIP_OK;
 }
 
-enum class Kind { Path, Wavefront, Deferred, Backward, BackwardPrimal };
+enum class Kind { Path, Wavefront, Deferred, Backward, BackwardPrimal, Tangent };
 
 // stack: LDS bytes of one lane's traversal stack
 size_t lds_bytes(Kind kind, uint32_t tp, uint32_t T, uint32_t bs, uint32_t stack)
@@ -234,6 +234,7 @@ size_t lds_bytes(Kind kind, uint32_t tp, uint32_t T, uint32_t bs, uint32_t stack
     case Kind::Wavefront: return trhip::wavefront_lds_bytes(tp, T, bs, stack);
     case Kind::Deferred: return trhip::deferred_lds_bytes(tp, T, bs, stack);
     case Kind::Backward: return trhip::backward_lds_bytes(tp, T, bs, stack, false);
+    case Kind::Tangent: return trhip::tangent_lds_bytes(tp, T, bs, stack);
     default: return trhip::backward_lds_bytes(tp, T, bs, stack, true);
     }
 }
@@ -437,6 +438,28 @@ trhip_status trhip_render_phasor(trhip_scene* scene, const trhip_render_desc* re
     for (uint32_t j = 0; j < n_freq; ++j) L.freq[j] = freqs[j];
     hipError_t e = launch_forward(kind, scene->view, L, block, (hipStream_t)stream, nullptr);
     if (e != hipSuccess) return hip_fail(e, "phasor launch");
+    return TRHIP_OK;
+}
+
+trhip_status trhip_render_transient_tangent(trhip_scene* scene, const trhip_render_desc* render,
+                                            const float* tangent_albedo, const float* tangent_roughness, float* film,
+                                            float* dfilm, float* steady, void* stream)
+{
+    trhip_status st = check_scene(scene);
+    if (st != TRHIP_OK) return st;
+    if ((st = validate_render(scene, render)) != TRHIP_OK) return st;
+    if (!film || !dfilm) return fail(TRHIP_ERR_INVALID_ARG, "film and dfilm must be non-NULL");
+    uint32_t tile = 0, block = 0;
+    if ((st = choose_shape(scene, render, Kind::Tangent, &tile, &block)) != TRHIP_OK) return st;
+    trhip::LaunchArgs L;
+    fill_launch(scene, render, tile, &L);
+    L.film = film;
+    L.dfilm = dfilm;
+    L.steady = steady;
+    L.tan_albedo = tangent_albedo;
+    L.tan_rough = tangent_roughness;
+    hipError_t e = trhip::launch_render_tangent(scene->view, L, block, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "tangent launch");
     return TRHIP_OK;
 }
 

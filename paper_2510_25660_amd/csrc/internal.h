@@ -53,6 +53,9 @@ hipError_t launch_render_wavefront(const SceneView& S, const LaunchArgs& L, uint
 // max_cont 2 or 7: single-trace adjoint with a per-path stash of that many
 // continuation vertices; anything else: path replay (two traces per path)
 hipError_t launch_backward(const SceneView& S, const LaunchArgs& L, uint32_t block, int max_cont, hipStream_t stream);
+size_t tangent_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes);
+// forward-mode render: film and its derivative along (tan_albedo, tan_rough)
+hipError_t launch_render_tangent(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream);
 size_t deferred_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes);
 size_t batch_lds_bytes(uint32_t film_words, uint32_t block, uint32_t stack_bytes, bool deferred);
 // resets the cursor and launches the persistent kernel (groups workgroups);

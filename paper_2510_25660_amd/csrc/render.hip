@@ -1296,6 +1296,83 @@ struct AdjointScatterSink {
     }
 };
 
+// Forward mode (Sec. 4.4): the derivative of the film along a direction
+// (v_albedo, v_roughness) of the per-triangle parameters, at a fixed seed
+// with detached sampling.  Contribution j of a path is
+// c_j = prod_{v<j} w_v * (NEE factor at j), so its derivative is
+// c_j * (sum_{v<j} d log w_v + d log f_nee(j)) along the direction: the sink
+// carries the running sum over the continuations of the path.
+struct TangentSink {
+    static constexpr bool kWantsGradients = true;
+    float* row;          // LDS primal row of the pixel
+    float* drow;         // LDS tangent row
+    const float* v_alb;  // direction (caller order), may be NULL
+    const float* v_rough;
+    float tang;          // sum of d log w of the path's continuations so far
+    float steady;
+    __device__ __forceinline__ float along(int k, float g_alb, float g_rough) const
+    {
+        if (k < 0) return 0.0f;
+        float d = 0.0f;
+        if (v_alb) d = v_alb[k] * g_alb;
+        if (v_rough) d = fmaf(v_rough[k], g_rough, d);
+        return d;
+    }
+    __device__ __forceinline__ void contribution(int, int k, float c, int bin, float, float g_alb_nee,
+                                                 float g_rough_nee)
+    {
+        steady += c;
+        if (bin < 0) return;
+        atomicAdd(row + bin, c);
+        atomicAdd(drow + bin, c * (tang + along(k, g_alb_nee, g_rough_nee)));
+    }
+    __device__ __forceinline__ void continuation(int, int k, float g_alb_c, float g_rough_c)
+    {
+        tang += along(k, g_alb_c, g_rough_c);
+    }
+};
+
+template <class W>
+__global__ void __launch_bounds__(256) k_render_tangent(SceneView S, LaunchArgs L)
+{
+    Tally<false> tally;
+    extern __shared__ float lds[];
+    const uint32_t T = S.n_bins;
+    const uint32_t TP = L.tile_pixels;
+    float* tfilm = lds;
+    float* tdfilm = lds + (size_t)TP * T;
+    float* tsteady = tdfilm + (size_t)TP * T;
+    W* stk = reinterpret_cast<W*>(tsteady + TP) + threadIdx.x;
+    const int stride = (int)blockDim.x;
+    const uint32_t p0 = blockIdx.x * TP;
+    const uint32_t npix = min(TP, L.n_pixels - p0);
+    for (uint32_t i = threadIdx.x; i < 2 * TP * T + TP; i += blockDim.x) lds[i] = 0.0f;
+    __syncthreads();
+
+    const uint32_t work = npix * L.spp;
+    for (uint32_t w = threadIdx.x; w < work; w += blockDim.x) {
+        const uint32_t pl = w / L.spp;
+        const uint32_t s = w - pl * L.spp;
+        TangentSink sink{tfilm + (size_t)pl * T, tdfilm + (size_t)pl * T, L.tan_albedo, L.tan_rough, 0.0f, 0.0f};
+        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, sink, tally);
+        atomicAdd(tsteady + pl, sink.steady);
+    }
+    __syncthreads();
+
+    const bool acc = (L.flags & kFlagAccumulate) != 0;
+    const size_t base = (size_t)p0 * T;
+    for (uint32_t i = threadIdx.x; i < npix * T; i += blockDim.x) {
+        const float v = tfilm[i] * L.norm, dv = tdfilm[i] * L.norm;
+        L.film[base + i] = acc ? L.film[base + i] + v : v;
+        L.dfilm[base + i] = acc ? L.dfilm[base + i] + dv : dv;
+    }
+    if (L.steady && threadIdx.x < npix) {
+        const uint32_t p = p0 + threadIdx.x;
+        const float v = tsteady[threadIdx.x] * L.norm;
+        L.steady[p] = acc ? L.steady[p] + v : v;
+    }
+}
+
 template <class W>
 __global__ void __launch_bounds__(256) k_backward(SceneView S, LaunchArgs L)
 {
@@ -1475,6 +1552,22 @@ size_t wavefront_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block
 {
     return ((size_t)tile_pixels * n_bins + 2ull * tile_pixels) * sizeof(float) +
            (size_t)kWfWords * block * sizeof(float) + (size_t)block * stack_bytes;
+}
+
+size_t tangent_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes)
+{
+    return (2ull * tile_pixels * n_bins + tile_pixels) * sizeof(float) + (size_t)block * stack_bytes;
+}
+
+hipError_t launch_render_tangent(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream)
+{
+    const size_t lds = tangent_lds_bytes(L.tile_pixels, S.n_bins, block, stack_lane_bytes(S.n_tris, S.stack_depth));
+    const dim3 grid((L.n_pixels + L.tile_pixels - 1) / L.tile_pixels);
+    if (short_stack(S.n_tris))
+        hipLaunchKernelGGL((k_render_tangent<uint16_t>), grid, dim3(block), lds, stream, S, L);
+    else
+        hipLaunchKernelGGL((k_render_tangent<uint32_t>), grid, dim3(block), lds, stream, S, L);
+    return hipGetLastError();
 }
 
 size_t backward_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes, bool primal)

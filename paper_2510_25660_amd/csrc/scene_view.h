@@ -77,6 +77,9 @@ struct LaunchArgs {
     double* g_alb;
     double* g_rough;
     float* primal;
+    const float* tan_albedo;    // forward mode: direction of the albedo (caller order), may be NULL
+    const float* tan_rough;     // forward mode: direction of the roughness, may be NULL
+    float* dfilm;               // forward mode: derivative film
     // phasor film (n_freq > 0): film is [n_pixels][n_freq][2] (re, im) of
     // sum c exp(-2 pi i f tof) over all contributions, f = freq[j] in cycles
     // per metre of optical path; n_freq = 0: the time histogram
