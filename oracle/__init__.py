@@ -73,6 +73,7 @@ class _Render(C.Structure):
         ("frozen_proposal", C.c_int),
         ("albedo", C.POINTER(C.c_float)),
         ("roughness", C.POINTER(C.c_float)),
+        ("nlos_area", C.c_int),
     ]
 
 
@@ -106,6 +107,8 @@ def lib():
         L.orc_release.argtypes = [C.c_void_p]
         L.orc_pad.restype = C.c_float
         L.orc_pad.argtypes = [C.c_void_p]
+        L.orc_area_total.restype = C.c_double
+        L.orc_area_total.argtypes = [C.c_void_p]
         L.orc_trace_path.argtypes = [C.c_void_p, C.POINTER(_Render), C.c_uint32, C.c_uint32, C.POINTER(_Path)]
         L.orc_render_film.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, dp, dp, dp, C.c_int]
         L.orc_render_tangent.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, dp, dp, dp, dp, dp, C.c_int]
@@ -290,8 +293,9 @@ class Oracle:
         return lib().orc_pad(self._h)
 
     def _render_desc(self, spp, seed, max_depth, sample_offset=0, stream_id=0, pixel_centre=False,
-                     frozen=False, albedo=None, roughness=None):
+                     frozen=False, albedo=None, roughness=None, nlos_area=False):
         r = _Render()
+        r.nlos_area = int(bool(nlos_area))
         r.spp = int(spp)
         r.sample_offset = int(sample_offset)
         r.max_depth = int(max_depth)

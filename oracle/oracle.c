@@ -244,6 +244,10 @@ struct orc_prepared {
     onode* nodes;
     int n_nodes;
     int* order;
+    /* NLOS area sampling (confocal): inclusive prefix sums of the sampling
+     * weights (triangle areas, zero on the relay wall's plane) */
+    double* area_cdf;
+    double area_total;
 };
 
 #define ORC_BRUTE_MAX 64
@@ -355,6 +359,41 @@ orc_prepared* orc_prepare(const orc_scene* sc)
         build_rec(P, cen, 0, nt);
         free(cen);
     }
+    if (sc->sensor == ORC_SENSOR_CONFOCAL) {
+        /* Area of every triangle in FP64 (float differences are exact in
+         * double); triangles whose three vertices lie on the relay wall's
+         * plane (through the first scan point, along the wall normal) get
+         * weight 0: seen from a scan point they subtend no solid angle. */
+        double acc = 0.0, tol, n[3], s0[3];
+        int a;
+        for (a = 0; a < 3; ++a) {
+            n[a] = (double)sc->wall_normal[a];
+            s0[a] = (double)P->scan[a];
+        }
+        tol = 1e-6 * (1.0 + (double)maxabs);
+        P->area_cdf = (double*)malloc(sizeof(double) * (size_t)nt);
+        for (k = 0; k < nt; ++k) {
+            const float* t = P->tri + 9 * k;
+            double e1[3], e2[3], c[3], w = 0.0;
+            int on_wall = 1, j;
+            for (j = 0; j < 3; ++j) {
+                double h = ((double)t[3 * j] - s0[0]) * n[0] + ((double)t[3 * j + 1] - s0[1]) * n[1] +
+                           ((double)t[3 * j + 2] - s0[2]) * n[2];
+                if (fabs(h) > tol) on_wall = 0;
+            }
+            for (a = 0; a < 3; ++a) {
+                e1[a] = (double)t[3 + a] - (double)t[a];
+                e2[a] = (double)t[6 + a] - (double)t[a];
+            }
+            c[0] = e1[1] * e2[2] - e1[2] * e2[1];
+            c[1] = e1[2] * e2[0] - e1[0] * e2[2];
+            c[2] = e1[0] * e2[1] - e1[1] * e2[0];
+            if (!on_wall) w = 0.5 * sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+            acc += w;
+            P->area_cdf[k] = acc;
+        }
+        P->area_total = acc;
+    }
     return P;
 }
 
@@ -362,11 +401,12 @@ void orc_release(orc_prepared* P)
 {
     if (!P) return;
     free(P->tri); free(P->box); free(P->mat); free(P->albedo); free(P->rough);
-    free(P->scan); free(P->nodes); free(P->order);
+    free(P->scan); free(P->nodes); free(P->order); free(P->area_cdf);
     free(P);
 }
 
 float orc_pad(const orc_prepared* P) { return P->pad; }
+double orc_area_total(const orc_prepared* P) { return P->area_total; }
 
 /* ------------------------------------------------------------------------ */
 /* Ray - box (slab) and ray - triangle (Moller-Trumbore) tests.             */
@@ -761,9 +801,9 @@ int orc_trace_path(const orc_prepared* P, const orc_render* R, uint32_t pix, uin
     const orc_scene* sc = &P->sc;
     int confocal = (sc->sensor == ORC_SENSOR_CONFOCAL);
     int has_medium = (sc->sigma_t > 0.0f);
-    float u[4], beta, opl = 0.0f, u_ff;
+    float u[4], beta, opl = 0.0f, u_ff, forced_t = 0.0f;
     v3 o, d, target, wall_n = vload(sc->wall_normal);
-    int prev = -1, vmax, v;
+    int prev = -1, vmax, v, forced_k = -1;
 
     path_reset(rec);
     draw(R, pix, sample, 0, u);
@@ -782,7 +822,7 @@ int orc_trace_path(const orc_prepared* P, const orc_render* R, uint32_t pix, uin
         beta = 1.0f;
         vmax = R->max_depth - 1;
         target = vload(sc->light_pos);
-    } else {
+    } else if (!R->nlos_area) {
         /* the traced path starts at the scan point on the relay wall: a
          * Lambertian vertex whose cosine-sampling weight is its albedo */
         v3 xs = vload(P->scan + 3 * pix), t, b;
@@ -794,6 +834,50 @@ int orc_trace_path(const orc_prepared* P, const orc_render* R, uint32_t pix, uin
         beta = sc->wall_albedo;
         vmax = R->max_depth - 3;
         target = xs;
+    } else {
+        /* NLOS area sampling: the hidden vertex is a point drawn uniformly
+         * by area on the sampling set (triangle by u0 through the prefix
+         * sums, point by u1, u2), the first segment joins it to the offset
+         * scan point; its throughput is f_wall cos_s / p_w with the solid
+         * angle pdf p_w = p_A r^2 / cos_h, p_A = 1 / (total area).  Its
+         * visibility is the shadow test of the connection back to the scan
+         * point, which runs the same segment. */
+        v3 xs = vload(P->scan + 3 * pix), e1, e2, v0, xh, dv, ng;
+        const double target_area = (double)u[0] * P->area_total;
+        int lo = 0, hi = sc->n_tris - 1;
+        float su, b1, b2, r2, r, cos_s0, cos_h, g;
+        if (!(P->area_total > 0.0)) return 0;
+        while (lo < hi) { /* first triangle whose prefix sum exceeds the target */
+            int mid = (lo + hi) / 2;
+            if (P->area_cdf[mid] > target_area) hi = mid;
+            else lo = mid + 1;
+        }
+        {
+            const float* tr = P->tri + 9 * lo;
+            v0 = vload(tr);
+            e1 = vsub(vload(tr + 3), v0);
+            e2 = vsub(vload(tr + 6), v0);
+        }
+        su = sqrtf(u[1]);
+        b1 = su * (1.0f - u[2]);
+        b2 = su * u[2];
+        xh = mk(fmaf(b1, e1.x, fmaf(b2, e2.x, v0.x)), fmaf(b1, e1.y, fmaf(b2, e2.y, v0.y)),
+                fmaf(b1, e1.z, fmaf(b2, e2.z, v0.z)));
+        o = offset_ray(xs, wall_n);
+        dv = vsub(xh, o);
+        r2 = vdot(dv, dv);
+        r = sqrtf(r2);
+        d = vscale(dv, 1.0f / r);
+        ng = vnormalize(vcross(e1, e2));
+        cos_s0 = vdot(wall_n, d);
+        cos_h = fabsf(vdot(ng, d));
+        if (!(cos_s0 > 0.0f) || !(cos_h > 0.0f)) return 0;
+        g = (cos_s0 * cos_h) / r2;
+        beta = ((sc->wall_albedo * (float)P->area_total) * ORC_INV_PI_F) * g;
+        vmax = R->max_depth - 3;
+        target = xs;
+        forced_k = lo;
+        forced_t = r;
     }
 
     for (v = 1; v <= vmax; ++v) {
@@ -803,7 +887,13 @@ int orc_trace_path(const orc_prepared* P, const orc_render* R, uint32_t pix, uin
         v3 x, n, wo, dl, wl;
         double dn_alb = 0.0, dn_rough = 0.0;
         orc_vertex* vert;
-        hit = closest(P, &ray, prev, &t_hit, &k);
+        if (v == 1 && forced_k >= 0) {
+            hit = 1;
+            k = forced_k;
+            t_hit = forced_t;
+        } else {
+            hit = closest(P, &ray, prev, &t_hit, &k);
+        }
         if (has_medium) {
             float t_ff = -orc_log1m(u_ff) / sc->sigma_t;
             if (!hit || t_ff < t_hit) {
@@ -1093,6 +1183,17 @@ static int run_jobs(job_t* base, int nthreads, void* (*fn)(void*))
     return 0;
 }
 
+/* Area sampling of the hidden vertex is defined for the three-bounce
+ * confocal path (max_depth 4: one hidden vertex, whose visibility is the
+ * shadow test back to the scan point) without a participating medium. */
+static int render_ok(const orc_prepared* P, const orc_render* R)
+{
+    if (!P || !R || R->spp <= 0 || R->max_depth < 1) return 0;
+    if (!R->nlos_area) return 1;
+    return P->sc.sensor == ORC_SENSOR_CONFOCAL && R->max_depth == 4 && !(P->sc.sigma_t > 0.0f) &&
+           P->area_total > 0.0;
+}
+
 int orc_render_film(const orc_prepared* P, const orc_render* R, const int32_t* pixels, int n_pix,
                     double* film, double* steady, double* oow, int nthreads)
 {
@@ -1100,7 +1201,7 @@ int orc_render_film(const orc_prepared* P, const orc_render* R, const int32_t* p
     int i;
     size_t T = (size_t)P->sc.n_bins;
     double inv_n;
-    if (!P || !R || R->spp <= 0 || R->max_depth < 1) return -1;
+    if (!render_ok(P, R)) return -1;
     memset(&J, 0, sizeof(J));
     J.P = P; J.R = R; J.pixels = pixels; J.n_pix = n_pix;
     J.film = film; J.steady = steady; J.oow = oow;
@@ -1127,7 +1228,7 @@ int orc_render_tangent(const orc_prepared* P, const orc_render* R, const int32_t
     int i;
     size_t b, T = (size_t)P->sc.n_bins;
     double inv_n;
-    if (!P || !R || R->spp <= 0 || R->max_depth < 1 || !film || !dfilm) return -1;
+    if (!render_ok(P, R) || !film || !dfilm) return -1;
     memset(&J, 0, sizeof(J));
     J.P = P; J.R = R; J.pixels = pixels; J.n_pix = n_pix;
     J.v_alb = v_alb; J.v_rough = v_rough; J.film = film; J.dfilm = dfilm; J.steady = steady;
@@ -1153,7 +1254,7 @@ int orc_render_phasor(const orc_prepared* P, const orc_render* R, const int32_t*
     int i;
     size_t k, n2 = 2 * (size_t)n_freq;
     double inv_n;
-    if (!P || !R || R->spp <= 0 || R->max_depth < 1 || n_freq < 1 || !freqs || !phasor) return -1;
+    if (!render_ok(P, R) || n_freq < 1 || !freqs || !phasor) return -1;
     memset(&J, 0, sizeof(J));
     J.P = P; J.R = R; J.pixels = pixels; J.n_pix = n_pix;
     J.freqs = freqs; J.n_freq = n_freq; J.phasor = phasor; J.steady = steady;
@@ -1176,7 +1277,7 @@ int orc_backward(const orc_prepared* P, const orc_render* R, const int32_t* pixe
     double *ga_all, *gr_all;
     pthread_t th[256];
     job_t jobs[256];
-    if (!P || !R || R->spp <= 0 || R->max_depth < 1) return -1;
+    if (!render_ok(P, R)) return -1;
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
     memset(&J, 0, sizeof(J));

@@ -48,6 +48,7 @@ typedef struct {
     int frozen_proposal;      /* GGX: sample with scene roughness, evaluate with `roughness` */
     const float* albedo;      /* optional per-triangle overrides */
     const float* roughness;
+    int nlos_area;            /* confocal: area-sample the hidden vertex (Sec. 4.5) */
 } orc_render;
 
 typedef struct {
@@ -67,6 +68,7 @@ typedef struct orc_prepared orc_prepared;
 orc_prepared* orc_prepare(const orc_scene* sc);
 void orc_release(orc_prepared* p);
 float orc_pad(const orc_prepared* p);
+double orc_area_total(const orc_prepared* p);
 
 int orc_trace_path(const orc_prepared* p, const orc_render* r, uint32_t pix, uint32_t sample, orc_path* rec);
 int orc_render_film(const orc_prepared* p, const orc_render* r, const int32_t* pixels, int n_pix,

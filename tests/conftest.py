@@ -16,6 +16,8 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def oracle_mod():
     import oracle
-    if not os.path.exists(oracle.LIB_PATH):
+    stale = (not os.path.exists(oracle.LIB_PATH) or
+             os.path.getmtime(oracle.LIB_PATH) < os.path.getmtime(oracle.SRC_PATH))
+    if stale:
         oracle.build()
     return oracle

@@ -1,0 +1,83 @@
+"""Pins of the oracle's NLOS area sampling (confocal, Sec. 4.5): the hidden
+vertex drawn uniformly by area and connected to the scan point.
+
+* A square plane z = d centred in front of the scan point: every OPL bin
+  whose radius stays inside the square's inscribed circle receives the disk
+  closed form K pi d^4 / 3 (r_a^-6 - r_b^-6) / pi = K/(3 d^2) (mu_a^6 - mu_b^6),
+  K = rho_w^2 rho_h Phi / pi^2 (mu = d / r, OPL = 2 r); area sampling and the
+  (separately pinned) cosine sampling both match it.
+* On the blob scene the two estimators agree in expectation (steady image).
+* The sampling set excludes the relay wall: its area is the blob's alone.
+"""
+import math
+
+import numpy as np
+
+from paper_2510_25660_amd import scenes
+
+
+def _plane():
+    d, width, start = 0.4, 0.0024, 0.7
+    sc = scenes.parallel_plane_confocal(d=d, half=0.5, grid=1, n_bins=512, bin_width=width, bin_start=start,
+                                        spp=16384)
+    return sc, d, width, start
+
+
+def test_area_sampling_matches_disk_closed_form(oracle_mod):
+    sc, d, width, start = _plane()
+    O = oracle_mod.Oracle(sc)
+    films = np.array([O.render(seed=1000 + i, nlos_area=True)[0][0] for i in range(8)])
+    group = 16
+    g = films.reshape(len(films), -1, group).sum(2)
+    mean, sem = g.mean(0), g.std(0, ddof=1) / math.sqrt(len(g))
+    edges = start + width * group * np.arange(g.shape[1] + 1)
+    ra, rb = edges[:-1] / 2.0, edges[1:] / 2.0
+    K = 1.0 * 1.0 * 0.7 * 1.0 / math.pi**2
+    mu_a, mu_b = np.minimum(1.0, d / np.maximum(ra, 1e-9)), np.minimum(1.0, d / rb)
+    expect = K / (3 * d**2) * (mu_a**6 - mu_b**6)
+    inside = (rb <= math.sqrt(0.5**2 + d**2) - 1e-9) & (np.sqrt(np.maximum(rb**2 - d**2, 0)) <= 0.5)
+    m = inside & (expect > 1e-3 * expect.max())
+    assert m.sum() >= 8
+    z = np.abs(mean[m] - expect[m]) / (sem[m] + 1e-4 * expect[m])
+    assert (z < 5).all(), z.max()
+    # causality: nothing before the first return at OPL 2d
+    b0 = int(math.floor((2 * d - start) / width))
+    assert (films[:, :b0] == 0).all() and (films[:, b0] > 0).all()
+
+
+def test_area_and_cosine_sampling_agree(oracle_mod):
+    """Same expectation on the blob: per-pixel steady images over 4 seeds,
+    compared with the pooled standard error of the two estimators."""
+    sc = scenes.confocal_nlos(grid=4, spp=8192)
+    O = oracle_mod.Oracle(sc)
+    a = np.array([O.render(seed=50 + i, nlos_area=True)[1] for i in range(4)])
+    c = np.array([O.render(seed=90 + i)[1] for i in range(4)])
+    se = np.sqrt(a.var(0, ddof=1) / len(a) + c.var(0, ddof=1) / len(c))
+    z = np.abs(a.mean(0) - c.mean(0)) / (se + 1e-3 * c.mean(0))
+    assert (z < 5).all(), z.max()
+    # area sampling: every sample of a scan point that sees the blob counts
+    assert a.std(0).mean() < c.std(0).mean()
+
+
+def test_sampling_set_excludes_the_wall(oracle_mod):
+    sc = scenes.confocal_nlos(grid=4)
+    O = oracle_mod.Oracle(sc)
+    tri = sc.triangles().astype(np.float64).reshape(-1, 3, 3)
+    area = 0.5 * np.linalg.norm(np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0]), axis=1)
+    wall = np.all(np.abs(tri[:, :, 2]) < 1e-9, axis=1)
+    assert wall.sum() == 2
+    total = oracle_mod.lib().orc_area_total(O._h)
+    assert abs(total - area[~wall].sum()) <= 1e-12 * total
+
+
+def test_area_sampling_domain(oracle_mod):
+    """Defined for the three-bounce confocal path only: other depths and the
+    other sensors are rejected."""
+    import pytest
+    O = oracle_mod.Oracle(scenes.confocal_nlos(grid=2, spp=4))
+    O.render(nlos_area=True, max_depth=4)
+    with pytest.raises(ValueError):
+        O.render(nlos_area=True, max_depth=5)
+    P = oracle_mod.Oracle(scenes.box_scene(width=4, height=4, spp=2))
+    with pytest.raises(ValueError):
+        P.render(nlos_area=True)
