@@ -205,6 +205,7 @@ def main():
     ap.add_argument("--builder", default="ploc", choices=["ploc", "lbvh"])
     ap.add_argument("--phasor-freqs", type=int, default=16,
                     help="also time the frequency-space film with this many frequencies (0: skip)")
+    ap.add_argument("--no-nlos-area", action="store_true", help="skip the NLOS area-sampling measurement")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a device copy of this many MiB (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -253,6 +254,28 @@ def main():
                                   args.steps, args.warmup)
             phasor = {"n_freq": len(freqs), "freq_range_per_m": [0.5, 16.6], "ms_per_step": round(ms / args.steps, 4),
                       "mpaths_per_s": round(paths / (ms / args.steps * 1e-3) / 1e6, 3)}
+        nlos = None
+        if sc.sensor == 1 and sc.max_depth == 4 and not args.no_nlos_area:
+            # NLOS area sampling of the hidden vertex (Sec. 4.5) on the same
+            # scan: its rate, and the variance of the steady image relative
+            # to the default cosine sampling at equal spp (from the squared
+            # differences of two independent renders of each estimator)
+            ms, _ = time_launches(lambda: tr.render_transient(dev, film=film, steady=steady, nlos_area=True),
+                                  args.steps, args.warmup)
+            ms_path, _ = time_launches(lambda: tr.render_transient(dev, film=film, steady=steady, nlos_area=True,
+                                                                   kernel="path"), args.steps, args.warmup)
+            _, _, area_counts = tr.render_transient_counted(dev, nlos_area=True)
+            diff = []
+            for area in (True, False):
+                a = tr.render_transient(dev, seed=11, nlos_area=area)[0].double()
+                b = tr.render_transient(dev, seed=12, nlos_area=area)[0].double()
+                diff.append(float(((a - b) ** 2).mean()))
+            nlos = {"ms_per_step": round(ms / args.steps, 4),
+                    "mpaths_per_s": round(paths / (ms / args.steps * 1e-3) / 1e6, 3),
+                    "path_form_mpaths_per_s": round(paths / (ms_path / args.steps * 1e-3) / 1e6, 3),
+                    "variance_vs_cosine": round(diff[0] / diff[1], 5),
+                    "efficiency_vs_cosine": round((diff[1] / diff[0]) * (total_ms / ms), 3),
+                    "counts": area_counts}
     ms_per_step = total_ms / args.steps
     value = paths / (ms_per_step * 1e-3) / 1e6
     launch_ms = float(np.mean(per))
@@ -286,6 +309,8 @@ def main():
         out["kernel_forms_mpaths_per_s"] = forms
     if phasor:
         out["phasor_film"] = phasor
+    if nlos:
+        out["nlos_area_sampling"] = nlos
     if not args.no_backward:
         ratio, f_ms, b_ms, rep_ms, t_ms = backward_forward_ratio(tr)
         out["backward_forward_ratio"] = round(ratio, 3)

@@ -54,9 +54,34 @@ enum { TRHIP_MAT_LAMBERT = 0, TRHIP_MAT_GGX = 1 };
 enum {
     TRHIP_FLAG_PIXEL_CENTRE = 1u << 0,    /* no sub-pixel jitter (pinhole) */
     TRHIP_FLAG_ACCUMULATE = 1u << 1,      /* add into the output buffers instead of overwriting */
-    TRHIP_FLAG_FROZEN_PROPOSAL = 1u << 2  /* GGX: sample with the scene's roughness, evaluate
+    TRHIP_FLAG_FROZEN_PROPOSAL = 1u << 2, /* GGX: sample with the scene's roughness, evaluate
                                              with roughness_override (finite-difference mode) */
+    TRHIP_FLAG_NLOS_AREA_SAMPLING = 1u << 3 /* confocal: area-sample the hidden vertex (below) */
 };
+
+/*
+ * TRHIP_FLAG_NLOS_AREA_SAMPLING -- sampling specific to non-line-of-sight
+ * scenes (Sec. 4.5 adds NLOS-tailored samplers from the work it cites; this
+ * is the area-sampling one, which aims every path at the hidden geometry
+ * instead of the hemisphere above the relay wall).  The first path vertex
+ * after the scan point is drawn uniformly by area over the scene's triangles
+ * that do not lie in the relay wall's plane (the plane through the first
+ * scan point with normal wall_normal, within 1e-6 * (1 + largest |vertex
+ * coordinate|)): the triangle with probability proportional to its FP64
+ * area, the point by the square-root warp of two uniforms.  The vertex
+ * carries the weight wall_albedo / pi * cos_wall * cos_hidden / r^2 * A,
+ * A the sampling set's area; its visibility is the next-event shadow test
+ * back to the scan point, which runs along the same segment.  The estimate
+ * has the expectation of the default (cosine-sampled) render.
+ * Valid for the confocal sensor with max_depth == 4 (the three-bounce
+ * path, whose only hidden vertex is the sampled one) and no medium
+ * (sigma_t == 0); any kernel form but TRHIP_KERNEL_WAVEFRONT (the deferred
+ * form, the automatic choice, orders each batch of samples by the BVH
+ * position of the sampled triangle, so that a wave's shadow rays leave one
+ * region of the hidden surface).  Anything else returns
+ * TRHIP_ERR_UNSUPPORTED, as does a scene whose sampling set is empty.  Accepted by trhip_render_transient,
+ * _counted, _phasor, _tangent and _backward; not by the batch API.
+ */
 
 /*
  * Scene description (all pointers are HOST pointers, read during

@@ -20,14 +20,15 @@ from typing import Optional
 import numpy as np
 
 from . import scenes
-from ._binding import (FLAG_ACCUMULATE, FLAG_FROZEN_PROPOSAL, FLAG_PIXEL_CENTRE, BatchInfo, BatchOpts, RenderDesc,
-                       SceneDesc, SceneInfo, TrhipError, check, lib)
+from ._binding import (FLAG_ACCUMULATE, FLAG_FROZEN_PROPOSAL, FLAG_NLOS_AREA_SAMPLING, FLAG_PIXEL_CENTRE, BatchInfo,
+                       BatchOpts, RenderDesc, SceneDesc, SceneInfo, TrhipError, check, lib)
 
 __all__ = [
     "scenes", "upload", "DeviceScene", "render_transient", "render_transient_backward", "render_transient_counted",
     "render_transient_tangent", "render_phasor", "poisson_noise",
     "TransientRender", "Batch",
-    "TrhipError", "FLAG_PIXEL_CENTRE", "FLAG_ACCUMULATE", "FLAG_FROZEN_PROPOSAL", "version",
+    "TrhipError", "FLAG_PIXEL_CENTRE", "FLAG_ACCUMULATE", "FLAG_FROZEN_PROPOSAL", "FLAG_NLOS_AREA_SAMPLING",
+    "version",
 ]
 
 
@@ -147,7 +148,7 @@ def _ptr(t) -> Optional[int]:
 
 def make_render_desc(dev: DeviceScene, spp=None, seed=None, max_depth=None, sample_offset=0, norm_spp=0,
                      stream_id=0, pixel_centre=False, accumulate=False, frozen=False, albedo=None,
-                     roughness=None, tile_pixels=0, block_size=0, kernel="auto") -> RenderDesc:
+                     roughness=None, tile_pixels=0, block_size=0, kernel="auto", nlos_area=False) -> RenderDesc:
     sc = dev.scene
     r = RenderDesc()
     r.spp = int(sc.spp if spp is None else spp)
@@ -157,7 +158,7 @@ def make_render_desc(dev: DeviceScene, spp=None, seed=None, max_depth=None, samp
     r.seed = int(sc.seed if seed is None else seed)
     r.stream_id = int(stream_id)
     r.flags = ((FLAG_PIXEL_CENTRE if pixel_centre else 0) | (FLAG_ACCUMULATE if accumulate else 0)
-               | (FLAG_FROZEN_PROPOSAL if frozen else 0))
+               | (FLAG_FROZEN_PROPOSAL if frozen else 0) | (FLAG_NLOS_AREA_SAMPLING if nlos_area else 0))
     r.albedo_override = _ptr(albedo)
     r.roughness_override = _ptr(roughness)
     r.tile_pixels = int(tile_pixels)

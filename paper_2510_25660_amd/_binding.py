@@ -19,6 +19,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "OOM", 3: "HIP", 4: "UNSUPPORTED",
 FLAG_PIXEL_CENTRE = 1 << 0
 FLAG_ACCUMULATE = 1 << 1
 FLAG_FROZEN_PROPOSAL = 1 << 2
+FLAG_NLOS_AREA_SAMPLING = 1 << 3
 
 BUILDERS = {"ploc": 0, "lbvh": 1}
 

@@ -65,6 +65,11 @@ struct trhip_scene {
     float* d_rough;
     float* d_scan;
     double* d_grad;  // 2 * n_tris doubles of backward workspace
+    double* d_area_cdf;      // confocal: NLOS area-sampling prefix sums (caller order)
+    uint32_t* d_sorted_of;   // confocal: BVH-order index of each caller triangle
+    uint32_t* d_area_guide;  // confocal: guide table of the prefix sums
+    uint32_t guide_cells;
+    double area_total;
     uint32_t n_pixels;
     size_t device_bytes;
 };
@@ -97,6 +102,9 @@ void free_scene(trhip_scene* s)
     (void)hipFree(s->d_rough);
     (void)hipFree(s->d_scan);
     (void)hipFree(s->d_grad);
+    (void)hipFree(s->d_area_cdf);
+    (void)hipFree(s->d_sorted_of);
+    (void)hipFree(s->d_area_guide);
     s->magic = 0;
     delete s;
 }
@@ -162,6 +170,66 @@ trhip_status validate_desc(const trhip_scene_desc* d, std::vector<float>& tri9)
     return TRHIP_OK;
 }
 
+// Sampling weights of NLOS area sampling, accumulated in caller order into
+// cdf: the FP64 area of every triangle (differences of FP32 coordinates are
+// exact in FP64), 0 for a triangle whose three vertices lie in the relay
+// wall's plane -- the plane through scan point s0 with normal wn, within
+// 1e-6 * (1 + largest |coordinate|) -- since seen from a scan point it
+// subtends no solid angle.  Returns the total.
+double area_prefix_sums(const std::vector<float>& tri9, uint32_t nt, const float* s0, const float* wn,
+                        std::vector<double>& cdf)
+{
+#pragma clang fp contract(off)
+    float maxabs = 0.0f;
+    for (const float c : tri9) maxabs = std::max(maxabs, std::fabs(c));
+    const double tol = 1e-6 * (1.0 + (double)maxabs);
+    cdf.resize(nt);
+    double acc = 0.0;
+    for (uint32_t k = 0; k < nt; ++k) {
+        const float* t = &tri9[9ull * k];
+        bool on_wall = true;
+        for (int j = 0; j < 3; ++j) {
+            const double h = ((double)t[3 * j] - (double)s0[0]) * (double)wn[0] +
+                             ((double)t[3 * j + 1] - (double)s0[1]) * (double)wn[1] +
+                             ((double)t[3 * j + 2] - (double)s0[2]) * (double)wn[2];
+            if (std::fabs(h) > tol) on_wall = false;
+        }
+        double w = 0.0;
+        if (!on_wall) {
+            double e1[3], e2[3];
+            for (int a = 0; a < 3; ++a) {
+                e1[a] = (double)t[3 + a] - (double)t[a];
+                e2[a] = (double)t[6 + a] - (double)t[a];
+            }
+            const double cx = e1[1] * e2[2] - e1[2] * e2[1];
+            const double cy = e1[2] * e2[0] - e1[0] * e2[2];
+            const double cz = e1[0] * e2[1] - e1[1] * e2[0];
+            w = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+        }
+        acc += w;
+        cdf[k] = acc;
+    }
+    return acc;
+}
+
+// Guide table of the prefix sums (cutpoint method): cells = the smallest
+// power of two >= nt, at most 2^22; guide[m] = first k with
+// cdf[k] > (m / cells) * total, or nt - 1 if none, for m = 0 .. cells.
+uint32_t area_guide(const std::vector<double>& cdf, double total, std::vector<uint32_t>& guide)
+{
+    const uint32_t nt = (uint32_t)cdf.size();
+    uint32_t cells = 1;
+    while (cells < nt && cells < (1u << 22)) cells <<= 1;
+    guide.resize(cells + 1ull);
+    uint32_t k = 0;
+    for (uint32_t m = 0; m <= cells; ++m) {
+        const double t = ((double)m / (double)cells) * total;
+        while (k < nt - 1 && !(cdf[k] > t)) ++k;
+        guide[m] = k;
+    }
+    return cells;
+}
+
 template <class T>
 hipError_t upload(T** dst, const T* src, size_t n, hipStream_t s)
 {
@@ -207,6 +275,11 @@ void fill_view(trhip_scene* s, const trhip_scene_desc* d)
     v.bin_width = d->bin_width;
     v.bin_start = d->bin_start;
     v.unwarp = d->camera_unwarp ? 1 : 0;
+    v.area_cdf = s->d_area_cdf;
+    v.sorted_of = s->d_sorted_of;
+    v.area_total = s->area_total;
+    v.area_guide = s->d_area_guide;
+    v.guide_cells = (float)s->guide_cells;
 }
 
 trhip_status validate_render(const trhip_scene* s, const trhip_render_desc* r)
@@ -218,9 +291,21 @@ trhip_status validate_render(const trhip_scene* s, const trhip_render_desc* r)
         return fail(TRHIP_ERR_INVALID_ARG, "sample index range exceeds 32 bits");
     if (r->block_size != 0 && (r->block_size % 64 != 0 || r->block_size > kMaxBlock))
         return fail(TRHIP_ERR_INVALID_ARG, "block_size must be a multiple of 64 and <= %u", kMaxBlock);
-    if (r->flags & ~(uint32_t)(TRHIP_FLAG_PIXEL_CENTRE | TRHIP_FLAG_ACCUMULATE | TRHIP_FLAG_FROZEN_PROPOSAL))
+    if (r->flags & ~(uint32_t)(TRHIP_FLAG_PIXEL_CENTRE | TRHIP_FLAG_ACCUMULATE | TRHIP_FLAG_FROZEN_PROPOSAL |
+                               TRHIP_FLAG_NLOS_AREA_SAMPLING))
         return fail(TRHIP_ERR_INVALID_ARG, "unknown flag bits");
     if (r->kernel > TRHIP_KERNEL_DEFERRED) return fail(TRHIP_ERR_INVALID_ARG, "unknown kernel %u", r->kernel);
+    if (r->flags & TRHIP_FLAG_NLOS_AREA_SAMPLING) {
+        if (s->view.sensor != TRHIP_SENSOR_CONFOCAL)
+            return fail(TRHIP_ERR_UNSUPPORTED, "NLOS area sampling needs the confocal sensor");
+        if (r->max_depth != 4)
+            return fail(TRHIP_ERR_UNSUPPORTED, "NLOS area sampling is defined for max_depth 4 (three bounces)");
+        if (s->view.sigma_t > 0.0f) return fail(TRHIP_ERR_UNSUPPORTED, "NLOS area sampling excludes media");
+        if (!(s->area_total > 0.0))
+            return fail(TRHIP_ERR_UNSUPPORTED, "NLOS area sampling: no triangle off the relay wall's plane");
+        if (r->kernel == TRHIP_KERNEL_WAVEFRONT)
+            return fail(TRHIP_ERR_UNSUPPORTED, "the wavefront form has no NLOS area sampling");
+    }
     return TRHIP_OK;
 }
 
@@ -341,12 +426,22 @@ trhip_status trhip_scene_create(const trhip_scene_desc* desc, void* stream, trhi
     if (e == hipSuccess) e = upload(&sc->d_mat, desc->mat_type, nt, s);
     if (e == hipSuccess) e = upload(&sc->d_albedo, desc->albedo, nt, s);
     if (e == hipSuccess) e = upload(&sc->d_rough, desc->roughness, nt, s);
-    if (e == hipSuccess && desc->sensor == TRHIP_SENSOR_CONFOCAL)
+    std::vector<double> cdf;
+    std::vector<uint32_t> guide;
+    if (e == hipSuccess && desc->sensor == TRHIP_SENSOR_CONFOCAL) {
         e = upload(&sc->d_scan, desc->scan_points, 3ull * sc->n_pixels, s);
+        sc->area_total = area_prefix_sums(tri9, nt, desc->scan_points, desc->wall_normal, cdf);
+        sc->guide_cells = area_guide(cdf, sc->area_total, guide);
+        if (e == hipSuccess) e = upload(&sc->d_area_cdf, cdf.data(), nt, s);
+        if (e == hipSuccess) e = upload(&sc->d_area_guide, guide.data(), guide.size(), s);
+        if (e == hipSuccess) e = hipMalloc(&sc->d_sorted_of, (size_t)nt * sizeof(uint32_t));
+    }
     if (e == hipSuccess) e = hipMalloc(&sc->d_grad, 2ull * nt * sizeof(double));
     if (e == hipSuccess)
         e = trhip::build_bvh(d_tri9, nt, desc->bvh_builder == TRHIP_BVH_LBVH ? trhip::kBuilderLbvh : trhip::kBuilderPloc,
                              s, &sc->bvh);
+    if (e == hipSuccess && sc->d_sorted_of) e = trhip::launch_sorted_of(sc->bvh.tris, nt, sc->d_sorted_of, s);
+    if (e == hipSuccess && sc->d_sorted_of) e = hipStreamSynchronize(s);
     (void)hipFree(d_tri9);
     if (e != hipSuccess) {
         free_scene(sc);
@@ -359,7 +454,7 @@ trhip_status trhip_scene_create(const trhip_scene_desc* desc, void* stream, trhi
         g_live.insert(sc);
     }
     sc->device_bytes = (size_t)sc->bvh.n_internal * sizeof(trhip::BvhNode) + (size_t)nt * sizeof(trhip::TriRec) +
-                       (size_t)nt * (1 + 4 + 4 + 16) + (sc->d_scan ? 12ull * sc->n_pixels : 0);
+                       (size_t)nt * (1 + 4 + 4 + 16) + (sc->d_scan ? 12ull * sc->n_pixels + 12ull * nt + 4ull * (sc->guide_cells + 1) : 0);
     *out = sc;
     return TRHIP_OK;
 }

@@ -525,4 +525,22 @@ done:
     return err;
 }
 
+namespace {
+
+// inverse of the BVH order: out[caller index] = BVH-order index
+__global__ void k_sorted_of(uint32_t n, const TriRec* __restrict__ tris, uint32_t* __restrict__ out)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) out[tris[j].prim] = j;
+}
+
+}  // namespace
+
+hipError_t launch_sorted_of(const TriRec* tris, uint32_t nt, uint32_t* out, hipStream_t stream)
+{
+    if (nt == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sorted_of, dim3((nt + 255) / 256), dim3(256), 0, stream, nt, tris, out);
+    return hipGetLastError();
+}
+
 }  // namespace trhip

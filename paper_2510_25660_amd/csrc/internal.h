@@ -26,6 +26,9 @@ constexpr int kBuilderLbvh = 1;
 // synchronises `stream`.  On failure nothing stays allocated.
 hipError_t build_bvh(const float* d_tri9, uint32_t nt, int builder, hipStream_t stream, BvhBuild* out);
 
+// out[tris[j].prim] = j for the nt triangle records of a built BVH
+hipError_t launch_sorted_of(const TriRec* tris, uint32_t nt, uint32_t* out, hipStream_t stream);
+
 // Traversal stacks hold one BVH link per level.  With at most 32,768
 // triangles every link (internal node index, or ~sorted triangle index)
 // fits in 16 bits, which halves the stacks' LDS; larger scenes use 32 bits.

@@ -359,6 +359,72 @@ __device__ __forceinline__ void begin_path(const SceneView& S, const LaunchArgs&
     ps.v = 1;
 }
 
+// NLOS area sampling (confocal, three bounces; the NLOS-tailored sampling
+// of Sec. 4.5): generation draws the hidden vertex itself, uniformly by area
+// on the triangles off the relay wall's plane -- the triangle through the
+// FP64 prefix sums of the areas (u0), the point by the square-root warp
+// (u1, u2) -- and joins it to the offset scan point.  Converting the area
+// density 1/A to solid angle at the scan point (r^2 / cos_hidden) gives the
+// weight f_wall cos_wall / p = wall_albedo / pi * A * cos_wall cos_hidden /
+// r^2.  The segment's visibility is left to the next-event shadow ray of
+// the vertex, which tests the same segment back to the scan point.  Returns
+// false when the pair faces away (no contribution); otherwise sets ps and
+// the vertex's hit h (distance r, caller and BVH-order triangle).
+// caller index of the area-sampled triangle: the first whose prefix sum
+// exceeds u0 * A, found by bisection between two guide-table entries (the
+// cutpoint method).  With m = floor(u0 * M), m / M <= u0 < (m + 1) / M
+// exactly, and FP64 rounding is monotone, so the thresholds of entries m
+// and m + 1 bracket u0 * A and their first indices bracket the answer.
+// u0 is a multiple of 2^-24 and M a power of two <= 2^22: u0 * M is exact.
+__device__ __forceinline__ uint32_t area_pick(const SceneView& S, float u0)
+{
+    const double target = (double)u0 * S.area_total;
+    const uint32_t m = (uint32_t)(u0 * S.guide_cells);
+    uint32_t lo = S.area_guide[m], hi = S.area_guide[m + 1];
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (S.area_cdf[mid] > target) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool begin_area(const SceneView& S, const LaunchArgs& L, uint32_t pix, uint32_t sample,
+                                           PathState& ps, Hit& h)
+{
+    const rand4 u = draw4(pix, sample, 0u, L.stream_id, L.key0, L.key1);
+    ps.u_ff = u.u2;
+    const uint32_t lo = area_pick(S, u.u0);
+    const uint32_t j = S.sorted_of[lo];
+    const TriRec tr = load_tri(S.tris, j);
+    const vec3 e1 = v3(tr.e1x, tr.e1y, tr.e1z), e2 = v3(tr.e2x, tr.e2y, tr.e2z);
+    const float su = sqrtf(u.u1);
+    const float b1 = su * (1.0f - u.u2), b2 = su * u.u2;
+    const vec3 x = v3(fmaf(b1, e1.x, fmaf(b2, e2.x, tr.v0x)), fmaf(b1, e1.y, fmaf(b2, e2.y, tr.v0y)),
+                      fmaf(b1, e1.z, fmaf(b2, e2.z, tr.v0z)));
+    const vec3 wall_n = ld3(S.wall_n);
+    const vec3 o = nudge(ld3(S.scan + 3ull * pix), wall_n);
+    const vec3 dv = sub(x, o);
+    const float r2 = dot(dv, dv);
+    const float r = sqrtf(r2);
+    const vec3 d = scale(dv, 1.0f / r);
+    const vec3 ng = normalize(cross(e1, e2));
+    const float cos_s = dot(wall_n, d);
+    const float cos_h = fabsf(dot(ng, d));
+    if (!(cos_s > 0.0f) || !(cos_h > 0.0f)) return false;
+    const float g = (cos_s * cos_h) / r2;
+    ps.beta = ((S.wall_albedo * (float)S.area_total) * kInvPi) * g;
+    ps.o = o;
+    ps.d = d;
+    ps.opl = 0.0f;
+    ps.prev = -1;
+    ps.v = 1;
+    h.t = r;
+    h.prim = (int)lo;
+    h.sorted = (int)j;
+    return true;
+}
+
 // Free flight in the medium against the surface hit: returns whether a
 // vertex exists and sets its distance and kind.
 __device__ __forceinline__ bool resolve_event(const SceneView& S, const PathState& ps, const Hit& h, float& t_hit,
@@ -560,6 +626,11 @@ __device__ void trace_path(const SceneView& S, const LaunchArgs& L, uint32_t pix
 {
     tally.add(kTallyDraws);
     PathState ps;
+    if (L.flags & kFlagNlosArea) {
+        Hit h;
+        if (begin_area(S, L, pix, sample, ps, h)) continue_path(S, L, pix, sample, ps, h, stk, stride, sink, tally);
+        return;
+    }
     begin_path(S, L, pix, sample, ps);
     if (last_vertex(S, L) < 1) return;
     const Hit h = closest_hit(S, make_ray(ps.o, ps.d), ps.prev, stk, stride, tally);
@@ -748,6 +819,17 @@ __device__ __forceinline__ uint32_t first_ray_cell(const LaunchArgs& L, uint32_t
     return m;
 }
 
+// sort cell of an area-sampled path: the BVH-order (Morton) position of its
+// hidden triangle, so that a wave's shadow rays leave one patch of the
+// hidden surface toward the same scan point
+__device__ __forceinline__ uint32_t area_cell(const SceneView& S, const LaunchArgs& L, uint32_t pix,
+                                              uint32_t sample)
+{
+    const rand4 u = draw4(pix, sample, 0u, L.stream_id, L.key0, L.key1);
+    const uint32_t j = S.sorted_of[area_pick(S, u.u0)];
+    return (uint32_t)(((uint64_t)j * kDirCells) / S.n_tris);
+}
+
 constexpr int kRefill = 32;
 
 // Closest hits of the sorted first rays [0, nvalid) of a batch, appended
@@ -811,7 +893,10 @@ __device__ __forceinline__ void trace_first_hits(const SceneView& S, const Launc
     }
 }
 
-template <class W, class TallyT>
+// kArea: NLOS area sampling, whose first vertex needs no traversal; the
+// batch is sorted by area_cell and each lane follows the sorted paths
+// directly (phase 1b and 2 in one).
+template <bool kArea, class W, class TallyT>
 __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const LaunchArgs& L, uint32_t p0,
                                                      float* lds_film, const float* freq, const DeferredLds& fh,
                                                      W* stk, int stride, TallyT& tally)
@@ -851,7 +936,8 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
             if (w < work && has_vertex) {
                 const uint32_t pl = w / L.spp;
                 tally.add(kTallyDraws);
-                cell[k] = first_ray_cell(L, p0 + pl, L.sample_offset + (w - pl * L.spp));
+                const uint32_t sample = L.sample_offset + (w - pl * L.spp);
+                cell[k] = kArea ? area_cell(S, L, p0 + pl, sample) : first_ray_cell(L, p0 + pl, sample);
                 atomicAdd(fh.start + cell[k], 1u);
             }
         }
@@ -887,9 +973,32 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
             if (cell[k] != 0xffffffffu)
                 fh.order[fh.start[cell[k]] + atomicAdd(fh.fill + cell[k], 1u)] = base + k * nb + tid;
         __syncthreads();
+        const uint32_t nvalid = fh.count[1];
+        if (kArea) {
+            for (uint32_t jj = tid; jj < nvalid; jj += nb) {
+                const uint32_t wj = fh.order[jj];
+                const uint32_t pl = wj / L.spp;
+                const uint32_t sample = L.sample_offset + (wj - pl * L.spp);
+                if (pl != cur) {
+                    if (cur != 0xffffffffu) {
+                        atomicAdd(tsteady + cur, sink.steady);
+                        atomicAdd(toow + cur, sink.oow);
+                    }
+                    cur = pl;
+                    sink.row = tfilm + (size_t)pl * T;
+                    sink.steady = 0.0f;
+                    sink.oow = 0.0f;
+                }
+                PathState ps;
+                Hit h;
+                if (begin_area(S, L, p0 + pl, sample, ps, h))
+                    continue_path(S, L, p0 + pl, sample, ps, h, stk, stride, sink, tally);
+            }
+            __syncthreads();  // the next batch reuses the order
+            continue;
+        }
         // phase 1b: first rays in cell order; phase 2 whenever the buffer
         // holds a block's worth (or at the end of the tile)
-        const uint32_t nvalid = fh.count[1];
         const bool last_batch = base + batch >= work;
         for (;;) {
             trace_first_hits(S, L, p0, fh, nvalid, stk, stride, tally);
@@ -969,7 +1078,7 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
 
 // Five waves per SIMD (at most 96 VGPRs, a few spilled outside the
 // traversal loops) beat four without spills by 15% on confocal scans.
-template <bool kCount, class W>
+template <bool kCount, class W, bool kArea>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 k_render_deferred(SceneView S, LaunchArgs L, unsigned long long* counts)
 {
@@ -986,7 +1095,7 @@ k_render_deferred(SceneView S, LaunchArgs L, unsigned long long* counts)
     float* after_film = lds + (size_t)TP * film_words(S, L) + 2 * TP;
     const DeferredLds fh = carve_deferred(after_film, blockDim.x);
     W* stk = reinterpret_cast<W*>(after_film + deferred_words(blockDim.x)) + threadIdx.x;
-    render_tile_deferred(S, Lc, tile * TP, lds, s_freq, fh, stk, (int)blockDim.x, tally);
+    render_tile_deferred<kArea>(S, Lc, tile * TP, lds, s_freq, fh, stk, (int)blockDim.x, tally);
     tally.flush(counts);
 }
 
@@ -1033,8 +1142,8 @@ __global__ void __launch_bounds__(256) k_batch(BatchTables B)
         const SceneView* __restrict__ views = B.views;
         const LaunchArgs* __restrict__ args = B.args;
         if (kDeferred)
-            render_tile_deferred(views[scene], args[scene], tile * args[scene].tile_pixels, lds, nullptr, fh, stk,
-                                 (int)blockDim.x, tally);
+            render_tile_deferred<false>(views[scene], args[scene], tile * args[scene].tile_pixels, lds, nullptr, fh,
+                                        stk, (int)blockDim.x, tally);
         else
             render_tile(views[scene], args[scene], tile * args[scene].tile_pixels, lds, nullptr, stk,
                         (int)blockDim.x, tally);
@@ -1617,10 +1726,16 @@ void launch_deferred_w(const SceneView& S, const LaunchArgs& L, uint32_t block, 
                        unsigned long long* counts)
 {
     const dim3 grid(tiles_of(L) * L.chunks);
-    if (counts)
-        hipLaunchKernelGGL((k_render_deferred<true, W>), grid, dim3(block), lds, stream, S, L, counts);
-    else
-        hipLaunchKernelGGL((k_render_deferred<false, W>), grid, dim3(block), lds, stream, S, L, counts);
+    if (L.flags & kFlagNlosArea) {
+        if (counts)
+            hipLaunchKernelGGL((k_render_deferred<true, W, true>), grid, dim3(block), lds, stream, S, L, counts);
+        else
+            hipLaunchKernelGGL((k_render_deferred<false, W, true>), grid, dim3(block), lds, stream, S, L, counts);
+    } else if (counts) {
+        hipLaunchKernelGGL((k_render_deferred<true, W, false>), grid, dim3(block), lds, stream, S, L, counts);
+    } else {
+        hipLaunchKernelGGL((k_render_deferred<false, W, false>), grid, dim3(block), lds, stream, S, L, counts);
+    }
 }
 
 void launch_zero_f32(float* p, size_t n, hipStream_t stream)

@@ -52,6 +52,18 @@ struct SceneView {
     uint32_t n_bins;
     float bin_width, bin_start;
     int32_t unwarp;
+
+    // NLOS area sampling (confocal): inclusive FP64 prefix sums of the
+    // sampling weights in caller order (triangle area, 0 on the relay wall's
+    // plane), their total, and the BVH-order index of each caller triangle;
+    // guide table of the inversion: area_guide[m] is the first triangle
+    // whose prefix sum exceeds (m / guide_cells) * area_total (clamped to
+    // n_tris - 1), m = 0 .. guide_cells; guide_cells a power of two <= 2^22
+    const double* area_cdf;
+    const uint32_t* sorted_of;
+    const uint32_t* area_guide;
+    double area_total;
+    float guide_cells;
 };
 
 constexpr uint32_t kMaxFreq = 32;  // frequencies of one phasor film
@@ -59,6 +71,7 @@ constexpr uint32_t kMaxFreq = 32;  // frequencies of one phasor film
 constexpr uint32_t kFlagPixelCentre = 1u << 0;
 constexpr uint32_t kFlagAccumulate = 1u << 1;
 constexpr uint32_t kFlagFrozen = 1u << 2;
+constexpr uint32_t kFlagNlosArea = 1u << 3;
 
 struct LaunchArgs {
     uint32_t spp, sample_offset, max_depth, stream_id;
