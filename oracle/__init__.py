@@ -59,6 +59,9 @@ class _Scene(C.Structure):
         ("bin_width", C.c_float),
         ("bin_start", C.c_float),
         ("camera_unwarp", C.c_int),
+        ("ior", C.POINTER(C.c_float)),
+        ("delay", C.POINTER(C.c_float)),
+        ("medium_ior", C.c_float),
     ]
 
 
@@ -107,6 +110,8 @@ def lib():
         L.orc_release.argtypes = [C.c_void_p]
         L.orc_pad.restype = C.c_float
         L.orc_pad.argtypes = [C.c_void_p]
+        L.orc_fresnel.restype = C.c_float
+        L.orc_fresnel.argtypes = [C.c_float, C.c_float, C.c_float]
         L.orc_area_total.restype = C.c_double
         L.orc_area_total.argtypes = [C.c_void_p]
         L.orc_trace_path.argtypes = [C.c_void_p, C.POINTER(_Render), C.c_uint32, C.c_uint32, C.POINTER(_Path)]
@@ -278,6 +283,12 @@ class Oracle:
         s.bin_width = scene.bin_width
         s.bin_start = scene.bin_start
         s.camera_unwarp = int(bool(scene.camera_unwarp))
+        ior, delay = getattr(scene, "ior", None), getattr(scene, "delay", None)
+        self._ior = np.ascontiguousarray(ior, np.float32) if ior is not None else None
+        self._delay = np.ascontiguousarray(delay, np.float32) if delay is not None else None
+        s.ior = _fptr(self._ior) if self._ior is not None else None
+        s.delay = _fptr(self._delay) if self._delay is not None else None
+        s.medium_ior = float(getattr(scene, "medium_ior", 1.0))
         self._s = s
         self._h = lib().orc_prepare(C.byref(s))
         if not self._h:

@@ -49,6 +49,7 @@ typedef struct { float x, y, z; } v3;
 
 static v3 mk(float x, float y, float z) { v3 r; r.x = x; r.y = y; r.z = z; return r; }
 static v3 vsub(v3 a, v3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+static v3 vadd(v3 a, v3 b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
 static v3 vscale(v3 a, float s) { return mk(a.x * s, a.y * s, a.z * s); }
 static v3 vneg(v3 a) { return mk(-a.x, -a.y, -a.z); }
 /* dot(a,b) = fma(ax,bx, fma(ay,by, az*bz)) */
@@ -239,6 +240,8 @@ struct orc_prepared {
     float* albedo;
     float* rough;
     float* scan;        /* [n_scan][3] (confocal) */
+    float* ior;         /* [nt] or NULL */
+    float* delay;       /* [nt] or NULL */
     float pad;
     /* BVH (used when nt > ORC_BRUTE_MAX) */
     onode* nodes;
@@ -316,6 +319,8 @@ orc_prepared* orc_prepare(const orc_scene* sc)
     int k, nt = sc->n_tris;
     float maxabs = 0.0f;
     if (nt <= 0 || !sc->tri) return NULL;
+    for (k = 0; k < nt; ++k)
+        if (sc->mat[k] == ORC_MAT_DIELECTRIC && (!sc->ior || !(sc->ior[k] > 0.0f))) return NULL;
     P = (struct orc_prepared*)calloc(1, sizeof(*P));
     P->sc = *sc;
     P->tri = (float*)malloc(sizeof(float) * 9 * (size_t)nt);
@@ -332,8 +337,17 @@ orc_prepared* orc_prepare(const orc_scene* sc)
         P->scan = (float*)malloc(sizeof(float) * 3 * ns);
         memcpy(P->scan, sc->scan_points, sizeof(float) * 3 * ns);
     }
+    if (sc->ior) {
+        P->ior = (float*)malloc(sizeof(float) * (size_t)nt);
+        memcpy(P->ior, sc->ior, sizeof(float) * (size_t)nt);
+    }
+    if (sc->delay) {
+        P->delay = (float*)malloc(sizeof(float) * (size_t)nt);
+        memcpy(P->delay, sc->delay, sizeof(float) * (size_t)nt);
+    }
     P->sc.tri = P->tri; P->sc.mat = P->mat; P->sc.albedo = P->albedo;
     P->sc.roughness = P->rough; P->sc.scan_points = P->scan;
+    P->sc.ior = P->ior; P->sc.delay = P->delay;
     /* box padding: (largest |coordinate|) * 2^-16, an exact scaling */
     for (k = 0; k < 9 * nt; ++k) maxabs = fmaxf(maxabs, fabsf(P->tri[k]));
     P->pad = maxabs * 0x1p-16f;
@@ -401,7 +415,7 @@ void orc_release(orc_prepared* P)
 {
     if (!P) return;
     free(P->tri); free(P->box); free(P->mat); free(P->albedo); free(P->rough);
-    free(P->scan); free(P->nodes); free(P->order); free(P->area_cdf);
+    free(P->scan); free(P->nodes); free(P->order); free(P->area_cdf); free(P->ior); free(P->delay);
     free(P);
 }
 
@@ -782,6 +796,62 @@ static float surface_sample(const struct orc_prepared* P, const orc_render* R, i
     }
 }
 
+/* Smooth dielectric interface between the space around the meshes (index
+ * eta_amb) and the inside of triangle k's mesh (index eta_k), the inside
+ * lying against the winding normal ng = e1 x e2.  wo is the direction back
+ * along the arriving ray, n = ng or -ng on wo's side.  The event is
+ * reflection with the unpolarised Fresnel reflectance F (1 beyond the
+ * critical angle), else refraction by Snell's law, each sampled with its own
+ * probability; the weight is 1 for reflection and (eta_i / eta_t)^2 for
+ * refraction, since radiance divided by eta^2 is what crosses the interface
+ * unchanged (times 1 - F).  u0 decides.  Sets the new direction, the
+ * offset origin, the index of the medium the path continues in and whether
+ * that is the inside; returns the weight. */
+/* Unpolarised Fresnel reflectance of light arriving at cosine ci from the
+ * side of index eta_i: the mean of the squared s and p amplitude ratios,
+ * 1 beyond the critical angle; *ct = cosine of the refracted direction. */
+static float fresnel_dielectric(float ci, float eta_i, float eta_t, float* ct)
+{
+    float eta_r = eta_i / eta_t;
+    float st2 = (eta_r * eta_r) * (1.0f - ci * ci);
+    float rs, rp;
+    *ct = 0.0f;
+    if (!(st2 < 1.0f)) return 1.0f;
+    *ct = sqrtf(1.0f - st2);
+    rs = (eta_i * ci - eta_t * *ct) / (eta_i * ci + eta_t * *ct);
+    rp = (eta_t * ci - eta_i * *ct) / (eta_t * ci + eta_i * *ct);
+    return 0.5f * (rs * rs + rp * rp);
+}
+
+float orc_fresnel(float ci, float eta_i, float eta_t)
+{
+    float ct;
+    return fresnel_dielectric(ci, eta_i, eta_t, &ct);
+}
+
+static float dielectric_sample(v3 x, v3 ng, v3 n, v3 wo, float eta_amb, float eta_k, float u0, v3* wi, v3* o,
+                               float* eta_out, int* inside_out)
+{
+    int entering = !(vdot(ng, wo) < 0.0f);
+    float ci = vdot(n, wo);
+    float eta_i = entering ? eta_amb : eta_k, eta_t = entering ? eta_k : eta_amb;
+    float eta_r = eta_i / eta_t;
+    float ct;
+    float F = fresnel_dielectric(ci, eta_i, eta_t, &ct);
+    if (u0 < F) {
+        *wi = vnormalize(vsub(vscale(n, 2.0f * ci), wo));
+        *o = offset_ray(x, n);
+        *inside_out = !entering;
+        *eta_out = eta_i;
+        return 1.0f;
+    }
+    *wi = vnormalize(vadd(vscale(wo, -eta_r), vscale(n, eta_r * ci - ct)));
+    *o = offset_ray(x, vneg(n));
+    *inside_out = entering;
+    *eta_out = eta_t;
+    return eta_r * eta_r;
+}
+
 static void record(orc_path* rec, int tri, float c, float opl_c, const orc_scene* sc,
                    double dn_alb, double dn_rough)
 {
@@ -804,6 +874,12 @@ int orc_trace_path(const orc_prepared* P, const orc_render* R, uint32_t pix, uin
     float u[4], beta, opl = 0.0f, u_ff, forced_t = 0.0f;
     v3 o, d, target, wall_n = vload(sc->wall_normal);
     int prev = -1, vmax, v, forced_k = -1;
+    /* index of the medium the path is in (Eq. 3: a segment's time of flight
+     * is its length times eta) and whether that is a dielectric's inside;
+     * the participating medium fills only the space around the meshes */
+    const float eta_amb = (sc->medium_ior > 0.0f) ? sc->medium_ior : 1.0f;
+    float eta = eta_amb;
+    int inside = 0;
 
     path_reset(rec);
     draw(R, pix, sample, 0, u);
@@ -884,7 +960,7 @@ int orc_trace_path(const orc_prepared* P, const orc_render* R, uint32_t pix, uin
         ray_t ray = make_ray(o, d);
         float t_hit = INFINITY, seg, fcos, em, cos_s;
         int k = -1, hit, medium_event = 0;
-        v3 x, n, wo, dl, wl;
+        v3 x, n, wo, dl, wl, ng = mk(0.0f, 0.0f, 0.0f);
         double dn_alb = 0.0, dn_rough = 0.0;
         orc_vertex* vert;
         if (v == 1 && forced_k >= 0) {
@@ -894,7 +970,7 @@ int orc_trace_path(const orc_prepared* P, const orc_render* R, uint32_t pix, uin
         } else {
             hit = closest(P, &ray, prev, &t_hit, &k);
         }
-        if (has_medium) {
+        if (has_medium && !inside) {
             float t_ff = -orc_log1m(u_ff) / sc->sigma_t;
             if (!hit || t_ff < t_hit) {
                 medium_event = 1;
@@ -904,7 +980,7 @@ int orc_trace_path(const orc_prepared* P, const orc_render* R, uint32_t pix, uin
         if (!hit && !medium_event) break;
         seg = t_hit;
         x = vray(o, d, t_hit);
-        if (!(sc->camera_unwarp && !confocal && v == 1)) opl = opl + seg;
+        if (!(sc->camera_unwarp && !confocal && v == 1)) opl = opl + seg * eta;
         wo = vneg(d);
         vert = &rec->v[rec->n_vert++];
         memset(vert, 0, sizeof(*vert));
@@ -930,11 +1006,10 @@ int orc_trace_path(const orc_prepared* P, const orc_render* R, uint32_t pix, uin
                     if (!occluded(P, &sh, -1, dist * SHADOW_SHRINK)) {
                         float c = ((beta * ORC_INV_4PI_F) * em) / d2;
                         c = c * expf(-(sc->sigma_t * dist));
-                        record(rec, -1, c, opl + dist, sc, 0.0, 0.0);
+                        record(rec, -1, c, opl + dist * eta, sc, 0.0, 0.0);
                     }
                 }
             } else {
-                v3 ng;
                 const float* tr = P->tri + 9 * k;
                 v3 e1 = vsub(vload(tr + 3), vload(tr)), e2 = vsub(vload(tr + 6), vload(tr));
                 ng = vnormalize(vcross(e1, e2));
@@ -943,13 +1018,23 @@ int orc_trace_path(const orc_prepared* P, const orc_render* R, uint32_t pix, uin
                     rec->n_vert--;
                     break;
                 }
-                fcos = surface_fcos(P, R, k, n, wo, wl, &dn_alb, &dn_rough);
-                if (fcos > 0.0f && em > 0.0f) {
-                    ray_t sh = make_ray(offset_ray(x, n), wl);
-                    if (!occluded(P, &sh, k, dist * SHADOW_SHRINK)) {
-                        float c = ((beta * fcos) * em) / d2;
-                        if (has_medium) c = c * expf(-(sc->sigma_t * dist));
-                        record(rec, k, c, opl + dist, sc, dn_alb, dn_rough);
+                /* scattering delay (Eq. 10): exponentially distributed with
+                 * the triangle's mean, word 2 of the vertex's Philox block;
+                 * it delays every contribution from this vertex on */
+                if (P->delay && P->delay[k] > 0.0f) {
+                    float ud[4];
+                    draw(R, pix, sample, (uint32_t)v, ud);
+                    opl = opl + P->delay[k] * -orc_log1m(ud[2]);
+                }
+                if (P->mat[k] != ORC_MAT_DIELECTRIC) {
+                    fcos = surface_fcos(P, R, k, n, wo, wl, &dn_alb, &dn_rough);
+                    if (fcos > 0.0f && em > 0.0f) {
+                        ray_t sh = make_ray(offset_ray(x, n), wl);
+                        if (!occluded(P, &sh, k, dist * SHADOW_SHRINK)) {
+                            float c = ((beta * fcos) * em) / d2;
+                            if (has_medium && !inside) c = c * expf(-(sc->sigma_t * dist));
+                            record(rec, k, c, opl + dist * eta, sc, dn_alb, dn_rough);
+                        }
                     }
                 }
             }
@@ -965,6 +1050,16 @@ int orc_trace_path(const orc_prepared* P, const orc_render* R, uint32_t pix, uin
             o = x;
             vert->dc_alb = 0.0;
             vert->dc_rough = 0.0;
+        } else if (P->mat[k] == ORC_MAT_DIELECTRIC) {
+            /* a delta interface: no next-event connection above, no
+             * parameter of the gradients */
+            v3 wi, on;
+            float w = dielectric_sample(x, ng, n, wo, eta_amb, P->ior[k], u[0], &wi, &on, &eta, &inside);
+            vert->has_cont = 1;
+            beta = beta * w;
+            d = wi;
+            o = on;
+            prev = k;
         } else {
             v3 wi;
             double ca, cr;

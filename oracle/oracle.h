@@ -15,6 +15,7 @@ extern "C" {
 #define ORC_SENSOR_CONFOCAL 1
 #define ORC_MAT_LAMBERT 0
 #define ORC_MAT_GGX 1
+#define ORC_MAT_DIELECTRIC 2   /* smooth interface; inside = against e1 x e2 */
 #define ORC_MAX_VERT 64
 
 typedef struct {
@@ -36,6 +37,10 @@ typedef struct {
     int n_bins;
     float bin_width, bin_start;
     int camera_unwarp;
+    /* refractive indices and scattering delays (Eqs. 3 and 10) */
+    const float* ior;         /* [n_tris] index inside dielectric triangles' meshes, or NULL */
+    const float* delay;       /* [n_tris] mean scattering delay (metres of OPL), or NULL = none */
+    float medium_ior;         /* index of the space around the meshes (0 means 1) */
 } orc_scene;
 
 typedef struct {
@@ -69,6 +74,7 @@ orc_prepared* orc_prepare(const orc_scene* sc);
 void orc_release(orc_prepared* p);
 float orc_pad(const orc_prepared* p);
 double orc_area_total(const orc_prepared* p);
+float orc_fresnel(float ci, float eta_i, float eta_t); /* unpolarised dielectric reflectance */
 
 int orc_trace_path(const orc_prepared* p, const orc_render* r, uint32_t pix, uint32_t sample, orc_path* rec);
 int orc_render_film(const orc_prepared* p, const orc_render* r, const int32_t* pixels, int n_pix,

@@ -19,7 +19,8 @@ structure of the paper's use cases (Sec. 3 and Sec. 4):
                           (the backward-mode example of Sec. 4.4);
 * ``batched_nlos``    -- many confocal scenes of uneven size (Sec. 4.5).
 
-Distances are metres of optical path length (c = 1, eta = 1).
+Distances are metres (c = 1): a segment's optical path length is its length
+times the refractive index it runs in.
 """
 from __future__ import annotations
 
@@ -31,6 +32,7 @@ import numpy as np
 
 MAT_LAMBERT = 0
 MAT_GGX = 1
+MAT_DIELECTRIC = 2   # smooth interface; the mesh's inside lies against the winding normal e1 x e2
 
 SENSOR_PINHOLE = 0
 SENSOR_CONFOCAL = 1
@@ -66,6 +68,11 @@ class Scene:
     sigma_t: float = 0.0
     medium_albedo: float = 0.0
     camera_unwarp: bool = False
+    # refractive index inside dielectric meshes (per triangle), scattering
+    # delay means in metres of OPL (per triangle), index of the surrounding space
+    ior: Optional[np.ndarray] = None
+    delay: Optional[np.ndarray] = None
+    medium_ior: float = 1.0
     # default render settings of the workload
     spp: int = 16
     max_depth: int = 4
@@ -125,6 +132,21 @@ def box_mesh(lo, hi):
                   [0, 3, 7], [0, 7, 4],   # x0
                   [1, 5, 6], [1, 6, 2]],  # x1
                  np.int64)
+    return v, f
+
+
+def outward(verts, faces):
+    """Rewinds the triangles of a mesh that is star-shaped about the centroid
+    of the vertices it uses so that every winding normal e1 x e2 points away
+    from it (the orientation a dielectric mesh needs: its inside lies against
+    e1 x e2)."""
+    v = np.asarray(verts, np.float64)
+    f = np.array(faces, np.int64, copy=True)
+    c = v[np.unique(f)].mean(axis=0)
+    t = v[f]
+    nrm = np.cross(t[:, 1] - t[:, 0], t[:, 2] - t[:, 0])
+    flip = np.einsum("ij,ij->i", nrm, t.mean(axis=1) - c) < 0
+    f[flip] = f[flip][:, [0, 2, 1]]
     return v, f
 
 
@@ -511,3 +533,71 @@ CONFIGS = {
     "large": large_scene,
     "diff": diff_scene,
 }
+
+
+# --------------------------------------------------------------------------
+# refractive indices and scattering delays (Eqs. 3 and 10)
+# --------------------------------------------------------------------------
+def glass_tank_scene(ior=1.5, width=16, height=16, n_bins=8192, bin_width=0.001, spp=256) -> Scene:
+    """Closed dielectric box [-2,2]^2 x [-1,1] (index ior) holding a
+    Lambertian plane z=-0.5 (albedo 0.6) and the point light (0.2, 0.1, 0.3);
+    pinhole at (0.1, -0.05, 3) looking down -z, 30 degree vfov; max_depth 3:
+    the camera ray refracts into the tank and the plane connects to the light
+    inside it."""
+    tank = outward(*box_mesh((-2.0, -2.0, -1.0), (2.0, 2.0, 1.0)))
+    plane = quad([-1.5, -1.5, -0.5], [1.5, -1.5, -0.5], [1.5, 1.5, -0.5], [-1.5, 1.5, -0.5])
+    v, f = merge([tank, plane])
+    mat = np.array([MAT_DIELECTRIC] * 12 + [MAT_LAMBERT] * 2)
+    alb = np.array([1.0] * 12 + [0.6] * 2)
+    cam = look_at([0.1, -0.05, 3.0], [0.1, -0.05, 0.0], [0, 1, 0], 30.0, width, height)
+    return _finish(v, f, mat, alb, np.full(14, 0.3), n_bins=n_bins, bin_width=bin_width, bin_start=0.0,
+                   width=width, height=height, light_pos=(0.2, 0.1, 0.3), light_intensity=1.0,
+                   ior=np.full(14, ior, np.float32), spp=spp, max_depth=3, name="tank", **cam)
+
+
+def glass_slab_scene(ior=1.5, width=16, height=16, n_bins=8192, bin_width=0.001, spp=256) -> Scene:
+    """Dielectric slab [-3,3]^2 x [0.8,1.0] (index ior) over a Lambertian
+    plane z=0 (albedo 0.5); point light (0.3, 0.2, 0.4) between them; pinhole
+    at (0.1, -0.05, 2.5) looking down -z, 30 degree vfov; max_depth 4: the
+    camera ray crosses both faces of the slab before reaching the plane."""
+    slab = outward(*box_mesh((-3.0, -3.0, 0.8), (3.0, 3.0, 1.0)))
+    plane = quad([-4, -4, 0], [4, -4, 0], [4, 4, 0], [-4, 4, 0])
+    v, f = merge([slab, plane])
+    mat = np.array([MAT_DIELECTRIC] * 12 + [MAT_LAMBERT] * 2)
+    alb = np.array([1.0] * 12 + [0.5] * 2)
+    cam = look_at([0.1, -0.05, 2.5], [0.1, -0.05, 0.0], [0, 1, 0], 30.0, width, height)
+    return _finish(v, f, mat, alb, np.full(14, 0.3), n_bins=n_bins, bin_width=bin_width, bin_start=0.0,
+                   width=width, height=height, light_pos=(0.3, 0.2, 0.4), light_intensity=1.0,
+                   ior=np.full(14, ior, np.float32), spp=spp, max_depth=4, name="slab", **cam)
+
+
+def glass_box_scene(ior=1.5, seed: int = BASE_SEED + 12, width=64, height=64, n_bins=256, bin_width=0.01,
+                    spp=16, max_depth=8, delay_mean=0.0) -> Scene:
+    """The box room with its short box made of a dielectric of index ior
+    (the setting of the paper's index-of-refraction example, Sec. 4.4);
+    optionally every room triangle has a scattering delay of mean delay_mean
+    (metres of OPL), the fluorescent-surface case of Eq. 10."""
+    sc = box_scene(seed=seed, width=width, height=height, n_bins=n_bins, bin_width=bin_width, spp=spp,
+                   max_depth=max_depth)
+    nt = sc.n_tris
+    short = slice(10, 22)  # the short box's 12 triangles follow the room's 10
+    v = sc.vertices.astype(np.float64)
+    f = sc.indices.astype(np.int64)
+    _, bf = outward(v, f[short])
+    f = f.copy()
+    f[short] = bf
+    mat = sc.mat_type.copy()
+    mat[short] = MAT_DIELECTRIC
+    ior_a = np.ones(nt, np.float32)
+    ior_a[short] = ior
+    delay = None
+    if delay_mean > 0.0:
+        delay = np.zeros(nt, np.float32)
+        delay[:10] = delay_mean
+    sc.indices = np.ascontiguousarray(f, np.uint32)
+    sc.mat_type = mat
+    sc.ior = ior_a
+    sc.delay = delay
+    sc.name = "glass_box"
+    return sc
+
