@@ -48,7 +48,7 @@ enum {
 };
 
 enum { TRHIP_SENSOR_PINHOLE = 0, TRHIP_SENSOR_CONFOCAL = 1 };
-enum { TRHIP_MAT_LAMBERT = 0, TRHIP_MAT_GGX = 1 };
+enum { TRHIP_MAT_LAMBERT = 0, TRHIP_MAT_GGX = 1, TRHIP_MAT_DIELECTRIC = 2 };
 
 /* render flags */
 enum {
@@ -92,7 +92,29 @@ enum {
  * non-finite triangles are rejected (TRHIP_ERR_INVALID_ARG).
  * Materials per triangle: mat_type (TRHIP_MAT_*), albedo (Lambertian albedo,
  * or the constant reflectance F of the GGX conductor), roughness (GGX alpha,
- * unused for Lambertian).  Albedo must lie in (0, 1], roughness in (0, 1].
+ * unused for Lambertian).  Albedo must lie in (0, 1], roughness in (0, 1]
+ * (both ignored, and not checked, for dielectric triangles).
+ *
+ * Refractive indices and scattering delays (Eqs. 3 and 10):
+ *  - medium_ior: index of the space around the meshes, where the camera,
+ *    the light and the relay wall are (0 means 1); every segment's time of
+ *    flight is its length times the index of the medium it runs in.
+ *  - TRHIP_MAT_DIELECTRIC triangles form closed meshes of a smooth
+ *    dielectric whose inside, of index ior[k], lies on the side opposite to
+ *    the winding normal (v1 - v0) x (v2 - v0): wind them outward.  At such
+ *    a triangle a path reflects with the unpolarised Fresnel reflectance
+ *    (1 beyond the critical angle) or refracts by Snell's law, with weight
+ *    1 or (eta_i / eta_t)^2; there is no next-event connection (a delta
+ *    interface) and no gradient parameter.  Dielectric meshes must not
+ *    overlap or nest (leaving one always returns to medium_ior); a
+ *    participating medium (sigma_t) fills only the space around them, and
+ *    they block shadow rays like any triangle.  ior may be NULL if no
+ *    triangle is dielectric; entries must be finite and in (0, 100].
+ *  - delay (NULL = none): per triangle the mean tau >= 0 (metres of optical
+ *    path) of an exponentially distributed scattering delay: at every
+ *    surface vertex on a triangle with tau > 0 the path's time of flight
+ *    grows by tau * E, E ~ Exp(1) drawn from the vertex's random numbers;
+ *    the delay applies to that vertex's contribution and all later ones.
  *
  * Emitter: an isotropic point light of intensity light_intensity (W/sr) at
  * light_pos (pinhole sensor).  For the confocal sensor the emitter is the
@@ -152,6 +174,10 @@ typedef struct {
     float bin_start;
     int32_t camera_unwarp;
     int32_t bvh_builder;
+
+    const float* ior;       /* [n_triangles] or NULL (see above) */
+    const float* delay;     /* [n_triangles] or NULL */
+    float medium_ior;       /* 0 = 1 */
 } trhip_scene_desc;
 
 enum { TRHIP_BVH_PLOC = 0, TRHIP_BVH_LBVH = 1 };

@@ -95,6 +95,13 @@ def make_scene_desc(sc: "scenes.Scene", builder="ploc"):
     d.camera_unwarp = int(bool(sc.camera_unwarp))
     from ._binding import BUILDERS
     d.bvh_builder = BUILDERS[builder] if isinstance(builder, str) else int(builder)
+    for name in ("ior", "delay"):
+        arr = getattr(sc, name, None)
+        if arr is not None:
+            arr = np.ascontiguousarray(arr, np.float32)
+            keep.append(arr)
+            setattr(d, name, arr.ctypes.data_as(fp))
+    d.medium_ior = float(getattr(sc, "medium_ior", 1.0))
     return d, keep
 
 

@@ -72,6 +72,9 @@ class SceneDesc(C.Structure):
         ("bin_start", C.c_float),
         ("camera_unwarp", C.c_int32),
         ("bvh_builder", C.c_int32),
+        ("ior", C.POINTER(C.c_float)),
+        ("delay", C.POINTER(C.c_float)),
+        ("medium_ior", C.c_float),
     ]
 
 

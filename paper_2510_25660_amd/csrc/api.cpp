@@ -64,6 +64,8 @@ struct trhip_scene {
     float* d_albedo;
     float* d_rough;
     float* d_scan;
+    float* d_ior;    // nullptr: no dielectric triangle
+    float* d_delay;  // nullptr: no scattering delay
     double* d_grad;  // 2 * n_tris doubles of backward workspace
     double* d_area_cdf;      // confocal: NLOS area-sampling prefix sums (caller order)
     uint32_t* d_sorted_of;   // confocal: BVH-order index of each caller triangle
@@ -101,6 +103,8 @@ void free_scene(trhip_scene* s)
     (void)hipFree(s->d_albedo);
     (void)hipFree(s->d_rough);
     (void)hipFree(s->d_scan);
+    (void)hipFree(s->d_ior);
+    (void)hipFree(s->d_delay);
     (void)hipFree(s->d_grad);
     (void)hipFree(s->d_area_cdf);
     (void)hipFree(s->d_sorted_of);
@@ -129,6 +133,8 @@ trhip_status validate_desc(const trhip_scene_desc* d, std::vector<float>& tri9)
         return fail(TRHIP_ERR_INVALID_ARG, "sigma_t must be >= 0");
     if (d->sigma_t > 0.0f && !(d->medium_albedo >= 0.0f && d->medium_albedo <= 1.0f))
         return fail(TRHIP_ERR_INVALID_ARG, "medium_albedo must lie in [0, 1]");
+    if (!(d->medium_ior == 0.0f || (d->medium_ior > 0.0f && d->medium_ior <= 100.0f)))
+        return fail(TRHIP_ERR_INVALID_ARG, "medium_ior must be 0 (= 1) or in (0, 100]");
     if (d->sensor == TRHIP_SENSOR_PINHOLE) {
         if (!finite3(d->cam_origin) || !finite3(d->cam_right) || !finite3(d->cam_up) || !finite3(d->cam_fwd) ||
             !std::isfinite(d->tan_x) || !std::isfinite(d->tan_y))
@@ -160,12 +166,21 @@ trhip_status validate_desc(const trhip_scene_desc* d, std::vector<float>& tri9)
                     cz = e1[0] * e2[1] - e1[1] * e2[0];
         if (cx == 0.0f && cy == 0.0f && cz == 0.0f)
             return fail(TRHIP_ERR_INVALID_ARG, "triangle %u has zero area", k);
-        if (d->mat_type[k] != TRHIP_MAT_LAMBERT && d->mat_type[k] != TRHIP_MAT_GGX)
+        if (d->mat_type[k] != TRHIP_MAT_LAMBERT && d->mat_type[k] != TRHIP_MAT_GGX &&
+            d->mat_type[k] != TRHIP_MAT_DIELECTRIC)
             return fail(TRHIP_ERR_INVALID_ARG, "triangle %u: unknown material %u", k, d->mat_type[k]);
-        if (!(d->albedo[k] > 0.0f && d->albedo[k] <= 1.0f))
-            return fail(TRHIP_ERR_INVALID_ARG, "triangle %u: albedo must lie in (0, 1]", k);
-        if (!(d->roughness[k] > 0.0f && d->roughness[k] <= 1.0f))
-            return fail(TRHIP_ERR_INVALID_ARG, "triangle %u: roughness must lie in (0, 1]", k);
+        if (d->mat_type[k] == TRHIP_MAT_DIELECTRIC) {
+            if (!d->ior) return fail(TRHIP_ERR_INVALID_ARG, "triangle %u is dielectric but ior is NULL", k);
+            if (!(d->ior[k] > 0.0f && d->ior[k] <= 100.0f))
+                return fail(TRHIP_ERR_INVALID_ARG, "triangle %u: ior must lie in (0, 100]", k);
+        } else {
+            if (!(d->albedo[k] > 0.0f && d->albedo[k] <= 1.0f))
+                return fail(TRHIP_ERR_INVALID_ARG, "triangle %u: albedo must lie in (0, 1]", k);
+            if (!(d->roughness[k] > 0.0f && d->roughness[k] <= 1.0f))
+                return fail(TRHIP_ERR_INVALID_ARG, "triangle %u: roughness must lie in (0, 1]", k);
+        }
+        if (d->delay && !(d->delay[k] >= 0.0f && std::isfinite(d->delay[k])))
+            return fail(TRHIP_ERR_INVALID_ARG, "triangle %u: delay must be finite and >= 0", k);
     }
     return TRHIP_OK;
 }
@@ -280,6 +295,9 @@ void fill_view(trhip_scene* s, const trhip_scene_desc* d)
     v.area_total = s->area_total;
     v.area_guide = s->d_area_guide;
     v.guide_cells = (float)s->guide_cells;
+    v.ior = s->d_ior;
+    v.delay = s->d_delay;
+    v.eta0 = d->medium_ior > 0.0f ? d->medium_ior : 1.0f;
 }
 
 trhip_status validate_render(const trhip_scene* s, const trhip_render_desc* r)
@@ -436,6 +454,13 @@ trhip_status trhip_scene_create(const trhip_scene_desc* desc, void* stream, trhi
         if (e == hipSuccess) e = upload(&sc->d_area_guide, guide.data(), guide.size(), s);
         if (e == hipSuccess) e = hipMalloc(&sc->d_sorted_of, (size_t)nt * sizeof(uint32_t));
     }
+    bool any_dielectric = false, any_delay = false;
+    for (uint32_t k = 0; k < nt; ++k) {
+        any_dielectric = any_dielectric || desc->mat_type[k] == TRHIP_MAT_DIELECTRIC;
+        any_delay = any_delay || (desc->delay && desc->delay[k] > 0.0f);
+    }
+    if (e == hipSuccess && any_dielectric) e = upload(&sc->d_ior, desc->ior, nt, s);
+    if (e == hipSuccess && any_delay) e = upload(&sc->d_delay, desc->delay, nt, s);
     if (e == hipSuccess) e = hipMalloc(&sc->d_grad, 2ull * nt * sizeof(double));
     if (e == hipSuccess)
         e = trhip::build_bvh(d_tri9, nt, desc->bvh_builder == TRHIP_BVH_LBVH ? trhip::kBuilderLbvh : trhip::kBuilderPloc,
@@ -454,7 +479,8 @@ trhip_status trhip_scene_create(const trhip_scene_desc* desc, void* stream, trhi
         g_live.insert(sc);
     }
     sc->device_bytes = (size_t)sc->bvh.n_internal * sizeof(trhip::BvhNode) + (size_t)nt * sizeof(trhip::TriRec) +
-                       (size_t)nt * (1 + 4 + 4 + 16) + (sc->d_scan ? 12ull * sc->n_pixels + 12ull * nt + 4ull * (sc->guide_cells + 1) : 0);
+                       (size_t)nt * (1 + 4 + 4 + 16) + (sc->d_scan ? 12ull * sc->n_pixels + 12ull * nt + 4ull * (sc->guide_cells + 1) : 0) +
+                       (sc->d_ior ? 4ull * nt : 0) + (sc->d_delay ? 4ull * nt : 0);
     *out = sc;
     return TRHIP_OK;
 }

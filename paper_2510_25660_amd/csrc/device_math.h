@@ -19,6 +19,7 @@ struct vec3 {
 
 __device__ __forceinline__ vec3 v3(float x, float y, float z) { return vec3{x, y, z}; }
 __device__ __forceinline__ vec3 sub(vec3 a, vec3 b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ vec3 add(vec3 a, vec3 b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
 __device__ __forceinline__ vec3 scale(vec3 a, float s) { return v3(a.x * s, a.y * s, a.z * s); }
 __device__ __forceinline__ vec3 neg(vec3 a) { return v3(-a.x, -a.y, -a.z); }
 // dot = fma(x, x', fma(y, y', z*z'))

@@ -296,6 +296,7 @@ struct PathState {
     float beta;    // throughput
     float opl;     // optical path length so far
     float u_ff;    // uniform of the next free flight
+    float eta;     // index of the medium the ray runs in; negative: inside a dielectric mesh
     int prev;      // caller index of the triangle the ray leaves (-1: none)
     int v;         // index of the vertex the next ray creates (1-based)
 };
@@ -355,6 +356,7 @@ __device__ __forceinline__ void begin_path(const SceneView& S, const LaunchArgs&
         ps.beta = S.wall_albedo;
     }
     ps.opl = 0.0f;
+    ps.eta = S.eta0;
     ps.prev = -1;
     ps.v = 1;
 }
@@ -417,6 +419,7 @@ __device__ __forceinline__ bool begin_area(const SceneView& S, const LaunchArgs&
     ps.o = o;
     ps.d = d;
     ps.opl = 0.0f;
+    ps.eta = S.eta0;
     ps.prev = -1;
     ps.v = 1;
     h.t = r;
@@ -433,7 +436,7 @@ __device__ __forceinline__ bool resolve_event(const SceneView& S, const PathStat
     const bool hit = h.prim >= 0;
     t_hit = h.t;
     med = false;
-    if (S.sigma_t > 0.0f) {
+    if (S.sigma_t > 0.0f && ps.eta > 0.0f) {  // the medium fills the space around the meshes
         const float t_ff = -log_one_minus(ps.u_ff) / S.sigma_t;
         if (!hit || t_ff < t_hit) {
             med = true;
@@ -441,6 +444,42 @@ __device__ __forceinline__ bool resolve_event(const SceneView& S, const PathStat
         }
     }
     return hit || med;
+}
+
+// Smooth dielectric interface (Eq. 3 with an index per medium): the mesh of
+// triangle k has index S.ior[k] inside, the side against its winding normal
+// ng = e1 x e2, and the surrounding space S.eta0 outside.  Reflection with
+// the unpolarised Fresnel reflectance F (1 beyond the critical angle), else
+// refraction by Snell's law, each with its own probability (u0 decides);
+// radiance over eta^2 is what crosses the interface (times 1 - F), so a
+// refraction weighs (eta_i / eta_t)^2 and a reflection 1.  Updates the
+// direction, offset origin, throughput and the medium of ps.
+__device__ __forceinline__ void dielectric_event(const SceneView& S, int k, const vec3& x, const vec3& ng,
+                                                 const vec3& n, const vec3& wo, float u0, PathState& ps)
+{
+    const bool entering = !(dot(ng, wo) < 0.0f);
+    const float ci = dot(n, wo);
+    const float eta_k = S.ior[k];
+    const float eta_i = entering ? S.eta0 : eta_k, eta_t = entering ? eta_k : S.eta0;
+    const float eta_r = eta_i / eta_t;
+    const float st2 = (eta_r * eta_r) * (1.0f - ci * ci);
+    float F = 1.0f, ct = 0.0f;
+    if (st2 < 1.0f) {
+        ct = sqrtf(1.0f - st2);
+        const float rs = (eta_i * ci - eta_t * ct) / (eta_i * ci + eta_t * ct);
+        const float rp = (eta_t * ci - eta_i * ct) / (eta_t * ci + eta_i * ct);
+        F = 0.5f * (rs * rs + rp * rp);
+    }
+    if (u0 < F) {
+        ps.d = normalize(sub(scale(n, 2.0f * ci), wo));
+        ps.o = nudge(x, n);
+        ps.eta = entering ? eta_i : -eta_i;
+    } else {
+        ps.d = normalize(add(scale(wo, -eta_r), scale(n, eta_r * ci - ct)));
+        ps.o = nudge(x, neg(n));
+        ps.beta = ps.beta * (eta_r * eta_r);
+        ps.eta = entering ? -eta_t : eta_t;
+    }
 }
 
 // Everything at one vertex except the two traversals: the next-event
@@ -463,7 +502,10 @@ __device__ __forceinline__ void shade_vertex(const SceneView& S, const LaunchArg
     cont.g_rough = 0.0f;
     const vec3 target = confocal ? ld3(S.scan + 3ull * pix) : ld3(S.light);
     const vec3 x = along(ps.o, ps.d, t_hit);
-    if (!(S.unwarp && !confocal && v == 1)) ps.opl = ps.opl + t_hit;
+    // Eq. 3: a segment's time of flight is its length times the index
+    const float eta = fabsf(ps.eta);
+    const bool outside = ps.eta > 0.0f;
+    if (!(S.unwarp && !confocal && v == 1)) ps.opl = ps.opl + t_hit * eta;
     const vec3 wo = neg(ps.d);
     const vec3 dl = sub(target, x);
     const float d2 = dot(dl, dl);
@@ -476,13 +518,17 @@ __device__ __forceinline__ void shade_vertex(const SceneView& S, const LaunchArg
     } else {
         em = S.intensity;
     }
-    const float opl_c = ps.opl + dist;
-    const float q = (opl_c - S.bin_start) / S.bin_width;
-    nee.bin = (q >= 0.0f && q < (float)S.n_bins) ? (int)q : -1;
-    nee.tof = opl_c;
     nee.sd = wl;
     nee.tmax = dist * kShadowShrink;
+    // time of the connected path and its bin (after this vertex's delay)
+    auto bin_of = [&]() {
+        const float opl_c = ps.opl + dist * eta;
+        const float q = (opl_c - S.bin_start) / S.bin_width;
+        nee.bin = (q >= 0.0f && q < (float)S.n_bins) ? (int)q : -1;
+        nee.tof = opl_c;
+    };
     if (med) {
+        bin_of();
         ps.beta = ps.beta * S.medium_albedo;
         if (em > 0.0f) {
             float c = ((ps.beta * kInv4Pi) * em) / d2;
@@ -517,7 +563,37 @@ __device__ __forceinline__ void shade_vertex(const SceneView& S, const LaunchArg
     const vec3 n = (dot(ng, wo) < 0.0f) ? neg(ng) : ng;
     if (!(dot(n, wo) > 0.0f)) return;
     const int k = h.prim;
-    const bool ggx = S.mat[k] == 1;
+    // Eq. 10: a scattering delay, exponential with the triangle's mean, from
+    // word 2 of the vertex's Philox block; it delays this vertex's
+    // contribution and every later one
+    rand4 u;
+    bool have_u = false;
+    if (S.delay) {
+        const float tau = S.delay[k];
+        if (tau > 0.0f) {
+            tally.add(kTallyDraws);
+            u = draw4(pix, sample, (uint32_t)v, L.stream_id, L.key0, L.key1);
+            have_u = true;
+            ps.opl = ps.opl + tau * -log_one_minus(u.u2);
+        }
+    }
+    bin_of();
+    const uint32_t mat = S.mat[k];
+    if (mat == kMatDielectric) {
+        // a delta interface: no next-event connection, no gradient factor
+        if (v == vmax) return;
+        if (!have_u) {
+            tally.add(kTallyDraws);
+            u = draw4(pix, sample, (uint32_t)v, L.stream_id, L.key0, L.key1);
+        }
+        dielectric_event(S, k, x, ng, n, wo, u.u0, ps);
+        cont.alive = true;
+        ps.prev = k;
+        ps.u_ff = u.u3;
+        ps.v = v + 1;
+        return;
+    }
+    const bool ggx = mat == 1;
     const float albedo = L.albedo[k];
     vec3 tb, bb;
     basis(n, tb, bb);
@@ -541,7 +617,7 @@ __device__ __forceinline__ void shade_vertex(const SceneView& S, const LaunchArg
     }
     if (fcos > 0.0f && em > 0.0f) {
         float c = ((ps.beta * fcos) * em) / d2;
-        if (medium) c = c * expf(-(S.sigma_t * dist));
+        if (medium && outside) c = c * expf(-(S.sigma_t * dist));
         nee.valid = true;
         nee.so = nudge(x, n);
         nee.excl = k;
@@ -551,8 +627,10 @@ __device__ __forceinline__ void shade_vertex(const SceneView& S, const LaunchArg
         nee.g_rough = g_rough;
     }
     if (v == vmax) return;
-    tally.add(kTallyDraws);
-    const rand4 u = draw4(pix, sample, (uint32_t)v, L.stream_id, L.key0, L.key1);
+    if (!have_u) {
+        tally.add(kTallyDraws);
+        u = draw4(pix, sample, (uint32_t)v, L.stream_id, L.key0, L.key1);
+    }
     vec3 wi;
     float w;
     float gc_rough = 0.0f;
@@ -1171,10 +1249,10 @@ __global__ void k_reset_cursor(uint32_t* cursor)
 // with a barrier between stages.  Compaction into queues keeps the costly
 // stages dense: a wave that has no entry in a queue skips that stage and
 // leaves its SIMD to other waves.
-constexpr int kWfWords = 31;  // 32-bit words of LDS per slot
+constexpr int kWfWords = 32;  // 32-bit words of LDS per slot
 
 struct WfSlots {
-    float *ox, *oy, *oz, *dx, *dy, *dz, *beta, *opl, *uff;
+    float *ox, *oy, *oz, *dx, *dy, *dz, *beta, *opl, *uff, *eta;
     int *prev, *v, *pl, *live;
     uint32_t* sample;
     float* ht;
@@ -1192,7 +1270,7 @@ __device__ __forceinline__ WfSlots carve_slots(float* base, int ns)
     auto take_i = [&]() { int* r = reinterpret_cast<int*>(f); f += ns; return r; };
     w.ox = take_f(); w.oy = take_f(); w.oz = take_f();
     w.dx = take_f(); w.dy = take_f(); w.dz = take_f();
-    w.beta = take_f(); w.opl = take_f(); w.uff = take_f();
+    w.beta = take_f(); w.opl = take_f(); w.uff = take_f(); w.eta = take_f();
     w.prev = take_i(); w.v = take_i(); w.pl = take_i(); w.live = take_i();
     w.sample = reinterpret_cast<uint32_t*>(take_i());
     w.ht = take_f(); w.hprim = take_i(); w.hsorted = take_i(); w.hmed = take_i();
@@ -1208,7 +1286,7 @@ __device__ __forceinline__ void store_state(const WfSlots& w, int i, const PathS
 {
     w.ox[i] = ps.o.x; w.oy[i] = ps.o.y; w.oz[i] = ps.o.z;
     w.dx[i] = ps.d.x; w.dy[i] = ps.d.y; w.dz[i] = ps.d.z;
-    w.beta[i] = ps.beta; w.opl[i] = ps.opl; w.uff[i] = ps.u_ff;
+    w.beta[i] = ps.beta; w.opl[i] = ps.opl; w.uff[i] = ps.u_ff; w.eta[i] = ps.eta;
     w.prev[i] = ps.prev; w.v[i] = ps.v;
 }
 
@@ -1217,7 +1295,7 @@ __device__ __forceinline__ PathState load_state(const WfSlots& w, int i)
     PathState ps;
     ps.o = v3(w.ox[i], w.oy[i], w.oz[i]);
     ps.d = v3(w.dx[i], w.dy[i], w.dz[i]);
-    ps.beta = w.beta[i]; ps.opl = w.opl[i]; ps.u_ff = w.uff[i];
+    ps.beta = w.beta[i]; ps.opl = w.opl[i]; ps.u_ff = w.uff[i]; ps.eta = w.eta[i];
     ps.prev = w.prev[i]; ps.v = w.v[i];
     return ps;
 }

@@ -64,7 +64,16 @@ struct SceneView {
     const uint32_t* area_guide;
     double area_total;
     float guide_cells;
+
+    // refractive indices and scattering delays (caller order; nullptr when
+    // the scene has no dielectric / no delay) and the index of the space
+    // around the meshes
+    const float* ior;
+    const float* delay;
+    float eta0;
 };
+
+constexpr uint32_t kMatDielectric = 2;
 
 constexpr uint32_t kMaxFreq = 32;  // frequencies of one phasor film
 

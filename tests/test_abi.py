@@ -91,6 +91,42 @@ def test_scene_create_validation(B):
     expect_invalid(bad_mat, "unknown material")
 
 
+def test_dielectric_and_delay_validation(B):
+    """Refractive indices and scattering delays are checked on the host
+    before any device call."""
+    from paper_2510_25660_amd import scenes
+    L = B.lib()
+    h = C.c_void_p()
+    sc = scenes.glass_box_scene(delay_mean=0.05)
+
+    def expect_invalid(mutate, msg):
+        d, keep = _desc(copy.deepcopy(sc))
+        mutate(d, keep)
+        st = L.trhip_scene_create(C.byref(d), None, C.byref(h))
+        assert st == 1, (msg, st)
+        assert msg in L.trhip_last_error().decode(), L.trhip_last_error()
+
+    expect_invalid(lambda d, k: setattr(d, "ior", None), "ior is NULL")
+
+    def bad_ior(d, k):
+        k[5][12] = 0.0           # a triangle of the glass box
+    expect_invalid(bad_ior, "ior must lie")
+
+    def nan_ior(d, k):
+        k[5][12] = np.nan
+    expect_invalid(nan_ior, "ior must lie")
+
+    def bad_delay(d, k):
+        k[6][0] = -1.0
+    expect_invalid(bad_delay, "delay")
+
+    def inf_delay(d, k):
+        k[6][0] = np.inf
+    expect_invalid(inf_delay, "delay")
+    expect_invalid(lambda d, k: setattr(d, "medium_ior", -1.0), "medium_ior")
+    expect_invalid(lambda d, k: setattr(d, "medium_ior", float("nan")), "medium_ior")
+
+
 def test_confocal_validation(B):
     from paper_2510_25660_amd import scenes
     L = B.lib()
