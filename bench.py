@@ -49,6 +49,8 @@ WORKLOADS = {
     "box": dict(desc="box room 34 tris, 64x64 pinhole, 256 bins x 0.01 m from 0, 16 spp, max depth 4, FP32"),
     "large": dict(desc="terrain + 49 displaced spheres 998,608 tris, fog sigma_t 0.1, 512x512, 1024 bins x 5 mm "
                        "from 4.5 m, 64 spp, max depth 8, FP32"),
+    "glass": dict(desc="box room 34 tris with a glass box (index 1.5) and fluorescent room walls (scattering delay "
+                       "mean 5 cm), 64x64 pinhole, 256 bins x 0.01 m from 0, 16 spp, max depth 8, FP32"),
     "batched": dict(desc="256 confocal NLOS scenes: blob triangles log-uniform 1k-50k, scan grids 16^2-64^2, "
                          "256-1024 bins x 2.4 mm from 0.9 m, 256 spp, 3 bounces, one graph launch, FP32"),
 }
@@ -86,6 +88,8 @@ def make_scene(name):
         return scenes.box_scene()
     if name == "large":
         return scenes.large_scene()
+    if name == "glass":
+        return scenes.glass_box_scene(delay_mean=0.05)
     raise ValueError(name)
 
 
@@ -170,6 +174,21 @@ def run_batched(args, tr):
     return out
 
 
+def glass_room(tr, steps, warmup):
+    """The glass-box room (dielectric interfaces, Eq. 3; scattering delays,
+    Eq. 10): Mpath-samples/s of the path form."""
+    import torch
+    sc = make_scene("glass")
+    with tr.upload(sc) as dev:
+        film = torch.empty((sc.height, sc.width, sc.n_bins), device="cuda", dtype=torch.float32)
+        steady = torch.empty((sc.height, sc.width), device="cuda", dtype=torch.float32)
+        ms, _ = time_launches(lambda: tr.render_transient(dev, film=film, steady=steady), 4 * steps, warmup)
+        _, _, counts = tr.render_transient_counted(dev)
+    ms /= 4 * steps
+    return {"workload": WORKLOADS["glass"]["desc"], "ms_per_step": round(ms, 4),
+            "mpaths_per_s": round(sc.n_pixels * sc.spp / (ms * 1e-3) / 1e6, 3), "counts": counts}
+
+
 def cpu_baseline(sc, max_threads=16):
     """The oracle on the host cores over a bounded sample of the workload."""
     import oracle
@@ -206,12 +225,13 @@ def main():
     ap.add_argument("--phasor-freqs", type=int, default=16,
                     help="also time the frequency-space film with this many frequencies (0: skip)")
     ap.add_argument("--no-nlos-area", action="store_true", help="skip the NLOS area-sampling measurement")
+    ap.add_argument("--no-glass", action="store_true", help="skip the glass-room measurement")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a device copy of this many MiB (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(the path shards by pixel tiles or sample ranges, see DESIGN.md)", file=sys.stderr)
+              f"(the path would shard by pixel tiles or sample ranges)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -311,6 +331,8 @@ def main():
         out["phasor_film"] = phasor
     if nlos:
         out["nlos_area_sampling"] = nlos
+    if args.workload == "confocal" and not args.no_glass:
+        out["glass_room"] = glass_room(tr, args.steps, args.warmup)
     if not args.no_backward:
         ratio, f_ms, b_ms, rep_ms, t_ms = backward_forward_ratio(tr)
         out["backward_forward_ratio"] = round(ratio, 3)
