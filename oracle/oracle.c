@@ -250,7 +250,9 @@ struct orc_prepared {
     /* NLOS area sampling (confocal): inclusive prefix sums of the sampling
      * weights (triangle areas, zero on the relay wall's plane) */
     double* area_cdf;
-    double area_total;
+    float* area_invp;   /* W A_k / w_k: the inverse area density, per triangle */
+    double weight_total;
+    double area_total;  /* area of the sampling set */
 };
 
 #define ORC_BRUTE_MAX 64
@@ -374,39 +376,83 @@ orc_prepared* orc_prepare(const orc_scene* sc)
         free(cen);
     }
     if (sc->sensor == ORC_SENSOR_CONFOCAL) {
-        /* Area of every triangle in FP64 (float differences are exact in
-         * double); triangles whose three vertices lie on the relay wall's
-         * plane (through the first scan point, along the wall normal) get
-         * weight 0: seen from a scan point they subtend no solid angle. */
-        double acc = 0.0, tol, n[3], s0[3];
+        /* NLOS area sampling.  Sampling set: every triangle not lying in the
+         * relay wall's plane (through the first scan point, along the wall
+         * normal): seen from a scan point those subtend no solid angle.
+         * Triangle k of the set is drawn with probability w_k / W,
+         * w_k = A_k (g_k + g_max / 20): A_k its area, g_k = (cos_s cos_h / r^2)^2
+         * the square of the geometry term between the scan grid's centroid c
+         * and the triangle's centroid m_k (d = m_k - c, r = |d|, cos_s = the
+         * wall normal's cosine with d, clamped at 0, cos_h = |n_k . d| / r),
+         * g_max the largest g_k; the floor keeps every triangle of the set
+         * drawable (uniform by area if every g_k is 0).  The point is uniform
+         * within the triangle, so its area density is w_k / (W A_k); area_invp
+         * holds W A_k / w_k.  All in FP64 (float differences are exact). */
+        const size_t ns = (size_t)sc->width * (size_t)sc->height;
+        double acc = 0.0, area_sum = 0.0, tol, n[3], s0[3], cs[3] = {0.0, 0.0, 0.0}, gmax = 0.0, floor_w;
+        double* area = (double*)malloc(sizeof(double) * (size_t)nt);
+        double* geo = (double*)malloc(sizeof(double) * (size_t)nt);
+        size_t i;
         int a;
         for (a = 0; a < 3; ++a) {
             n[a] = (double)sc->wall_normal[a];
             s0[a] = (double)P->scan[a];
         }
+        for (i = 0; i < ns; ++i)
+            for (a = 0; a < 3; ++a) cs[a] += (double)P->scan[3 * i + a];
+        for (a = 0; a < 3; ++a) cs[a] = cs[a] / (double)ns;
         tol = 1e-6 * (1.0 + (double)maxabs);
-        P->area_cdf = (double*)malloc(sizeof(double) * (size_t)nt);
         for (k = 0; k < nt; ++k) {
             const float* t = P->tri + 9 * k;
-            double e1[3], e2[3], c[3], w = 0.0;
+            double e1[3], e2[3], c[3], len, m[3], dd[3], r2, r, cos_s, cos_h, q;
             int on_wall = 1, j;
             for (j = 0; j < 3; ++j) {
                 double h = ((double)t[3 * j] - s0[0]) * n[0] + ((double)t[3 * j + 1] - s0[1]) * n[1] +
                            ((double)t[3 * j + 2] - s0[2]) * n[2];
                 if (fabs(h) > tol) on_wall = 0;
             }
+            area[k] = 0.0;
+            geo[k] = 0.0;
+            if (on_wall) continue;
             for (a = 0; a < 3; ++a) {
                 e1[a] = (double)t[3 + a] - (double)t[a];
                 e2[a] = (double)t[6 + a] - (double)t[a];
+                m[a] = (((double)t[a] + (double)t[3 + a]) + (double)t[6 + a]) / 3.0;
+                dd[a] = m[a] - cs[a];
             }
             c[0] = e1[1] * e2[2] - e1[2] * e2[1];
             c[1] = e1[2] * e2[0] - e1[0] * e2[2];
             c[2] = e1[0] * e2[1] - e1[1] * e2[0];
-            if (!on_wall) w = 0.5 * sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+            len = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+            area[k] = 0.5 * len;
+            r2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
+            if (r2 > 0.0) {
+                r = sqrt(r2);
+                cos_s = (n[0] * dd[0] + n[1] * dd[1] + n[2] * dd[2]) / r;
+                if (cos_s < 0.0) cos_s = 0.0;
+                cos_h = fabs((c[0] / len) * dd[0] + (c[1] / len) * dd[1] + (c[2] / len) * dd[2]) / r;
+                q = (cos_s * cos_h) / r2;
+                geo[k] = q * q;
+            }
+            if (geo[k] > gmax) gmax = geo[k];
+        }
+        floor_w = (gmax > 0.0) ? gmax / 20.0 : 1.0;
+        P->area_cdf = (double*)malloc(sizeof(double) * (size_t)nt);
+        P->area_invp = (float*)malloc(sizeof(float) * (size_t)nt);
+        for (k = 0; k < nt; ++k) {
+            const double w = area[k] * (geo[k] + floor_w);
             acc += w;
+            area_sum += area[k];
             P->area_cdf[k] = acc;
         }
-        P->area_total = acc;
+        for (k = 0; k < nt; ++k) {
+            const double w = area[k] * (geo[k] + floor_w);
+            P->area_invp[k] = (w > 0.0) ? (float)((acc * area[k]) / w) : 0.0f;
+        }
+        P->weight_total = acc;
+        P->area_total = area_sum;
+        free(area);
+        free(geo);
     }
     return P;
 }
@@ -415,7 +461,7 @@ void orc_release(orc_prepared* P)
 {
     if (!P) return;
     free(P->tri); free(P->box); free(P->mat); free(P->albedo); free(P->rough);
-    free(P->scan); free(P->nodes); free(P->order); free(P->area_cdf); free(P->ior); free(P->delay);
+    free(P->scan); free(P->nodes); free(P->order); free(P->area_cdf); free(P->area_invp); free(P->ior); free(P->delay);
     free(P);
 }
 
@@ -911,18 +957,18 @@ int orc_trace_path(const orc_prepared* P, const orc_render* R, uint32_t pix, uin
         vmax = R->max_depth - 3;
         target = xs;
     } else {
-        /* NLOS area sampling: the hidden vertex is a point drawn uniformly
-         * by area on the sampling set (triangle by u0 through the prefix
-         * sums, point by u1, u2), the first segment joins it to the offset
-         * scan point; its throughput is f_wall cos_s / p_w with the solid
-         * angle pdf p_w = p_A r^2 / cos_h, p_A = 1 / (total area).  Its
-         * visibility is the shadow test of the connection back to the scan
-         * point, which runs the same segment. */
+        /* NLOS area sampling: the hidden vertex is a point drawn on the
+         * sampling set (triangle by u0 through the prefix sums of the
+         * weights, point uniformly within it by u1, u2), the first segment
+         * joins it to the offset scan point; its throughput is
+         * f_wall cos_s / p_w with the solid angle pdf p_w = p_A r^2 / cos_h,
+         * p_A = w_k / (W A_k).  Its visibility is the shadow test of the
+         * connection back to the scan point, which runs the same segment. */
         v3 xs = vload(P->scan + 3 * pix), e1, e2, v0, xh, dv, ng;
-        const double target_area = (double)u[0] * P->area_total;
+        const double target_area = (double)u[0] * P->weight_total;
         int lo = 0, hi = sc->n_tris - 1;
         float su, b1, b2, r2, r, cos_s0, cos_h, g;
-        if (!(P->area_total > 0.0)) return 0;
+        if (!(P->weight_total > 0.0)) return 0;
         while (lo < hi) { /* first triangle whose prefix sum exceeds the target */
             int mid = (lo + hi) / 2;
             if (P->area_cdf[mid] > target_area) hi = mid;
@@ -949,7 +995,7 @@ int orc_trace_path(const orc_prepared* P, const orc_render* R, uint32_t pix, uin
         cos_h = fabsf(vdot(ng, d));
         if (!(cos_s0 > 0.0f) || !(cos_h > 0.0f)) return 0;
         g = (cos_s0 * cos_h) / r2;
-        beta = ((sc->wall_albedo * (float)P->area_total) * ORC_INV_PI_F) * g;
+        beta = ((sc->wall_albedo * P->area_invp[lo]) * ORC_INV_PI_F) * g;
         vmax = R->max_depth - 3;
         target = xs;
         forced_k = lo;
