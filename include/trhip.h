@@ -64,15 +64,18 @@ enum {
  * scenes (Sec. 4.5 adds NLOS-tailored samplers from the work it cites; this
  * is the area-sampling one, which aims every path at the hidden geometry
  * instead of the hemisphere above the relay wall).  The first path vertex
- * after the scan point is drawn uniformly by area over the scene's triangles
- * that do not lie in the relay wall's plane (the plane through the first
- * scan point with normal wall_normal, within 1e-6 * (1 + largest |vertex
- * coordinate|)): the triangle with probability proportional to its FP64
- * area, the point by the square-root warp of two uniforms.  The vertex
- * carries the weight wall_albedo / pi * cos_wall * cos_hidden / r^2 * A,
- * A the sampling set's area; its visibility is the next-event shadow test
- * back to the scan point, which runs along the same segment.  The estimate
- * has the expectation of the default (cosine-sampled) render.
+ * after the scan point is drawn on the scene's triangles that do not lie in
+ * the relay wall's plane (the plane through the first scan point with
+ * normal wall_normal, within 1e-6 * (1 + largest |vertex coordinate|)):
+ * triangle k with probability w_k / W, w_k = A_k (g_k + g_max / 20) in FP64
+ * (A_k its area, g_k = (cos_s cos_h / r^2)^2 the squared geometry term
+ * between the centroid of the scan points and the triangle's centroid,
+ * g_max the largest), the point uniformly within it (square-root warp of
+ * two uniforms).  The vertex carries the weight wall_albedo / pi *
+ * cos_wall * cos_hidden / r^2 * W A_k / w_k; its visibility is the
+ * next-event shadow test back to the scan point, which runs along the same
+ * segment.  The estimate has the expectation of the default
+ * (cosine-sampled) render.
  * Valid for the confocal sensor with max_depth == 4 (the three-bounce
  * path, whose only hidden vertex is the sampled one) and no medium
  * (sigma_t == 0); any kernel form but TRHIP_KERNEL_WAVEFRONT (the deferred

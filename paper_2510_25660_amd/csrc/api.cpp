@@ -67,11 +67,12 @@ struct trhip_scene {
     float* d_ior;    // nullptr: no dielectric triangle
     float* d_delay;  // nullptr: no scattering delay
     double* d_grad;  // 2 * n_tris doubles of backward workspace
-    double* d_area_cdf;      // confocal: NLOS area-sampling prefix sums (caller order)
+    double* d_area_cdf;      // confocal: NLOS area-sampling prefix sums of the weights (caller order)
+    float* d_area_invp;      // confocal: inverse area density per triangle
     uint32_t* d_sorted_of;   // confocal: BVH-order index of each caller triangle
     uint32_t* d_area_guide;  // confocal: guide table of the prefix sums
     uint32_t guide_cells;
-    double area_total;
+    double area_total;       // confocal: W, the total of the sampling weights
     uint32_t n_pixels;
     size_t device_bytes;
 };
@@ -107,6 +108,7 @@ void free_scene(trhip_scene* s)
     (void)hipFree(s->d_delay);
     (void)hipFree(s->d_grad);
     (void)hipFree(s->d_area_cdf);
+    (void)hipFree(s->d_area_invp);
     (void)hipFree(s->d_sorted_of);
     (void)hipFree(s->d_area_guide);
     s->magic = 0;
@@ -185,45 +187,79 @@ trhip_status validate_desc(const trhip_scene_desc* d, std::vector<float>& tri9)
     return TRHIP_OK;
 }
 
-// Sampling weights of NLOS area sampling, accumulated in caller order into
-// cdf: the FP64 area of every triangle (differences of FP32 coordinates are
-// exact in FP64), 0 for a triangle whose three vertices lie in the relay
-// wall's plane -- the plane through scan point s0 with normal wn, within
-// 1e-6 * (1 + largest |coordinate|) -- since seen from a scan point it
-// subtends no solid angle.  Returns the total.
-double area_prefix_sums(const std::vector<float>& tri9, uint32_t nt, const float* s0, const float* wn,
-                        std::vector<double>& cdf)
+// Sampling weights of NLOS area sampling.  The sampling set is every
+// triangle not lying in the relay wall's plane (the plane through scan point
+// s0 with normal wn, within 1e-6 * (1 + largest |coordinate|)): seen from a
+// scan point those subtend no solid angle.  Triangle k of the set has weight
+// w_k = A_k (g_k + g_max / 20), A_k its area and g_k = (cos_s cos_h / r^2)^2
+// the squared geometry term between the centroid c of the np scan points
+// and the triangle's centroid (d = centroid - c, r = |d|, cos_s = wn . d / r
+// clamped at 0, cos_h = |n_k . d| / r); the floor keeps every triangle of
+// the set drawable (all weights A_k if every g_k is 0).  Fills the inclusive
+// prefix sums in caller order (cdf), invp[k] = W A_k / w_k (the inverse area
+// density of a point drawn uniformly on triangle k; 0 outside the set) and
+// the set's area; returns W.  FP64 throughout: differences of FP32
+// coordinates are exact there.
+double area_prefix_sums(const std::vector<float>& tri9, uint32_t nt, const float* scan, size_t np, const float* wn,
+                        std::vector<double>& cdf, std::vector<float>& invp, double* set_area)
 {
 #pragma clang fp contract(off)
     float maxabs = 0.0f;
     for (const float c : tri9) maxabs = std::max(maxabs, std::fabs(c));
     const double tol = 1e-6 * (1.0 + (double)maxabs);
-    cdf.resize(nt);
-    double acc = 0.0;
+    double cs[3] = {0.0, 0.0, 0.0};
+    for (size_t i = 0; i < np; ++i)
+        for (int a = 0; a < 3; ++a) cs[a] += (double)scan[3 * i + a];
+    for (int a = 0; a < 3; ++a) cs[a] = cs[a] / (double)np;
+    const double n[3] = {(double)wn[0], (double)wn[1], (double)wn[2]};
+    std::vector<double> area(nt, 0.0), geo(nt, 0.0);
+    double gmax = 0.0;
     for (uint32_t k = 0; k < nt; ++k) {
         const float* t = &tri9[9ull * k];
         bool on_wall = true;
         for (int j = 0; j < 3; ++j) {
-            const double h = ((double)t[3 * j] - (double)s0[0]) * (double)wn[0] +
-                             ((double)t[3 * j + 1] - (double)s0[1]) * (double)wn[1] +
-                             ((double)t[3 * j + 2] - (double)s0[2]) * (double)wn[2];
+            const double h = ((double)t[3 * j] - (double)scan[0]) * n[0] +
+                             ((double)t[3 * j + 1] - (double)scan[1]) * n[1] +
+                             ((double)t[3 * j + 2] - (double)scan[2]) * n[2];
             if (std::fabs(h) > tol) on_wall = false;
         }
-        double w = 0.0;
-        if (!on_wall) {
-            double e1[3], e2[3];
-            for (int a = 0; a < 3; ++a) {
-                e1[a] = (double)t[3 + a] - (double)t[a];
-                e2[a] = (double)t[6 + a] - (double)t[a];
-            }
-            const double cx = e1[1] * e2[2] - e1[2] * e2[1];
-            const double cy = e1[2] * e2[0] - e1[0] * e2[2];
-            const double cz = e1[0] * e2[1] - e1[1] * e2[0];
-            w = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+        if (on_wall) continue;
+        double e1[3], e2[3], d[3];
+        for (int a = 0; a < 3; ++a) {
+            e1[a] = (double)t[3 + a] - (double)t[a];
+            e2[a] = (double)t[6 + a] - (double)t[a];
+            d[a] = (((double)t[a] + (double)t[3 + a]) + (double)t[6 + a]) / 3.0 - cs[a];
         }
-        acc += w;
+        const double cx = e1[1] * e2[2] - e1[2] * e2[1];
+        const double cy = e1[2] * e2[0] - e1[0] * e2[2];
+        const double cz = e1[0] * e2[1] - e1[1] * e2[0];
+        const double len = std::sqrt(cx * cx + cy * cy + cz * cz);
+        area[k] = 0.5 * len;
+        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (r2 > 0.0) {
+            const double r = std::sqrt(r2);
+            double cos_s = (n[0] * d[0] + n[1] * d[1] + n[2] * d[2]) / r;
+            if (cos_s < 0.0) cos_s = 0.0;
+            const double cos_h = std::fabs((cx / len) * d[0] + (cy / len) * d[1] + (cz / len) * d[2]) / r;
+            const double q = (cos_s * cos_h) / r2;
+            geo[k] = q * q;
+        }
+        if (geo[k] > gmax) gmax = geo[k];
+    }
+    const double floor_w = gmax > 0.0 ? gmax / 20.0 : 1.0;
+    cdf.resize(nt);
+    invp.resize(nt);
+    double acc = 0.0, sum_area = 0.0;
+    for (uint32_t k = 0; k < nt; ++k) {
+        acc += area[k] * (geo[k] + floor_w);
+        sum_area += area[k];
         cdf[k] = acc;
     }
+    for (uint32_t k = 0; k < nt; ++k) {
+        const double w = area[k] * (geo[k] + floor_w);
+        invp[k] = w > 0.0 ? (float)((acc * area[k]) / w) : 0.0f;
+    }
+    *set_area = sum_area;
     return acc;
 }
 
@@ -293,6 +329,7 @@ void fill_view(trhip_scene* s, const trhip_scene_desc* d)
     v.area_cdf = s->d_area_cdf;
     v.sorted_of = s->d_sorted_of;
     v.area_total = s->area_total;
+    v.area_invp = s->d_area_invp;
     v.area_guide = s->d_area_guide;
     v.guide_cells = (float)s->guide_cells;
     v.ior = s->d_ior;
@@ -446,11 +483,15 @@ trhip_status trhip_scene_create(const trhip_scene_desc* desc, void* stream, trhi
     if (e == hipSuccess) e = upload(&sc->d_rough, desc->roughness, nt, s);
     std::vector<double> cdf;
     std::vector<uint32_t> guide;
+    std::vector<float> invp;
     if (e == hipSuccess && desc->sensor == TRHIP_SENSOR_CONFOCAL) {
         e = upload(&sc->d_scan, desc->scan_points, 3ull * sc->n_pixels, s);
-        sc->area_total = area_prefix_sums(tri9, nt, desc->scan_points, desc->wall_normal, cdf);
+        double set_area = 0.0;
+        sc->area_total = area_prefix_sums(tri9, nt, desc->scan_points, (size_t)sc->n_pixels, desc->wall_normal, cdf,
+                                          invp, &set_area);
         sc->guide_cells = area_guide(cdf, sc->area_total, guide);
         if (e == hipSuccess) e = upload(&sc->d_area_cdf, cdf.data(), nt, s);
+        if (e == hipSuccess) e = upload(&sc->d_area_invp, invp.data(), nt, s);
         if (e == hipSuccess) e = upload(&sc->d_area_guide, guide.data(), guide.size(), s);
         if (e == hipSuccess) e = hipMalloc(&sc->d_sorted_of, (size_t)nt * sizeof(uint32_t));
     }
@@ -479,7 +520,7 @@ trhip_status trhip_scene_create(const trhip_scene_desc* desc, void* stream, trhi
         g_live.insert(sc);
     }
     sc->device_bytes = (size_t)sc->bvh.n_internal * sizeof(trhip::BvhNode) + (size_t)nt * sizeof(trhip::TriRec) +
-                       (size_t)nt * (1 + 4 + 4 + 16) + (sc->d_scan ? 12ull * sc->n_pixels + 12ull * nt + 4ull * (sc->guide_cells + 1) : 0) +
+                       (size_t)nt * (1 + 4 + 4 + 16) + (sc->d_scan ? 12ull * sc->n_pixels + 16ull * nt + 4ull * (sc->guide_cells + 1) : 0) +
                        (sc->d_ior ? 4ull * nt : 0) + (sc->d_delay ? 4ull * nt : 0);
     *out = sc;
     return TRHIP_OK;

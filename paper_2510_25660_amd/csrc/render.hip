@@ -361,22 +361,11 @@ __device__ __forceinline__ void begin_path(const SceneView& S, const LaunchArgs&
     ps.v = 1;
 }
 
-// NLOS area sampling (confocal, three bounces; the NLOS-tailored sampling
-// of Sec. 4.5): generation draws the hidden vertex itself, uniformly by area
-// on the triangles off the relay wall's plane -- the triangle through the
-// FP64 prefix sums of the areas (u0), the point by the square-root warp
-// (u1, u2) -- and joins it to the offset scan point.  Converting the area
-// density 1/A to solid angle at the scan point (r^2 / cos_hidden) gives the
-// weight f_wall cos_wall / p = wall_albedo / pi * A * cos_wall cos_hidden /
-// r^2.  The segment's visibility is left to the next-event shadow ray of
-// the vertex, which tests the same segment back to the scan point.  Returns
-// false when the pair faces away (no contribution); otherwise sets ps and
-// the vertex's hit h (distance r, caller and BVH-order triangle).
 // caller index of the area-sampled triangle: the first whose prefix sum
-// exceeds u0 * A, found by bisection between two guide-table entries (the
+// exceeds u0 * W, found by bisection between two guide-table entries (the
 // cutpoint method).  With m = floor(u0 * M), m / M <= u0 < (m + 1) / M
 // exactly, and FP64 rounding is monotone, so the thresholds of entries m
-// and m + 1 bracket u0 * A and their first indices bracket the answer.
+// and m + 1 bracket u0 * W and their first indices bracket the answer.
 // u0 is a multiple of 2^-24 and M a power of two <= 2^22: u0 * M is exact.
 __device__ __forceinline__ uint32_t area_pick(const SceneView& S, float u0)
 {
@@ -391,6 +380,19 @@ __device__ __forceinline__ uint32_t area_pick(const SceneView& S, float u0)
     return lo;
 }
 
+// NLOS area sampling (confocal, three bounces; the NLOS-tailored sampling
+// of Sec. 4.5): generation draws the hidden vertex itself -- triangle k of
+// the sampling set (the triangles off the relay wall's plane) with
+// probability w_k / W through the FP64 prefix sums of the weights (u0), the
+// point uniformly within it by the square-root warp (u1, u2) -- and joins it
+// to the offset scan point.  The area density w_k / (W A_k) converted to
+// solid angle at the scan point (times r^2 / cos_hidden) gives the weight
+// f_wall cos_wall / p = wall_albedo / pi * (W A_k / w_k) * cos_wall
+// cos_hidden / r^2.  The segment's visibility is left to the next-event
+// shadow ray of the vertex, which tests the same segment back to the scan
+// point.  Returns false when the pair faces away (no contribution);
+// otherwise sets ps and the vertex's hit h (distance r, caller and
+// BVH-order triangle).
 __device__ __forceinline__ bool begin_area(const SceneView& S, const LaunchArgs& L, uint32_t pix, uint32_t sample,
                                            PathState& ps, Hit& h)
 {
@@ -415,7 +417,7 @@ __device__ __forceinline__ bool begin_area(const SceneView& S, const LaunchArgs&
     const float cos_h = fabsf(dot(ng, d));
     if (!(cos_s > 0.0f) || !(cos_h > 0.0f)) return false;
     const float g = (cos_s * cos_h) / r2;
-    ps.beta = ((S.wall_albedo * (float)S.area_total) * kInvPi) * g;
+    ps.beta = ((S.wall_albedo * S.area_invp[lo]) * kInvPi) * g;
     ps.o = o;
     ps.d = d;
     ps.opl = 0.0f;

@@ -54,12 +54,14 @@ struct SceneView {
     int32_t unwarp;
 
     // NLOS area sampling (confocal): inclusive FP64 prefix sums of the
-    // sampling weights in caller order (triangle area, 0 on the relay wall's
-    // plane), their total, and the BVH-order index of each caller triangle;
+    // triangles' sampling weights in caller order (0 on the relay wall's
+    // plane), their total, the inverse area density W A_k / w_k of a point
+    // drawn on triangle k, and the BVH-order index of each caller triangle;
     // guide table of the inversion: area_guide[m] is the first triangle
     // whose prefix sum exceeds (m / guide_cells) * area_total (clamped to
     // n_tris - 1), m = 0 .. guide_cells; guide_cells a power of two <= 2^22
     const double* area_cdf;
+    const float* area_invp;
     const uint32_t* sorted_of;
     const uint32_t* area_guide;
     double area_total;
