@@ -1008,6 +1008,7 @@ int orc_trace_path(const orc_prepared* P, const orc_render* R, uint32_t pix, uin
         int k = -1, hit, medium_event = 0;
         v3 x, n, wo, dl, wl, ng = mk(0.0f, 0.0f, 0.0f);
         double dn_alb = 0.0, dn_rough = 0.0;
+        int first_blocked = 0;
         orc_vertex* vert;
         if (v == 1 && forced_k >= 0) {
             hit = 1;
@@ -1083,9 +1084,16 @@ int orc_trace_path(const orc_prepared* P, const orc_render* R, uint32_t pix, uin
                         }
                     }
                 }
+                if (forced_k >= 0 && v == 1 && v < vmax) {
+                    /* a path continued from the drawn hidden vertex needs its
+                     * first segment unoccluded: the shadow test back to the
+                     * scan point runs along that segment */
+                    ray_t sh = make_ray(offset_ray(x, n), wl);
+                    first_blocked = occluded(P, &sh, k, dist * SHADOW_SHRINK);
+                }
             }
         }
-        if (v == vmax) break;
+        if (v == vmax || first_blocked) break;
         draw(R, pix, sample, (uint32_t)v, u);
         if (medium_event) {
             float z = 1.0f - (u[0] + u[0]);
@@ -1324,14 +1332,13 @@ static int run_jobs(job_t* base, int nthreads, void* (*fn)(void*))
     return 0;
 }
 
-/* Area sampling of the hidden vertex is defined for the three-bounce
- * confocal path (max_depth 4: one hidden vertex, whose visibility is the
- * shadow test back to the scan point) without a participating medium. */
+/* Area sampling of the hidden vertex is defined for confocal paths with at
+ * least one hidden vertex (max_depth >= 4) without a participating medium. */
 static int render_ok(const orc_prepared* P, const orc_render* R)
 {
     if (!P || !R || R->spp <= 0 || R->max_depth < 1) return 0;
     if (!R->nlos_area) return 1;
-    return P->sc.sensor == ORC_SENSOR_CONFOCAL && R->max_depth == 4 && !(P->sc.sigma_t > 0.0f) &&
+    return P->sc.sensor == ORC_SENSOR_CONFOCAL && R->max_depth >= 4 && !(P->sc.sigma_t > 0.0f) &&
            P->area_total > 0.0;
 }
 

@@ -535,6 +535,25 @@ CONFIGS = {
 }
 
 
+def occluded_nlos_scene(grid=4, spp=4096, n_bins=512, bin_width=0.01, bin_start=0.4, bounces=4) -> Scene:
+    """Confocal scan points near the origin of the relay wall z=0; a square
+    occluder [-0.2,0.2]^2 at z=0.3 hides a square plane of the same size at
+    z=0.6 from every scan point; a plane x=0.5 (|y| <= 1, 0 <= z <= 1) is in
+    direct view.  Light reaches the hidden square only around the occluder,
+    so a path drawn on it must carry the visibility of its first segment."""
+    (wv, wf), pts = relay_wall(grid, grid, half=0.02)
+    wv = wv * 50.0  # the wall itself spans [-1, 1]^2
+    occ = quad([-0.2, -0.2, 0.3], [0.2, -0.2, 0.3], [0.2, 0.2, 0.3], [-0.2, 0.2, 0.3])
+    hid = quad([-0.2, -0.2, 0.6], [0.2, -0.2, 0.6], [0.2, 0.2, 0.6], [-0.2, 0.2, 0.6])
+    side = quad([0.5, -1.0, 0.0], [0.5, 1.0, 0.0], [0.5, 1.0, 1.0], [0.5, -1.0, 1.0])
+    v, f = merge([(wv, wf), occ, hid, side])
+    alb = np.array([1.0, 1.0, 0.6, 0.6, 0.8, 0.8, 0.7, 0.7])
+    return _finish(v, f, np.zeros(8), alb, np.full(8, 0.3), n_bins=n_bins, bin_width=bin_width,
+                   bin_start=bin_start, sensor=SENSOR_CONFOCAL, width=grid, height=grid, scan_points=pts,
+                   wall_normal=(0.0, 0.0, 1.0), wall_albedo=1.0, laser_power=1.0, spp=spp,
+                   max_depth=bounces + 1, name="occluded_nlos")
+
+
 # --------------------------------------------------------------------------
 # refractive indices and scattering delays (Eqs. 3 and 10)
 # --------------------------------------------------------------------------
