@@ -75,9 +75,10 @@ enum {
  * cos_wall * cos_hidden / r^2 * W A_k / w_k; its visibility is the
  * next-event shadow test back to the scan point, which runs along the same
  * segment.  The estimate has the expectation of the default
- * (cosine-sampled) render.
- * Valid for the confocal sensor with max_depth == 4 (the three-bounce
- * path, whose only hidden vertex is the sampled one) and no medium
+ * (cosine-sampled) render.  A longer path continues from the drawn vertex
+ * only if that shadow test finds its first segment unoccluded.
+ * Valid for the confocal sensor with max_depth >= 4 (at least one hidden
+ * vertex) and no medium
  * (sigma_t == 0); any kernel form but TRHIP_KERNEL_WAVEFRONT (the deferred
  * form, the automatic choice, orders each batch of samples by the BVH
  * position of the sampled triangle, so that a wave's shadow rays leave one

@@ -353,8 +353,8 @@ trhip_status validate_render(const trhip_scene* s, const trhip_render_desc* r)
     if (r->flags & TRHIP_FLAG_NLOS_AREA_SAMPLING) {
         if (s->view.sensor != TRHIP_SENSOR_CONFOCAL)
             return fail(TRHIP_ERR_UNSUPPORTED, "NLOS area sampling needs the confocal sensor");
-        if (r->max_depth != 4)
-            return fail(TRHIP_ERR_UNSUPPORTED, "NLOS area sampling is defined for max_depth 4 (three bounces)");
+        if (r->max_depth < 4)
+            return fail(TRHIP_ERR_UNSUPPORTED, "NLOS area sampling needs a hidden vertex (max_depth >= 4)");
         if (s->view.sigma_t > 0.0f) return fail(TRHIP_ERR_UNSUPPORTED, "NLOS area sampling excludes media");
         if (!(s->area_total > 0.0))
             return fail(TRHIP_ERR_UNSUPPORTED, "NLOS area sampling: no triangle off the relay wall's plane");

@@ -565,6 +565,8 @@ __device__ __forceinline__ void shade_vertex(const SceneView& S, const LaunchArg
     const vec3 n = (dot(ng, wo) < 0.0f) ? neg(ng) : ng;
     if (!(dot(n, wo) > 0.0f)) return;
     const int k = h.prim;
+    nee.so = nudge(x, n);
+    nee.excl = k;
     // Eq. 10: a scattering delay, exponential with the triangle's mean, from
     // word 2 of the vertex's Philox block; it delays this vertex's
     // contribution and every later one
@@ -621,8 +623,6 @@ __device__ __forceinline__ void shade_vertex(const SceneView& S, const LaunchArg
         float c = ((ps.beta * fcos) * em) / d2;
         if (medium && outside) c = c * expf(-(S.sigma_t * dist));
         nee.valid = true;
-        nee.so = nudge(x, n);
-        nee.excl = k;
         nee.c = c;
         nee.k = k;
         nee.g_alb = 1.0f / albedo;
@@ -688,11 +688,22 @@ __device__ void continue_path(const SceneView& S, const LaunchArgs& L, uint32_t 
         Nee nee;
         Cont cont;
         shade_vertex<Sink::kWantsGradients>(S, L, pix, sample, ps, h, t_hit, med, nee, cont, tally);
-        if (nee.valid && !occluded(S, make_ray(nee.so, nee.sd), nee.excl, nee.tmax, stk, stride, tally)) {
-            tally.add(kTallyContrib);
-            sink.contribution(v, nee.k, nee.c, nee.bin, nee.tof, nee.g_alb, nee.g_rough);
+        bool blocked = true;
+        if (nee.valid) {
+            blocked = occluded(S, make_ray(nee.so, nee.sd), nee.excl, nee.tmax, stk, stride, tally);
+            if (!blocked) {
+                tally.add(kTallyContrib);
+                sink.contribution(v, nee.k, nee.c, nee.bin, nee.tof, nee.g_alb, nee.g_rough);
+            }
         }
         if (!cont.alive) break;
+        // a path drawn by NLOS area sampling continues from its hidden vertex
+        // only if the first segment is unoccluded: the shadow test back to
+        // the scan point runs along it
+        if (v == 1 && (L.flags & kFlagNlosArea)) {
+            if (!nee.valid) blocked = occluded(S, make_ray(nee.so, nee.sd), nee.excl, nee.tmax, stk, stride, tally);
+            if (blocked) break;
+        }
         if (cont.k >= 0) sink.continuation(v, cont.k, cont.g_alb, cont.g_rough);
         if (ps.v > vmax) break;
         h = closest_hit(S, make_ray(ps.o, ps.d), ps.prev, stk, stride, tally);

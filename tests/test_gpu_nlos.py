@@ -87,6 +87,46 @@ def test_area_sampling_two_triangle_plane(tr, oracle_mod, kernel):
     compare_vec(gst, ost, what="steady")
 
 
+@pytest.mark.parametrize("kernel", ["deferred", "path"])
+def test_area_sampling_deeper_paths(tr, oracle_mod, kernel):
+    """Five bounces on the blob (16 x 16, 256 spp) and four behind an
+    occluder: paths continue from the drawn vertex only when its first
+    segment is unoccluded."""
+    _announce(f"nlos area deeper {kernel}")
+    sc = scenes.confocal_nlos(grid=16, n_tris=4000, spp=256, bounces=5)
+    gst, g = _film(tr, sc, kernel=kernel)
+    o, ost, _ = oracle_mod.Oracle(sc).render(nlos_area=True)
+    compare_films(g, o)
+    compare_vec(gst, ost, what="steady")
+    sc = scenes.occluded_nlos_scene(grid=4, spp=1024, bounces=4)
+    gst, g = _film(tr, sc, kernel=kernel)
+    o, ost, _ = oracle_mod.Oracle(sc).render(nlos_area=True)
+    compare_films(g, o)
+    compare_vec(gst, ost, what="steady")
+
+
+def test_area_sampling_adjoint_deeper(tr, oracle_mod):
+    """Albedo gradients with two hidden vertices (path replay and stash)."""
+    import torch
+    sc = scenes.confocal_nlos(grid=8, n_tris=2000, spp=128, bounces=4)
+    ta = np.clip(sc.albedo * np.random.default_rng(9).uniform(0.7, 1.3, sc.n_tris), 0.05, 1.0).astype(np.float32)
+    _announce("nlos area adjoint deeper")
+    O = oracle_mod.Oracle(sc)
+    target, _, _ = O.render(stream_id=1, albedo=ta, nlos_area=True)
+    film_o, _, _ = O.render(nlos_area=True)
+    delta = (2.0 * (film_o - target)).astype(np.float32)
+    ga_o, _ = O.backward(delta, nlos_area=True)
+    scale = np.abs(ga_o).max()
+    assert scale > 0
+    with tr.upload(sc) as dev:
+        d = torch.from_numpy(delta.reshape(sc.height, sc.width, sc.n_bins)).cuda()
+        for kernel in ("auto", "path"):
+            ga, _ = tr.render_transient_backward(dev, d, kernel=kernel, nlos_area=True)
+            torch.cuda.synchronize()
+            ga = ga.cpu().numpy().astype(np.float64)
+            assert np.abs(ga - ga_o).max() <= 1e-4 * scale, (kernel, np.abs(ga - ga_o).max() / scale)
+
+
 def test_area_sampling_unbiased_on_gpu(tr):
     """Same expectation as cosine sampling: 4-seed steady images of both
     estimators agree within 5 pooled standard errors; area sampling has
@@ -178,7 +218,7 @@ def test_area_sampling_rejections(tr):
         assert e.value.status == STATUS_UNSUPPORTED
     sc = scenes.confocal_nlos(grid=4, n_tris=500, spp=4)
     with tr.upload(sc) as dev:
-        for kw in ({"max_depth": 5}, {"max_depth": 3}, {"kernel": "wavefront"}):
+        for kw in ({"max_depth": 3}, {"kernel": "wavefront"}):
             with pytest.raises(tr.TrhipError) as e:
                 tr.render_transient(dev, nlos_area=True, **kw)
             assert e.value.status == STATUS_UNSUPPORTED, kw
