@@ -174,6 +174,43 @@ def run_batched(args, tr):
     return out
 
 
+def box_room_graph(tr, replays=200):
+    """The box-room workload (65,536 paths: too small to fill the GPU, so
+    launch overhead matters): one render captured in a hipGraph, GPU time of
+    each of `replays` replays; median and per-render latency."""
+    import torch
+    sc = make_scene("box")
+    with tr.upload(sc) as dev:
+        film = torch.empty((sc.height, sc.width, sc.n_bins), device="cuda", dtype=torch.float32)
+        steady = torch.empty((sc.height, sc.width), device="cuda", dtype=torch.float32)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(3):
+                tr.render_transient(dev, film=film, steady=steady)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            tr.render_transient(dev, film=film, steady=steady)
+        stream = torch.cuda.current_stream()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(replays)]
+        for _ in range(5):
+            graph.replay()
+        torch.cuda.synchronize()
+        for a, b in ev:
+            a.record(stream)
+            graph.replay()
+            b.record(stream)
+        torch.cuda.synchronize()
+        per_us = sorted(a.elapsed_time(b) * 1e3 for a, b in ev)
+        del graph
+    med = per_us[len(per_us) // 2]
+    return {"workload": WORKLOADS["box"]["desc"], "replays": replays, "median_us": round(med, 2),
+            "min_us": round(per_us[0], 2), "max_us": round(per_us[-1], 2),
+            "mpaths_per_s": round(sc.n_pixels * sc.spp / (med * 1e-6) / 1e6, 3)}
+
+
 def glass_room(tr, steps, warmup):
     """The glass-box room (dielectric interfaces, Eq. 3; scattering delays,
     Eq. 10): Mpath-samples/s of the path form."""
@@ -226,6 +263,7 @@ def main():
                     help="also time the frequency-space film with this many frequencies (0: skip)")
     ap.add_argument("--no-nlos-area", action="store_true", help="skip the NLOS area-sampling measurement")
     ap.add_argument("--no-glass", action="store_true", help="skip the glass-room measurement")
+    ap.add_argument("--no-box-graph", action="store_true", help="skip the graph-replayed box-room latency")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a device copy of this many MiB (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -333,6 +371,8 @@ def main():
         out["nlos_area_sampling"] = nlos
     if args.workload == "confocal" and not args.no_glass:
         out["glass_room"] = glass_room(tr, args.steps, args.warmup)
+    if args.workload == "confocal" and not args.no_box_graph:
+        out["box_room_graph"] = box_room_graph(tr)
     if not args.no_backward:
         ratio, f_ms, b_ms, rep_ms, t_ms = backward_forward_ratio(tr)
         out["backward_forward_ratio"] = round(ratio, 3)
