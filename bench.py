@@ -31,7 +31,7 @@ PEAK_VALU_LANE_OPS = 256 * 64 * 2.4e9
 
 # Algorithmic lane-ops per counted event, from the operation counts of the
 # formulas the kernel evaluates (one add / mul / fma / min / max / compare /
-# select / divide / square root / integer op = 1); see the design doc.
+# select / divide / square root / integer op = 1).
 OPS_PER = {
     "nodes": 46,          # two slab tests (12 fma, 12 min/max, 8 reductions, 6 compares) + ordering
     "tris": 46,           # Moller-Trumbore + box-entry acceptance + closest/tie update
@@ -268,7 +268,7 @@ def main():
                     help="first run a device copy of this many MiB (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the renderer runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the path would shard by pixel tiles or sample ranges)", file=sys.stderr)
         sys.exit(2)
 
@@ -289,6 +289,14 @@ def main():
     sc = make_scene(args.workload)
     shape = dict(tile_pixels=args.tile_pixels, block_size=args.block_size, kernel=args.kernel)
     paths = sc.n_pixels * sc.spp
+    # scene upload + BVH build (off the timed loop; the first build also warms the runtime, so time a second one)
+    tr.upload(sc, builder=args.builder).destroy()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dev0 = tr.upload(sc, builder=args.builder)
+    torch.cuda.synchronize()
+    upload_ms = (time.perf_counter() - t0) * 1e3
+    dev0.destroy()
     with tr.upload(sc, builder=args.builder) as dev:
         info = dev.info()
         steady = torch.empty((sc.height, sc.width), device="cuda", dtype=torch.float32)
@@ -357,6 +365,7 @@ def main():
         "data": "synthetic (seeded scene generators)",
         "config": {"workload": WORKLOADS[args.workload]["desc"], "paths_per_step": paths,
                    "triangles": info["n_triangles"], "bvh_depth": info["bvh_depth"]},
+        "scene_upload_and_bvh_build_ms": round(upload_ms, 2),
         "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(PEAK_VALU_LANE_OPS / 1e12, 2),
                      "unit": "T lane-ops/s", "frac": round(achieved / PEAK_VALU_LANE_OPS, 4),
                      "traffic": measured_traffic(args.workload), "traffic_unit": "bytes/launch",
