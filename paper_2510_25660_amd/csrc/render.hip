@@ -1334,7 +1334,8 @@ __global__ void __launch_bounds__(256) k_render_wf(SceneView S, LaunchArgs L, un
     w.live[tid] = 0;
     if (tid < 4) ctr[tid] = 0u;
     __syncthreads();
-    const uint32_t work = npix * L.spp;
+    // paths without a vertex (max_depth too small) contribute nothing
+    const uint32_t work = last_vertex(S, L) >= 1 ? npix * L.spp : 0u;
 
     while (true) {
         // GEN: dead slots take new samples
