@@ -249,13 +249,15 @@ struct orc_prepared {
     int* order;
     /* NLOS area sampling (confocal): inclusive prefix sums of the sampling
      * weights (triangle areas, zero on the relay wall's plane) */
-    double* area_cdf;
-    float* area_invp;   /* W A_k / w_k: the inverse area density, per triangle */
-    double weight_total;
+    double* area_cdf;   /* [region][nt] inclusive prefix sums of the weights */
+    float* area_invp;   /* [region][nt] W_r A_k / w_k: the inverse area density */
+    double* weight_total; /* [region] W_r */
+    int* pix_region;    /* [scan point] its region */
     double area_total;  /* area of the sampling set */
 };
 
 #define ORC_BRUTE_MAX 64
+#define ORC_AREA_G 4 /* NLOS area sampling: scan-point regions per axis */
 
 static float f3min(float a, float b, float c) { return fminf(fminf(a, b), c); }
 static float f3max(float a, float b, float c) { return fmaxf(fmaxf(a, b), c); }
@@ -379,32 +381,77 @@ orc_prepared* orc_prepare(const orc_scene* sc)
         /* NLOS area sampling.  Sampling set: every triangle not lying in the
          * relay wall's plane (through the first scan point, along the wall
          * normal): seen from a scan point those subtend no solid angle.
-         * Triangle k of the set is drawn with probability w_k / W,
-         * w_k = A_k (g_k + g_max / 20): A_k its area, g_k = (cos_s cos_h / r^2)^2
-         * the square of the geometry term between the scan grid's centroid c
-         * and the triangle's centroid m_k (d = m_k - c, r = |d|, cos_s = the
-         * wall normal's cosine with d, clamped at 0, cos_h = |n_k . d| / r),
-         * g_max the largest g_k; the floor keeps every triangle of the set
-         * drawable (uniform by area if every g_k is 0).  The point is uniform
-         * within the triangle, so its area density is w_k / (W A_k); area_invp
-         * holds W A_k / w_k.  All in FP64 (float differences are exact). */
+         * The scan points are split into ORC_AREA_G x ORC_AREA_G regions of
+         * their bounding box, over the two axes of largest extent (the
+         * larger first, ties to the lower axis); region r has its own
+         * triangle pdf: triangle k of the set with probability w_k / W_r,
+         * w_k = A_k (g_k + g_max / 20), A_k its area, g_k = (cos_s cos_h / r^2)^2
+         * the square of the geometry term between the region's
+         * representative c (the mean of its scan points; the mean of all of
+         * them for an empty region) and the triangle's centroid m_k (d = m_k
+         * - c, r = |d|, cos_s = the wall normal's cosine with d, clamped at
+         * 0, cos_h = |n_k . d| / r), g_max the region's largest g_k; the floor
+         * keeps every triangle of the set drawable (uniform by area if every
+         * g_k is 0).  The point is uniform within the triangle, so its area
+         * density is w_k / (W_r A_k); area_invp holds W_r A_k / w_k.  All in
+         * FP64 (float differences are exact there). */
         const size_t ns = (size_t)sc->width * (size_t)sc->height;
-        double acc = 0.0, area_sum = 0.0, tol, n[3], s0[3], cs[3] = {0.0, 0.0, 0.0}, gmax = 0.0, floor_w;
+        const int nreg = ORC_AREA_G * ORC_AREA_G;
+        double area_sum = 0.0, tol, n[3], s0[3], lo[3], hi[3], ext[3], all[3] = {0.0, 0.0, 0.0};
+        double (*repr)[3] = (double(*)[3])calloc((size_t)nreg, sizeof(double[3]));
+        double* cnt = (double*)calloc((size_t)nreg, sizeof(double));
         double* area = (double*)malloc(sizeof(double) * (size_t)nt);
+        double* nrm = (double*)malloc(sizeof(double) * 3 * (size_t)nt);
+        double* cen3 = (double*)malloc(sizeof(double) * 3 * (size_t)nt);
         double* geo = (double*)malloc(sizeof(double) * (size_t)nt);
         size_t i;
-        int a;
+        int a, ax0, ax1, r;
         for (a = 0; a < 3; ++a) {
             n[a] = (double)sc->wall_normal[a];
             s0[a] = (double)P->scan[a];
+            lo[a] = hi[a] = (double)P->scan[a];
         }
         for (i = 0; i < ns; ++i)
-            for (a = 0; a < 3; ++a) cs[a] += (double)P->scan[3 * i + a];
-        for (a = 0; a < 3; ++a) cs[a] = cs[a] / (double)ns;
+            for (a = 0; a < 3; ++a) {
+                const double v = (double)P->scan[3 * i + a];
+                all[a] += v;
+                if (v < lo[a]) lo[a] = v;
+                if (v > hi[a]) hi[a] = v;
+            }
+        for (a = 0; a < 3; ++a) {
+            all[a] = all[a] / (double)ns;
+            ext[a] = hi[a] - lo[a];
+        }
+        /* the two axes of largest extent */
+        ax0 = 0;
+        for (a = 1; a < 3; ++a)
+            if (ext[a] > ext[ax0]) ax0 = a;
+        ax1 = (ax0 == 0) ? 1 : 0;
+        for (a = 0; a < 3; ++a)
+            if (a != ax0 && ext[a] > ext[ax1]) ax1 = a;
+        P->pix_region = (int*)malloc(sizeof(int) * ns);
+        for (i = 0; i < ns; ++i) {
+            int cell[2], q;
+            const int axes[2] = {ax0, ax1};
+            for (q = 0; q < 2; ++q) {
+                const int b = axes[q];
+                const double f = ext[b] > 0.0 ? ((double)P->scan[3 * i + b] - lo[b]) / ext[b] : 0.0;
+                int c = (int)floor(f * (double)ORC_AREA_G);
+                if (c < 0) c = 0;
+                if (c > ORC_AREA_G - 1) c = ORC_AREA_G - 1;
+                cell[q] = c;
+            }
+            r = cell[0] * ORC_AREA_G + cell[1];
+            P->pix_region[i] = r;
+            cnt[r] += 1.0;
+            for (a = 0; a < 3; ++a) repr[r][a] += (double)P->scan[3 * i + a];
+        }
+        for (r = 0; r < nreg; ++r)
+            for (a = 0; a < 3; ++a) repr[r][a] = cnt[r] > 0.0 ? repr[r][a] / cnt[r] : all[a];
         tol = 1e-6 * (1.0 + (double)maxabs);
         for (k = 0; k < nt; ++k) {
             const float* t = P->tri + 9 * k;
-            double e1[3], e2[3], c[3], len, m[3], dd[3], r2, r, cos_s, cos_h, q;
+            double e1[3], e2[3], c[3], len;
             int on_wall = 1, j;
             for (j = 0; j < 3; ++j) {
                 double h = ((double)t[3 * j] - s0[0]) * n[0] + ((double)t[3 * j + 1] - s0[1]) * n[1] +
@@ -412,47 +459,54 @@ orc_prepared* orc_prepare(const orc_scene* sc)
                 if (fabs(h) > tol) on_wall = 0;
             }
             area[k] = 0.0;
-            geo[k] = 0.0;
             if (on_wall) continue;
             for (a = 0; a < 3; ++a) {
                 e1[a] = (double)t[3 + a] - (double)t[a];
                 e2[a] = (double)t[6 + a] - (double)t[a];
-                m[a] = (((double)t[a] + (double)t[3 + a]) + (double)t[6 + a]) / 3.0;
-                dd[a] = m[a] - cs[a];
+                cen3[3 * k + a] = (((double)t[a] + (double)t[3 + a]) + (double)t[6 + a]) / 3.0;
             }
             c[0] = e1[1] * e2[2] - e1[2] * e2[1];
             c[1] = e1[2] * e2[0] - e1[0] * e2[2];
             c[2] = e1[0] * e2[1] - e1[1] * e2[0];
             len = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
             area[k] = 0.5 * len;
-            r2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
-            if (r2 > 0.0) {
-                r = sqrt(r2);
-                cos_s = (n[0] * dd[0] + n[1] * dd[1] + n[2] * dd[2]) / r;
-                if (cos_s < 0.0) cos_s = 0.0;
-                cos_h = fabs((c[0] / len) * dd[0] + (c[1] / len) * dd[1] + (c[2] / len) * dd[2]) / r;
-                q = (cos_s * cos_h) / r2;
-                geo[k] = q * q;
-            }
-            if (geo[k] > gmax) gmax = geo[k];
-        }
-        floor_w = (gmax > 0.0) ? gmax / 20.0 : 1.0;
-        P->area_cdf = (double*)malloc(sizeof(double) * (size_t)nt);
-        P->area_invp = (float*)malloc(sizeof(float) * (size_t)nt);
-        for (k = 0; k < nt; ++k) {
-            const double w = area[k] * (geo[k] + floor_w);
-            acc += w;
+            for (a = 0; a < 3; ++a) nrm[3 * k + a] = c[a] / len;
             area_sum += area[k];
-            P->area_cdf[k] = acc;
         }
-        for (k = 0; k < nt; ++k) {
-            const double w = area[k] * (geo[k] + floor_w);
-            P->area_invp[k] = (w > 0.0) ? (float)((acc * area[k]) / w) : 0.0f;
+        P->area_cdf = (double*)malloc(sizeof(double) * (size_t)nt * (size_t)nreg);
+        P->area_invp = (float*)malloc(sizeof(float) * (size_t)nt * (size_t)nreg);
+        P->weight_total = (double*)malloc(sizeof(double) * (size_t)nreg);
+        for (r = 0; r < nreg; ++r) {
+            double gmax = 0.0, floor_w, acc = 0.0;
+            for (k = 0; k < nt; ++k) {
+                double dd[3], r2;
+                geo[k] = 0.0;
+                if (!(area[k] > 0.0)) continue;
+                for (a = 0; a < 3; ++a) dd[a] = cen3[3 * k + a] - repr[r][a];
+                r2 = dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2];
+                if (r2 > 0.0) {
+                    const double rr = sqrt(r2);
+                    double cos_s = (n[0] * dd[0] + n[1] * dd[1] + n[2] * dd[2]) / rr, cos_h, q;
+                    if (cos_s < 0.0) cos_s = 0.0;
+                    cos_h = fabs(nrm[3 * k] * dd[0] + nrm[3 * k + 1] * dd[1] + nrm[3 * k + 2] * dd[2]) / rr;
+                    q = (cos_s * cos_h) / r2;
+                    geo[k] = q * q;
+                }
+                if (geo[k] > gmax) gmax = geo[k];
+            }
+            floor_w = (gmax > 0.0) ? gmax / 20.0 : 1.0;
+            for (k = 0; k < nt; ++k) {
+                acc += area[k] * (geo[k] + floor_w);
+                P->area_cdf[(size_t)r * nt + k] = acc;
+            }
+            for (k = 0; k < nt; ++k) {
+                const double w = area[k] * (geo[k] + floor_w);
+                P->area_invp[(size_t)r * nt + k] = (w > 0.0) ? (float)((acc * area[k]) / w) : 0.0f;
+            }
+            P->weight_total[r] = acc;
         }
-        P->weight_total = acc;
         P->area_total = area_sum;
-        free(area);
-        free(geo);
+        free(repr); free(cnt); free(area); free(nrm); free(cen3); free(geo);
     }
     return P;
 }
@@ -462,6 +516,7 @@ void orc_release(orc_prepared* P)
     if (!P) return;
     free(P->tri); free(P->box); free(P->mat); free(P->albedo); free(P->rough);
     free(P->scan); free(P->nodes); free(P->order); free(P->area_cdf); free(P->area_invp); free(P->ior); free(P->delay);
+    free(P->weight_total); free(P->pix_region);
     free(P);
 }
 
@@ -965,13 +1020,15 @@ int orc_trace_path(const orc_prepared* P, const orc_render* R, uint32_t pix, uin
          * p_A = w_k / (W A_k).  Its visibility is the shadow test of the
          * connection back to the scan point, which runs the same segment. */
         v3 xs = vload(P->scan + 3 * pix), e1, e2, v0, xh, dv, ng;
-        const double target_area = (double)u[0] * P->weight_total;
+        const int region = P->pix_region[pix];
+        const double* cdf = P->area_cdf + (size_t)region * (size_t)sc->n_tris;
+        const double target_area = (double)u[0] * P->weight_total[region];
         int lo = 0, hi = sc->n_tris - 1;
         float su, b1, b2, r2, r, cos_s0, cos_h, g;
-        if (!(P->weight_total > 0.0)) return 0;
+        if (!(P->weight_total[region] > 0.0)) return 0;
         while (lo < hi) { /* first triangle whose prefix sum exceeds the target */
             int mid = (lo + hi) / 2;
-            if (P->area_cdf[mid] > target_area) hi = mid;
+            if (cdf[mid] > target_area) hi = mid;
             else lo = mid + 1;
         }
         {
@@ -995,7 +1052,7 @@ int orc_trace_path(const orc_prepared* P, const orc_render* R, uint32_t pix, uin
         cos_h = fabsf(vdot(ng, d));
         if (!(cos_s0 > 0.0f) || !(cos_h > 0.0f)) return 0;
         g = (cos_s0 * cos_h) / r2;
-        beta = ((sc->wall_albedo * P->area_invp[lo]) * ORC_INV_PI_F) * g;
+        beta = ((sc->wall_albedo * P->area_invp[(size_t)region * (size_t)sc->n_tris + lo]) * ORC_INV_PI_F) * g;
         vmax = R->max_depth - 3;
         target = xs;
         forced_k = lo;
