@@ -66,13 +66,16 @@ enum {
  * instead of the hemisphere above the relay wall).  The first path vertex
  * after the scan point is drawn on the scene's triangles that do not lie in
  * the relay wall's plane (the plane through the first scan point with
- * normal wall_normal, within 1e-6 * (1 + largest |vertex coordinate|)):
- * triangle k with probability w_k / W, w_k = A_k (g_k + g_max / 20) in FP64
+ * normal wall_normal, within 1e-6 * (1 + largest |vertex coordinate|)).
+ * The scan points are split into 4 x 4 regions of their bounding box (over
+ * its two axes of largest extent); for a scan point of region r, triangle k
+ * is drawn with probability w_k / W_r, w_k = A_k (g_k + g_max / 20) in FP64
  * (A_k its area, g_k = (cos_s cos_h / r^2)^2 the squared geometry term
- * between the centroid of the scan points and the triangle's centroid,
- * g_max the largest), the point uniformly within it (square-root warp of
- * two uniforms).  The vertex carries the weight wall_albedo / pi *
- * cos_wall * cos_hidden / r^2 * W A_k / w_k; its visibility is the
+ * between the mean of the region's scan points and the triangle's
+ * centroid, g_max the region's largest), the point uniformly within it
+ * (square-root warp of two uniforms).  The vertex carries the weight
+ * wall_albedo / pi * cos_wall * cos_hidden / r^2 * W_r A_k / w_k; its
+ * visibility is the
  * next-event shadow test back to the scan point, which runs along the same
  * segment.  The estimate has the expectation of the default
  * (cosine-sampled) render.  A longer path continues from the drawn vertex

@@ -67,12 +67,15 @@ struct trhip_scene {
     float* d_ior;    // nullptr: no dielectric triangle
     float* d_delay;  // nullptr: no scattering delay
     double* d_grad;  // 2 * n_tris doubles of backward workspace
-    double* d_area_cdf;      // confocal: NLOS area-sampling prefix sums of the weights (caller order)
-    float* d_area_invp;      // confocal: inverse area density per triangle
-    uint32_t* d_sorted_of;   // confocal: BVH-order index of each caller triangle
-    uint32_t* d_area_guide;  // confocal: guide table of the prefix sums
+    // confocal: NLOS area-sampling tables, one set per scan region
+    double* d_area_cdf;      // [region][n_tris] prefix sums of the weights (caller order)
+    float* d_area_invp;      // [region][n_tris] inverse area densities
+    uint32_t* d_area_guide;  // [region][guide_cells + 1] guide tables
+    double* d_area_wtotal;   // [region] weight totals
+    uint8_t* d_area_region;  // [scan point] region
+    uint32_t* d_sorted_of;   // BVH-order index of each caller triangle
     uint32_t guide_cells;
-    double area_total;       // confocal: W, the total of the sampling weights
+    double area_total;       // area of the sampling set
     uint32_t n_pixels;
     size_t device_bytes;
 };
@@ -111,6 +114,8 @@ void free_scene(trhip_scene* s)
     (void)hipFree(s->d_area_invp);
     (void)hipFree(s->d_sorted_of);
     (void)hipFree(s->d_area_guide);
+    (void)hipFree(s->d_area_wtotal);
+    (void)hipFree(s->d_area_region);
     s->magic = 0;
     delete s;
 }
@@ -187,33 +192,75 @@ trhip_status validate_desc(const trhip_scene_desc* d, std::vector<float>& tri9)
     return TRHIP_OK;
 }
 
-// Sampling weights of NLOS area sampling.  The sampling set is every
-// triangle not lying in the relay wall's plane (the plane through scan point
-// s0 with normal wn, within 1e-6 * (1 + largest |coordinate|)): seen from a
-// scan point those subtend no solid angle.  Triangle k of the set has weight
-// w_k = A_k (g_k + g_max / 20), A_k its area and g_k = (cos_s cos_h / r^2)^2
-// the squared geometry term between the centroid c of the np scan points
-// and the triangle's centroid (d = centroid - c, r = |d|, cos_s = wn . d / r
-// clamped at 0, cos_h = |n_k . d| / r); the floor keeps every triangle of
-// the set drawable (all weights A_k if every g_k is 0).  Fills the inclusive
-// prefix sums in caller order (cdf), invp[k] = W A_k / w_k (the inverse area
-// density of a point drawn uniformly on triangle k; 0 outside the set) and
-// the set's area; returns W.  FP64 throughout: differences of FP32
-// coordinates are exact there.
-double area_prefix_sums(const std::vector<float>& tri9, uint32_t nt, const float* scan, size_t np, const float* wn,
-                        std::vector<double>& cdf, std::vector<float>& invp, double* set_area)
+constexpr int kAreaG = 4;                  // scan-point regions per axis
+constexpr int kAreaRegions = kAreaG * kAreaG;
+
+// Tables of NLOS area sampling.  The sampling set is every triangle not
+// lying in the relay wall's plane (the plane through the first scan point
+// with normal wn, within 1e-6 * (1 + largest |coordinate|)): seen from a scan
+// point those subtend no solid angle.  The np scan points are split into
+// kAreaG x kAreaG regions of their bounding box over its two axes of
+// largest extent (the larger first, ties to the lower axis); region r has
+// its own triangle pdf: triangle k of the set with weight
+// w_k = A_k (g_k + g_max / 20), A_k its area and g_k = (cos_s cos_h / r^2)^2 the
+// squared geometry term between the region's representative c (the mean of
+// its scan points; of all scan points if it has none) and the triangle's
+// centroid (d = centroid - c, r = |d|, cos_s = wn . d / r clamped at 0,
+// cos_h = |n_k . d| / r), g_max the region's largest g_k; the floor keeps
+// every triangle of the set drawable (all weights A_k if every g_k is 0).
+// Fills, region after region, the inclusive prefix sums in caller order
+// (cdf, [region][nt]), invp = W_r A_k / w_k (the inverse area density of a
+// point drawn uniformly on triangle k; 0 outside the set), the totals W_r,
+// each scan point's region, and returns the set's area.  FP64 throughout:
+// differences of FP32 coordinates are exact there.
+double area_tables(const std::vector<float>& tri9, uint32_t nt, const float* scan, size_t np, const float* wn,
+                   std::vector<double>& cdf, std::vector<float>& invp, std::vector<double>& wtotal,
+                   std::vector<uint8_t>& region)
 {
 #pragma clang fp contract(off)
     float maxabs = 0.0f;
     for (const float c : tri9) maxabs = std::max(maxabs, std::fabs(c));
     const double tol = 1e-6 * (1.0 + (double)maxabs);
-    double cs[3] = {0.0, 0.0, 0.0};
-    for (size_t i = 0; i < np; ++i)
-        for (int a = 0; a < 3; ++a) cs[a] += (double)scan[3 * i + a];
-    for (int a = 0; a < 3; ++a) cs[a] = cs[a] / (double)np;
     const double n[3] = {(double)wn[0], (double)wn[1], (double)wn[2]};
-    std::vector<double> area(nt, 0.0), geo(nt, 0.0);
-    double gmax = 0.0;
+    double lo[3], hi[3], ext[3], all[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < 3; ++a) lo[a] = hi[a] = (double)scan[a];
+    for (size_t i = 0; i < np; ++i)
+        for (int a = 0; a < 3; ++a) {
+            const double v = (double)scan[3 * i + a];
+            all[a] += v;
+            if (v < lo[a]) lo[a] = v;
+            if (v > hi[a]) hi[a] = v;
+        }
+    for (int a = 0; a < 3; ++a) {
+        all[a] = all[a] / (double)np;
+        ext[a] = hi[a] - lo[a];
+    }
+    int ax0 = 0;
+    for (int a = 1; a < 3; ++a)
+        if (ext[a] > ext[ax0]) ax0 = a;
+    int ax1 = ax0 == 0 ? 1 : 0;
+    for (int a = 0; a < 3; ++a)
+        if (a != ax0 && ext[a] > ext[ax1]) ax1 = a;
+    double repr[kAreaRegions][3] = {}, cnt[kAreaRegions] = {};
+    region.resize(np);
+    for (size_t i = 0; i < np; ++i) {
+        const int axes[2] = {ax0, ax1};
+        int cell[2];
+        for (int q = 0; q < 2; ++q) {
+            const int b = axes[q];
+            const double f = ext[b] > 0.0 ? ((double)scan[3 * i + b] - lo[b]) / ext[b] : 0.0;
+            int c = (int)std::floor(f * (double)kAreaG);
+            cell[q] = std::min(kAreaG - 1, std::max(0, c));
+        }
+        const int r = cell[0] * kAreaG + cell[1];
+        region[i] = (uint8_t)r;
+        cnt[r] += 1.0;
+        for (int a = 0; a < 3; ++a) repr[r][a] += (double)scan[3 * i + a];
+    }
+    for (int r = 0; r < kAreaRegions; ++r)
+        for (int a = 0; a < 3; ++a) repr[r][a] = cnt[r] > 0.0 ? repr[r][a] / cnt[r] : all[a];
+    std::vector<double> area(nt, 0.0), nrm(3ull * nt, 0.0), cen(3ull * nt, 0.0), geo(nt, 0.0);
+    double set_area = 0.0;
     for (uint32_t k = 0; k < nt; ++k) {
         const float* t = &tri9[9ull * k];
         bool on_wall = true;
@@ -224,61 +271,73 @@ double area_prefix_sums(const std::vector<float>& tri9, uint32_t nt, const float
             if (std::fabs(h) > tol) on_wall = false;
         }
         if (on_wall) continue;
-        double e1[3], e2[3], d[3];
+        double e1[3], e2[3];
         for (int a = 0; a < 3; ++a) {
             e1[a] = (double)t[3 + a] - (double)t[a];
             e2[a] = (double)t[6 + a] - (double)t[a];
-            d[a] = (((double)t[a] + (double)t[3 + a]) + (double)t[6 + a]) / 3.0 - cs[a];
+            cen[3 * k + a] = (((double)t[a] + (double)t[3 + a]) + (double)t[6 + a]) / 3.0;
         }
-        const double cx = e1[1] * e2[2] - e1[2] * e2[1];
-        const double cy = e1[2] * e2[0] - e1[0] * e2[2];
-        const double cz = e1[0] * e2[1] - e1[1] * e2[0];
-        const double len = std::sqrt(cx * cx + cy * cy + cz * cz);
+        const double c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                             e1[0] * e2[1] - e1[1] * e2[0]};
+        const double len = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
         area[k] = 0.5 * len;
-        const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-        if (r2 > 0.0) {
-            const double r = std::sqrt(r2);
-            double cos_s = (n[0] * d[0] + n[1] * d[1] + n[2] * d[2]) / r;
-            if (cos_s < 0.0) cos_s = 0.0;
-            const double cos_h = std::fabs((cx / len) * d[0] + (cy / len) * d[1] + (cz / len) * d[2]) / r;
-            const double q = (cos_s * cos_h) / r2;
-            geo[k] = q * q;
+        for (int a = 0; a < 3; ++a) nrm[3 * k + a] = c[a] / len;
+        set_area += area[k];
+    }
+    cdf.resize((size_t)kAreaRegions * nt);
+    invp.resize((size_t)kAreaRegions * nt);
+    wtotal.resize(kAreaRegions);
+    for (int r = 0; r < kAreaRegions; ++r) {
+        double gmax = 0.0;
+        for (uint32_t k = 0; k < nt; ++k) {
+            geo[k] = 0.0;
+            if (!(area[k] > 0.0)) continue;
+            double d[3];
+            for (int a = 0; a < 3; ++a) d[a] = cen[3 * k + a] - repr[r][a];
+            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (r2 > 0.0) {
+                const double rr = std::sqrt(r2);
+                double cos_s = (n[0] * d[0] + n[1] * d[1] + n[2] * d[2]) / rr;
+                if (cos_s < 0.0) cos_s = 0.0;
+                const double cos_h = std::fabs(nrm[3 * k] * d[0] + nrm[3 * k + 1] * d[1] + nrm[3 * k + 2] * d[2]) / rr;
+                const double q = (cos_s * cos_h) / r2;
+                geo[k] = q * q;
+            }
+            if (geo[k] > gmax) gmax = geo[k];
         }
-        if (geo[k] > gmax) gmax = geo[k];
+        const double floor_w = gmax > 0.0 ? gmax / 20.0 : 1.0;
+        double acc = 0.0;
+        for (uint32_t k = 0; k < nt; ++k) {
+            acc += area[k] * (geo[k] + floor_w);
+            cdf[(size_t)r * nt + k] = acc;
+        }
+        for (uint32_t k = 0; k < nt; ++k) {
+            const double w = area[k] * (geo[k] + floor_w);
+            invp[(size_t)r * nt + k] = w > 0.0 ? (float)((acc * area[k]) / w) : 0.0f;
+        }
+        wtotal[r] = acc;
     }
-    const double floor_w = gmax > 0.0 ? gmax / 20.0 : 1.0;
-    cdf.resize(nt);
-    invp.resize(nt);
-    double acc = 0.0, sum_area = 0.0;
-    for (uint32_t k = 0; k < nt; ++k) {
-        acc += area[k] * (geo[k] + floor_w);
-        sum_area += area[k];
-        cdf[k] = acc;
-    }
-    for (uint32_t k = 0; k < nt; ++k) {
-        const double w = area[k] * (geo[k] + floor_w);
-        invp[k] = w > 0.0 ? (float)((acc * area[k]) / w) : 0.0f;
-    }
-    *set_area = sum_area;
-    return acc;
+    return set_area;
 }
 
-// Guide table of the prefix sums (cutpoint method): cells = the smallest
-// power of two >= nt, at most 2^22; guide[m] = first k with
-// cdf[k] > (m / cells) * total, or nt - 1 if none, for m = 0 .. cells.
-uint32_t area_guide(const std::vector<double>& cdf, double total, std::vector<uint32_t>& guide)
+// Guide table of one region's prefix sums (cutpoint method): cells = the
+// smallest power of two >= nt / 4 (at least 1, at most 2^20); guide[m] = first
+// k with cdf[k] > (m / cells) * total, or nt - 1 if none, for m = 0 .. cells.
+uint32_t guide_cells_for(uint32_t nt)
 {
-    const uint32_t nt = (uint32_t)cdf.size();
     uint32_t cells = 1;
-    while (cells < nt && cells < (1u << 22)) cells <<= 1;
-    guide.resize(cells + 1ull);
+    while (cells < (nt + 3) / 4 && cells < (1u << 20)) cells <<= 1;
+    return cells;
+}
+
+void area_guide(const double* cdf, uint32_t nt, double total, uint32_t cells, uint32_t* guide)
+{
     uint32_t k = 0;
     for (uint32_t m = 0; m <= cells; ++m) {
         const double t = ((double)m / (double)cells) * total;
         while (k < nt - 1 && !(cdf[k] > t)) ++k;
         guide[m] = k;
     }
-    return cells;
 }
 
 template <class T>
@@ -328,9 +387,10 @@ void fill_view(trhip_scene* s, const trhip_scene_desc* d)
     v.unwarp = d->camera_unwarp ? 1 : 0;
     v.area_cdf = s->d_area_cdf;
     v.sorted_of = s->d_sorted_of;
-    v.area_total = s->area_total;
     v.area_invp = s->d_area_invp;
     v.area_guide = s->d_area_guide;
+    v.area_wtotal = s->d_area_wtotal;
+    v.area_region = s->d_area_region;
     v.guide_cells = (float)s->guide_cells;
     v.ior = s->d_ior;
     v.delay = s->d_delay;
@@ -481,18 +541,24 @@ trhip_status trhip_scene_create(const trhip_scene_desc* desc, void* stream, trhi
     if (e == hipSuccess) e = upload(&sc->d_mat, desc->mat_type, nt, s);
     if (e == hipSuccess) e = upload(&sc->d_albedo, desc->albedo, nt, s);
     if (e == hipSuccess) e = upload(&sc->d_rough, desc->roughness, nt, s);
-    std::vector<double> cdf;
+    std::vector<double> cdf, wtotal;
     std::vector<uint32_t> guide;
     std::vector<float> invp;
+    std::vector<uint8_t> region;
     if (e == hipSuccess && desc->sensor == TRHIP_SENSOR_CONFOCAL) {
         e = upload(&sc->d_scan, desc->scan_points, 3ull * sc->n_pixels, s);
-        double set_area = 0.0;
-        sc->area_total = area_prefix_sums(tri9, nt, desc->scan_points, (size_t)sc->n_pixels, desc->wall_normal, cdf,
-                                          invp, &set_area);
-        sc->guide_cells = area_guide(cdf, sc->area_total, guide);
-        if (e == hipSuccess) e = upload(&sc->d_area_cdf, cdf.data(), nt, s);
-        if (e == hipSuccess) e = upload(&sc->d_area_invp, invp.data(), nt, s);
+        sc->area_total = area_tables(tri9, nt, desc->scan_points, (size_t)sc->n_pixels, desc->wall_normal, cdf, invp,
+                                     wtotal, region);
+        sc->guide_cells = guide_cells_for(nt);
+        guide.resize((size_t)kAreaRegions * (sc->guide_cells + 1));
+        for (int r = 0; r < kAreaRegions; ++r)
+            area_guide(cdf.data() + (size_t)r * nt, nt, wtotal[r], sc->guide_cells,
+                       guide.data() + (size_t)r * (sc->guide_cells + 1));
+        if (e == hipSuccess) e = upload(&sc->d_area_cdf, cdf.data(), cdf.size(), s);
+        if (e == hipSuccess) e = upload(&sc->d_area_invp, invp.data(), invp.size(), s);
         if (e == hipSuccess) e = upload(&sc->d_area_guide, guide.data(), guide.size(), s);
+        if (e == hipSuccess) e = upload(&sc->d_area_wtotal, wtotal.data(), wtotal.size(), s);
+        if (e == hipSuccess) e = upload(&sc->d_area_region, region.data(), region.size(), s);
         if (e == hipSuccess) e = hipMalloc(&sc->d_sorted_of, (size_t)nt * sizeof(uint32_t));
     }
     bool any_dielectric = false, any_delay = false;
@@ -520,7 +586,7 @@ trhip_status trhip_scene_create(const trhip_scene_desc* desc, void* stream, trhi
         g_live.insert(sc);
     }
     sc->device_bytes = (size_t)sc->bvh.n_internal * sizeof(trhip::BvhNode) + (size_t)nt * sizeof(trhip::TriRec) +
-                       (size_t)nt * (1 + 4 + 4 + 16) + (sc->d_scan ? 12ull * sc->n_pixels + 16ull * nt + 4ull * (sc->guide_cells + 1) : 0) +
+                       (size_t)nt * (1 + 4 + 4 + 16) + (sc->d_scan ? 13ull * sc->n_pixels + 4ull * nt + (size_t)kAreaRegions * (12ull * nt + 4ull * (sc->guide_cells + 1) + 8) : 0) +
                        (sc->d_ior ? 4ull * nt : 0) + (sc->d_delay ? 4ull * nt : 0);
     *out = sc;
     return TRHIP_OK;

@@ -361,34 +361,37 @@ __device__ __forceinline__ void begin_path(const SceneView& S, const LaunchArgs&
     ps.v = 1;
 }
 
-// caller index of the area-sampled triangle: the first whose prefix sum
-// exceeds u0 * W, found by bisection between two guide-table entries (the
-// cutpoint method).  With m = floor(u0 * M), m / M <= u0 < (m + 1) / M
-// exactly, and FP64 rounding is monotone, so the thresholds of entries m
-// and m + 1 bracket u0 * W and their first indices bracket the answer.
-// u0 is a multiple of 2^-24 and M a power of two <= 2^22: u0 * M is exact.
-__device__ __forceinline__ uint32_t area_pick(const SceneView& S, float u0)
+// caller index of the area-sampled triangle for scan region r: the first
+// whose prefix sum exceeds u0 * W_r, found by bisection between two
+// guide-table entries (the cutpoint method).  With m = floor(u0 * M),
+// m / M <= u0 < (m + 1) / M exactly, and FP64 rounding is monotone, so the
+// thresholds of entries m and m + 1 bracket u0 * W_r and their first indices
+// bracket the answer.  u0 is a multiple of 2^-24 and M a power of two
+// <= 2^20: u0 * M is exact.
+__device__ __forceinline__ uint32_t area_pick(const SceneView& S, uint32_t r, float u0)
 {
-    const double target = (double)u0 * S.area_total;
+    const double* cdf = S.area_cdf + (size_t)r * S.n_tris;
+    const uint32_t* guide = S.area_guide + (size_t)r * ((uint32_t)S.guide_cells + 1u);
+    const double target = (double)u0 * S.area_wtotal[r];
     const uint32_t m = (uint32_t)(u0 * S.guide_cells);
-    uint32_t lo = S.area_guide[m], hi = S.area_guide[m + 1];
+    uint32_t lo = guide[m], hi = guide[m + 1];
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (S.area_cdf[mid] > target) hi = mid;
+        if (cdf[mid] > target) hi = mid;
         else lo = mid + 1;
     }
     return lo;
 }
 
-// NLOS area sampling (confocal, three bounces; the NLOS-tailored sampling
-// of Sec. 4.5): generation draws the hidden vertex itself -- triangle k of
-// the sampling set (the triangles off the relay wall's plane) with
-// probability w_k / W through the FP64 prefix sums of the weights (u0), the
-// point uniformly within it by the square-root warp (u1, u2) -- and joins it
-// to the offset scan point.  The area density w_k / (W A_k) converted to
-// solid angle at the scan point (times r^2 / cos_hidden) gives the weight
-// f_wall cos_wall / p = wall_albedo / pi * (W A_k / w_k) * cos_wall
-// cos_hidden / r^2.  The segment's visibility is left to the next-event
+// NLOS area sampling (confocal; the NLOS-tailored sampling of Sec. 4.5):
+// generation draws the hidden vertex itself -- triangle k of the sampling
+// set (the triangles off the relay wall's plane) with probability w_k / W_r
+// through the FP64 prefix sums of the weights of the scan point's region r
+// (u0), the point uniformly within it by the square-root warp (u1, u2) --
+// and joins it to the offset scan point.  The area density w_k / (W_r A_k)
+// converted to solid angle at the scan point (times r^2 / cos_hidden) gives
+// the weight f_wall cos_wall / p = wall_albedo / pi * (W_r A_k / w_k) *
+// cos_wall cos_hidden / r^2.  The segment's visibility is left to the next-event
 // shadow ray of the vertex, which tests the same segment back to the scan
 // point.  Returns false when the pair faces away (no contribution);
 // otherwise sets ps and the vertex's hit h (distance r, caller and
@@ -398,7 +401,8 @@ __device__ __forceinline__ bool begin_area(const SceneView& S, const LaunchArgs&
 {
     const rand4 u = draw4(pix, sample, 0u, L.stream_id, L.key0, L.key1);
     ps.u_ff = u.u2;
-    const uint32_t lo = area_pick(S, u.u0);
+    const uint32_t region = S.area_region[pix];
+    const uint32_t lo = area_pick(S, region, u.u0);
     const uint32_t j = S.sorted_of[lo];
     const TriRec tr = load_tri(S.tris, j);
     const vec3 e1 = v3(tr.e1x, tr.e1y, tr.e1z), e2 = v3(tr.e2x, tr.e2y, tr.e2z);
@@ -417,7 +421,7 @@ __device__ __forceinline__ bool begin_area(const SceneView& S, const LaunchArgs&
     const float cos_h = fabsf(dot(ng, d));
     if (!(cos_s > 0.0f) || !(cos_h > 0.0f)) return false;
     const float g = (cos_s * cos_h) / r2;
-    ps.beta = ((S.wall_albedo * S.area_invp[lo]) * kInvPi) * g;
+    ps.beta = ((S.wall_albedo * S.area_invp[(size_t)region * S.n_tris + lo]) * kInvPi) * g;
     ps.o = o;
     ps.d = d;
     ps.opl = 0.0f;
@@ -917,7 +921,7 @@ __device__ __forceinline__ uint32_t area_cell(const SceneView& S, const LaunchAr
                                               uint32_t sample)
 {
     const rand4 u = draw4(pix, sample, 0u, L.stream_id, L.key0, L.key1);
-    const uint32_t j = S.sorted_of[area_pick(S, u.u0)];
+    const uint32_t j = S.sorted_of[area_pick(S, S.area_region[pix], u.u0)];
     return (uint32_t)(((uint64_t)j * kDirCells) / S.n_tris);
 }
 

@@ -53,18 +53,21 @@ struct SceneView {
     float bin_width, bin_start;
     int32_t unwarp;
 
-    // NLOS area sampling (confocal): inclusive FP64 prefix sums of the
-    // triangles' sampling weights in caller order (0 on the relay wall's
-    // plane), their total, the inverse area density W A_k / w_k of a point
-    // drawn on triangle k, and the BVH-order index of each caller triangle;
-    // guide table of the inversion: area_guide[m] is the first triangle
-    // whose prefix sum exceeds (m / guide_cells) * area_total (clamped to
-    // n_tris - 1), m = 0 .. guide_cells; guide_cells a power of two <= 2^22
+    // NLOS area sampling (confocal), one set of tables per scan region
+    // (area_region[scan point]): inclusive FP64 prefix sums of the triangles'
+    // sampling weights in caller order ([region][n_tris], 0 on the relay
+    // wall's plane), their totals ([region]), the inverse area densities
+    // W_r A_k / w_k of a point drawn on triangle k ([region][n_tris]), and
+    // guide tables of the inversion ([region][guide_cells + 1]: entry m is
+    // the first triangle whose prefix sum exceeds (m / guide_cells) * W_r,
+    // clamped to n_tris - 1; guide_cells a power of two <= 2^20); plus the
+    // BVH-order index of each caller triangle
     const double* area_cdf;
     const float* area_invp;
-    const uint32_t* sorted_of;
     const uint32_t* area_guide;
-    double area_total;
+    const double* area_wtotal;
+    const uint8_t* area_region;
+    const uint32_t* sorted_of;
     float guide_cells;
 
     // refractive indices and scattering delays (caller order; nullptr when
