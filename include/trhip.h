@@ -87,7 +87,8 @@ enum {
  * position of the sampled triangle, so that a wave's shadow rays leave one
  * region of the hidden surface).  Anything else returns
  * TRHIP_ERR_UNSUPPORTED, as does a scene whose sampling set is empty.  Accepted by trhip_render_transient,
- * _counted, _phasor, _tangent and _backward; not by the batch API.
+ * _counted, _phasor, _tangent and _backward, and by the batch API (where
+ * such scenes run in the path form).
  */
 
 /*
@@ -318,7 +319,8 @@ trhip_status trhip_render_transient_counted(trhip_scene* scene, const trhip_rend
  *
  * scenes: HOST array of n_scenes live scene handles; renders: HOST array of
  * n_scenes render descriptions (overrides must be NULL; flags may only hold
- * TRHIP_FLAG_PIXEL_CENTRE; kernel/tile/block fields are ignored); films:
+ * TRHIP_FLAG_PIXEL_CENTRE and TRHIP_FLAG_NLOS_AREA_SAMPLING; kernel/tile/block
+ * fields are ignored); films:
  * HOST array of n_scenes DEVICE pointers, films[i] of scene i's film layout.
  * Unlike every other entry point, the batch keeps the scene handles and
  * the film pointers: the caller keeps them valid until trhip_batch_destroy.

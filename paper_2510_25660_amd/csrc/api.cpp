@@ -893,8 +893,9 @@ trhip_status trhip_batch_create(trhip_scene* const* scenes, const trhip_render_d
         if ((st = validate_render(scenes[i], &renders[i])) != TRHIP_OK) return st;
         if (renders[i].albedo_override || renders[i].roughness_override)
             return fail(TRHIP_ERR_INVALID_ARG, "scene %u: batched renders take no parameter overrides", i);
-        if (renders[i].flags & ~(uint32_t)TRHIP_FLAG_PIXEL_CENTRE)
-            return fail(TRHIP_ERR_INVALID_ARG, "scene %u: batched renders accept only TRHIP_FLAG_PIXEL_CENTRE", i);
+        if (renders[i].flags & ~(uint32_t)(TRHIP_FLAG_PIXEL_CENTRE | TRHIP_FLAG_NLOS_AREA_SAMPLING))
+            return fail(TRHIP_ERR_INVALID_ARG,
+                        "scene %u: batched renders accept only TRHIP_FLAG_PIXEL_CENTRE and TRHIP_FLAG_NLOS_AREA_SAMPLING", i);
         if (!films[i]) return fail(TRHIP_ERR_INVALID_ARG, "scene %u: film is NULL", i);
     }
     hipStream_t s = (hipStream_t)stream;

@@ -1236,7 +1236,9 @@ __global__ void __launch_bounds__(256) k_batch(BatchTables B)
         const uint32_t tile = item - B.item_start[lo];
         const SceneView* __restrict__ views = B.views;
         const LaunchArgs* __restrict__ args = B.args;
-        if (kDeferred)
+        // NLOS area sampling needs no first-hit traversal to defer: such
+        // scenes take the path-per-lane tile (same LDS film and stacks)
+        if (kDeferred && !(args[scene].flags & kFlagNlosArea))
             render_tile_deferred<false>(views[scene], args[scene], tile * args[scene].tile_pixels, lds, nullptr, fh,
                                         stk, (int)blockDim.x, tally);
         else

@@ -127,6 +127,30 @@ def test_area_sampling_adjoint_deeper(tr, oracle_mod):
             assert np.abs(ga - ga_o).max() <= 1e-4 * scale, (kernel, np.abs(ga - ga_o).max() / scale)
 
 
+@pytest.mark.parametrize("autotune", [False, True])
+def test_area_sampling_batch(tr, autotune):
+    """A batch mixing area-sampled and cosine-sampled confocal scans of
+    different sizes: every film equals its single render."""
+    import torch
+    scs = [scenes.confocal_nlos(grid=12, n_tris=3000, spp=256), scenes.confocal_nlos(grid=8, n_tris=1000, spp=128),
+           scenes.confocal_nlos(grid=10, n_tris=2000, spp=64, bounces=4)]
+    renders = [{"nlos_area": True}, {}, {"nlos_area": True}]
+    _announce(f"nlos area batch autotune={autotune}")
+    devs = [tr.upload(sc) for sc in scs]
+    try:
+        with tr.Batch(devs, renders=renders, autotune=autotune) as b:
+            films = [f.clone() for f in b.render()]
+            torch.cuda.synchronize()
+        for dev, kw, f in zip(devs, renders, films):
+            _, ref = tr.render_transient(dev, **kw)
+            torch.cuda.synchronize()
+            compare_films(f.cpu().numpy().reshape(dev.scene.n_pixels, -1),
+                          ref.cpu().numpy().reshape(dev.scene.n_pixels, -1).astype(np.float64), what="batch film")
+    finally:
+        for d in devs:
+            d.destroy()
+
+
 def test_area_sampling_unbiased_on_gpu(tr):
     """Same expectation as cosine sampling: 4-seed steady images of both
     estimators agree within 5 pooled standard errors; area sampling has
@@ -208,8 +232,8 @@ def test_area_sampling_adjoint(tr, oracle_mod, kernel):
 
 
 def test_area_sampling_rejections(tr):
-    """Other sensors, depths, media, the other kernel forms, the batch API
-    and a scene with nothing off the relay wall are refused (no launch)."""
+    """Other sensors, shallow depths, media, the wavefront form and a scene
+    with nothing off the relay wall are refused (no launch)."""
     _announce("nlos area rejections")
     box = scenes.box_scene(width=8, height=8, spp=2)
     with tr.upload(box) as dev:
@@ -222,8 +246,6 @@ def test_area_sampling_rejections(tr):
             with pytest.raises(tr.TrhipError) as e:
                 tr.render_transient(dev, nlos_area=True, **kw)
             assert e.value.status == STATUS_UNSUPPORTED, kw
-        with pytest.raises(tr.TrhipError):
-            tr.Batch([dev], renders=[{"nlos_area": True}], autotune=False)
     fog = scenes.confocal_nlos(grid=4, n_tris=500, spp=4)
     fog.sigma_t, fog.medium_albedo = 0.5, 0.8
     with tr.upload(fog) as dev:
