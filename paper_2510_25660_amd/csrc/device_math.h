@@ -54,9 +54,10 @@ __device__ __forceinline__ u32x4 philox4x32_10(u32x4 x, uint32_t k0, uint32_t k1
     constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t hi0 = __umulhi(kM0, x.a), lo0 = kM0 * x.a;
-        const uint32_t hi1 = __umulhi(kM1, x.c), lo1 = kM1 * x.c;
-        x = u32x4{hi1 ^ x.b ^ k0, lo1, hi0 ^ x.d ^ k1, lo0};
+        // one 32 x 32 -> 64-bit product per multiplier (v_mad_u64_u32),
+        // not separate high and low multiplies
+        const uint64_t p0 = (uint64_t)kM0 * x.a, p1 = (uint64_t)kM1 * x.c;
+        x = u32x4{(uint32_t)(p1 >> 32) ^ x.b ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ x.d ^ k1, (uint32_t)p0};
         k0 += kW0;
         k1 += kW1;
     }

@@ -121,7 +121,9 @@ __device__ __forceinline__ int link_of(uint16_t w) { return (int)(int16_t)w; }
 // Closest accepted triangle: smallest t, then smallest caller index.  A
 // triangle is accepted at t only if t is not before the entry of its own
 // padded box (the box stored for it in its parent), which makes the result
-// independent of the traversal order.
+// independent of the traversal order.  The caller-index check comes last,
+// so that the three loads of the record issue together instead of the last
+// one waiting for the first.
 template <class TallyT>
 __device__ __forceinline__ void leaf_closest(const SceneView& S, const Ray& r, int sorted, float tn, int exclude,
                                              Hit& h, TallyT& tally)
@@ -129,9 +131,8 @@ __device__ __forceinline__ void leaf_closest(const SceneView& S, const Ray& r, i
     tally.add(kTallyTris);
     const TriRec tr = load_tri(S.tris, sorted);
     const int prim = (int)tr.prim;
-    if (prim == exclude) return;
     float t;
-    if (!intersect_tri(r, tr, t) || tn > t) return;
+    if (!intersect_tri(r, tr, t) || tn > t || prim == exclude) return;
     if (t < h.t || (t == h.t && prim < h.prim)) {
         h.t = t;
         h.prim = prim;
@@ -229,9 +230,8 @@ __device__ __forceinline__ bool leaf_blocks(const SceneView& S, const Ray& r, in
 {
     tally.add(kTallyTris);
     const TriRec tr = load_tri(S.tris, sorted);
-    if ((int)tr.prim == exclude) return false;
     float t;
-    return intersect_tri(r, tr, t) && !(tn > t) && t < tmax;
+    return intersect_tri(r, tr, t) && !(tn > t) && t < tmax && (int)tr.prim != exclude;
 }
 
 // any accepted triangle other than `exclude` with t < tmax
