@@ -57,13 +57,16 @@ __device__ __forceinline__ void slab(const Ray& r, float lx, float ly, float lz,
     tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz));
 }
 
-// two-sided Moller-Trumbore on (v0, e1, e2)
-__device__ __forceinline__ bool intersect_tri(const Ray& r, const TriRec& tr, float& t)
+// two-sided Moller-Trumbore on (v0, e1, e2), for a triangle other than
+// `exclude` (its caller index is checked with the determinant, so the first
+// branch already needs the record's words and none of its loads is moved
+// behind it)
+__device__ __forceinline__ bool intersect_tri(const Ray& r, const TriRec& tr, int exclude, float& t)
 {
     const vec3 e1 = v3(tr.e1x, tr.e1y, tr.e1z), e2 = v3(tr.e2x, tr.e2y, tr.e2z);
     const vec3 p = cross(r.d, e2);
     const float det = dot(e1, p);
-    if (det == 0.0f) return false;
+    if (det == 0.0f || (int)tr.prim == exclude) return false;
     const float inv = 1.0f / det;
     const vec3 s = sub(r.o, v3(tr.v0x, tr.v0y, tr.v0z));
     const float u = dot(s, p) * inv;
@@ -73,6 +76,77 @@ __device__ __forceinline__ bool intersect_tri(const Ray& r, const TriRec& tr, fl
     if (v < 0.0f || u + v > 1.0f) return false;
     t = dot(e2, q) * inv;
     return t > 0.0f;
+}
+
+// Scenes with 16-bit links (at most 32,768 triangles, so nodes and
+// triangle records span a few MB) fetch them with buffer loads: a 32-bit
+// byte offset against a descriptor held in scalar registers, where a global
+// load needs a 64-bit address per lane (the 48-byte record stride costs a
+// quarter-rate 64-bit multiply).  Larger scenes use global loads.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ float4 buffer_f4(__amdgpu_buffer_rsrc_t R, uint32_t off)
+{
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(R, (int)off, 0, 0);
+    return make_float4(__uint_as_float(v[0]), __uint_as_float(v[1]), __uint_as_float(v[2]), __uint_as_float(v[3]));
+}
+
+__device__ __forceinline__ TriRec tri_of(float4 a, float4 b, float4 c)
+{
+    TriRec t;
+    t.v0x = a.x; t.v0y = a.y; t.v0z = a.z; t.prim = __float_as_uint(a.w);
+    t.e1x = b.x; t.e1y = b.y; t.e1z = b.z; t.unused0 = 0.0f;
+    t.e2x = c.x; t.e2y = c.y; t.e2z = c.z; t.unused1 = 0.0f;
+    return t;
+}
+
+// The triangle record of a leaf test.  On the global-load path the empty
+// asm statement takes v0 as an input, so that the compiler cannot move
+// v0's load behind the first early exit of the test (which needs only the
+// edges): all three loads are in flight together (+8 % on a 1M-triangle
+// scene).
+template <bool kBuf>
+__device__ __forceinline__ TriRec leaf_tri(const SceneView& S, int j)
+{
+    if constexpr (kBuf) {
+        const __amdgpu_buffer_rsrc_t R = buffer_of(S.tris, S.n_tris * (uint32_t)sizeof(TriRec));
+        const uint32_t off = (uint32_t)j * (uint32_t)sizeof(TriRec);
+        return tri_of(buffer_f4(R, off), buffer_f4(R, off + 16u), buffer_f4(R, off + 32u));
+    } else {
+        const float4* p = reinterpret_cast<const float4*>(S.tris + j);
+        const TriRec t = tri_of(p[0], p[1], p[2]);
+        asm volatile("" ::"v"(t.v0x), "v"(t.v0y), "v"(t.v0z));
+        return t;
+    }
+}
+
+// the 64-byte node n: child boxes in a, b, d; links in l.x, l.y
+struct NodeRec {
+    float4 a, b, d, l;
+};
+
+template <bool kBuf>
+__device__ __forceinline__ NodeRec load_node(const SceneView& S, int n)
+{
+    NodeRec v;
+    if constexpr (kBuf) {
+        const __amdgpu_buffer_rsrc_t R = buffer_of(S.nodes, S.n_tris * 64u);
+        const uint32_t off = (uint32_t)n << 6;
+        v.a = buffer_f4(R, off);
+        v.b = buffer_f4(R, off + 16u);
+        v.d = buffer_f4(R, off + 32u);
+        v.l = buffer_f4(R, off + 48u);
+    } else {
+        const float4* nodes = reinterpret_cast<const float4*>(S.nodes);
+        v.a = nodes[4 * n + 0];
+        v.b = nodes[4 * n + 1];
+        v.d = nodes[4 * n + 2];
+        v.l = nodes[4 * n + 3];
+    }
+    return v;
 }
 
 __device__ __forceinline__ TriRec load_tri(const TriRec* __restrict__ tris, int j)
@@ -121,18 +195,16 @@ __device__ __forceinline__ int link_of(uint16_t w) { return (int)(int16_t)w; }
 // Closest accepted triangle: smallest t, then smallest caller index.  A
 // triangle is accepted at t only if t is not before the entry of its own
 // padded box (the box stored for it in its parent), which makes the result
-// independent of the traversal order.  The caller-index check comes last,
-// so that the three loads of the record issue together instead of the last
-// one waiting for the first.
-template <class TallyT>
+// independent of the traversal order.
+template <bool kBuf = false, class TallyT>
 __device__ __forceinline__ void leaf_closest(const SceneView& S, const Ray& r, int sorted, float tn, int exclude,
                                              Hit& h, TallyT& tally)
 {
     tally.add(kTallyTris);
-    const TriRec tr = load_tri(S.tris, sorted);
+    const TriRec tr = leaf_tri<kBuf>(S, sorted);
     const int prim = (int)tr.prim;
     float t;
-    if (!intersect_tri(r, tr, t) || tn > t || prim == exclude) return;
+    if (!intersect_tri(r, tr, exclude, t) || tn > t) return;
     if (t < h.t || (t == h.t && prim < h.prim)) {
         h.t = t;
         h.prim = prim;
@@ -176,11 +248,9 @@ __device__ __forceinline__ bool closest_step(const SceneView& S, const Ray& r, i
     if (c.visits >= S.n_tris) return true;
     ++c.visits;
     tally.add(kTallyNodes);
-    const float4* nodes = reinterpret_cast<const float4*>(S.nodes);
-    const float4 a = nodes[4 * c.node + 0];
-    const float4 b = nodes[4 * c.node + 1];
-    const float4 d = nodes[4 * c.node + 2];
-    const float4 l = nodes[4 * c.node + 3];
+    constexpr bool kBuf = sizeof(W) == 2;
+    const NodeRec nd = load_node<kBuf>(S, c.node);
+    const float4 a = nd.a, b = nd.b, d = nd.d, l = nd.l;
     const int c0 = __float_as_int(l.x), c1 = __float_as_int(l.y);
     float tn0, tf0, tn1, tf1;
     slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tn0, tf0);
@@ -188,11 +258,11 @@ __device__ __forceinline__ bool closest_step(const SceneView& S, const Ray& r, i
     bool h0 = tn0 <= tf0 && tf0 >= 0.0f && tn0 <= c.h.t;
     bool h1 = tn1 <= tf1 && tf1 >= 0.0f && tn1 <= c.h.t;
     if (h0 && c0 < 0) {
-        leaf_closest(S, r, ~c0, tn0, exclude, c.h, tally);
+        leaf_closest<kBuf>(S, r, ~c0, tn0, exclude, c.h, tally);
         h0 = false;
     }
     if (h1 && c1 < 0) {
-        leaf_closest(S, r, ~c1, tn1, exclude, c.h, tally);
+        leaf_closest<kBuf>(S, r, ~c1, tn1, exclude, c.h, tally);
         h1 = false;
     }
     h0 = h0 && tn0 <= c.h.t;
@@ -224,14 +294,14 @@ __device__ Hit closest_hit(const SceneView& S, const Ray& r, int exclude, W* stk
     return c.h;
 }
 
-template <class TallyT>
+template <bool kBuf = false, class TallyT>
 __device__ __forceinline__ bool leaf_blocks(const SceneView& S, const Ray& r, int sorted, float tn, int exclude,
                                             float tmax, TallyT& tally)
 {
     tally.add(kTallyTris);
-    const TriRec tr = load_tri(S.tris, sorted);
+    const TriRec tr = leaf_tri<kBuf>(S, sorted);
     float t;
-    return intersect_tri(r, tr, t) && !(tn > t) && t < tmax && (int)tr.prim != exclude;
+    return intersect_tri(r, tr, exclude, t) && !(tn > t) && t < tmax;
 }
 
 // any accepted triangle other than `exclude` with t < tmax
@@ -247,13 +317,11 @@ __device__ bool occluded(const SceneView& S, const Ray& r, int exclude, float tm
     }
     int node = S.root;
     int sp = 0;
-    const float4* nodes = reinterpret_cast<const float4*>(S.nodes);
+    constexpr bool kBuf = sizeof(W) == 2;
     const int max_sp = (int)S.stack_depth;
     for (uint32_t visits = 0; visits < S.n_tris; ++visits) {
-        const float4 a = nodes[4 * node + 0];
-        const float4 b = nodes[4 * node + 1];
-        const float4 c = nodes[4 * node + 2];
-        const float4 l = nodes[4 * node + 3];
+        const NodeRec nd = load_node<kBuf>(S, node);
+        const float4 a = nd.a, b = nd.b, c = nd.d, l = nd.l;
         const int c0 = __float_as_int(l.x), c1 = __float_as_int(l.y);
         float tn0, tf0, tn1, tf1;
         slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tn0, tf0);
@@ -262,11 +330,11 @@ __device__ bool occluded(const SceneView& S, const Ray& r, int exclude, float tm
         bool h0 = tn0 <= tf0 && tf0 >= 0.0f && tn0 <= tmax;
         bool h1 = tn1 <= tf1 && tf1 >= 0.0f && tn1 <= tmax;
         if (h0 && c0 < 0) {
-            if (leaf_blocks(S, r, ~c0, tn0, exclude, tmax, tally)) return true;
+            if (leaf_blocks<kBuf>(S, r, ~c0, tn0, exclude, tmax, tally)) return true;
             h0 = false;
         }
         if (h1 && c1 < 0) {
-            if (leaf_blocks(S, r, ~c1, tn1, exclude, tmax, tally)) return true;
+            if (leaf_blocks<kBuf>(S, r, ~c1, tn1, exclude, tmax, tally)) return true;
             h1 = false;
         }
         if (h0 && h1 && sp < max_sp) {
