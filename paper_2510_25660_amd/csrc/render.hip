@@ -57,20 +57,26 @@ __device__ __forceinline__ void slab(const Ray& r, float lx, float ly, float lz,
     tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fmaxf(az, bz));
 }
 
-// two-sided Moller-Trumbore on (v0, e1, e2), for a triangle other than
-// `exclude` (its caller index is checked with the determinant, so the first
-// branch already needs the record's words and none of its loads is moved
-// behind it)
+// Two-sided Moller-Trumbore on (v0, e1, e2), for a triangle other than
+// `exclude`.  kEarly leaves at a zero determinant or at the excluded
+// triangle before the division (records fetched by buffer loads, which the
+// compiler issues together).  Otherwise those checks join the first test on
+// u, which needs v0: an early exit that needs only the edges lets the
+// compiler move v0's global load behind it, and the test then waits for two
+// round trips to memory instead of one.  Both orders compute the same
+// values; the division by a zero determinant is discarded.
+template <bool kEarly>
 __device__ __forceinline__ bool intersect_tri(const Ray& r, const TriRec& tr, int exclude, float& t)
 {
     const vec3 e1 = v3(tr.e1x, tr.e1y, tr.e1z), e2 = v3(tr.e2x, tr.e2y, tr.e2z);
     const vec3 p = cross(r.d, e2);
     const float det = dot(e1, p);
-    if (det == 0.0f || (int)tr.prim == exclude) return false;
+    const bool skip = det == 0.0f || (int)tr.prim == exclude;
+    if (kEarly && skip) return false;
     const float inv = 1.0f / det;
     const vec3 s = sub(r.o, v3(tr.v0x, tr.v0y, tr.v0z));
     const float u = dot(s, p) * inv;
-    if (u < 0.0f || u > 1.0f) return false;
+    if ((!kEarly && skip) || u < 0.0f || u > 1.0f) return false;
     const vec3 q = cross(s, e1);
     const float v = dot(r.d, q) * inv;
     if (v < 0.0f || u + v > 1.0f) return false;
@@ -103,11 +109,7 @@ __device__ __forceinline__ TriRec tri_of(float4 a, float4 b, float4 c)
     return t;
 }
 
-// The triangle record of a leaf test.  On the global-load path the empty
-// asm statement takes v0 as an input, so that the compiler cannot move
-// v0's load behind the first early exit of the test (which needs only the
-// edges): all three loads are in flight together (+8 % on a 1M-triangle
-// scene).
+// the triangle record of a leaf test
 template <bool kBuf>
 __device__ __forceinline__ TriRec leaf_tri(const SceneView& S, int j)
 {
@@ -117,9 +119,7 @@ __device__ __forceinline__ TriRec leaf_tri(const SceneView& S, int j)
         return tri_of(buffer_f4(R, off), buffer_f4(R, off + 16u), buffer_f4(R, off + 32u));
     } else {
         const float4* p = reinterpret_cast<const float4*>(S.tris + j);
-        const TriRec t = tri_of(p[0], p[1], p[2]);
-        asm volatile("" ::"v"(t.v0x), "v"(t.v0y), "v"(t.v0z));
-        return t;
+        return tri_of(p[0], p[1], p[2]);
     }
 }
 
@@ -204,7 +204,7 @@ __device__ __forceinline__ void leaf_closest(const SceneView& S, const Ray& r, i
     const TriRec tr = leaf_tri<kBuf>(S, sorted);
     const int prim = (int)tr.prim;
     float t;
-    if (!intersect_tri(r, tr, exclude, t) || tn > t) return;
+    if (!intersect_tri<kBuf>(r, tr, exclude, t) || tn > t) return;
     if (t < h.t || (t == h.t && prim < h.prim)) {
         h.t = t;
         h.prim = prim;
@@ -301,7 +301,7 @@ __device__ __forceinline__ bool leaf_blocks(const SceneView& S, const Ray& r, in
     tally.add(kTallyTris);
     const TriRec tr = leaf_tri<kBuf>(S, sorted);
     float t;
-    return intersect_tri(r, tr, exclude, t) && !(tn > t) && t < tmax;
+    return intersect_tri<kBuf>(r, tr, exclude, t) && !(tn > t) && t < tmax;
 }
 
 // any accepted triangle other than `exclude` with t < tmax
