@@ -60,6 +60,13 @@ KERNEL_SOURCES = ["paper_2510_25660_amd/csrc/render.hip", "paper_2510_25660_amd/
                   "paper_2510_25660_amd/csrc/scene_view.h", "paper_2510_25660_amd/csrc/bvh.hip"]
 
 
+def active_lanes(counts):
+    """Mean active lanes (of 64) when a wave runs a node visit, a triangle
+    test or a vertex, from the counting build's per-lane and per-wave counts."""
+    return {k: round(counts[k] / counts["wave_" + w], 2) if counts["wave_" + w] else None
+            for k, w in (("nodes", "nodes"), ("tris", "tris"), ("vertices", "vertices"))}
+
+
 def measured_traffic(workload):
     """HBM bytes per launch of the render kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary, or None when there is none or the kernel
@@ -345,7 +352,7 @@ def main():
     ms_per_step = total_ms / args.steps
     value = paths / (ms_per_step * 1e-3) / 1e6
     launch_ms = float(np.mean(per))
-    ops = sum(OPS_PER[k] * v for k, v in counts.items())
+    ops = sum(OPS_PER[k] * counts[k] for k in OPS_PER)
     # the kernel the automatic choice runs: the deferred form for the confocal sensor
     form = args.kernel if args.kernel != "auto" else ("deferred" if sc.sensor == 1 else "path")
     kernel_name = {"path": "k_render", "deferred": "k_render_deferred", "wavefront": "k_render_wf"}[form]
@@ -370,7 +377,8 @@ def main():
                      "unit": "T lane-ops/s", "frac": round(achieved / PEAK_VALU_LANE_OPS, 4),
                      "traffic": measured_traffic(args.workload), "traffic_unit": "bytes/launch",
                      "kernel": kernel_name, "launch_ms": round(launch_ms, 4),
-                     "ops_per_launch": int(ops), "counts": counts},
+                     "ops_per_launch": int(ops), "counts": counts,
+                     "active_lanes_per_wave": active_lanes(counts)},
     }
     if forms:
         out["kernel_forms_mpaths_per_s"] = forms

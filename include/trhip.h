@@ -293,19 +293,26 @@ trhip_status trhip_render_transient_backward(trhip_scene* scene, const trhip_ren
  * Diagnostic variant of trhip_render_transient: the same render (same
  * output, same paths) by a build of the kernel that also counts its work.
  * counts: HOST uint64[TRHIP_COUNT_N], overwritten, indexed by TRHIP_COUNT_*.
- * Synchronous (returns after the render has finished); allocates a small
- * device buffer.  Errors: as trhip_render_transient, plus INVALID_ARG for
- * a NULL counts.
+ * The first seven count work per path (lane); the WAVE_* entries count how
+ * many times a wave executed the block with at least one lane, so that
+ * TRHIP_COUNT_NODES / TRHIP_COUNT_WAVE_NODES is the mean number of active
+ * lanes (of 64) in a node visit, and likewise for triangle tests and
+ * vertices.  Synchronous (returns after the render has finished); allocates
+ * a small device buffer.  Errors: as trhip_render_transient, plus
+ * INVALID_ARG for a NULL counts.
  */
 enum {
-    TRHIP_COUNT_NODES = 0,    /* BVH internal-node visits (both child boxes tested) */
-    TRHIP_COUNT_TRIS = 1,     /* ray-triangle tests */
-    TRHIP_COUNT_RAYS = 2,     /* closest-hit rays */
-    TRHIP_COUNT_SHADOW = 3,   /* shadow (any-hit) rays */
-    TRHIP_COUNT_VERTS = 4,    /* scattering vertices (surface or medium) */
-    TRHIP_COUNT_DRAWS = 5,    /* Philox4x32-10 evaluations */
-    TRHIP_COUNT_CONTRIB = 6,  /* contributions scattered into the film */
-    TRHIP_COUNT_N = 7
+    TRHIP_COUNT_NODES = 0,       /* BVH internal-node visits (both child boxes tested) */
+    TRHIP_COUNT_TRIS = 1,        /* ray-triangle tests */
+    TRHIP_COUNT_RAYS = 2,        /* closest-hit rays */
+    TRHIP_COUNT_SHADOW = 3,      /* shadow (any-hit) rays */
+    TRHIP_COUNT_VERTS = 4,       /* scattering vertices (surface or medium) */
+    TRHIP_COUNT_DRAWS = 5,       /* Philox4x32-10 evaluations */
+    TRHIP_COUNT_CONTRIB = 6,     /* contributions scattered into the film */
+    TRHIP_COUNT_WAVE_NODES = 7,  /* wave executions of a node visit */
+    TRHIP_COUNT_WAVE_TRIS = 8,   /* wave executions of a triangle test */
+    TRHIP_COUNT_WAVE_VERTS = 9,  /* wave executions of a vertex */
+    TRHIP_COUNT_N = 10
 };
 trhip_status trhip_render_transient_counted(trhip_scene* scene, const trhip_render_desc* render, float* film,
                                             float* steady, float* oow, uint64_t* counts, void* stream);

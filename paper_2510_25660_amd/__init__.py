@@ -259,7 +259,9 @@ def render_transient_counted(dev: DeviceScene, spp=None, seed=None, max_depth=No
     """Same render as render_transient by the counting build of the kernel;
     returns (steady, film, counts) with counts a dict of work counters
     (BVH node visits, triangle tests, rays, shadow rays, vertices, Philox
-    draws, contributions).  Synchronous."""
+    draws, contributions, per path) and of wave executions of node visits,
+    triangle tests and vertices (their ratios are the mean active lanes).
+    Synchronous."""
     torch = _torch()
     from ._binding import COUNT_NAMES
     sc = dev.scene

@@ -32,7 +32,8 @@ EXPORTED_SYMBOLS = (
     "trhip_batch_destroy", "trhip_poisson_noise", "trhip_render_phasor", "trhip_render_transient_tangent",
 )
 
-COUNT_NAMES = ("nodes", "tris", "rays", "shadow_rays", "vertices", "draws", "contributions")
+COUNT_NAMES = ("nodes", "tris", "rays", "shadow_rays", "vertices", "draws", "contributions", "wave_nodes",
+               "wave_tris", "wave_vertices")
 
 
 class TrhipError(RuntimeError):

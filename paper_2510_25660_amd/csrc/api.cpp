@@ -24,6 +24,8 @@
 #include "internal.h"
 #include "scene_view.h"
 
+static_assert(trhip::kWorkCounters == TRHIP_COUNT_N, "counting build and ABI agree");
+
 namespace {
 
 constexpr uint32_t kSceneMagic = 0x54524850u;  // "TRHP"

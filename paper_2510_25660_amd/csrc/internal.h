@@ -40,6 +40,9 @@ inline uint32_t stack_lane_bytes(uint32_t n_tris, uint32_t stack_depth)
     return stack_depth * (short_stack(n_tris) ? 2u : 4u);
 }
 
+// entries of the counting build's output (TRHIP_COUNT_N)
+constexpr int kWorkCounters = 10;
+
 // LDS bytes of one render / backward workgroup (stack_bytes per lane)
 size_t render_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes);
 size_t wavefront_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes);

@@ -168,18 +168,39 @@ struct Hit {
 
 // Work counters of the profiling build (compiled out otherwise): node
 // visits, triangle tests, closest-hit rays, shadow rays, scattering
-// vertices, Philox draws, contributions.
-enum { kTallyNodes, kTallyTris, kTallyRays, kTallyShadow, kTallyVerts, kTallyDraws, kTallyContrib, kTallyN };
+// vertices, Philox draws, contributions (per lane), then wave executions of
+// node visits, triangle tests and vertices (once per wave, by its first
+// active lane).  Same order as TRHIP_COUNT_*.
+enum {
+    kTallyNodes,
+    kTallyTris,
+    kTallyRays,
+    kTallyShadow,
+    kTallyVerts,
+    kTallyDraws,
+    kTallyContrib,
+    kTallyWaveNodes,
+    kTallyWaveTris,
+    kTallyWaveVerts,
+    kTallyN
+};
+static_assert(kTallyN == kWorkCounters, "one tally per work counter");
 
 template <bool kOn>
 struct Tally {
     __device__ __forceinline__ void add(int, uint32_t = 1u) {}
+    __device__ __forceinline__ void wave(int) {}
     __device__ __forceinline__ void flush(unsigned long long*) {}
 };
 template <>
 struct Tally<true> {
-    uint32_t n[kTallyN] = {0, 0, 0, 0, 0, 0, 0};
+    uint32_t n[kTallyN] = {};
     __device__ __forceinline__ void add(int i, uint32_t v = 1u) { n[i] += v; }
+    __device__ __forceinline__ void wave(int i)
+    {
+        const uint64_t active = __builtin_amdgcn_read_exec();
+        if (__lane_id() == (uint32_t)__builtin_ctzll(active)) n[i] += 1u;
+    }
     __device__ __forceinline__ void flush(unsigned long long* out)
     {
         for (int i = 0; i < kTallyN; ++i) atomicAdd(out + i, (unsigned long long)n[i]);
@@ -201,6 +222,7 @@ __device__ __forceinline__ void leaf_closest(const SceneView& S, const Ray& r, i
                                              Hit& h, TallyT& tally)
 {
     tally.add(kTallyTris);
+    tally.wave(kTallyWaveTris);
     const TriRec tr = leaf_tri<kBuf>(S, sorted);
     const int prim = (int)tr.prim;
     float t;
@@ -248,6 +270,7 @@ __device__ __forceinline__ bool closest_step(const SceneView& S, const Ray& r, i
     if (c.visits >= S.n_tris) return true;
     ++c.visits;
     tally.add(kTallyNodes);
+    tally.wave(kTallyWaveNodes);
     constexpr bool kBuf = sizeof(W) == 2;
     const NodeRec nd = load_node<kBuf>(S, c.node);
     const float4 a = nd.a, b = nd.b, d = nd.d, l = nd.l;
@@ -299,6 +322,7 @@ __device__ __forceinline__ bool leaf_blocks(const SceneView& S, const Ray& r, in
                                             float tmax, TallyT& tally)
 {
     tally.add(kTallyTris);
+    tally.wave(kTallyWaveTris);
     const TriRec tr = leaf_tri<kBuf>(S, sorted);
     float t;
     return intersect_tri<kBuf>(r, tr, exclude, t) && !(tn > t) && t < tmax;
@@ -327,6 +351,7 @@ __device__ bool occluded(const SceneView& S, const Ray& r, int exclude, float tm
         slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tn0, tf0);
         slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tn1, tf1);
         tally.add(kTallyNodes);
+        tally.wave(kTallyWaveNodes);
         bool h0 = tn0 <= tf0 && tf0 >= 0.0f && tn0 <= tmax;
         bool h1 = tn1 <= tf1 && tf1 >= 0.0f && tn1 <= tmax;
         if (h0 && c0 < 0) {
@@ -569,6 +594,7 @@ __device__ __forceinline__ void shade_vertex(const SceneView& S, const LaunchArg
     const int vmax = last_vertex(S, L);
     const int v = ps.v;
     tally.add(kTallyVerts);
+    tally.wave(kTallyWaveVerts);
     nee.valid = false;
     cont.alive = false;
     cont.k = med ? -1 : h.prim;
