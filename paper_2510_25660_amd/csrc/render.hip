@@ -1267,6 +1267,22 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
 
 // Five waves per SIMD (at most 96 VGPRs, a few spilled outside the
 // traversal loops) beat four without spills by 15% on confocal scans.
+// Workgroups go to the 8 XCDs in turn (workgroup b runs on XCD b mod 8),
+// and each XCD has its own L2.  The launch index is remapped so that, within
+// every run of 8 * kXcdGroup workgroups, XCD x takes kXcdGroup consecutive
+// tiles: the tiles an XCD holds at once are neighbours, whose rays meet the
+// same part of the scene in its L2, while all XCDs still sweep the image
+// together.  Workgroups past the last full run keep their index.
+constexpr uint32_t kXcds = 8, kXcdGroup = 64;
+__device__ __forceinline__ uint32_t xcd_block()
+{
+    const uint32_t b = blockIdx.x, n = gridDim.x;
+    constexpr uint32_t run = kXcds * kXcdGroup;
+    if (b >= (n / run) * run) return b;
+    const uint32_t x = b % kXcds, k = b / kXcds;  // the k-th workgroup of XCD x
+    return (k / kXcdGroup) * run + x * kXcdGroup + k % kXcdGroup;
+}
+
 template <bool kCount, class W, bool kArea>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 k_render_deferred(SceneView S, LaunchArgs L, unsigned long long* counts)
@@ -1275,7 +1291,8 @@ k_render_deferred(SceneView S, LaunchArgs L, unsigned long long* counts)
     extern __shared__ float lds[];
     const uint32_t TP = L.tile_pixels;
     // workgroup -> (tile, chunk of the tile's samples)
-    const uint32_t tile = blockIdx.x / L.chunks, chunk = blockIdx.x - tile * L.chunks;
+    const uint32_t wg = xcd_block();
+    const uint32_t tile = wg / L.chunks, chunk = wg - tile * L.chunks;
     LaunchArgs Lc = L;
     Lc.sample_offset = L.sample_offset + chunk * L.chunk_spp;
     Lc.spp = min(L.chunk_spp, L.spp - chunk * L.chunk_spp);
@@ -1297,7 +1314,7 @@ __global__ void __launch_bounds__(256) k_render(SceneView S, LaunchArgs L, unsig
     __shared__ float s_freq[kMaxFreq];
     load_freqs(L, s_freq);
     W* stk = reinterpret_cast<W*>(lds + (size_t)TP * film_words(S, L) + 2 * TP) + threadIdx.x;
-    render_tile(S, L, blockIdx.x * TP, lds, s_freq, stk, (int)blockDim.x, tally);
+    render_tile(S, L, xcd_block() * TP, lds, s_freq, stk, (int)blockDim.x, tally);
     tally.flush(counts);
 }
 
@@ -1428,7 +1445,7 @@ __global__ void __launch_bounds__(256) k_render_wf(SceneView S, LaunchArgs L, un
     float* toow = tsteady + TP;
     const WfSlots w = carve_slots(toow + TP, nb);
     W* stk = reinterpret_cast<W*>(toow + TP + (size_t)kWfWords * nb) + tid;
-    const uint32_t p0 = blockIdx.x * TP;
+    const uint32_t p0 = xcd_block() * TP;
     const uint32_t npix = min(TP, L.n_pixels - p0);
     for (uint32_t i = tid; i < TP * T + 2 * TP; i += nb) lds[i] = 0.0f;
     w.live[tid] = 0;
@@ -1645,7 +1662,7 @@ __global__ void __launch_bounds__(256) k_render_tangent(SceneView S, LaunchArgs 
     float* tsteady = tdfilm + (size_t)TP * T;
     W* stk = reinterpret_cast<W*>(tsteady + TP) + threadIdx.x;
     const int stride = (int)blockDim.x;
-    const uint32_t p0 = blockIdx.x * TP;
+    const uint32_t p0 = xcd_block() * TP;
     const uint32_t npix = min(TP, L.n_pixels - p0);
     for (uint32_t i = threadIdx.x; i < 2 * TP * T + TP; i += blockDim.x) lds[i] = 0.0f;
     __syncthreads();
@@ -1686,7 +1703,7 @@ __global__ void __launch_bounds__(256) k_backward(SceneView S, LaunchArgs L)
     float* tprimal = lds + (size_t)TP * T;
     W* stk = reinterpret_cast<W*>(tprimal + (want_primal ? (size_t)TP * T : 0)) + threadIdx.x;
     const int stride = (int)blockDim.x;
-    const uint32_t p0 = blockIdx.x * TP;
+    const uint32_t p0 = xcd_block() * TP;
     const uint32_t npix = min(TP, L.n_pixels - p0);
     const size_t base = (size_t)p0 * T;
     for (uint32_t i = threadIdx.x; i < TP * T; i += blockDim.x) {
@@ -1797,7 +1814,7 @@ k_backward_stash(SceneView S, LaunchArgs L)
     float* tprimal = lds + (size_t)TP * T;
     W* stk = reinterpret_cast<W*>(tprimal + (want_primal ? (size_t)TP * T : 0)) + threadIdx.x;
     const int stride = (int)blockDim.x;
-    const uint32_t p0 = blockIdx.x * TP;
+    const uint32_t p0 = xcd_block() * TP;
     const uint32_t npix = min(TP, L.n_pixels - p0);
     const size_t base = (size_t)p0 * T;
     for (uint32_t i = threadIdx.x; i < TP * T; i += blockDim.x) {
