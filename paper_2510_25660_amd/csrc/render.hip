@@ -1583,6 +1583,61 @@ struct AdjointSumSink {
     __device__ __forceinline__ void continuation(int, int, float, float) {}
 };
 
+// Per-workgroup gradient cache in LDS.  The paths of a tile keep meeting
+// the same triangles, so instead of one FP64 global atomic per vertex and
+// parameter, a workgroup sums its gradients in an open-addressing table of
+// kGradSlots slots keyed by triangle (LDS atomics), and adds each touched
+// triangle's two sums to the global gradients once, at the end of the tile.
+// A triangle that finds no slot within kGradProbes probes goes straight to
+// the global gradients.  Layout from an 8-byte aligned base: FP64 albedo
+// sums, FP64 roughness sums, int keys (-1 = empty).
+constexpr uint32_t kGradSlots = 512;
+constexpr int kGradProbes = 8;
+constexpr uint32_t kGradCacheFloats = kGradSlots * 5;  // 2 doubles + 1 int per slot, in 4-byte words
+
+__device__ __forceinline__ void grad_add(double* cache, double* g_alb, double* g_rough, int k, double a, double r)
+{
+    if (a == 0.0 && r == 0.0) return;
+    double* ga = cache;
+    double* gr = cache + kGradSlots;
+    int* key = reinterpret_cast<int*>(cache + 2 * kGradSlots);
+    const uint32_t h = ((uint32_t)k * 2654435761u) >> 23;
+    for (int p = 0; p < kGradProbes; ++p) {
+        const uint32_t slot = (h + (uint32_t)p) & (kGradSlots - 1);
+        int cur = key[slot];
+        if (cur == -1) cur = atomicCAS(key + slot, -1, k);
+        if (cur == -1 || cur == k) {
+            if (a != 0.0) unsafeAtomicAdd(ga + slot, a);
+            if (r != 0.0) unsafeAtomicAdd(gr + slot, r);
+            return;
+        }
+    }
+    if (a != 0.0) unsafeAtomicAdd(g_alb + k, a);
+    if (r != 0.0) unsafeAtomicAdd(g_rough + k, r);
+}
+
+__device__ __forceinline__ void grad_cache_clear(double* cache)
+{
+    int* key = reinterpret_cast<int*>(cache + 2 * kGradSlots);
+    for (uint32_t i = threadIdx.x; i < kGradSlots; i += blockDim.x) {
+        cache[i] = 0.0;
+        cache[kGradSlots + i] = 0.0;
+        key[i] = -1;
+    }
+}
+
+// after a barrier: the table's sums to the global gradients
+__device__ __forceinline__ void grad_cache_flush(const double* cache, double* g_alb, double* g_rough)
+{
+    const int* key = reinterpret_cast<const int*>(cache + 2 * kGradSlots);
+    for (uint32_t i = threadIdx.x; i < kGradSlots; i += blockDim.x) {
+        const int k = key[i];
+        if (k < 0) continue;
+        if (cache[i] != 0.0) unsafeAtomicAdd(g_alb + k, cache[i]);
+        if (cache[kGradSlots + i] != 0.0) unsafeAtomicAdd(g_rough + k, cache[kGradSlots + i]);
+    }
+}
+
 struct AdjointScatterSink {
     static constexpr bool kWantsGradients = true;
     const float* delta;
@@ -1592,6 +1647,7 @@ struct AdjointScatterSink {
     double prefix;      // sum of a_j so far
     double* g_alb;
     double* g_rough;
+    double* cache;      // the workgroup's LDS gradient table
     __device__ __forceinline__ void contribution(int, int k, float c, int bin, float, float g_alb_nee,
                                                  float g_rough_nee)
     {
@@ -1599,18 +1655,12 @@ struct AdjointScatterSink {
         if (primal_row) atomicAdd(primal_row + bin, c);
         const double a = (double)delta[bin] * (double)c * (double)norm;
         prefix += a;
-        if (k >= 0 && a != 0.0) {
-            unsafeAtomicAdd(g_alb + k, a * (double)g_alb_nee);
-            if (g_rough_nee != 0.0f) unsafeAtomicAdd(g_rough + k, a * (double)g_rough_nee);
-        }
+        if (k >= 0 && a != 0.0) grad_add(cache, g_alb, g_rough, k, a * (double)g_alb_nee, a * (double)g_rough_nee);
     }
     __device__ __forceinline__ void continuation(int, int k, float g_alb_c, float g_rough_c)
     {
         const double rest = total - prefix;
-        if (rest != 0.0) {
-            unsafeAtomicAdd(g_alb + k, rest * (double)g_alb_c);
-            if (g_rough_c != 0.0f) unsafeAtomicAdd(g_rough + k, rest * (double)g_rough_c);
-        }
+        if (rest != 0.0) grad_add(cache, g_alb, g_rough, k, rest * (double)g_alb_c, rest * (double)g_rough_c);
     }
 };
 
@@ -1699,8 +1749,9 @@ __global__ void __launch_bounds__(256) k_backward(SceneView S, LaunchArgs L)
     const uint32_t T = S.n_bins;
     const uint32_t TP = L.tile_pixels;
     const bool want_primal = L.primal != nullptr;
-    float* tdelta = lds;
-    float* tprimal = lds + (size_t)TP * T;
+    double* cache = reinterpret_cast<double*>(lds);
+    float* tdelta = lds + kGradCacheFloats;
+    float* tprimal = tdelta + (size_t)TP * T;
     W* stk = reinterpret_cast<W*>(tprimal + (want_primal ? (size_t)TP * T : 0)) + threadIdx.x;
     const int stride = (int)blockDim.x;
     const uint32_t p0 = xcd_block() * TP;
@@ -1710,6 +1761,7 @@ __global__ void __launch_bounds__(256) k_backward(SceneView S, LaunchArgs L)
         tdelta[i] = (i < npix * T) ? L.grad_film[base + i] : 0.0f;
         if (want_primal) tprimal[i] = 0.0f;
     }
+    grad_cache_clear(cache);
     __syncthreads();
 
     const uint32_t work = npix * L.spp;
@@ -1720,13 +1772,13 @@ __global__ void __launch_bounds__(256) k_backward(SceneView S, LaunchArgs L)
         AdjointSumSink first{drow, L.norm, 0.0};
         trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, first, tally);
         AdjointScatterSink second{drow, want_primal ? tprimal + (size_t)pl * T : nullptr, L.norm, first.total, 0.0,
-                                  L.g_alb, L.g_rough};
+                                  L.g_alb, L.g_rough, cache};
         trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, second, tally);
     }
-    if (want_primal) {
-        __syncthreads();
+    __syncthreads();
+    grad_cache_flush(cache, L.g_alb, L.g_rough);
+    if (want_primal)
         for (uint32_t i = threadIdx.x; i < npix * T; i += blockDim.x) L.primal[base + i] = tprimal[i] * L.norm;
-    }
 }
 
 // Single-trace adjoint for paths of at most kMaxCont continuations.  The
@@ -1744,6 +1796,7 @@ struct AdjointStashSink {
     float norm;
     double* g_alb;
     double* g_rough;
+    double* cache;  // the workgroup's LDS gradient table
     int nv = 0;
     int k[kMaxCont];
     float ca[kMaxCont], cr[kMaxCont], na[kMaxCont], nr[kMaxCont], R[kMaxCont];
@@ -1785,17 +1838,13 @@ struct AdjointStashSink {
     }
     __device__ __forceinline__ void finish()
     {
-        if (pending) {
-            if (pa != 0.0f) unsafeAtomicAdd(g_alb + pk, (double)pa);
-            if (pr != 0.0f) unsafeAtomicAdd(g_rough + pk, (double)pr);
-        }
+        if (pending) grad_add(cache, g_alb, g_rough, pk, (double)pa, (double)pr);
 #pragma unroll
         for (int i = 0; i < kMaxCont; ++i)
             if (i < nv) {
                 const double ga = (double)na[i] + (double)R[i] * (double)ca[i];
                 const double gr = (double)nr[i] + (double)R[i] * (double)cr[i];
-                if (ga != 0.0) unsafeAtomicAdd(g_alb + k[i], ga);
-                if (gr != 0.0) unsafeAtomicAdd(g_rough + k[i], gr);
+                grad_add(cache, g_alb, g_rough, k[i], ga, gr);
             }
     }
 };
@@ -1810,8 +1859,9 @@ k_backward_stash(SceneView S, LaunchArgs L)
     const uint32_t T = S.n_bins;
     const uint32_t TP = L.tile_pixels;
     const bool want_primal = L.primal != nullptr;
-    float* tdelta = lds;
-    float* tprimal = lds + (size_t)TP * T;
+    double* cache = reinterpret_cast<double*>(lds);
+    float* tdelta = lds + kGradCacheFloats;
+    float* tprimal = tdelta + (size_t)TP * T;
     W* stk = reinterpret_cast<W*>(tprimal + (want_primal ? (size_t)TP * T : 0)) + threadIdx.x;
     const int stride = (int)blockDim.x;
     const uint32_t p0 = xcd_block() * TP;
@@ -1821,6 +1871,7 @@ k_backward_stash(SceneView S, LaunchArgs L)
         tdelta[i] = (i < npix * T) ? L.grad_film[base + i] : 0.0f;
         if (want_primal) tprimal[i] = 0.0f;
     }
+    grad_cache_clear(cache);
     __syncthreads();
     const uint32_t work = npix * L.spp;
     for (uint32_t w = threadIdx.x; w < work; w += blockDim.x) {
@@ -1832,13 +1883,14 @@ k_backward_stash(SceneView S, LaunchArgs L)
         sink.norm = L.norm;
         sink.g_alb = L.g_alb;
         sink.g_rough = L.g_rough;
+        sink.cache = cache;
         trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, sink, tally);
         sink.finish();
     }
-    if (want_primal) {
-        __syncthreads();
+    __syncthreads();
+    grad_cache_flush(cache, L.g_alb, L.g_rough);
+    if (want_primal)
         for (uint32_t i = threadIdx.x; i < npix * T; i += blockDim.x) L.primal[base + i] = tprimal[i] * L.norm;
-    }
 }
 
 __global__ void k_zero_f32(float* p, size_t n)
@@ -1890,7 +1942,8 @@ hipError_t launch_render_tangent(const SceneView& S, const LaunchArgs& L, uint32
 
 size_t backward_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes, bool primal)
 {
-    return (size_t)tile_pixels * n_bins * sizeof(float) * (primal ? 2 : 1) + (size_t)block * stack_bytes;
+    return (size_t)kGradCacheFloats * sizeof(float) + (size_t)tile_pixels * n_bins * sizeof(float) * (primal ? 2 : 1) +
+           (size_t)block * stack_bytes;
 }
 
 size_t deferred_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes)
