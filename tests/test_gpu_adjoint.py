@@ -220,3 +220,29 @@ def test_adjoint_stack_link_widths(tr, oracle_mod, n_tris, kernel):
     assert np.abs(ga_o).max() > 0 and np.abs(gr_o).max() > 0
     assert np.abs(ga - ga_o).max() <= 1e-4 * np.abs(ga_o).max()
     assert np.abs(gr - gr_o).max() <= 1e-4 * np.abs(gr_o).max()
+
+
+@pytest.mark.parametrize("kernel", ["path", "auto"])
+def test_adjoint_gradient_table_overflow(tr, oracle_mod, kernel):
+    """One workgroup renders the whole 16 x 16 image of a box cluttered with
+    20,000 small triangles (8,192 paths), so its paths touch far more
+    triangles than the workgroup's 512-slot LDS gradient table holds: the
+    overflow goes to the global gradients directly.  Both adjoints against
+    the oracle's."""
+    import torch
+    sc = scenes.cluttered_box(20000, width=16, height=16, n_bins=16, bin_width=0.16, spp=32)
+    ta, trough = scenes.perturbed_params(sc, seed=7)
+    _announce(f"adjoint gradient table overflow {kernel}")
+    O = oracle_mod.Oracle(sc)
+    target, _, _ = O.render(stream_id=1, albedo=ta, roughness=trough)
+    film_o, _, _ = O.render()
+    delta = (2.0 * (film_o - target)).astype(np.float32)
+    ga_o, gr_o = O.backward(delta)
+    assert np.count_nonzero(ga_o) > 2 * 512  # one tile touched them all
+    with tr.upload(sc) as dev:
+        d = torch.from_numpy(delta.reshape(sc.height, sc.width, sc.n_bins)).cuda()
+        ga, gr = tr.render_transient_backward(dev, d, kernel=kernel, tile_pixels=sc.n_pixels, block_size=256)
+        torch.cuda.synchronize()
+        ga, gr = ga.cpu().numpy().astype(np.float64), gr.cpu().numpy().astype(np.float64)
+    assert np.abs(ga - ga_o).max() <= 1e-4 * np.abs(ga_o).max()
+    assert np.abs(gr - gr_o).max() <= 1e-4 * np.abs(gr_o).max()
