@@ -1283,6 +1283,25 @@ __device__ __forceinline__ uint32_t xcd_block()
     return (k / kXcdGroup) * run + x * kXcdGroup + k % kXcdGroup;
 }
 
+// First pixel of this workgroup's tile (tiles of TP consecutive pixels, in
+// the XCD-aware order).  In scenes too large for an XCD's L2 (more than
+// 32,768 triangles: 3.7 MB of nodes and triangle records), one-pixel tiles
+// of a camera image whose sides are multiples of 8 walk the image in 8 x 8
+// pixel blocks instead of rows, so the 64 tiles an XCD takes at a time are
+// a square of pixels, whose rays share more of the scene than a row
+// segment's (+2 % on a 1M-triangle scene; on a 9,826-triangle scene that
+// fits in L2 the squares only cost, -5 % forward).
+__device__ __forceinline__ uint32_t tile_first_pixel(const SceneView& S, const LaunchArgs& L, uint32_t TP)
+{
+    const uint32_t t = xcd_block();
+    if (TP == 1 && S.sensor == 0 && S.n_tris > 32768u && (S.width & 7u) == 0 && (S.height & 7u) == 0 &&
+        L.n_pixels == S.width * S.height) {
+        const uint32_t blk = t >> 6, in = t & 63u, bw = S.width >> 3;
+        return ((blk / bw) * 8u + (in >> 3)) * S.width + (blk % bw) * 8u + (in & 7u);
+    }
+    return t * TP;
+}
+
 template <bool kCount, class W, bool kArea>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 k_render_deferred(SceneView S, LaunchArgs L, unsigned long long* counts)
@@ -1314,7 +1333,7 @@ __global__ void __launch_bounds__(256) k_render(SceneView S, LaunchArgs L, unsig
     __shared__ float s_freq[kMaxFreq];
     load_freqs(L, s_freq);
     W* stk = reinterpret_cast<W*>(lds + (size_t)TP * film_words(S, L) + 2 * TP) + threadIdx.x;
-    render_tile(S, L, xcd_block() * TP, lds, s_freq, stk, (int)blockDim.x, tally);
+    render_tile(S, L, tile_first_pixel(S, L, TP), lds, s_freq, stk, (int)blockDim.x, tally);
     tally.flush(counts);
 }
 
@@ -1445,7 +1464,7 @@ __global__ void __launch_bounds__(256) k_render_wf(SceneView S, LaunchArgs L, un
     float* toow = tsteady + TP;
     const WfSlots w = carve_slots(toow + TP, nb);
     W* stk = reinterpret_cast<W*>(toow + TP + (size_t)kWfWords * nb) + tid;
-    const uint32_t p0 = xcd_block() * TP;
+    const uint32_t p0 = tile_first_pixel(S, L, TP);
     const uint32_t npix = min(TP, L.n_pixels - p0);
     for (uint32_t i = tid; i < TP * T + 2 * TP; i += nb) lds[i] = 0.0f;
     w.live[tid] = 0;
@@ -1712,7 +1731,7 @@ __global__ void __launch_bounds__(256) k_render_tangent(SceneView S, LaunchArgs 
     float* tsteady = tdfilm + (size_t)TP * T;
     W* stk = reinterpret_cast<W*>(tsteady + TP) + threadIdx.x;
     const int stride = (int)blockDim.x;
-    const uint32_t p0 = xcd_block() * TP;
+    const uint32_t p0 = tile_first_pixel(S, L, TP);
     const uint32_t npix = min(TP, L.n_pixels - p0);
     for (uint32_t i = threadIdx.x; i < 2 * TP * T + TP; i += blockDim.x) lds[i] = 0.0f;
     __syncthreads();
@@ -1754,7 +1773,7 @@ __global__ void __launch_bounds__(256) k_backward(SceneView S, LaunchArgs L)
     float* tprimal = tdelta + (size_t)TP * T;
     W* stk = reinterpret_cast<W*>(tprimal + (want_primal ? (size_t)TP * T : 0)) + threadIdx.x;
     const int stride = (int)blockDim.x;
-    const uint32_t p0 = xcd_block() * TP;
+    const uint32_t p0 = tile_first_pixel(S, L, TP);
     const uint32_t npix = min(TP, L.n_pixels - p0);
     const size_t base = (size_t)p0 * T;
     for (uint32_t i = threadIdx.x; i < TP * T; i += blockDim.x) {
@@ -1864,7 +1883,7 @@ k_backward_stash(SceneView S, LaunchArgs L)
     float* tprimal = tdelta + (size_t)TP * T;
     W* stk = reinterpret_cast<W*>(tprimal + (want_primal ? (size_t)TP * T : 0)) + threadIdx.x;
     const int stride = (int)blockDim.x;
-    const uint32_t p0 = xcd_block() * TP;
+    const uint32_t p0 = tile_first_pixel(S, L, TP);
     const uint32_t npix = min(TP, L.n_pixels - p0);
     const size_t base = (size_t)p0 * T;
     for (uint32_t i = threadIdx.x; i < TP * T; i += blockDim.x) {
