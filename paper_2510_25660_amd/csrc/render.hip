@@ -88,7 +88,11 @@ __device__ __forceinline__ bool intersect_tri(const Ray& r, const TriRec& tr, in
 // triangle records span a few MB) fetch them with buffer loads: a 32-bit
 // byte offset against a descriptor held in scalar registers, where a global
 // load needs a 64-bit address per lane (the 48-byte record stride costs a
-// quarter-rate 64-bit multiply).  Larger scenes use global loads.
+// quarter-rate 64-bit multiply).  Larger scenes use global loads.  The
+// descriptor has stride 0 (raw, byte-addressed), `bytes` as its range (a
+// load past it returns zeros instead of faulting) and 0x00020000 as its
+// fourth word, the value for untyped 32-bit access on gfx9-family GPUs
+// (gfx950 included).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void* p, uint32_t bytes)
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
