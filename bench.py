@@ -122,6 +122,25 @@ def time_launches(fn, steps, warmup):
     return t_all0.elapsed_time(t_all1), per
 
 
+def film_atomic_rate(film, sc, launch_ms, reps=20):
+    """The deferred form splits a pixel's 4096 samples over two workgroups
+    (2048-sample chunks) that add their partial films with HBM atomics: at
+    most one float add per chunk and non-zero bin.  Their rate against a
+    scatter-add (torch index_add_) of as many float adds at the same bins."""
+    import torch
+    chunks = max(1, -(-sc.spp // 2048))
+    nz = torch.nonzero(film.reshape(-1)).reshape(-1)
+    idx = nz.repeat(chunks)
+    vals = torch.ones(idx.numel(), device="cuda", dtype=torch.float32)
+    buf = torch.zeros(film.numel(), device="cuda", dtype=torch.float32)
+    ms, _ = time_launches(lambda: buf.index_add_(0, idx, vals), reps, 3)
+    per_launch = int(idx.numel())
+    rate = per_launch / (launch_ms * 1e-3)
+    peak = per_launch / (ms / reps * 1e-3)
+    return {"per_launch_at_most": per_launch, "rate_per_s": round(rate, 1), "scatter_add_rate_per_s": round(peak, 1),
+            "frac": round(rate / peak, 4)}
+
+
 def backward_forward_ratio(tr, steps=5, warmup=1):
     """Backward (path-replay adjoint) over forward time on the differentiable
     box room (9,826 triangles, 64x64, 256 bins, 1024 spp, depth 4)."""
@@ -271,6 +290,8 @@ def main():
     ap.add_argument("--no-nlos-area", action="store_true", help="skip the NLOS area-sampling measurement")
     ap.add_argument("--no-glass", action="store_true", help="skip the glass-room measurement")
     ap.add_argument("--no-box-graph", action="store_true", help="skip the graph-replayed box-room latency")
+    ap.add_argument("--atomic-calibration", action="store_true",
+                    help="compare the render's film atomics with a scatter-add of as many float adds at the same bins")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a device copy of this many MiB (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -352,9 +373,12 @@ def main():
     ms_per_step = total_ms / args.steps
     value = paths / (ms_per_step * 1e-3) / 1e6
     launch_ms = float(np.mean(per))
+    # the deferred form adds split pixels' partial films with HBM atomics
+    form = args.kernel if args.kernel != "auto" else ("deferred" if sc.sensor == 1 else "path")
+    atomics = (film_atomic_rate(film, sc, launch_ms)
+               if args.atomic_calibration and form == "deferred" and sc.spp > 2048 else None)
     ops = sum(OPS_PER[k] * counts[k] for k in OPS_PER)
     # the kernel the automatic choice runs: the deferred form for the confocal sensor
-    form = args.kernel if args.kernel != "auto" else ("deferred" if sc.sensor == 1 else "path")
     kernel_name = {"path": "k_render", "deferred": "k_render_deferred", "wavefront": "k_render_wf"}[form]
     achieved = ops / (launch_ms * 1e-3)
     out = {
@@ -382,6 +406,8 @@ def main():
     }
     if forms:
         out["kernel_forms_mpaths_per_s"] = forms
+    if atomics:
+        out["film_atomics"] = atomics
     if phasor:
         out["phasor_film"] = phasor
     if nlos:
