@@ -43,7 +43,7 @@ enum {
     TRHIP_ERR_INVALID_ARG = 1, /* a bad pointer, size, enum or value */
     TRHIP_ERR_OOM = 2,         /* a device or host allocation failed */
     TRHIP_ERR_HIP = 3,         /* a HIP runtime call failed (message has the hipError_t) */
-    TRHIP_ERR_UNSUPPORTED = 4, /* a valid request this build cannot serve (e.g. LDS budget) */
+    TRHIP_ERR_UNSUPPORTED = 4, /* a valid request the library cannot serve (e.g. LDS budget) */
     TRHIP_ERR_BAD_HANDLE = 5   /* NULL, destroyed or foreign handle */
 };
 
