@@ -8,6 +8,7 @@ header of ``oracle.c`` for what each part follows.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -100,42 +101,62 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        L = C.CDLL(LIB_PATH)
-        fp = C.POINTER(C.c_float)
-        dp = C.POINTER(C.c_double)
-        ip = C.POINTER(C.c_int32)
-        up = C.POINTER(C.c_uint32)
-        L.orc_prepare.restype = C.c_void_p
-        L.orc_prepare.argtypes = [C.POINTER(_Scene)]
-        L.orc_release.argtypes = [C.c_void_p]
-        L.orc_pad.restype = C.c_float
-        L.orc_pad.argtypes = [C.c_void_p]
-        L.orc_fresnel.restype = C.c_float
-        L.orc_fresnel.argtypes = [C.c_float, C.c_float, C.c_float]
-        L.orc_area_total.restype = C.c_double
-        L.orc_area_total.argtypes = [C.c_void_p]
-        L.orc_trace_path.argtypes = [C.c_void_p, C.POINTER(_Render), C.c_uint32, C.c_uint32, C.POINTER(_Path)]
-        L.orc_render_film.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, dp, dp, dp, C.c_int]
-        L.orc_render_tangent.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, dp, dp, dp, dp, dp, C.c_int]
-        L.orc_render_phasor.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, dp, C.c_int, dp, dp, C.c_int]
-        L.orc_backward.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, fp, dp, dp, dp, C.c_int]
-        L.orc_closest_hit.argtypes = [C.c_void_p, fp, fp, C.c_int, C.c_int, fp, ip]
-        L.orc_philox_n.argtypes = [C.c_int64, up, up, up]
-        L.orc_sincos2pi_n.argtypes = [C.c_int64, fp, fp, fp]
-        L.orc_log1m_n.argtypes = [C.c_int64, fp, fp]
-        L.orc_ggx_f.restype = C.c_float
-        L.orc_ggx_f.argtypes = [fp, fp, C.c_float, C.c_float]
-        L.orc_ggx_pdf.restype = C.c_float
-        L.orc_ggx_pdf.argtypes = [fp, fp, C.c_float]
-        L.orc_ggx_sample.argtypes = [fp, C.c_float, C.c_float, C.c_float, fp]
-        L.orc_ggx_dlogf_dalpha.restype = C.c_double
-        L.orc_ggx_dlogf_dalpha.argtypes = [fp, fp, C.c_double]
-        L.orc_cosine_sample.argtypes = [C.c_float, C.c_float, fp]
-        L.orc_ggx_eval_n.argtypes = [C.c_int64, fp, fp, fp, fp, fp, fp]
-        L.orc_ggx_sample_n.argtypes = [C.c_int64, fp, fp, fp, fp, C.c_int, fp, fp, fp, fp]
-        L.orc_cosine_sample_n.argtypes = [C.c_int64, fp, fp, fp]
-        _lib = L
+        _lib = _load(LIB_PATH)
     return _lib
+
+
+@contextlib.contextmanager
+def using_library(path: str):
+    """Within the block, the oracle functions and every Oracle created there
+    run the library at `path`: another build of ``oracle.c``, used by the
+    tests that plant a mistake in a copy of the source and check that a pin
+    catches it."""
+    global _lib
+    saved = lib()
+    _lib = _load(path)
+    try:
+        yield _lib
+    finally:
+        _lib = saved
+
+
+def _load(path: str):
+    L = C.CDLL(path)
+    fp = C.POINTER(C.c_float)
+    dp = C.POINTER(C.c_double)
+    ip = C.POINTER(C.c_int32)
+    up = C.POINTER(C.c_uint32)
+    L.orc_prepare.restype = C.c_void_p
+    L.orc_prepare.argtypes = [C.POINTER(_Scene)]
+    L.orc_release.argtypes = [C.c_void_p]
+    L.orc_pad.restype = C.c_float
+    L.orc_pad.argtypes = [C.c_void_p]
+    L.orc_fresnel.restype = C.c_float
+    L.orc_fresnel.argtypes = [C.c_float, C.c_float, C.c_float]
+    L.orc_area_total.restype = C.c_double
+    L.orc_area_total.argtypes = [C.c_void_p]
+    L.orc_trace_path.argtypes = [C.c_void_p, C.POINTER(_Render), C.c_uint32, C.c_uint32, C.POINTER(_Path)]
+    L.orc_render_film.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, dp, dp, dp, C.c_int]
+    L.orc_render_tangent.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, dp, dp, dp, dp, dp, C.c_int]
+    L.orc_render_phasor.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, dp, C.c_int, dp, dp, C.c_int]
+    L.orc_backward.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, fp, dp, dp, dp, C.c_int]
+    L.orc_closest_hit.argtypes = [C.c_void_p, fp, fp, C.c_int, C.c_int, fp, ip]
+    L.orc_philox_n.argtypes = [C.c_int64, up, up, up]
+    L.orc_sincos2pi_n.argtypes = [C.c_int64, fp, fp, fp]
+    L.orc_log1m_n.argtypes = [C.c_int64, fp, fp]
+    L.orc_ggx_f.restype = C.c_float
+    L.orc_ggx_f.argtypes = [fp, fp, C.c_float, C.c_float]
+    L.orc_ggx_pdf.restype = C.c_float
+    L.orc_ggx_pdf.argtypes = [fp, fp, C.c_float]
+    L.orc_ggx_sample.argtypes = [fp, C.c_float, C.c_float, C.c_float, fp]
+    L.orc_ggx_dlogf_dalpha.restype = C.c_double
+    L.orc_ggx_dlogf_dalpha.argtypes = [fp, fp, C.c_double]
+    L.orc_cosine_sample.argtypes = [C.c_float, C.c_float, fp]
+    L.orc_ggx_eval_n.argtypes = [C.c_int64, fp, fp, fp, fp, fp, fp]
+    L.orc_ggx_sample_n.argtypes = [C.c_int64, fp, fp, fp, fp, C.c_int, fp, fp, fp, fp]
+    L.orc_cosine_sample_n.argtypes = [C.c_int64, fp, fp, fp]
+    L.orc_phase_sample_n.argtypes = [C.c_int64, fp, fp, fp]
+    return L
 
 
 def _fptr(a):
@@ -217,6 +238,15 @@ def cosine_sample_n(u0, u1):
     return out
 
 
+def phase_sample_n(u0, u1):
+    """Directions of the medium's isotropic phase sampler [n, 3]."""
+    u0 = _f32c(u0)
+    u1 = _f32c(u1)
+    out = np.empty((len(u0), 3), np.float32)
+    lib().orc_phase_sample_n(len(u0), _fptr(u0), _fptr(u1), _fptr(out))
+    return out
+
+
 def ggx_f(wo, wi, alpha, F):
     return lib().orc_ggx_f(_f3(wo), _f3(wi), float(alpha), float(F))
 
@@ -290,18 +320,19 @@ class Oracle:
         s.delay = _fptr(self._delay) if self._delay is not None else None
         s.medium_ior = float(getattr(scene, "medium_ior", 1.0))
         self._s = s
-        self._h = lib().orc_prepare(C.byref(s))
+        self._L = lib()
+        self._h = self._L.orc_prepare(C.byref(s))
         if not self._h:
             raise ValueError("oracle: invalid scene")
 
     def __del__(self):
-        if getattr(self, "_h", None) and _lib is not None:
-            _lib.orc_release(self._h)
+        if getattr(self, "_h", None) and getattr(self, "_L", None) is not None:
+            self._L.orc_release(self._h)
             self._h = None
 
     @property
     def pad(self) -> float:
-        return lib().orc_pad(self._h)
+        return self._L.orc_pad(self._h)
 
     def _render_desc(self, spp, seed, max_depth, sample_offset=0, stream_id=0, pixel_centre=False,
                      frozen=False, albedo=None, roughness=None, nlos_area=False):
@@ -344,7 +375,7 @@ class Oracle:
         if threads <= 0:
             threads = os.cpu_count() or 1
         D = C.POINTER(C.c_double)
-        rc = lib().orc_render_film(self._h, C.byref(r), pixels.ctypes.data_as(C.POINTER(C.c_int32)), n,
+        rc = self._L.orc_render_film(self._h, C.byref(r), pixels.ctypes.data_as(C.POINTER(C.c_int32)), n,
                                    film.ctypes.data_as(D), steady.ctypes.data_as(D), oow.ctypes.data_as(D),
                                    int(threads))
         if rc != 0:
@@ -372,7 +403,7 @@ class Oracle:
         r, keep = self._render_desc(spp, seed, max_depth, **kw)
         if threads <= 0:
             threads = os.cpu_count() or 1
-        rc = lib().orc_render_tangent(self._h, C.byref(r), pixels.ctypes.data_as(C.POINTER(C.c_int32)), n,
+        rc = self._L.orc_render_tangent(self._h, C.byref(r), pixels.ctypes.data_as(C.POINTER(C.c_int32)), n,
                                       None if va is None else va.ctypes.data_as(D),
                                       None if vr is None else vr.ctypes.data_as(D), film.ctypes.data_as(D),
                                       dfilm.ctypes.data_as(D), steady.ctypes.data_as(D), int(threads))
@@ -399,7 +430,7 @@ class Oracle:
         if threads <= 0:
             threads = os.cpu_count() or 1
         D = C.POINTER(C.c_double)
-        rc = lib().orc_render_phasor(self._h, C.byref(r), pixels.ctypes.data_as(C.POINTER(C.c_int32)), n,
+        rc = self._L.orc_render_phasor(self._h, C.byref(r), pixels.ctypes.data_as(C.POINTER(C.c_int32)), n,
                                      f.ctypes.data_as(D), int(f.size), out.ctypes.data_as(D),
                                      steady.ctypes.data_as(D), int(threads))
         if rc != 0:
@@ -425,7 +456,7 @@ class Oracle:
         if threads <= 0:
             threads = os.cpu_count() or 1
         D = C.POINTER(C.c_double)
-        rc = lib().orc_backward(self._h, C.byref(r), pixels.ctypes.data_as(C.POINTER(C.c_int32)),
+        rc = self._L.orc_backward(self._h, C.byref(r), pixels.ctypes.data_as(C.POINTER(C.c_int32)),
                                 len(pixels), _fptr(g), ga.ctypes.data_as(D), gr.ctypes.data_as(D),
                                 primal.ctypes.data_as(D) if primal is not None else None, int(threads))
         if rc != 0:
@@ -440,7 +471,7 @@ class Oracle:
         r, keep = self._render_desc(1, sc.seed if spp_seed is None else spp_seed,
                                     sc.max_depth if max_depth is None else max_depth, **kw)
         p = _Path()
-        n = lib().orc_trace_path(self._h, C.byref(r), int(pix), int(sample), C.byref(p))
+        n = self._L.orc_trace_path(self._h, C.byref(r), int(pix), int(sample), C.byref(p))
         out = []
         for i in range(n):
             v = p.v[i]
@@ -454,6 +485,6 @@ class Oracle:
         k = C.c_int32(-1)
         o = np.ascontiguousarray(o, np.float32)
         d = np.ascontiguousarray(d, np.float32)
-        hit = lib().orc_closest_hit(self._h, _fptr(o), _fptr(d), int(exclude), int(bool(use_bvh)),
+        hit = self._L.orc_closest_hit(self._h, _fptr(o), _fptr(d), int(exclude), int(bool(use_bvh)),
                                     C.byref(t), C.byref(k))
         return (t.value, k.value) if hit else (None, -1)

@@ -809,6 +809,19 @@ void orc_cosine_sample(float u0, float u1, float out[3])
     out[2] = sqrtf(1.0f - u0);
 }
 
+/* Isotropic phase function of the homogeneous medium (Sec. 4.1): a
+ * direction uniform on the unit sphere, z = 1 - 2 u0 uniform in [-1, 1] and
+ * the azimuth 2 pi u1 (Archimedes' hat-box theorem). */
+void orc_phase_sample(float u0, float u1, float out[3])
+{
+    float z = 1.0f - (u0 + u0);
+    float r = sqrtf(fmaxf(0.0f, 1.0f - z * z)), sn, cs;
+    orc_sincos2pi(u1, &sn, &cs);
+    out[0] = r * cs;
+    out[1] = r * sn;
+    out[2] = z;
+}
+
 /* ------------------------------------------------------------------------ */
 /* One path (Eqs. 1-9 and the histogram rule).                              */
 /* ------------------------------------------------------------------------ */
@@ -1153,10 +1166,9 @@ int orc_trace_path(const orc_prepared* P, const orc_render* R, uint32_t pix, uin
         if (v == vmax || first_blocked) break;
         draw(R, pix, sample, (uint32_t)v, u);
         if (medium_event) {
-            float z = 1.0f - (u[0] + u[0]);
-            float r = sqrtf(fmaxf(0.0f, 1.0f - z * z)), sn, cs;
-            orc_sincos2pi(u[1], &sn, &cs);
-            d = mk(r * cs, r * sn, z);
+            float w[3];
+            orc_phase_sample(u[0], u[1], w);
+            d = mk(w[0], w[1], w[2]);
             prev = -1;
             o = x;
             vert->dc_alb = 0.0;
@@ -1569,4 +1581,10 @@ void orc_cosine_sample_n(int64_t n, const float* u0, const float* u1, float* out
 {
     int64_t i;
     for (i = 0; i < n; ++i) orc_cosine_sample(u0[i], u1[i], out + 3 * i);
+}
+
+void orc_phase_sample_n(int64_t n, const float* u0, const float* u1, float* out)
+{
+    int64_t i;
+    for (i = 0; i < n; ++i) orc_phase_sample(u0[i], u1[i], out + 3 * i);
 }

@@ -99,6 +99,7 @@ float orc_uniform(uint32_t x);
 void orc_sincos2pi(float u, float* s, float* c);
 float orc_log1m(float u);
 void orc_cosine_sample(float u0, float u1, float out[3]);
+void orc_phase_sample(float u0, float u1, float out[3]);
 float orc_ggx_f(const float wo[3], const float wi[3], float alpha, float F);
 float orc_ggx_pdf(const float wo[3], const float wi[3], float alpha);
 void orc_ggx_sample(const float wo[3], float alpha, float u0, float u1, float wi[3]);
@@ -111,6 +112,7 @@ void orc_ggx_eval_n(int64_t n, const float* wo, const float* wi, const float* al
 void orc_ggx_sample_n(int64_t n, const float* wo, const float* alpha, const float* alpha_s, const float* F,
                       int frozen, const float* u0, const float* u1, float* wi_out, float* w_out);
 void orc_cosine_sample_n(int64_t n, const float* u0, const float* u1, float* out);
+void orc_phase_sample_n(int64_t n, const float* u0, const float* u1, float* out);
 void orc_philox_n(int64_t n, const uint32_t* ctr, const uint32_t* key, uint32_t* out);
 
 #ifdef __cplusplus

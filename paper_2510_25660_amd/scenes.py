@@ -466,14 +466,16 @@ def batched_nlos(n_scenes: int = 256, seed: int = BASE_SEED + 5, spp: int = 256,
 # --------------------------------------------------------------------------
 def plane_scene(h=1.0, albedo=0.6, half=50.0, width=16, height=16, n_bins=8192, bin_width=0.001,
                 bin_start=0.0, cam_height=2.0, vfov=60.0, mat=MAT_LAMBERT, roughness=0.3,
-                unwarp=False) -> Scene:
+                unwarp=False, sigma_t=0.0, medium_albedo=0.0) -> Scene:
     """Large plane y=0, point light at height h above the origin, pinhole
-    looking straight down from cam_height (single-bounce closed form)."""
+    looking straight down from cam_height (single-bounce closed form);
+    optionally filled with homogeneous fog (sigma_t > 0)."""
     v, f = quad([-half, 0, -half], [-half, 0, half], [half, 0, half], [half, 0, -half])
     cam = look_at([0.3, cam_height, 0.2], [0.3, 0.0, 0.2], [0, 0, -1], vfov, width, height)
     return _finish(v, f, np.full(2, mat), np.full(2, albedo), np.full(2, roughness), n_bins=n_bins,
                    bin_width=bin_width, bin_start=bin_start, width=width, height=height,
                    light_pos=(0.0, h, 0.0), light_intensity=1.0, camera_unwarp=unwarp,
+                   sigma_t=float(sigma_t), medium_albedo=float(medium_albedo),
                    spp=1, max_depth=2, name="plane", **cam)
 
 
