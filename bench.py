@@ -4,13 +4,18 @@
 One step = one transient render of the whole workload (every path sample
 traced with BVH traversal, BSDF sampling and next-event estimation, every
 contribution histogrammed into the pixel x time film), inputs resident in
-HBM.  Default workload: confocal NLOS, 64x64 scan points on a 1x1 m relay
-wall, 9,680-triangle hidden blob, 512 bins of 2.4 mm from 0.9 m, 4096 spp,
-3 bounces (16,777,216 path samples per step).
+HBM.  Headline workload (the largest configuration): the 998,608-triangle
+fogged terrain with 49 displaced Lambertian / GGX spheres, 512x512 pinhole
+film, 1024 bins of 5 mm from 4.5 m, 64 spp, max depth 8 (16,777,216 path
+samples per step).
 
-Prints one JSON line: Mpath-samples/s, the backward/forward time ratio of
-the differentiable box-room workload, the roofline of the render kernel and
-the CPU oracle timed on a bounded sample of the same workload.
+The JSON line also carries, each with its own rate and roofline, the
+confocal NLOS scan (64x64 scan points, 9,680-triangle blob, 512 bins of
+2.4 mm, 4096 spp; with its phasor film and NLOS area sampling), the batch of
+256 confocal scenes rendered by one graph launch, the box room's latency
+(graph replays), the glass room, and the backward/forward time ratio of the
+differentiable box room; then the CPU oracle timed on a bounded sample of
+the headline workload.
 """
 from __future__ import annotations
 
@@ -28,6 +33,7 @@ sys.path.insert(0, ROOT)
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T VALU lane-ops/s
 # (non-packed FP32 / INT32; an FMA counts as one op).
 PEAK_VALU_LANE_OPS = 256 * 64 * 2.4e9
+HBM_PEAK_GBPS = 8000.0
 
 # Algorithmic lane-ops per counted event, from the operation counts of the
 # formulas the kernel evaluates (one add / mul / fma / min / max / compare /
@@ -48,7 +54,8 @@ WORKLOADS = {
                      traffic="k_render_deferred_confocal_nlos_64x64x512_4096spp_hbm_traffic.txt"),
     "box": dict(desc="box room 34 tris, 64x64 pinhole, 256 bins x 0.01 m from 0, 16 spp, max depth 4, FP32"),
     "large": dict(desc="terrain + 49 displaced spheres 998,608 tris, fog sigma_t 0.1, 512x512, 1024 bins x 5 mm "
-                       "from 4.5 m, 64 spp, max depth 8, FP32"),
+                       "from 4.5 m, 64 spp, max depth 8, FP32",
+                  traffic="k_render_large_terrain_spheres_fog_512x512x1024_64spp_hbm_traffic.txt"),
     "glass": dict(desc="box room 34 tris with a glass box (index 1.5) and fluorescent room walls (scattering delay "
                        "mean 5 cm), 64x64 pinhole, 256 bins x 0.01 m from 0, 16 spp, max depth 8, FP32"),
     "batched": dict(desc="256 confocal NLOS scenes: blob triangles log-uniform 1k-50k, scan grids 16^2-64^2, "
@@ -122,25 +129,6 @@ def time_launches(fn, steps, warmup):
     return t_all0.elapsed_time(t_all1), per
 
 
-def film_atomic_rate(film, sc, launch_ms, reps=20):
-    """The deferred form splits a pixel's 4096 samples over two workgroups
-    (2048-sample chunks) that add their partial films with HBM atomics: at
-    most one float add per chunk and non-zero bin.  Their rate against a
-    scatter-add (torch index_add_) of as many float adds at the same bins."""
-    import torch
-    chunks = max(1, -(-sc.spp // 2048))
-    nz = torch.nonzero(film.reshape(-1)).reshape(-1)
-    idx = nz.repeat(chunks)
-    vals = torch.ones(idx.numel(), device="cuda", dtype=torch.float32)
-    buf = torch.zeros(film.numel(), device="cuda", dtype=torch.float32)
-    ms, _ = time_launches(lambda: buf.index_add_(0, idx, vals), reps, 3)
-    per_launch = int(idx.numel())
-    rate = per_launch / (launch_ms * 1e-3)
-    peak = per_launch / (ms / reps * 1e-3)
-    return {"per_launch_at_most": per_launch, "rate_per_s": round(rate, 1), "scatter_add_rate_per_s": round(peak, 1),
-            "frac": round(rate / peak, 4)}
-
-
 def backward_forward_ratio(tr, steps=5, warmup=1):
     """Backward (path-replay adjoint) over forward time on the differentiable
     box room (9,826 triangles, 64x64, 256 bins, 1024 spp, depth 4)."""
@@ -163,41 +151,6 @@ def backward_forward_ratio(tr, steps=5, warmup=1):
         tan_ms, _ = time_launches(lambda: tr.render_transient_tangent(dev, None, v, film=film, dfilm=dfilm, albedo=a,
                                                                       roughness=r), steps, warmup)
     return bwd_ms / fwd_ms, fwd_ms / steps, bwd_ms / steps, rep_ms / steps, tan_ms / steps
-
-
-def run_batched(args, tr):
-    """The batched workload: one graph launch renders all 256 scenes."""
-    import torch
-    from paper_2510_25660_amd import scenes
-    scs = scenes.batched_nlos()
-    devs = [tr.upload(s) for s in scs]
-    try:
-        b = tr.Batch(devs, autotune=True)
-        info = b.info()
-        total_ms, per = time_launches(b.render, args.steps, args.warmup)
-        seq = None
-        if args.compare_kernels:
-            films = b.films
-            seq_ms, _ = time_launches(lambda: [tr.render_transient(d, film=f) for d, f in zip(devs, films)],
-                                      max(1, args.steps // 4), 1)
-            seq = seq_ms / max(1, args.steps // 4)
-        b.destroy()
-    finally:
-        for d in devs:
-            d.destroy()
-    paths = sum(s.n_pixels * s.spp for s in scs)
-    ms = total_ms / args.steps
-    out = {
-        "metric": "Mpath-samples/s into transient film at 1 GPU; backward/forward time ratio",
-        "value": round(paths / (ms * 1e-3) / 1e6, 3), "unit": "Mpath-samples/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic (seeded scene generators)",
-        "config": {"workload": WORKLOADS["batched"]["desc"], "paths_per_step": paths,
-                   "triangles": int(sum(s.n_tris for s in scs)), "batch": info},
-    }
-    if seq is not None:
-        out["sequential_single_scene_ms"] = round(seq, 3)
-    return out
 
 
 def box_room_graph(tr, replays=200):
@@ -252,24 +205,202 @@ def glass_room(tr, steps, warmup):
             "mpaths_per_s": round(sc.n_pixels * sc.spp / (ms * 1e-3) / 1e6, 3), "counts": counts}
 
 
-def cpu_baseline(sc, max_threads=16):
-    """The oracle on the host cores over a bounded sample of the workload."""
+def host_cpu():
+    """Cores this process may run on, all cores of the host, and the CPU model."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return usable, os.cpu_count() or 1, model
+
+
+def cpu_baseline(sc, stride_all=2, stride_one=32):
+    """The unchanged oracle on the host cores over a bounded sample of the
+    workload: every `stride_all`-th pixel (or scan point) at the full spp on
+    all usable cores, and every `stride_one`-th on one thread."""
     import oracle
-    threads = max(1, min(max_threads, os.cpu_count() or 1))
+    usable, total, model = host_cpu()
     O = oracle.Oracle(sc)
-    if sc.sensor == 1:
-        pix = np.arange(sc.n_pixels, dtype=np.int32)
-        spp = sc.spp
-        sample = f"the whole workload: all {sc.n_pixels} scan points at the full {spp} spp"
-    else:
-        pix = np.arange(0, sc.n_pixels, max(1, sc.n_pixels // 4096), dtype=np.int32)
-        spp = min(sc.spp, 16)
-        sample = f"{len(pix)} of {sc.n_pixels} pixels at {spp} spp"
+    out = {}
+    for label, stride, threads in (("all", stride_all, usable), ("one", stride_one, 1)):
+        pix = np.arange(0, sc.n_pixels, stride, dtype=np.int32)
+        t0 = time.perf_counter()
+        O.render(pixels=pix, spp=sc.spp, threads=threads)
+        dt = time.perf_counter() - t0
+        out[label] = (len(pix), dt, threads)
+    n_all, dt_all, th = out["all"]
+    n_one, dt_one, _ = out["one"]
+    return {"value": round(n_all * sc.spp / dt_all / 1e6, 4), "unit": "Mpath-samples/s", "cores": th,
+            "kind": "oracle",
+            "sample": f"every {stride_all}th pixel ({n_all} of {sc.n_pixels}) at the full {sc.spp} spp, "
+                      f"threads over pixels",
+            "seconds": round(dt_all, 2), "host_nproc": total, "host_usable_cores": usable, "host_cpu_model": model,
+            "one_thread": {"value": round(n_one * sc.spp / dt_one / 1e6, 4), "unit": "Mpath-samples/s",
+                           "sample": f"every {stride_one}th pixel ({n_one}) at {sc.spp} spp",
+                           "seconds": round(dt_one, 2)}}
+
+
+def roofline_of(counts, launch_ms, kernel, traffic=None, algorithmic_bytes=None):
+    """VALU roofline of a render launch: algorithmic lane-ops (counted work x
+    per-event cost) over the launch time, against 39.3 T lane-ops/s; with the
+    HBM bytes per launch measured by rocprofv3 when they are current."""
+    ops = sum(OPS_PER[k] * counts[k] for k in OPS_PER)
+    achieved = ops / (launch_ms * 1e-3)
+    r = {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(PEAK_VALU_LANE_OPS / 1e12, 2),
+         "unit": "T lane-ops/s", "frac": round(achieved / PEAK_VALU_LANE_OPS, 4), "traffic": traffic,
+         "traffic_unit": "bytes/launch", "kernel": kernel, "launch_ms": round(launch_ms, 4), "ops_per_launch": int(ops),
+         "counts": counts}
+    if "wave_nodes" in counts:
+        r["active_lanes_per_wave"] = active_lanes(counts)
+    if algorithmic_bytes is not None:
+        hb = {"algorithmic_bytes_per_launch": int(algorithmic_bytes),
+              "algorithmic_gbps": round(algorithmic_bytes / (launch_ms * 1e-3) / 1e9, 2),
+              "peak_gbps": HBM_PEAK_GBPS}
+        hb["algorithmic_frac"] = round(hb["algorithmic_gbps"] / HBM_PEAK_GBPS, 5)
+        if traffic:
+            hb["measured_gbps"] = round(traffic / (launch_ms * 1e-3) / 1e9, 2)
+            hb["measured_frac"] = round(hb["measured_gbps"] / HBM_PEAK_GBPS, 4)
+            hb["measured_over_algorithmic"] = round(traffic / algorithmic_bytes, 2)
+        r["hbm"] = hb
+    return r
+
+
+def algorithmic_bytes(sc, info):
+    """Bytes the method itself must move per render: the film (and the steady
+    image) written once, the scene (BVH nodes, triangle records, materials)
+    read once."""
+    film = sc.n_pixels * (sc.n_bins + 1) * 4
+    return film + int(info["device_bytes"])
+
+
+def measure_single(tr, name, args, shape, extras):
+    """One workload: its rate, its counted work and its roofline (+ the
+    workload's extra measurements when `extras`)."""
+    import torch
+    sc = make_scene(name)
+    paths = sc.n_pixels * sc.spp
+    # scene upload + BVH build (off the timed loop; the first build also warms the runtime, so time a second one)
+    tr.upload(sc, builder=args.builder).destroy()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    O.render(pixels=pix, spp=spp, threads=threads)
-    dt = time.perf_counter() - t0
-    return {"value": round(len(pix) * spp / dt / 1e6, 4), "unit": "Mpath-samples/s", "cores": threads,
-            "kind": "oracle", "sample": sample, "seconds": round(dt, 2)}
+    dev0 = tr.upload(sc, builder=args.builder)
+    torch.cuda.synchronize()
+    upload_ms = (time.perf_counter() - t0) * 1e3
+    dev0.destroy()
+    out = {}
+    with tr.upload(sc, builder=args.builder) as dev:
+        info = dev.info()
+        steady = torch.empty((sc.height, sc.width), device="cuda", dtype=torch.float32)
+        film = torch.empty((sc.height, sc.width, sc.n_bins), device="cuda", dtype=torch.float32)
+        step = lambda: tr.render_transient(dev, film=film, steady=steady, **shape)
+        total_ms, per = time_launches(step, args.steps, args.warmup)
+        _, _, counts = tr.render_transient_counted(dev, **shape)
+        if args.compare_kernels:
+            forms = {}
+            for form in ("path", "deferred", "wavefront"):
+                sh = dict(shape, kernel=form)
+                ms, _ = time_launches(lambda: tr.render_transient(dev, film=film, steady=steady, **sh), args.steps,
+                                      args.warmup)
+                forms[form] = round(paths / (ms / args.steps * 1e-3) / 1e6, 3)
+            out["kernel_forms_mpaths_per_s"] = forms
+        if extras and args.phasor_freqs and sc.sensor == 1:
+            # the same paths into a phasor film (Sec. 4.3) instead of the histogram
+            freqs = list(np.linspace(0.5, 16.6, args.phasor_freqs))
+            ph = torch.empty((sc.height, sc.width, len(freqs), 2), device="cuda", dtype=torch.float32)
+            ms, _ = time_launches(lambda: tr.render_phasor(dev, freqs, phasor=ph, steady=steady, **shape),
+                                  args.steps, args.warmup)
+            out["phasor_film"] = {"n_freq": len(freqs), "freq_range_per_m": [0.5, 16.6],
+                                  "ms_per_step": round(ms / args.steps, 4),
+                                  "mpaths_per_s": round(paths / (ms / args.steps * 1e-3) / 1e6, 3)}
+        if extras and sc.sensor == 1 and sc.max_depth == 4 and not args.no_nlos_area:
+            # NLOS area sampling of the hidden vertex (Sec. 4.5) on the same
+            # scan: its rate, and the variance of the steady image relative
+            # to the default cosine sampling at equal spp (from the squared
+            # differences of two independent renders of each estimator)
+            ms, _ = time_launches(lambda: tr.render_transient(dev, film=film, steady=steady, nlos_area=True),
+                                  args.steps, args.warmup)
+            ms_path, _ = time_launches(lambda: tr.render_transient(dev, film=film, steady=steady, nlos_area=True,
+                                                                   kernel="path"), args.steps, args.warmup)
+            _, _, area_counts = tr.render_transient_counted(dev, nlos_area=True)
+            diff = []
+            for area in (True, False):
+                a = tr.render_transient(dev, seed=11, nlos_area=area)[0].double()
+                b = tr.render_transient(dev, seed=12, nlos_area=area)[0].double()
+                diff.append(float(((a - b) ** 2).mean()))
+            out["nlos_area_sampling"] = {
+                "ms_per_step": round(ms / args.steps, 4),
+                "mpaths_per_s": round(paths / (ms / args.steps * 1e-3) / 1e6, 3),
+                "path_form_mpaths_per_s": round(paths / (ms_path / args.steps * 1e-3) / 1e6, 3),
+                "variance_vs_cosine": round(diff[0] / diff[1], 5),
+                "efficiency_vs_cosine": round((diff[1] / diff[0]) * (total_ms / ms), 3),
+                "counts": area_counts}
+    ms_per_step = total_ms / args.steps
+    launch_ms = float(np.mean(per))
+    form = args.kernel if args.kernel != "auto" else ("deferred" if sc.sensor == 1 else "path")
+    kernel_name = {"path": "k_render", "deferred": "k_render_deferred", "wavefront": "k_render_wf"}[form]
+    res = {"value": round(paths / (ms_per_step * 1e-3) / 1e6, 3), "ms_per_step": round(ms_per_step, 4),
+           "config": {"workload": WORKLOADS[name]["desc"], "paths_per_step": paths,
+                      "triangles": info["n_triangles"], "bvh_depth": info["bvh_depth"]},
+           "scene_upload_and_bvh_build_ms": round(upload_ms, 2),
+           "roofline": roofline_of(counts, launch_ms, kernel_name, measured_traffic(name),
+                                   algorithmic_bytes(sc, info))}
+    res.update(out)
+    return res, sc
+
+
+def run_batched(args, tr, counted=True):
+    """The batched workload: one graph launch renders all 256 scenes; its
+    work counts are those of the scenes' single renders (same paths)."""
+    import torch
+    from paper_2510_25660_amd import scenes
+    scs = scenes.batched_nlos()
+    devs = [tr.upload(s) for s in scs]
+    try:
+        b = tr.Batch(devs, autotune=True)
+        info = b.info()
+        total_ms, per = time_launches(b.render, args.steps, args.warmup)
+        seq = None
+        if args.compare_kernels:
+            films = b.films
+            seq_ms, _ = time_launches(lambda: [tr.render_transient(d, film=f) for d, f in zip(devs, films)],
+                                      max(1, args.steps // 4), 1)
+            seq = seq_ms / max(1, args.steps // 4)
+        b.destroy()
+        counts = None
+        if counted:
+            counts = {}
+            for d in devs:
+                _, _, c = tr.render_transient_counted(d)
+                for k, v in c.items():
+                    counts[k] = counts.get(k, 0) + v
+    finally:
+        for d in devs:
+            d.destroy()
+    paths = sum(s.n_pixels * s.spp for s in scs)
+    ms = total_ms / args.steps
+    out = {"value": round(paths / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 4),
+           "config": {"workload": WORKLOADS["batched"]["desc"], "paths_per_step": paths,
+                      "triangles": int(sum(s.n_tris for s in scs)), "batch": info}}
+    if counts:
+        out["roofline"] = roofline_of(counts, float(np.mean(per)), "k_batch")
+    if seq is not None:
+        out["sequential_single_scene_ms"] = round(seq, 3)
+    return out
+
+
+def json_line(value, ms, args, config, unit="Mpath-samples/s"):
+    return {"metric": "Mpath-samples/s into transient film at 1 GPU; backward/forward time ratio",
+            "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic (seeded scene generators)", "config": config}
 
 
 def main():
@@ -277,7 +408,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="confocal", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS),
+                    help="headline workload (default: the large scene, the largest configuration)")
+    ap.add_argument("--only", action="store_true", help="measure the headline workload alone")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
     ap.add_argument("--tile-pixels", type=int, default=0)
@@ -288,10 +421,6 @@ def main():
     ap.add_argument("--phasor-freqs", type=int, default=16,
                     help="also time the frequency-space film with this many frequencies (0: skip)")
     ap.add_argument("--no-nlos-area", action="store_true", help="skip the NLOS area-sampling measurement")
-    ap.add_argument("--no-glass", action="store_true", help="skip the glass-room measurement")
-    ap.add_argument("--no-box-graph", action="store_true", help="skip the graph-replayed box-room latency")
-    ap.add_argument("--atomic-calibration", action="store_true",
-                    help="compare the render's film atomics with a scatter-add of as many float adds at the same bins")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a device copy of this many MiB (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -312,109 +441,22 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.workload == "batched":
-        print(json.dumps(run_batched(args, tr)), flush=True)
+        b = run_batched(args, tr, counted=not args.only)
+        out = json_line(b.pop("value"), b.pop("ms_per_step"), args, b.pop("config"))
+        out.update(b)
+        print(json.dumps(out), flush=True)
         return
-    sc = make_scene(args.workload)
     shape = dict(tile_pixels=args.tile_pixels, block_size=args.block_size, kernel=args.kernel)
-    paths = sc.n_pixels * sc.spp
-    # scene upload + BVH build (off the timed loop; the first build also warms the runtime, so time a second one)
-    tr.upload(sc, builder=args.builder).destroy()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    dev0 = tr.upload(sc, builder=args.builder)
-    torch.cuda.synchronize()
-    upload_ms = (time.perf_counter() - t0) * 1e3
-    dev0.destroy()
-    with tr.upload(sc, builder=args.builder) as dev:
-        info = dev.info()
-        steady = torch.empty((sc.height, sc.width), device="cuda", dtype=torch.float32)
-        film = torch.empty((sc.height, sc.width, sc.n_bins), device="cuda", dtype=torch.float32)
-        step = lambda: tr.render_transient(dev, film=film, steady=steady, **shape)
-        total_ms, per = time_launches(step, args.steps, args.warmup)
-        _, _, counts = tr.render_transient_counted(dev, **shape)
-        forms = {}
-        if args.compare_kernels:
-            for form in ("path", "deferred", "wavefront"):
-                sh = dict(shape, kernel=form)
-                ms, _ = time_launches(lambda: tr.render_transient(dev, film=film, steady=steady, **sh), args.steps,
-                                      args.warmup)
-                forms[form] = round(paths / (ms / args.steps * 1e-3) / 1e6, 3)
-        phasor = None
-        if args.phasor_freqs:
-            # the same paths into a phasor film (Sec. 4.3) instead of the histogram
-            freqs = list(np.linspace(0.5, 16.6, args.phasor_freqs))
-            ph = torch.empty((sc.height, sc.width, len(freqs), 2), device="cuda", dtype=torch.float32)
-            ms, _ = time_launches(lambda: tr.render_phasor(dev, freqs, phasor=ph, steady=steady, **shape),
-                                  args.steps, args.warmup)
-            phasor = {"n_freq": len(freqs), "freq_range_per_m": [0.5, 16.6], "ms_per_step": round(ms / args.steps, 4),
-                      "mpaths_per_s": round(paths / (ms / args.steps * 1e-3) / 1e6, 3)}
-        nlos = None
-        if sc.sensor == 1 and sc.max_depth == 4 and not args.no_nlos_area:
-            # NLOS area sampling of the hidden vertex (Sec. 4.5) on the same
-            # scan: its rate, and the variance of the steady image relative
-            # to the default cosine sampling at equal spp (from the squared
-            # differences of two independent renders of each estimator)
-            ms, _ = time_launches(lambda: tr.render_transient(dev, film=film, steady=steady, nlos_area=True),
-                                  args.steps, args.warmup)
-            ms_path, _ = time_launches(lambda: tr.render_transient(dev, film=film, steady=steady, nlos_area=True,
-                                                                   kernel="path"), args.steps, args.warmup)
-            _, _, area_counts = tr.render_transient_counted(dev, nlos_area=True)
-            diff = []
-            for area in (True, False):
-                a = tr.render_transient(dev, seed=11, nlos_area=area)[0].double()
-                b = tr.render_transient(dev, seed=12, nlos_area=area)[0].double()
-                diff.append(float(((a - b) ** 2).mean()))
-            nlos = {"ms_per_step": round(ms / args.steps, 4),
-                    "mpaths_per_s": round(paths / (ms / args.steps * 1e-3) / 1e6, 3),
-                    "path_form_mpaths_per_s": round(paths / (ms_path / args.steps * 1e-3) / 1e6, 3),
-                    "variance_vs_cosine": round(diff[0] / diff[1], 5),
-                    "efficiency_vs_cosine": round((diff[1] / diff[0]) * (total_ms / ms), 3),
-                    "counts": area_counts}
-    ms_per_step = total_ms / args.steps
-    value = paths / (ms_per_step * 1e-3) / 1e6
-    launch_ms = float(np.mean(per))
-    # the deferred form adds split pixels' partial films with HBM atomics
-    form = args.kernel if args.kernel != "auto" else ("deferred" if sc.sensor == 1 else "path")
-    atomics = (film_atomic_rate(film, sc, launch_ms)
-               if args.atomic_calibration and form == "deferred" and sc.spp > 2048 else None)
-    ops = sum(OPS_PER[k] * counts[k] for k in OPS_PER)
-    # the kernel the automatic choice runs: the deferred form for the confocal sensor
-    kernel_name = {"path": "k_render", "deferred": "k_render_deferred", "wavefront": "k_render_wf"}[form]
-    achieved = ops / (launch_ms * 1e-3)
-    out = {
-        "metric": "Mpath-samples/s into transient film at 1 GPU; backward/forward time ratio",
-        "value": round(value, 3),
-        "unit": "Mpath-samples/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic (seeded scene generators)",
-        "config": {"workload": WORKLOADS[args.workload]["desc"], "paths_per_step": paths,
-                   "triangles": info["n_triangles"], "bvh_depth": info["bvh_depth"]},
-        "scene_upload_and_bvh_build_ms": round(upload_ms, 2),
-        "roofline": {"bound": "alu", "achieved": round(achieved / 1e12, 4), "peak": round(PEAK_VALU_LANE_OPS / 1e12, 2),
-                     "unit": "T lane-ops/s", "frac": round(achieved / PEAK_VALU_LANE_OPS, 4),
-                     "traffic": measured_traffic(args.workload), "traffic_unit": "bytes/launch",
-                     "kernel": kernel_name, "launch_ms": round(launch_ms, 4),
-                     "ops_per_launch": int(ops), "counts": counts,
-                     "active_lanes_per_wave": active_lanes(counts)},
-    }
-    if forms:
-        out["kernel_forms_mpaths_per_s"] = forms
-    if atomics:
-        out["film_atomics"] = atomics
-    if phasor:
-        out["phasor_film"] = phasor
-    if nlos:
-        out["nlos_area_sampling"] = nlos
-    if args.workload == "confocal" and not args.no_glass:
+    head, sc = measure_single(tr, args.workload, args, shape, extras=True)
+    out = json_line(head.pop("value"), head.pop("ms_per_step"), args, head.pop("config"))
+    out.update(head)
+    if not args.only:
+        if args.workload != "confocal":
+            conf, _ = measure_single(tr, "confocal", args, dict(tile_pixels=0, block_size=0, kernel="auto"),
+                                     extras=True)
+            out["confocal"] = conf
+        out["batched"] = run_batched(args, tr)
         out["glass_room"] = glass_room(tr, args.steps, args.warmup)
-    if args.workload == "confocal" and not args.no_box_graph:
         out["box_room_graph"] = box_room_graph(tr)
     if not args.no_backward:
         ratio, f_ms, b_ms, rep_ms, t_ms = backward_forward_ratio(tr)

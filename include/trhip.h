@@ -318,6 +318,73 @@ trhip_status trhip_render_transient_counted(trhip_scene* scene, const trhip_rend
                                             float* steady, float* oow, uint64_t* counts, void* stream);
 
 /*
+ * Diagnostic variant of trhip_render_transient that also lists its
+ * contributions one by one, so that the bin index and the value of every
+ * next-event contribution (Sec. 3, "Path reuse and histogramming": a
+ * contribution c of a path of time of flight tof lands in bin
+ * floor((tof - b_start) / b_width)) can be compared with an independent
+ * implementation, not only their sums in the film.  The same render (same
+ * film, steady and oow, same paths, the kernel form render->kernel
+ * selects) by a build of that kernel that appends one trhip_record per
+ * contribution of every pixel p with pixel_mask[p] != 0.
+ *
+ * pixel_mask: DEVICE uint8[n_pixels].  records: DEVICE
+ * trhip_record[capacity] (NULL allowed when capacity is 0).  n_records:
+ * HOST uint64, receives the number of contributions of the marked pixels;
+ * when it exceeds capacity only `capacity` of them (in no particular order)
+ * were written.  Records come in no particular order.  film, steady, oow:
+ * as for trhip_render_transient.  Synchronous (returns after the render
+ * has finished); allocates a small device buffer.
+ * Errors: as trhip_render_transient, plus INVALID_ARG for a NULL
+ * pixel_mask, n_records, or records with capacity > 0; UNSUPPORTED for a
+ * phasor-style or batched render (only this entry records).
+ */
+typedef struct {
+    uint32_t pixel;   /* pixel or scan point (row-major index) */
+    uint32_t sample;  /* sample index, sample_offset included */
+    int32_t vertex;   /* scattering vertex of the connection, 1-based */
+    int32_t bin;      /* time bin, -1 outside the film window */
+    float value;      /* contribution c, before the 1/norm_spp normalisation */
+    float tof;        /* optical path length of the connected path (metres) */
+    int32_t tri;      /* caller index of the vertex's triangle, -1 for a medium vertex */
+    uint32_t reserved;
+} trhip_record;
+trhip_status trhip_render_transient_records(trhip_scene* scene, const trhip_render_desc* render,
+                                            const uint8_t* pixel_mask, trhip_record* records, uint64_t capacity,
+                                            uint64_t* n_records, float* film, float* steady, float* oow,
+                                            void* stream);
+
+/*
+ * Numerics probe.  Every hit, sampled direction, free-flight distance and
+ * bin index of the renderer is computed from a few FP32 and integer
+ * primitives that an independent implementation must reproduce bit for bit
+ * for bin indices to agree (the counter-based random numbers of the Monte
+ * Carlo estimator, Eq. 9; the sine and cosine of the direction samplers;
+ * ln(1 - u) of the free flight, Sec. 4.1; correctly rounded division and
+ * square root).  This entry evaluates one of them per element, on the
+ * device, with the same device functions and compiler flags as the render
+ * kernels:
+ *   TRHIP_PROBE_SINCOS2PI: out float[n][2] = (sin, cos)(2 pi u_i) with
+ *     u_i = (first + i) * 2^-24 (the uniforms the renderer draws);
+ *   TRHIP_PROBE_LOG1M: out float[n] = ln(1 - u_i), u_i as above;
+ *   TRHIP_PROBE_PHILOX: in uint32[n][6] = (counter words 0..3, key low,
+ *     key high), out uint32[n][4]: Philox4x32-10 (Salmon et al., SC 2011);
+ *   TRHIP_PROBE_DIV: in float[n][2], out float[n] = in[i][0] / in[i][1];
+ *   TRHIP_PROBE_SQRT: in float[n], out float[n] = sqrt(in[i]).
+ * in, out: DEVICE pointers (in is ignored, and may be NULL, for the first
+ * two).  first + n <= 2^24 for SINCOS2PI and LOG1M.  Asynchronous on
+ * `stream`.  Errors: INVALID_ARG (unknown op, NULL pointer, range), HIP.
+ */
+enum {
+    TRHIP_PROBE_SINCOS2PI = 0,
+    TRHIP_PROBE_LOG1M = 1,
+    TRHIP_PROBE_PHILOX = 2,
+    TRHIP_PROBE_DIV = 3,
+    TRHIP_PROBE_SQRT = 4
+};
+trhip_status trhip_numerics_probe(int32_t op, const void* in, void* out, uint64_t n, uint64_t first, void* stream);
+
+/*
  * Batched persistent rendering of many scenes (e.g. NLOS datasets, Sec. 4.5)
  * in one launch.  Work items are (scene, pixel tile) pairs, ordered by
  * estimated cost (largest first) and popped by persistent workgroups from a

@@ -137,6 +137,8 @@ def _load(path: str):
     L.orc_area_total.argtypes = [C.c_void_p]
     L.orc_trace_path.argtypes = [C.c_void_p, C.POINTER(_Render), C.c_uint32, C.c_uint32, C.POINTER(_Path)]
     L.orc_render_film.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, dp, dp, dp, C.c_int]
+    L.orc_render_records.restype = C.c_int64
+    L.orc_render_records.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, C.c_void_p, C.c_int64]
     L.orc_render_tangent.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, dp, dp, dp, dp, dp, C.c_int]
     L.orc_render_phasor.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, dp, C.c_int, dp, dp, C.c_int]
     L.orc_backward.argtypes = [C.c_void_p, C.POINTER(_Render), ip, C.c_int, fp, dp, dp, dp, C.c_int]
@@ -464,6 +466,30 @@ class Oracle:
         if want_primal:
             return ga, gr, primal
         return ga, gr
+
+    RECORD_FIELDS = [("pixel", "<u4"), ("sample", "<u4"), ("vertex", "<i4"), ("bin", "<i4"), ("value", "<f4"),
+                     ("tof", "<f4"), ("tri", "<i4"), ("reserved", "<u4")]
+
+    def records(self, pixels, spp=None, seed=None, max_depth=None, **kw):
+        """Every next-event contribution of the listed pixels' paths as a
+        structured array (pixel, sample, vertex, bin, value, tof, tri)."""
+        sc = self.scene
+        spp = sc.spp if spp is None else spp
+        seed = sc.seed if seed is None else seed
+        max_depth = sc.max_depth if max_depth is None else max_depth
+        pixels = np.ascontiguousarray(pixels, np.int32)
+        r, keep = self._render_desc(spp, seed, max_depth, **kw)
+        dt = np.dtype(self.RECORD_FIELDS)
+        cap = max(1, 8 * len(pixels) * int(spp))
+        while True:
+            out = np.zeros(cap, dt)
+            n = self._L.orc_render_records(self._h, C.byref(r), pixels.ctypes.data_as(C.POINTER(C.c_int32)),
+                                           len(pixels), out.ctypes.data, cap)
+            if n < 0:
+                raise ValueError("oracle records failed")
+            if n <= cap:
+                return out[:n]
+            cap = int(n)
 
     def trace(self, pix: int, sample: int, spp_seed=None, max_depth=None, **kw):
         """One path: list of dict per vertex."""

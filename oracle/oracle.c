@@ -1437,6 +1437,48 @@ int orc_render_film(const orc_prepared* P, const orc_render* R, const int32_t* p
     return 0;
 }
 
+/* Every next-event contribution of the listed pixels' paths, one entry
+ * per contribution (the terms that the histogram of Sec. 3, "Path reuse and
+ * histogramming", sums): pixel, sample, vertex (1-based), bin (-1 outside
+ * the window), value c (before the 1/N of Eq. 9), time of flight, triangle
+ * (-1 for a medium vertex).  Pixel by pixel, sample by sample, vertex by
+ * vertex; at most `cap` entries are written, the return value counts all
+ * (-1 for an invalid render). */
+int64_t orc_render_records(const orc_prepared* P, const orc_render* R, const int32_t* pixels, int n_pix,
+                           orc_record* out, int64_t cap)
+{
+    orc_path* rec;
+    int64_t n = 0;
+    int i, v;
+    uint32_t s;
+    if (!render_ok(P, R)) return -1;
+    rec = (orc_path*)malloc(sizeof(orc_path));
+    if (!rec) return -1;
+    for (i = 0; i < n_pix; ++i) {
+        for (s = 0; s < (uint32_t)R->spp; ++s) {
+            orc_trace_path(P, R, (uint32_t)pixels[i], R->sample_offset + s, rec);
+            for (v = 0; v < rec->n_vert; ++v) {
+                const orc_vertex* vx = &rec->v[v];
+                if (!vx->has_c) continue;
+                if (n < cap) {
+                    orc_record* o = &out[n];
+                    o->pixel = (uint32_t)pixels[i];
+                    o->sample = R->sample_offset + s;
+                    o->vertex = v + 1;
+                    o->bin = vx->bin;
+                    o->value = vx->c;
+                    o->tof = vx->opl_c;
+                    o->tri = vx->tri;
+                    o->reserved = 0;
+                }
+                ++n;
+            }
+        }
+    }
+    free(rec);
+    return n;
+}
+
 int orc_render_tangent(const orc_prepared* P, const orc_render* R, const int32_t* pixels, int n_pix,
                        const double* v_alb, const double* v_rough, double* film, double* dfilm, double* steady,
                        int nthreads)

@@ -68,6 +68,15 @@ typedef struct {
     orc_vertex v[ORC_MAX_VERT];
 } orc_path;
 
+/* one next-event contribution (orc_render_records) */
+typedef struct {
+    uint32_t pixel, sample;
+    int32_t vertex, bin;
+    float value, tof;
+    int32_t tri;
+    uint32_t reserved;
+} orc_record;
+
 typedef struct orc_prepared orc_prepared;
 
 orc_prepared* orc_prepare(const orc_scene* sc);
@@ -77,6 +86,8 @@ double orc_area_total(const orc_prepared* p);
 float orc_fresnel(float ci, float eta_i, float eta_t); /* unpolarised dielectric reflectance */
 
 int orc_trace_path(const orc_prepared* p, const orc_render* r, uint32_t pix, uint32_t sample, orc_path* rec);
+int64_t orc_render_records(const orc_prepared* p, const orc_render* r, const int32_t* pixels, int n_pix,
+                           orc_record* out, int64_t cap);
 int orc_render_film(const orc_prepared* p, const orc_render* r, const int32_t* pixels, int n_pix,
                     double* film, double* steady, double* oow, int nthreads);
 /* forward-mode derivative (Sec. 4.4): film and dfilm [n_pix][T], dfilm the

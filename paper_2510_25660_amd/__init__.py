@@ -25,7 +25,7 @@ from ._binding import (FLAG_ACCUMULATE, FLAG_FROZEN_PROPOSAL, FLAG_NLOS_AREA_SAM
 
 __all__ = [
     "scenes", "upload", "DeviceScene", "render_transient", "render_transient_backward", "render_transient_counted",
-    "render_transient_tangent", "render_phasor", "poisson_noise",
+    "render_transient_tangent", "render_phasor", "poisson_noise", "render_transient_records", "numerics_probe",
     "TransientRender", "Batch",
     "TrhipError", "FLAG_PIXEL_CENTRE", "FLAG_ACCUMULATE", "FLAG_FROZEN_PROPOSAL", "FLAG_NLOS_AREA_SAMPLING",
     "version",
@@ -184,6 +184,19 @@ def _check_param(t, n, name):
     return t
 
 
+def _out(t, shape, name, optional=False):
+    """A caller-supplied output buffer (checked: the kernels write exactly
+    prod(shape) floats through its pointer), or a new one."""
+    torch = _torch()
+    if t is None:
+        return None if optional else torch.empty(shape, device="cuda", dtype=torch.float32)
+    n = int(np.prod(shape))
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+            and t.numel() == n):
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor with {n} elements")
+    return t
+
+
 def render_transient(dev: DeviceScene, spp=None, seed=None, max_depth=None, film=None, steady=None, oow=None,
                      stream=None, return_oow=False, **kw):
     """Forward transient render.  Returns (steady [H, W], film [H, W, T])
@@ -194,12 +207,9 @@ def render_transient(dev: DeviceScene, spp=None, seed=None, max_depth=None, film
     n = sc.n_tris
     kw["albedo"] = _check_param(kw.get("albedo"), n, "albedo")
     kw["roughness"] = _check_param(kw.get("roughness"), n, "roughness")
-    if film is None:
-        film = torch.empty(shape + (sc.n_bins,), device="cuda", dtype=torch.float32)
-    if steady is None:
-        steady = torch.empty(shape, device="cuda", dtype=torch.float32)
-    if oow is None and return_oow:
-        oow = torch.empty(shape, device="cuda", dtype=torch.float32)
+    film = _out(film, shape + (sc.n_bins,), "film")
+    steady = _out(steady, shape, "steady")
+    oow = _out(oow, shape, "oow", optional=not return_oow)
     r = make_render_desc(dev, spp, seed, max_depth, **kw)
     check(lib().trhip_render_transient(dev.handle, C.byref(r), _ptr(film), _ptr(steady), _ptr(oow),
                                        _stream_handle(stream)))
@@ -220,10 +230,8 @@ def render_phasor(dev: DeviceScene, freqs, spp=None, seed=None, max_depth=None, 
     k = int(f.size)
     kw["albedo"] = _check_param(kw.get("albedo"), sc.n_tris, "albedo")
     kw["roughness"] = _check_param(kw.get("roughness"), sc.n_tris, "roughness")
-    if phasor is None:
-        phasor = torch.empty(shape + (k, 2), device="cuda", dtype=torch.float32)
-    if steady is None:
-        steady = torch.empty(shape, device="cuda", dtype=torch.float32)
+    phasor = _out(phasor, shape + (k, 2), "phasor")
+    steady = _out(steady, shape, "steady")
     r = make_render_desc(dev, spp, seed, max_depth, **kw)
     check(lib().trhip_render_phasor(dev.handle, C.byref(r), f.ctypes.data_as(C.POINTER(C.c_float)), k,
                                     _ptr(phasor), _ptr(steady), _stream_handle(stream)))
@@ -243,12 +251,9 @@ def render_transient_tangent(dev: DeviceScene, tangent_albedo=None, tangent_roug
     kw["roughness"] = _check_param(kw.get("roughness"), n, "roughness")
     ta = _check_param(tangent_albedo, n, "tangent_albedo")
     trr = _check_param(tangent_roughness, n, "tangent_roughness")
-    if film is None:
-        film = torch.empty(shape + (sc.n_bins,), device="cuda", dtype=torch.float32)
-    if dfilm is None:
-        dfilm = torch.empty(shape + (sc.n_bins,), device="cuda", dtype=torch.float32)
-    if steady is None:
-        steady = torch.empty(shape, device="cuda", dtype=torch.float32)
+    film = _out(film, shape + (sc.n_bins,), "film")
+    dfilm = _out(dfilm, shape + (sc.n_bins,), "dfilm")
+    steady = _out(steady, shape, "steady")
     r = make_render_desc(dev, spp, seed, max_depth, **kw)
     check(lib().trhip_render_transient_tangent(dev.handle, C.byref(r), _ptr(ta), _ptr(trr), _ptr(film), _ptr(dfilm),
                                                _ptr(steady), _stream_handle(stream)))
@@ -275,6 +280,69 @@ def render_transient_counted(dev: DeviceScene, spp=None, seed=None, max_depth=No
     check(lib().trhip_render_transient_counted(dev.handle, C.byref(r), _ptr(film), _ptr(steady), None, counts,
                                                _stream_handle(stream)))
     return steady, film, dict(zip(COUNT_NAMES, [int(c) for c in counts]))
+
+
+def render_transient_records(dev: DeviceScene, pixels, capacity=None, spp=None, seed=None, max_depth=None,
+                             stream=None, **kw):
+    """Same render as render_transient by the recording build of the kernel
+    (trhip_render_transient_records): every next-event contribution of the
+    listed pixels as a record (pixel, sample, vertex, bin, value, tof, tri).
+    Returns (records numpy structured array, steady, film, oow); raises if
+    the pixels made more than `capacity` contributions (default: 64 per
+    path sample of the listed pixels).  Synchronous."""
+    torch = _torch()
+    from ._binding import RECORD_FIELDS
+    sc = dev.scene
+    shape = (sc.height, sc.width)
+    kw["albedo"] = _check_param(kw.get("albedo"), sc.n_tris, "albedo")
+    kw["roughness"] = _check_param(kw.get("roughness"), sc.n_tris, "roughness")
+    pix = np.unique(np.asarray(pixels, np.int64).ravel())
+    if pix.size and (pix[0] < 0 or pix[-1] >= sc.n_pixels):
+        raise ValueError("pixel index out of range")
+    mask = torch.zeros(sc.n_pixels, device="cuda", dtype=torch.uint8)
+    mask[torch.from_numpy(pix).cuda()] = 1
+    r = make_render_desc(dev, spp, seed, max_depth, **kw)
+    if capacity is None:
+        capacity = max(1, 64 * int(pix.size) * int(r.spp))
+    recs = torch.empty((int(capacity), 8), device="cuda", dtype=torch.int32)
+    film = torch.empty(shape + (sc.n_bins,), device="cuda", dtype=torch.float32)
+    steady = torch.empty(shape, device="cuda", dtype=torch.float32)
+    oow = torch.empty(shape, device="cuda", dtype=torch.float32)
+    n = C.c_uint64(0)
+    check(lib().trhip_render_transient_records(dev.handle, C.byref(r), _ptr(mask), _ptr(recs), int(capacity),
+                                               C.byref(n), _ptr(film), _ptr(steady), _ptr(oow),
+                                               _stream_handle(stream)))
+    if n.value > capacity:
+        raise ValueError(f"{n.value} contributions exceed the record capacity {capacity}")
+    out = recs[:n.value].cpu().numpy().view(np.dtype(RECORD_FIELDS)).reshape(-1)
+    return out, steady, film, oow
+
+
+def numerics_probe(op: str, inp=None, n=None, first=0, out=None, stream=None):
+    """The renderer's primitives evaluated element by element on the device
+    (trhip_numerics_probe): op "sincos2pi" / "log1m" over u = (first + i) 2^-24
+    (n values; out float32 [n, 2] / [n]), "philox" (inp uint32 [n, 6] ->
+    out [n, 4]), "div" (float32 [n, 2] -> [n]), "sqrt" ([n] -> [n])."""
+    torch = _torch()
+    from ._binding import PROBES
+    code = PROBES[op]
+    if op in ("sincos2pi", "log1m"):
+        if n is None:
+            raise ValueError("n is required")
+        shape = (int(n), 2) if op == "sincos2pi" else (int(n),)
+        out = torch.empty(shape, device="cuda", dtype=torch.float32) if out is None else out
+        ip = None
+    else:
+        want = {"philox": (torch.int32, 6), "div": (torch.float32, 2), "sqrt": (torch.float32, 1)}[op]
+        if not (inp.is_cuda and inp.is_contiguous() and inp.dtype == want[0] and inp.numel() % want[1] == 0):
+            raise ValueError(f"{op}: input must be a contiguous CUDA {want[0]} tensor of rows of {want[1]}")
+        n = inp.numel() // want[1]
+        if out is None:
+            out = (torch.empty((n, 4), device="cuda", dtype=torch.int32) if op == "philox"
+                   else torch.empty(n, device="cuda", dtype=torch.float32))
+        ip = _ptr(inp)
+    check(lib().trhip_numerics_probe(code, ip, _ptr(out), int(n), int(first), _stream_handle(stream)))
+    return out
 
 
 def poisson_noise(film, scale=None, peak_count=1000.0, seed=0, out=None, stream=None):
@@ -331,8 +399,9 @@ class Batch:
         n = len(self.devs)
         renders = renders or [{} for _ in range(n)]
         if films is None:
-            films = [torch.empty((d.scene.height, d.scene.width, d.scene.n_bins), device="cuda",
-                                 dtype=torch.float32) for d in self.devs]
+            films = [None] * n
+        films = [_out(f, (d.scene.height, d.scene.width, d.scene.n_bins), f"films[{i}]")
+                 for i, (f, d) in enumerate(zip(films, self.devs))]
         self.films = films
         descs = (RenderDesc * n)()
         for i, (d, kw) in enumerate(zip(self.devs, renders)):

@@ -30,10 +30,18 @@ EXPORTED_SYMBOLS = (
     "trhip_render_transient_backward", "trhip_render_transient_counted", "trhip_status_string",
     "trhip_last_error", "trhip_version", "trhip_batch_create", "trhip_batch_render", "trhip_batch_get_info",
     "trhip_batch_destroy", "trhip_poisson_noise", "trhip_render_phasor", "trhip_render_transient_tangent",
+    "trhip_render_transient_records", "trhip_numerics_probe",
 )
+
+PROBES = {"sincos2pi": 0, "log1m": 1, "philox": 2, "div": 3, "sqrt": 4}
 
 COUNT_NAMES = ("nodes", "tris", "rays", "shadow_rays", "vertices", "draws", "contributions", "wave_nodes",
                "wave_tris", "wave_vertices")
+
+
+# numpy layout of trhip_record
+RECORD_FIELDS = [("pixel", "<u4"), ("sample", "<u4"), ("vertex", "<i4"), ("bin", "<i4"), ("value", "<f4"),
+                 ("tof", "<f4"), ("tri", "<i4"), ("reserved", "<u4")]
 
 
 class TrhipError(RuntimeError):
@@ -171,6 +179,11 @@ def lib():
         L.trhip_render_phasor.restype = C.c_int
         L.trhip_render_transient_tangent.argtypes = [vp, C.POINTER(RenderDesc), vp, vp, vp, vp, vp, vp]
         L.trhip_render_transient_tangent.restype = C.c_int
+        L.trhip_render_transient_records.argtypes = [vp, C.POINTER(RenderDesc), vp, vp, C.c_uint64,
+                                                     C.POINTER(C.c_uint64), vp, vp, vp, vp]
+        L.trhip_render_transient_records.restype = C.c_int
+        L.trhip_numerics_probe.argtypes = [C.c_int32, vp, vp, C.c_uint64, C.c_uint64, vp]
+        L.trhip_numerics_probe.restype = C.c_int
         L.trhip_poisson_noise.argtypes = [vp, vp, C.c_uint64, C.c_float, C.c_uint64, vp]
         L.trhip_poisson_noise.restype = C.c_int
         L.trhip_status_string.argtypes = [C.c_int]

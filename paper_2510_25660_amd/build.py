@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libtrhip.so")
-SOURCES = ["bvh.hip", "render.hip", "noise.hip", "api.cpp"]
+SOURCES = ["bvh.hip", "render.hip", "noise.hip", "probe.hip", "api.cpp"]
 ARCH = os.environ.get("TRHIP_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

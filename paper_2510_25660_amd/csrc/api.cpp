@@ -10,6 +10,7 @@
 #include <array>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -71,6 +72,11 @@ struct trhip_scene {
     float* d_ior;    // nullptr: no dielectric triangle
     float* d_delay;  // nullptr: no scattering delay
     double* d_grad;  // 2 * n_tris doubles of backward workspace
+    // deferred form with sample chunks: partial tiles and per-tile counters
+    float* d_chunk_scratch;
+    size_t chunk_scratch_floats;
+    uint32_t* d_tile_count;
+    size_t tile_count_n;
     // confocal: NLOS area-sampling tables, one set per scan region
     double* d_area_cdf;      // [region][n_tris] prefix sums of the weights (caller order)
     float* d_area_invp;      // [region][n_tris] inverse area densities
@@ -114,6 +120,8 @@ void free_scene(trhip_scene* s)
     (void)hipFree(s->d_ior);
     (void)hipFree(s->d_delay);
     (void)hipFree(s->d_grad);
+    (void)hipFree(s->d_chunk_scratch);
+    (void)hipFree(s->d_tile_count);
     (void)hipFree(s->d_area_cdf);
     (void)hipFree(s->d_area_invp);
     (void)hipFree(s->d_sorted_of);
@@ -505,13 +513,70 @@ Kind forward_kind(const trhip_scene* s, const trhip_render_desc* r)
                                                                                                  : Kind::Path;
 }
 
-hipError_t launch_forward(Kind kind, const trhip::SceneView& S, const trhip::LaunchArgs& L, uint32_t block,
-                          hipStream_t stream, unsigned long long* counts)
+// Scratch of the deferred form's sample chunks (partial tiles and per-tile
+// counters), grown on demand and kept by the scene (which one stream uses at
+// a time).  Nothing is allocated while the stream is being captured into a
+// graph: *ready stays false and the launch keeps one chunk per tile, which
+// renders the same film.
+hipError_t ensure_chunk_scratch(trhip_scene* sc, size_t floats, size_t tiles, hipStream_t s, bool* ready)
+{
+    *ready = false;
+    if (sc->chunk_scratch_floats >= floats && sc->tile_count_n >= tiles) {
+        *ready = true;
+        return hipSuccess;
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cs);
+    if (e != hipSuccess || cs != hipStreamCaptureStatusNone) return e;
+    e = hipStreamSynchronize(s);  // earlier launches may still use the old buffers
+    if (e != hipSuccess) return e;
+    (void)hipFree(sc->d_chunk_scratch);
+    (void)hipFree(sc->d_tile_count);
+    sc->d_chunk_scratch = nullptr;
+    sc->d_tile_count = nullptr;
+    sc->chunk_scratch_floats = 0;
+    sc->tile_count_n = 0;
+    e = hipMalloc(&sc->d_chunk_scratch, floats * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&sc->d_tile_count, tiles * sizeof(uint32_t));
+    if (e == hipSuccess) e = trhip::launch_zero_u32(sc->d_tile_count, tiles, s);
+    if (e != hipSuccess) {
+        (void)hipFree(sc->d_chunk_scratch);
+        (void)hipFree(sc->d_tile_count);
+        sc->d_chunk_scratch = nullptr;
+        sc->d_tile_count = nullptr;
+        return e;
+    }
+    sc->chunk_scratch_floats = floats;
+    sc->tile_count_n = tiles;
+    *ready = true;
+    return hipSuccess;
+}
+
+hipError_t launch_forward(trhip_scene* sc, Kind kind, trhip::LaunchArgs L, uint32_t block, hipStream_t stream,
+                          unsigned long long* counts)
 {
     switch (kind) {
-    case Kind::Wavefront: return trhip::launch_render_wavefront(S, L, block, stream, counts);
-    case Kind::Deferred: return trhip::launch_render_deferred(S, L, block, stream, counts);
-    default: return trhip::launch_render(S, L, block, stream, counts);
+    case Kind::Wavefront: return trhip::launch_render_wavefront(sc->view, L, block, stream, counts);
+    case Kind::Deferred: {
+        uint32_t chunk_spp = L.spp;
+        const uint32_t chunks = trhip::deferred_chunks(L.spp, block, &chunk_spp);
+        if (chunks > 1) {
+            const size_t tiles = (L.n_pixels + L.tile_pixels - 1) / L.tile_pixels;
+            const uint32_t words = L.n_freq ? 2 * L.n_freq : sc->view.n_bins;
+            const size_t floats = tiles * chunks * ((size_t)L.tile_pixels * words + 2ull * L.tile_pixels);
+            bool ready = false;
+            const hipError_t e = ensure_chunk_scratch(sc, floats, tiles, stream, &ready);
+            if (e != hipSuccess) return e;
+            if (ready) {
+                L.chunks = chunks;
+                L.chunk_spp = chunk_spp;
+                L.chunk_scratch = sc->d_chunk_scratch;
+                L.tile_count = sc->d_tile_count;
+            }
+        }
+        return trhip::launch_render_deferred(sc->view, L, block, stream, counts);
+    }
+    default: return trhip::launch_render(sc->view, L, block, stream, counts);
     }
 }
 
@@ -651,7 +716,7 @@ trhip_status trhip_render_transient(trhip_scene* scene, const trhip_render_desc*
     L.film = film;
     L.steady = steady;
     L.oow = oow;
-    hipError_t e = launch_forward(kind, scene->view, L, block, (hipStream_t)stream, nullptr);
+    hipError_t e = launch_forward(scene, kind, L, block, (hipStream_t)stream, nullptr);
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return TRHIP_OK;
 }
@@ -681,7 +746,7 @@ trhip_status trhip_render_phasor(trhip_scene* scene, const trhip_render_desc* re
     L.oow = nullptr;
     L.n_freq = n_freq;
     for (uint32_t j = 0; j < n_freq; ++j) L.freq[j] = freqs[j];
-    hipError_t e = launch_forward(kind, scene->view, L, block, (hipStream_t)stream, nullptr);
+    hipError_t e = launch_forward(scene, kind, L, block, (hipStream_t)stream, nullptr);
     if (e != hipSuccess) return hip_fail(e, "phasor launch");
     return TRHIP_OK;
 }
@@ -727,12 +792,70 @@ trhip_status trhip_render_transient_counted(trhip_scene* scene, const trhip_rend
     unsigned long long* d_counts = nullptr;
     hipError_t e = hipMalloc(&d_counts, TRHIP_COUNT_N * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMemsetAsync(d_counts, 0, TRHIP_COUNT_N * sizeof(unsigned long long), s);
-    if (e == hipSuccess) e = launch_forward(kind, scene->view, L, block, s, d_counts);
+    if (e == hipSuccess) e = launch_forward(scene, kind, L, block, s, d_counts);
     if (e == hipSuccess)
         e = hipMemcpyAsync(counts, d_counts, TRHIP_COUNT_N * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(d_counts);
     if (e != hipSuccess) return hip_fail(e, "counted render");
+    return TRHIP_OK;
+}
+
+static_assert(sizeof(trhip_record) == sizeof(trhip::ContribRecord), "record layout");
+static_assert(offsetof(trhip_record, value) == offsetof(trhip::ContribRecord, value), "record layout");
+static_assert(offsetof(trhip_record, tri) == offsetof(trhip::ContribRecord, tri), "record layout");
+
+trhip_status trhip_render_transient_records(trhip_scene* scene, const trhip_render_desc* render,
+                                            const uint8_t* pixel_mask, trhip_record* records, uint64_t capacity,
+                                            uint64_t* n_records, float* film, float* steady, float* oow,
+                                            void* stream)
+{
+    trhip_status st = check_scene(scene);
+    if (st != TRHIP_OK) return st;
+    if ((st = validate_render(scene, render)) != TRHIP_OK) return st;
+    if (!film || !pixel_mask || !n_records)
+        return fail(TRHIP_ERR_INVALID_ARG, "film, pixel_mask and n_records must be non-NULL");
+    if (capacity > 0 && !records) return fail(TRHIP_ERR_INVALID_ARG, "records is NULL with capacity > 0");
+    const Kind kind = forward_kind(scene, render);
+    uint32_t tile = 0, block = 0;
+    if ((st = choose_shape(scene, render, kind, &tile, &block)) != TRHIP_OK) return st;
+    trhip::LaunchArgs L;
+    fill_launch(scene, render, tile, &L);
+    L.film = film;
+    L.steady = steady;
+    L.oow = oow;
+    L.record_mask = pixel_mask;
+    L.records = reinterpret_cast<trhip::ContribRecord*>(records);
+    L.record_cap = capacity;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* d_count = nullptr;
+    hipError_t e = hipMalloc(&d_count, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemsetAsync(d_count, 0, sizeof(unsigned long long), s);
+    L.record_count = d_count;
+    if (e == hipSuccess) e = launch_forward(scene, kind, L, block, s, nullptr);
+    unsigned long long n = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&n, d_count, sizeof(n), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d_count);
+    if (e != hipSuccess) return hip_fail(e, "recording render");
+    *n_records = n;
+    return TRHIP_OK;
+}
+
+trhip_status trhip_numerics_probe(int32_t op, const void* in, void* out, uint64_t n, uint64_t first, void* stream)
+{
+    if (op < TRHIP_PROBE_SINCOS2PI || op > TRHIP_PROBE_SQRT) return fail(TRHIP_ERR_INVALID_ARG, "unknown probe %d", op);
+    if (n == 0) return TRHIP_OK;
+    if (!out) return fail(TRHIP_ERR_INVALID_ARG, "out is NULL");
+    const bool uniforms = op == TRHIP_PROBE_SINCOS2PI || op == TRHIP_PROBE_LOG1M;
+    if (!uniforms && !in) return fail(TRHIP_ERR_INVALID_ARG, "in is NULL");
+    if (uniforms && (first > (1ull << 24) || n > (1ull << 24) - first))
+        return fail(TRHIP_ERR_INVALID_ARG, "first + n must not exceed 2^24");
+    if (n > (1ull << 40)) return fail(TRHIP_ERR_INVALID_ARG, "n too large");
+    static_assert(TRHIP_PROBE_SINCOS2PI == trhip::kProbeSinCos2Pi && TRHIP_PROBE_SQRT == trhip::kProbeSqrt,
+                  "probe numbering");
+    hipError_t e = trhip::launch_probe(op, in, out, n, first, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "probe launch");
     return TRHIP_OK;
 }
 

@@ -70,10 +70,21 @@ hipError_t launch_batch(const BatchTables& B, uint32_t groups, uint32_t block, u
                         bool short_links, bool deferred, hipStream_t stream);
 hipError_t launch_render_deferred(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
                                   unsigned long long* counts = nullptr);
+// sample chunks per tile of the deferred form (sets the samples per chunk);
+// chunks > 1 need L.chunk_scratch (tiles * chunks * (tile_pixels * words +
+// 2 * tile_pixels) floats) and L.tile_count (tiles counters, zero between
+// launches)
+constexpr uint32_t kMaxChunks = 4;
+uint32_t deferred_chunks(uint32_t spp, uint32_t block, uint32_t* chunk_spp);
+hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t stream);
 hipError_t launch_zero_f64(double* p, size_t n, hipStream_t stream);
 // out[i] = Poisson(scale * film[i]) / scale (noise.hip)
 hipError_t launch_poisson(const float* film, float* out, uint64_t n, float scale, uint64_t seed, hipStream_t stream);
 hipError_t launch_f64_to_f32(const double* src, float* dst, size_t n, hipStream_t stream);
 hipError_t launch_scene_fill(const float* tri9, uint32_t nt, hipStream_t stream);
+
+// numerics probe (probe.hip): one primitive per element, TRHIP_PROBE_* order
+enum { kProbeSinCos2Pi = 0, kProbeLog1m = 1, kProbePhilox = 2, kProbeDiv = 3, kProbeSqrt = 4 };
+hipError_t launch_probe(int op, const void* in, void* out, uint64_t n, uint64_t first, hipStream_t stream);
 
 }  // namespace trhip

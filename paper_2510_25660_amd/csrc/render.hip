@@ -190,14 +190,37 @@ enum {
 };
 static_assert(kTallyN == kWorkCounters, "one tally per work counter");
 
-template <bool kOn>
+// Build of a kernel: plain, counting (the work counters above), or
+// recording (every next-event contribution of the pixels marked in the
+// launch's record mask appended to its record buffer, to compare bins and
+// values one by one with the oracle).
+enum { kPlain = 0, kCounting = 1, kRecording = 2 };
+
+template <int kMode>
 struct Tally {
     __device__ __forceinline__ void add(int, uint32_t = 1u) {}
     __device__ __forceinline__ void wave(int) {}
     __device__ __forceinline__ void flush(unsigned long long*) {}
+    __device__ __forceinline__ void record(const LaunchArgs&, uint32_t, uint32_t, int, int, float, int, float) {}
 };
 template <>
-struct Tally<true> {
+struct Tally<kRecording> {
+    __device__ __forceinline__ void add(int, uint32_t = 1u) {}
+    __device__ __forceinline__ void wave(int) {}
+    __device__ __forceinline__ void flush(unsigned long long*) {}
+    __device__ __forceinline__ void record(const LaunchArgs& L, uint32_t pix, uint32_t sample, int v, int k, float c,
+                                           int bin, float tof)
+    {
+        if (!L.record_mask[pix]) return;
+        const unsigned long long i = atomicAdd(L.record_count, 1ull);
+        if (i >= L.record_cap) return;
+        uint4* dst = reinterpret_cast<uint4*>(L.records + i);
+        dst[0] = make_uint4(pix, sample, (uint32_t)v, (uint32_t)bin);
+        dst[1] = make_uint4(__float_as_uint(c), __float_as_uint(tof), (uint32_t)k, 0u);
+    }
+};
+template <>
+struct Tally<kCounting> {
     uint32_t n[kTallyN] = {};
     __device__ __forceinline__ void add(int i, uint32_t v = 1u) { n[i] += v; }
     __device__ __forceinline__ void wave(int i)
@@ -209,6 +232,7 @@ struct Tally<true> {
     {
         for (int i = 0; i < kTallyN; ++i) atomicAdd(out + i, (unsigned long long)n[i]);
     }
+    __device__ __forceinline__ void record(const LaunchArgs&, uint32_t, uint32_t, int, int, float, int, float) {}
 };
 
 // A BVH link read back from a traversal stack: 32-bit words hold it as is,
@@ -795,6 +819,7 @@ __device__ void continue_path(const SceneView& S, const LaunchArgs& L, uint32_t 
             blocked = occluded(S, make_ray(nee.so, nee.sd), nee.excl, nee.tmax, stk, stride, tally);
             if (!blocked) {
                 tally.add(kTallyContrib);
+                tally.record(L, pix, sample, v, nee.k, nee.c, nee.bin, nee.tof);
                 sink.contribution(v, nee.k, nee.c, nee.bin, nee.tof, nee.g_alb, nee.g_rough);
             }
         }
@@ -1090,10 +1115,11 @@ __device__ __forceinline__ void trace_first_hits(const SceneView& S, const Launc
 // batch is sorted by area_cell and each lane follows the sorted paths
 // directly (phase 1b and 2 in one).
 template <bool kArea, class W, class TallyT>
-__device__ __forceinline__ void render_tile_deferred(const SceneView& S, const LaunchArgs& L, uint32_t p0,
-                                                     float* lds_film, const float* freq, const DeferredLds& fh,
-                                                     W* stk, int stride, TallyT& tally)
+__device__ __forceinline__ void render_tile_deferred(const SceneView& S, const LaunchArgs& L, uint32_t tile,
+                                                     uint32_t chunk, float* lds_film, const float* freq,
+                                                     const DeferredLds& fh, W* stk, int stride, TallyT& tally)
 {
+    const uint32_t p0 = tile * L.tile_pixels;
     const uint32_t T = film_words(S, L);
     const uint32_t TP = L.tile_pixels;
     float* tfilm = lds_film;
@@ -1239,19 +1265,47 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
 
     const size_t fbase = (size_t)p0 * T;
     const uint32_t nvals = npix * T;
-    if (L.chunks > 1) {  // other workgroups hold other samples of these pixels
+    const bool acc = (L.flags & kFlagAccumulate) != 0;
+    if (L.chunks > 1) {
+        // Other workgroups hold other samples of these pixels.  Every chunk
+        // leaves its partial tile (film rows, steady, oow; unnormalised) in
+        // its slot of the scratch; the last of the tile's chunks to finish
+        // adds the partials up in chunk order and writes the tile once with
+        // plain stores, then re-arms the tile's counter for the next launch.
+        // (Adding the partials into the film with device-scope atomics cost
+        // one 64-byte memory write per atomic: 10x the film's bytes.)
+        const uint32_t words = TP * T + 2 * TP;
+        float* slots = L.chunk_scratch + (size_t)tile * L.chunks * words;
+        for (uint32_t i = tid; i < words; i += nb) slots[(size_t)chunk * words + i] = lds_film[i];
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) fh.count[1] = (atomicAdd(L.tile_count + tile, 1u) == L.chunks - 1) ? 1u : 0u;
+        __syncthreads();
+        if (!fh.count[1]) return;
+        __threadfence();
+        auto total = [&](uint32_t i) {
+            float v = 0.0f;
+            for (uint32_t c = 0; c < L.chunks; ++c) v = v + (c == chunk ? lds_film[i] : slots[(size_t)c * words + i]);
+            return v;
+        };
         for (uint32_t i = tid; i < nvals; i += nb) {
-            const float v = tfilm[i] * L.norm;
-            if (v != 0.0f) unsafeAtomicAdd(L.film + fbase + i, v);
+            const float v = total(i) * L.norm;
+            L.film[fbase + i] = acc ? L.film[fbase + i] + v : v;
         }
         if (tid < npix) {
             const uint32_t p = p0 + tid;
-            if (L.steady) unsafeAtomicAdd(L.steady + p, tsteady[tid] * L.norm);
-            if (L.oow) unsafeAtomicAdd(L.oow + p, toow[tid] * L.norm);
+            if (L.steady) {
+                const float v = total(TP * T + tid) * L.norm;
+                L.steady[p] = acc ? L.steady[p] + v : v;
+            }
+            if (L.oow) {
+                const float v = total(TP * T + TP + tid) * L.norm;
+                L.oow[p] = acc ? L.oow[p] + v : v;
+            }
         }
+        if (tid == 0) L.tile_count[tile] = 0u;
         return;
     }
-    const bool acc = (L.flags & kFlagAccumulate) != 0;
     for (uint32_t i = tid; i < nvals; i += nb) {
         const float v = tfilm[i] * L.norm;
         L.film[fbase + i] = acc ? L.film[fbase + i] + v : v;
@@ -1306,11 +1360,11 @@ __device__ __forceinline__ uint32_t tile_first_pixel(const SceneView& S, const L
     return t * TP;
 }
 
-template <bool kCount, class W, bool kArea>
+template <int kMode, class W, bool kArea>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 k_render_deferred(SceneView S, LaunchArgs L, unsigned long long* counts)
 {
-    Tally<kCount> tally;
+    Tally<kMode> tally;
     extern __shared__ float lds[];
     const uint32_t TP = L.tile_pixels;
     // workgroup -> (tile, chunk of the tile's samples)
@@ -1324,14 +1378,14 @@ k_render_deferred(SceneView S, LaunchArgs L, unsigned long long* counts)
     float* after_film = lds + (size_t)TP * film_words(S, L) + 2 * TP;
     const DeferredLds fh = carve_deferred(after_film, blockDim.x);
     W* stk = reinterpret_cast<W*>(after_film + deferred_words(blockDim.x)) + threadIdx.x;
-    render_tile_deferred<kArea>(S, Lc, tile * TP, lds, s_freq, fh, stk, (int)blockDim.x, tally);
+    render_tile_deferred<kArea>(S, Lc, tile, chunk, lds, s_freq, fh, stk, (int)blockDim.x, tally);
     tally.flush(counts);
 }
 
-template <bool kCount, class W>
+template <int kMode, class W>
 __global__ void __launch_bounds__(256) k_render(SceneView S, LaunchArgs L, unsigned long long* counts)
 {
-    Tally<kCount> tally;
+    Tally<kMode> tally;
     extern __shared__ float lds[];
     const uint32_t TP = L.tile_pixels;
     __shared__ float s_freq[kMaxFreq];
@@ -1352,7 +1406,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchTables B)
 {
     extern __shared__ float lds[];
     __shared__ uint32_t s_item;
-    Tally<false> tally;
+    Tally<kPlain> tally;
     const DeferredLds fh = carve_deferred(lds + B.film_words, blockDim.x);
     W* stk = reinterpret_cast<W*>(lds + B.film_words + (kDeferred ? deferred_words(blockDim.x) : 0)) + threadIdx.x;
     while (true) {
@@ -1373,7 +1427,7 @@ __global__ void __launch_bounds__(256) k_batch(BatchTables B)
         // NLOS area sampling needs no first-hit traversal to defer: such
         // scenes take the path-per-lane tile (same LDS film and stacks)
         if (kDeferred && !(args[scene].flags & kFlagNlosArea))
-            render_tile_deferred<false>(views[scene], args[scene], tile * args[scene].tile_pixels, lds, nullptr, fh,
+            render_tile_deferred<false>(views[scene], args[scene], tile, 0u, lds, nullptr, fh,
                                         stk, (int)blockDim.x, tally);
         else
             render_tile(views[scene], args[scene], tile * args[scene].tile_pixels, lds, nullptr, stk,
@@ -1402,7 +1456,7 @@ __global__ void k_reset_cursor(uint32_t* cursor)
 // with a barrier between stages.  Compaction into queues keeps the costly
 // stages dense: a wave that has no entry in a queue skips that stage and
 // leaves its SIMD to other waves.
-constexpr int kWfWords = 32;  // 32-bit words of LDS per slot
+constexpr int kWfWords = 34;  // 32-bit words of LDS per slot
 
 struct WfSlots {
     float *ox, *oy, *oz, *dx, *dy, *dz, *beta, *opl, *uff, *eta;
@@ -1410,8 +1464,8 @@ struct WfSlots {
     uint32_t* sample;
     float* ht;
     int *hprim, *hsorted, *hmed;
-    float *sox, *soy, *soz, *sdx, *sdy, *sdz, *stmax, *sc;
-    int *sexcl, *sbin;
+    float *sox, *soy, *soz, *sdx, *sdy, *sdz, *stmax, *sc, *stof;
+    int *sexcl, *sbin, *sv;
     int *ray_q, *hit_q, *sh_q;
 };
 
@@ -1429,8 +1483,8 @@ __device__ __forceinline__ WfSlots carve_slots(float* base, int ns)
     w.ht = take_f(); w.hprim = take_i(); w.hsorted = take_i(); w.hmed = take_i();
     w.sox = take_f(); w.soy = take_f(); w.soz = take_f();
     w.sdx = take_f(); w.sdy = take_f(); w.sdz = take_f();
-    w.stmax = take_f(); w.sc = take_f();
-    w.sexcl = take_i(); w.sbin = take_i();
+    w.stmax = take_f(); w.sc = take_f(); w.stof = take_f();
+    w.sexcl = take_i(); w.sbin = take_i(); w.sv = take_i();
     w.ray_q = take_i(); w.hit_q = take_i(); w.sh_q = take_i();
     return w;
 }
@@ -1453,12 +1507,12 @@ __device__ __forceinline__ PathState load_state(const WfSlots& w, int i)
     return ps;
 }
 
-template <bool kCount, class W>
+template <int kMode, class W>
 __global__ void __launch_bounds__(256) k_render_wf(SceneView S, LaunchArgs L, unsigned long long* counts)
 {
     extern __shared__ float lds[];
     __shared__ uint32_t ctr[4];  // ray queue, hit queue, shadow queue, next work item
-    Tally<kCount> tally;
+    Tally<kMode> tally;
     const uint32_t T = S.n_bins;
     const uint32_t TP = L.tile_pixels;
     const int nb = (int)blockDim.x;
@@ -1522,6 +1576,7 @@ __global__ void __launch_bounds__(256) k_render_wf(SceneView S, LaunchArgs L, un
         for (int j = tid; j < nh; j += nb) {
             const int i = w.hit_q[j];
             PathState ps = load_state(w, i);
+            const int v = ps.v;
             Hit h;
             h.t = w.ht[i];
             h.prim = w.hprim[i];
@@ -1534,6 +1589,7 @@ __global__ void __launch_bounds__(256) k_render_wf(SceneView S, LaunchArgs L, un
                 w.sox[i] = nee.so.x; w.soy[i] = nee.so.y; w.soz[i] = nee.so.z;
                 w.sdx[i] = nee.sd.x; w.sdy[i] = nee.sd.y; w.sdz[i] = nee.sd.z;
                 w.stmax[i] = nee.tmax; w.sc[i] = nee.c; w.sexcl[i] = nee.excl; w.sbin[i] = nee.bin;
+                w.stof[i] = nee.tof; w.sv[i] = v;
                 w.sh_q[atomicAdd(&ctr[2], 1u)] = i;
             }
             if (cont.alive) {
@@ -1556,6 +1612,7 @@ __global__ void __launch_bounds__(256) k_render_wf(SceneView S, LaunchArgs L, un
                 const float c = w.sc[i];
                 const int bin = w.sbin[i];
                 const int pl = w.pl[i];
+                tally.record(L, p0 + (uint32_t)pl, w.sample[i], w.sv[i], w.sexcl[i], c, bin, w.stof[i]);
                 if (bin >= 0) atomicAdd(tfilm + (size_t)pl * T + bin, c);
                 else atomicAdd(toow + pl, c);
                 atomicAdd(tsteady + pl, c);
@@ -1726,7 +1783,7 @@ struct TangentSink {
 template <class W>
 __global__ void __launch_bounds__(256) k_render_tangent(SceneView S, LaunchArgs L)
 {
-    Tally<false> tally;
+    Tally<kPlain> tally;
     extern __shared__ float lds[];
     const uint32_t T = S.n_bins;
     const uint32_t TP = L.tile_pixels;
@@ -1767,7 +1824,7 @@ __global__ void __launch_bounds__(256) k_render_tangent(SceneView S, LaunchArgs 
 template <class W>
 __global__ void __launch_bounds__(256) k_backward(SceneView S, LaunchArgs L)
 {
-    Tally<false> tally;
+    Tally<kPlain> tally;
     extern __shared__ float lds[];
     const uint32_t T = S.n_bins;
     const uint32_t TP = L.tile_pixels;
@@ -1877,7 +1934,7 @@ template <int kMaxCont, class W>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_backward_stash(SceneView S, LaunchArgs L)
 {
-    Tally<false> tally;
+    Tally<kPlain> tally;
     extern __shared__ float lds[];
     const uint32_t T = S.n_bins;
     const uint32_t TP = L.tile_pixels;
@@ -1916,10 +1973,10 @@ k_backward_stash(SceneView S, LaunchArgs L)
         for (uint32_t i = threadIdx.x; i < npix * T; i += blockDim.x) L.primal[base + i] = tprimal[i] * L.norm;
 }
 
-__global__ void k_zero_f32(float* p, size_t n)
+__global__ void k_zero_u32(uint32_t* p, size_t n)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        p[i] = 0.0f;
+        p[i] = 0u;
 }
 
 __global__ void k_zero_f64(double* p, size_t n)
@@ -1986,48 +2043,66 @@ namespace {
 
 uint32_t tiles_of(const LaunchArgs& L) { return (L.n_pixels + L.tile_pixels - 1) / L.tile_pixels; }
 
+// the build a forward launch runs: recording when the launch carries a
+// record buffer, counting when it carries counters, plain otherwise
+int mode_of(const LaunchArgs& L, const unsigned long long* counts)
+{
+    return L.record_count ? kRecording : (counts ? kCounting : kPlain);
+}
+
 template <class W>
 void launch_render_w(const SceneView& S, const LaunchArgs& L, uint32_t block, size_t lds, hipStream_t stream,
                      unsigned long long* counts)
 {
-    if (counts)
-        hipLaunchKernelGGL((k_render<true, W>), dim3(tiles_of(L)), dim3(block), lds, stream, S, L, counts);
-    else
-        hipLaunchKernelGGL((k_render<false, W>), dim3(tiles_of(L)), dim3(block), lds, stream, S, L, counts);
+    const dim3 grid(tiles_of(L));
+    switch (mode_of(L, counts)) {
+    case kRecording: hipLaunchKernelGGL((k_render<kRecording, W>), grid, dim3(block), lds, stream, S, L, counts); break;
+    case kCounting: hipLaunchKernelGGL((k_render<kCounting, W>), grid, dim3(block), lds, stream, S, L, counts); break;
+    default: hipLaunchKernelGGL((k_render<kPlain, W>), grid, dim3(block), lds, stream, S, L, counts);
+    }
 }
 
 template <class W>
 void launch_wavefront_w(const SceneView& S, const LaunchArgs& L, uint32_t block, size_t lds, hipStream_t stream,
                         unsigned long long* counts)
 {
-    if (counts)
-        hipLaunchKernelGGL((k_render_wf<true, W>), dim3(tiles_of(L)), dim3(block), lds, stream, S, L, counts);
-    else
-        hipLaunchKernelGGL((k_render_wf<false, W>), dim3(tiles_of(L)), dim3(block), lds, stream, S, L, counts);
+    const dim3 grid(tiles_of(L));
+    switch (mode_of(L, counts)) {
+    case kRecording:
+        hipLaunchKernelGGL((k_render_wf<kRecording, W>), grid, dim3(block), lds, stream, S, L, counts);
+        break;
+    case kCounting: hipLaunchKernelGGL((k_render_wf<kCounting, W>), grid, dim3(block), lds, stream, S, L, counts); break;
+    default: hipLaunchKernelGGL((k_render_wf<kPlain, W>), grid, dim3(block), lds, stream, S, L, counts);
+    }
+}
+
+template <class W, bool kArea>
+void launch_deferred_wa(const SceneView& S, const LaunchArgs& L, uint32_t block, size_t lds, hipStream_t stream,
+                        unsigned long long* counts)
+{
+    const dim3 grid(tiles_of(L) * L.chunks);
+    switch (mode_of(L, counts)) {
+    case kRecording:
+        hipLaunchKernelGGL((k_render_deferred<kRecording, W, kArea>), grid, dim3(block), lds, stream, S, L, counts);
+        break;
+    case kCounting:
+        hipLaunchKernelGGL((k_render_deferred<kCounting, W, kArea>), grid, dim3(block), lds, stream, S, L, counts);
+        break;
+    default: hipLaunchKernelGGL((k_render_deferred<kPlain, W, kArea>), grid, dim3(block), lds, stream, S, L, counts);
+    }
 }
 
 template <class W>
 void launch_deferred_w(const SceneView& S, const LaunchArgs& L, uint32_t block, size_t lds, hipStream_t stream,
                        unsigned long long* counts)
 {
-    const dim3 grid(tiles_of(L) * L.chunks);
-    if (L.flags & kFlagNlosArea) {
-        if (counts)
-            hipLaunchKernelGGL((k_render_deferred<true, W, true>), grid, dim3(block), lds, stream, S, L, counts);
-        else
-            hipLaunchKernelGGL((k_render_deferred<false, W, true>), grid, dim3(block), lds, stream, S, L, counts);
-    } else if (counts) {
-        hipLaunchKernelGGL((k_render_deferred<true, W, false>), grid, dim3(block), lds, stream, S, L, counts);
-    } else {
-        hipLaunchKernelGGL((k_render_deferred<false, W, false>), grid, dim3(block), lds, stream, S, L, counts);
-    }
+    if (L.flags & kFlagNlosArea)
+        launch_deferred_wa<W, true>(S, L, block, lds, stream, counts);
+    else
+        launch_deferred_wa<W, false>(S, L, block, lds, stream, counts);
 }
 
-void launch_zero_f32(float* p, size_t n, hipStream_t stream)
-{
-    const unsigned g = (unsigned)std::min<size_t>(1024, (n + 255) / 256 + 1);
-    hipLaunchKernelGGL(k_zero_f32, dim3(g), dim3(256), 0, stream, p, n);
-}
+
 
 template <class W>
 void launch_backward_w(const SceneView& S, const LaunchArgs& L, uint32_t block, int max_cont, size_t lds,
@@ -2077,25 +2152,12 @@ hipError_t launch_render_wavefront(const SceneView& S, const LaunchArgs& L, uint
     return hipGetLastError();
 }
 
-// The deferred form splits a tile's samples into chunks of one sort batch
-// when there are more: shorter workgroups shrink the tail of the launch
-// (measured on the confocal workload, 4096 samples per pixel: +4.5%; one
-// workgroup per half batch loses more to per-workgroup work than it gains).
-// Chunks of one tile add their partial films atomically.
-hipError_t launch_render_deferred(const SceneView& S, const LaunchArgs& L0, uint32_t block, hipStream_t stream,
+// The deferred form may split a tile's samples into chunks of whole sort
+// batches (the caller sets L.chunks, L.chunk_spp and the scratch, see
+// deferred_chunks): shorter workgroups shrink the tail of the launch.
+hipError_t launch_render_deferred(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
                                   unsigned long long* counts)
 {
-    LaunchArgs L = L0;
-    const uint32_t c = kSortPerLane * block;
-    if (L.spp > c) {
-        L.chunk_spp = c;
-        L.chunks = (L.spp + c - 1) / c;
-        if ((L.flags & kFlagAccumulate) == 0) {
-            launch_zero_f32(L.film, (size_t)L.n_pixels * (L.n_freq ? 2 * L.n_freq : S.n_bins), stream);
-            if (L.steady) launch_zero_f32(L.steady, L.n_pixels, stream);
-            if (L.oow) launch_zero_f32(L.oow, L.n_pixels, stream);
-        }
-    }
     const uint32_t words = L.n_freq ? 2 * L.n_freq : S.n_bins;
     const size_t lds = deferred_lds_bytes(L.tile_pixels, words, block, stack_lane_bytes(S.n_tris, S.stack_depth));
     if (short_stack(S.n_tris))
@@ -2103,6 +2165,22 @@ hipError_t launch_render_deferred(const SceneView& S, const LaunchArgs& L0, uint
     else
         launch_deferred_w<uint32_t>(S, L, block, lds, stream, counts);
     return hipGetLastError();
+}
+
+// Sample chunks of the deferred form: a tile with more samples than one sort
+// batch (kSortPerLane * block) is split into at most kMaxChunks chunks of
+// whole batches, one workgroup each (measured on the confocal workload, 4096
+// samples per pixel in two chunks: +4.5%; one workgroup per half batch loses
+// more to per-workgroup work than it gains).
+uint32_t deferred_chunks(uint32_t spp, uint32_t block, uint32_t* chunk_spp)
+{
+    const uint32_t c = kSortPerLane * block;
+    uint32_t chunks = (spp + c - 1) / c;
+    if (chunks > kMaxChunks) chunks = kMaxChunks;
+    if (chunks < 1) chunks = 1;
+    const uint32_t batches = (spp + c - 1) / c;
+    *chunk_spp = ((batches + chunks - 1) / chunks) * c;
+    return (spp + *chunk_spp - 1) / *chunk_spp;
 }
 
 hipError_t launch_backward(const SceneView& S, const LaunchArgs& L, uint32_t block, int max_cont, hipStream_t stream)
@@ -2125,6 +2203,13 @@ hipError_t launch_batch(const BatchTables& B, uint32_t groups, uint32_t block, u
         launch_batch_w<uint16_t>(B, groups, block, lds, deferred, stream);
     else
         launch_batch_w<uint32_t>(B, groups, block, lds, deferred, stream);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t stream)
+{
+    const unsigned g = (unsigned)std::min<size_t>(1024, (n + 255) / 256 + 1);
+    hipLaunchKernelGGL(k_zero_u32, dim3(g), dim3(256), 0, stream, p, n);
     return hipGetLastError();
 }
 

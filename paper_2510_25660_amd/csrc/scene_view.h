@@ -87,12 +87,28 @@ constexpr uint32_t kFlagAccumulate = 1u << 1;
 constexpr uint32_t kFlagFrozen = 1u << 2;
 constexpr uint32_t kFlagNlosArea = 1u << 3;
 
+// One next-event contribution of the recording build (32 bytes; the layout
+// of trhip_record): the path's pixel or scan point and sample index, the
+// 1-based vertex of the connection, its bin (-1 outside the window), the
+// value c before the 1/N normalisation, the connected path's optical
+// length and the vertex's triangle (caller index, -1 for a medium vertex).
+struct alignas(16) ContribRecord {
+    uint32_t pixel, sample;
+    int32_t vertex, bin;
+    float value, tof;
+    int32_t tri;
+    uint32_t reserved;
+};
+static_assert(sizeof(ContribRecord) == 32, "ContribRecord must be 32 bytes");
+
 struct LaunchArgs {
     uint32_t spp, sample_offset, max_depth, stream_id;
     uint32_t key0, key1, flags;
     uint32_t tile_pixels, n_pixels;
-    uint32_t chunks;            // sample chunks per tile (deferred form): > 1 adds partial films atomically
+    uint32_t chunks;            // sample chunks per tile (deferred form), one workgroup each
     uint32_t chunk_spp;         // samples per chunk
+    float* chunk_scratch;       // chunks > 1: partial tiles, [tile][chunk][tile_pixels * words + 2 * tile_pixels]
+    uint32_t* tile_count;       // chunks > 1: finished chunks per tile (zero between launches)
     float norm;                 // 1 / norm_spp
     const float* albedo;        // evaluation albedo (caller order)
     const float* rough_eval;    // evaluation roughness
@@ -112,6 +128,13 @@ struct LaunchArgs {
     // per metre of optical path; n_freq = 0: the time histogram
     uint32_t n_freq;
     float freq[kMaxFreq];
+    // recording build: contributions of the pixels with record_mask[p] != 0
+    // are appended to records (the first record_cap of them; record_count
+    // counts all)
+    const uint8_t* record_mask;
+    ContribRecord* records;
+    unsigned long long record_cap;
+    unsigned long long* record_count;
 };
 
 // Tables of the batched persistent kernel (device memory).

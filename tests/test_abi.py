@@ -176,3 +176,23 @@ def test_product_path_has_no_oracle_or_fallback():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "oracle.h" not in text, f
+
+
+def test_records_and_probe_validation(B):
+    """The recording render and the numerics probe reject invalid arguments
+    on the host, before any HIP call."""
+    L = B.lib()
+    r = B.RenderDesc()
+    r.spp = 1
+    r.max_depth = 2
+    n = C.c_uint64(0)
+    fake = C.c_void_p(0xdeadbeef)
+    assert L.trhip_render_transient_records(fake, C.byref(r), C.c_void_p(16), C.c_void_p(16), 4, C.byref(n),
+                                            C.c_void_p(16), None, None, None) == 5
+    assert L.trhip_numerics_probe(-1, None, C.c_void_p(16), 4, 0, None) == 1
+    assert L.trhip_numerics_probe(5, None, C.c_void_p(16), 4, 0, None) == 1
+    assert L.trhip_numerics_probe(0, None, None, 4, 0, None) == 1
+    assert L.trhip_numerics_probe(2, None, C.c_void_p(16), 4, 0, None) == 1   # Philox needs its input
+    assert L.trhip_numerics_probe(1, None, C.c_void_p(16), 16, (1 << 24) - 8, None) == 1
+    assert b"2^24" in L.trhip_last_error()
+    assert L.trhip_numerics_probe(3, None, None, 0, 0, None) == 0   # nothing to do
