@@ -24,7 +24,10 @@
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream);
  *    all device work is enqueued on it, asynchronously;
  *  - the library never keeps a caller pointer after a call returns;
- *  - a scene may be used by one stream at a time.
+ *  - a scene may be used by one stream at a time: it owns the scratch
+ *    memory of its launches (the backward pass's gradient sums, the
+ *    deferred form's partial films), so calls on one scene that overlap in
+ *    time on different streams race; serialise them (one stream, or events).
  */
 #ifndef TRHIP_H
 #define TRHIP_H
@@ -56,8 +59,30 @@ enum {
     TRHIP_FLAG_ACCUMULATE = 1u << 1,      /* add into the output buffers instead of overwriting */
     TRHIP_FLAG_FROZEN_PROPOSAL = 1u << 2, /* GGX: sample with the scene's roughness, evaluate
                                              with roughness_override (finite-difference mode) */
-    TRHIP_FLAG_NLOS_AREA_SAMPLING = 1u << 3 /* confocal: area-sample the hidden vertex (below) */
+    TRHIP_FLAG_NLOS_AREA_SAMPLING = 1u << 3, /* confocal: area-sample the hidden vertex (below) */
+    TRHIP_FLAG_DETERMINISTIC = 1u << 4       /* order-independent sums, bit-reproducible (below) */
 };
+
+/*
+ * TRHIP_FLAG_DETERMINISTIC -- bit-reproducible films and gradients, for the
+ * finite-difference checks of the gradients of Sec. 4.4 (Eqs. 15-16) and for
+ * race detection: two renders with the same inputs then agree bit for bit,
+ * whatever the launch shape (tile_pixels, block_size), the scheduling or
+ * the GPU load.  Every contribution to the film, steady and oow sums, and
+ * every gradient term, is accumulated as a 128-bit two's-complement fixed
+ * point number with 64 fraction bits with integer atomics, which are
+ * associative; the sums are rounded to FP32 once, after division by
+ * norm_spp.  A film bin is then the exact sum of its FP32 contributions of
+ * magnitude >= 2^-41 (smaller ones are truncated to multiples of 2^-64),
+ * divided by N and rounded: it differs from an FP64 sum in path order only
+ * by that sum's own rounding.  Values and sums must stay below 2^63 in
+ * magnitude.  Accepted by trhip_render_transient (the path form runs; a
+ * render->kernel other than AUTO or PATH is UNSUPPORTED) and
+ * trhip_render_transient_backward (gradients; primal_film is not covered);
+ * the other entry points return UNSUPPORTED.  About 2x the LDS of the
+ * default film per pixel of a tile, so the automatic shape takes fewer
+ * pixels per workgroup.
+ */
 
 /*
  * TRHIP_FLAG_NLOS_AREA_SAMPLING -- sampling specific to non-line-of-sight
@@ -386,10 +411,16 @@ trhip_status trhip_numerics_probe(int32_t op, const void* in, void* out, uint64_
 
 /*
  * Batched persistent rendering of many scenes (e.g. NLOS datasets, Sec. 4.5)
- * in one launch.  Work items are (scene, pixel tile) pairs, ordered by
- * estimated cost (largest first) and popped by persistent workgroups from a
- * global cursor; the cursor reset and the persistent kernel are captured once
- * into a hipGraph, so trhip_batch_render is one graph launch.
+ * by one graph launch.  The scenes are split into classes by stack-link
+ * width (at most 32,768 triangles, or more) and film length (at most 640
+ * bins, or more); each class runs one persistent launch of its own shape,
+ * whose workgroups pop work items, (scene, pixel tile) pairs ordered by
+ * estimated cost (largest first), from a global cursor.  The classes'
+ * cursor resets and persistent kernels are captured once into a hipGraph,
+ * so trhip_batch_render is one graph launch.  tile_pixels, when the caller
+ * sets it, is every scene's pixels per item; when chosen, a scene with T
+ * bins takes max(1, floor(s * 1026 / (T + 2))) pixels per item for its
+ * class's scale s (so longer films take fewer pixels), and the info reports s.
  *
  * scenes: HOST array of n_scenes live scene handles; renders: HOST array of
  * n_scenes render descriptions (overrides must be NULL; flags may only hold
@@ -409,20 +440,23 @@ typedef struct {
     uint32_t groups_per_cu; /* persistent workgroups per compute unit; 0 = choose */
     uint32_t kernel;        /* TRHIP_KERNEL_PATH or TRHIP_KERNEL_DEFERRED per work item; 0 = choose */
     int32_t autotune;       /* nonzero: time the candidate shapes for every field left 0 during
-                               trhip_batch_create (renders into the films) and keep the fastest;
-                               the choice is cached per process for the same batch shape */
+                               trhip_batch_create (renders into the films), per class, and keep the
+                               fastest; the choice is cached for the same class shape in the process
+                               and in the file TRHIP_TUNE_CACHE (default ~/.cache/trhip/batch_tune.txt),
+                               which later processes load instead of tuning again */
 } trhip_batch_opts;
 
 typedef struct {
     uint32_t n_scenes;
-    uint32_t n_items;       /* work items per render */
-    uint32_t block_size, tile_pixels, groups;
-    uint32_t kernel;        /* TRHIP_KERNEL_PATH or TRHIP_KERNEL_DEFERRED */
+    uint32_t n_items;       /* work items per render, all classes */
+    uint32_t block_size, tile_pixels, groups; /* shape of the costliest class (tile_pixels: see below) */
+    uint32_t kernel;        /* TRHIP_KERNEL_PATH or TRHIP_KERNEL_DEFERRED, costliest class */
     uint32_t stack_depth;   /* deepest BVH of the batch */
-    size_t lds_bytes;       /* dynamic LDS per workgroup */
-    uint32_t candidates;    /* shapes timed by the autotuner (0: none, or cached) */
+    size_t lds_bytes;       /* dynamic LDS per workgroup, the largest class */
+    uint32_t candidates;    /* shapes timed by the autotuner, all classes (0: none, or cached) */
     float tune_ms;          /* wall time spent autotuning */
-    float best_ms;          /* measured render time of the chosen shape (0 if not timed) */
+    float best_ms;          /* measured render time of the chosen shapes, summed (0 if not timed) */
+    uint32_t n_classes;     /* persistent launches per render (scene classes) */
 } trhip_batch_info;
 
 /* Errors: INVALID_ARG, BAD_HANDLE (a scene), UNSUPPORTED (LDS), OOM, HIP.

@@ -20,14 +20,16 @@ from typing import Optional
 import numpy as np
 
 from . import scenes
-from ._binding import (FLAG_ACCUMULATE, FLAG_FROZEN_PROPOSAL, FLAG_NLOS_AREA_SAMPLING, FLAG_PIXEL_CENTRE, BatchInfo,
-                       BatchOpts, RenderDesc, SceneDesc, SceneInfo, TrhipError, check, lib)
+from ._binding import (FLAG_ACCUMULATE, FLAG_DETERMINISTIC, FLAG_FROZEN_PROPOSAL, FLAG_NLOS_AREA_SAMPLING,
+                       FLAG_PIXEL_CENTRE, BatchInfo, BatchOpts, RenderDesc, SceneDesc, SceneInfo, TrhipError, check,
+                       lib)
 
 __all__ = [
     "scenes", "upload", "DeviceScene", "render_transient", "render_transient_backward", "render_transient_counted",
     "render_transient_tangent", "render_phasor", "poisson_noise", "render_transient_records", "numerics_probe",
     "TransientRender", "Batch",
     "TrhipError", "FLAG_PIXEL_CENTRE", "FLAG_ACCUMULATE", "FLAG_FROZEN_PROPOSAL", "FLAG_NLOS_AREA_SAMPLING",
+    "FLAG_DETERMINISTIC",
     "version",
 ]
 
@@ -155,7 +157,8 @@ def _ptr(t) -> Optional[int]:
 
 def make_render_desc(dev: DeviceScene, spp=None, seed=None, max_depth=None, sample_offset=0, norm_spp=0,
                      stream_id=0, pixel_centre=False, accumulate=False, frozen=False, albedo=None,
-                     roughness=None, tile_pixels=0, block_size=0, kernel="auto", nlos_area=False) -> RenderDesc:
+                     roughness=None, tile_pixels=0, block_size=0, kernel="auto", nlos_area=False,
+                     deterministic=False) -> RenderDesc:
     sc = dev.scene
     r = RenderDesc()
     r.spp = int(sc.spp if spp is None else spp)
@@ -165,7 +168,8 @@ def make_render_desc(dev: DeviceScene, spp=None, seed=None, max_depth=None, samp
     r.seed = int(sc.seed if seed is None else seed)
     r.stream_id = int(stream_id)
     r.flags = ((FLAG_PIXEL_CENTRE if pixel_centre else 0) | (FLAG_ACCUMULATE if accumulate else 0)
-               | (FLAG_FROZEN_PROPOSAL if frozen else 0) | (FLAG_NLOS_AREA_SAMPLING if nlos_area else 0))
+               | (FLAG_FROZEN_PROPOSAL if frozen else 0) | (FLAG_NLOS_AREA_SAMPLING if nlos_area else 0)
+               | (FLAG_DETERMINISTIC if deterministic else 0))
     r.albedo_override = _ptr(albedo)
     r.roughness_override = _ptr(roughness)
     r.tile_pixels = int(tile_pixels)

@@ -20,6 +20,7 @@ FLAG_PIXEL_CENTRE = 1 << 0
 FLAG_ACCUMULATE = 1 << 1
 FLAG_FROZEN_PROPOSAL = 1 << 2
 FLAG_NLOS_AREA_SAMPLING = 1 << 3
+FLAG_DETERMINISTIC = 1 << 4
 
 BUILDERS = {"ploc": 0, "lbvh": 1}
 
@@ -139,6 +140,7 @@ class BatchInfo(C.Structure):
         ("candidates", C.c_uint32),
         ("tune_ms", C.c_float),
         ("best_ms", C.c_float),
+        ("n_classes", C.c_uint32),
     ]
 
 

@@ -5,6 +5,7 @@
 // workgroup size) within the LDS budget, and enqueue the kernels on the
 // caller's stream.
 #include <hip/hip_runtime.h>
+#include <sys/stat.h>
 
 #include <algorithm>
 #include <array>
@@ -13,6 +14,7 @@
 #include <cstddef>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -71,12 +73,10 @@ struct trhip_scene {
     float* d_scan;
     float* d_ior;    // nullptr: no dielectric triangle
     float* d_delay;  // nullptr: no scattering delay
-    double* d_grad;  // 2 * n_tris doubles of backward workspace
-    // deferred form with sample chunks: partial tiles and per-tile counters
+    double* d_grad;  // backward workspace: 2 * n_tris doubles, or [2][n_tris][2] fixed-point words (4 * n_tris)
+    // deferred form with sample chunks: partial films of chunks 1..
     float* d_chunk_scratch;
     size_t chunk_scratch_floats;
-    uint32_t* d_tile_count;
-    size_t tile_count_n;
     // confocal: NLOS area-sampling tables, one set per scan region
     double* d_area_cdf;      // [region][n_tris] prefix sums of the weights (caller order)
     float* d_area_invp;      // [region][n_tris] inverse area densities
@@ -121,7 +121,6 @@ void free_scene(trhip_scene* s)
     (void)hipFree(s->d_delay);
     (void)hipFree(s->d_grad);
     (void)hipFree(s->d_chunk_scratch);
-    (void)hipFree(s->d_tile_count);
     (void)hipFree(s->d_area_cdf);
     (void)hipFree(s->d_area_invp);
     (void)hipFree(s->d_sorted_of);
@@ -419,8 +418,10 @@ trhip_status validate_render(const trhip_scene* s, const trhip_render_desc* r)
     if (r->block_size != 0 && (r->block_size % 64 != 0 || r->block_size > kMaxBlock))
         return fail(TRHIP_ERR_INVALID_ARG, "block_size must be a multiple of 64 and <= %u", kMaxBlock);
     if (r->flags & ~(uint32_t)(TRHIP_FLAG_PIXEL_CENTRE | TRHIP_FLAG_ACCUMULATE | TRHIP_FLAG_FROZEN_PROPOSAL |
-                               TRHIP_FLAG_NLOS_AREA_SAMPLING))
+                               TRHIP_FLAG_NLOS_AREA_SAMPLING | TRHIP_FLAG_DETERMINISTIC))
         return fail(TRHIP_ERR_INVALID_ARG, "unknown flag bits");
+    if ((r->flags & TRHIP_FLAG_DETERMINISTIC) && r->kernel != TRHIP_KERNEL_AUTO && r->kernel != TRHIP_KERNEL_PATH)
+        return fail(TRHIP_ERR_UNSUPPORTED, "DETERMINISTIC renders run the path form only");
     if (r->kernel > TRHIP_KERNEL_DEFERRED) return fail(TRHIP_ERR_INVALID_ARG, "unknown kernel %u", r->kernel);
     if (r->flags & TRHIP_FLAG_NLOS_AREA_SAMPLING) {
         if (s->view.sensor != TRHIP_SENSOR_CONFOCAL)
@@ -436,7 +437,8 @@ trhip_status validate_render(const trhip_scene* s, const trhip_render_desc* r)
     return TRHIP_OK;
 }
 
-enum class Kind { Path, Wavefront, Deferred, Backward, BackwardPrimal, Tangent };
+enum class Kind { Path, Wavefront, Deferred, Backward, BackwardPrimal, Tangent, PathFixed, BackwardFixed,
+                  BackwardPrimalFixed, PathHbm };
 
 // stack: LDS bytes of one lane's traversal stack
 size_t lds_bytes(Kind kind, uint32_t tp, uint32_t T, uint32_t bs, uint32_t stack)
@@ -445,9 +447,13 @@ size_t lds_bytes(Kind kind, uint32_t tp, uint32_t T, uint32_t bs, uint32_t stack
     case Kind::Path: return trhip::render_lds_bytes(tp, T, bs, stack);
     case Kind::Wavefront: return trhip::wavefront_lds_bytes(tp, T, bs, stack);
     case Kind::Deferred: return trhip::deferred_lds_bytes(tp, T, bs, stack);
-    case Kind::Backward: return trhip::backward_lds_bytes(tp, T, bs, stack, false);
+    case Kind::Backward: return trhip::backward_lds_bytes(tp, T, bs, stack, false, false);
     case Kind::Tangent: return trhip::tangent_lds_bytes(tp, T, bs, stack);
-    default: return trhip::backward_lds_bytes(tp, T, bs, stack, true);
+    case Kind::PathFixed: return trhip::fixed_lds_bytes(tp, T, bs, stack);
+    case Kind::PathHbm: return trhip::hbm_lds_bytes(bs, stack);
+    case Kind::BackwardFixed: return trhip::backward_lds_bytes(tp, T, bs, stack, false, true);
+    case Kind::BackwardPrimalFixed: return trhip::backward_lds_bytes(tp, T, bs, stack, true, true);
+    default: return trhip::backward_lds_bytes(tp, T, bs, stack, true, false);
     }
 }
 
@@ -502,9 +508,15 @@ trhip_status choose_shape(const trhip_scene* s, const trhip_render_desc* r, Kind
 // most first rays leave the scene (confocal NLOS: +25%) and costs when
 // nearly all of them hit (closed pinhole scenes: -28%), so the automatic
 // choice follows the sensor; the wavefront form is never faster here.
-Kind forward_kind(const trhip_scene* s, const trhip_render_desc* r)
+// Film length from which the path form keeps the film in HBM (no LDS film).
+constexpr uint32_t kHbmFilmBins = 0xffffffffu;
+
+// histogram: a time histogram (the phasor film keeps its tile film in LDS)
+Kind forward_kind(const trhip_scene* s, const trhip_render_desc* r, bool histogram = true)
 {
-    if (r->kernel == TRHIP_KERNEL_PATH) return Kind::Path;
+    if (r->flags & TRHIP_FLAG_DETERMINISTIC) return Kind::PathFixed;
+    if (r->kernel == TRHIP_KERNEL_PATH || (r->kernel == TRHIP_KERNEL_AUTO && s->view.sensor != TRHIP_SENSOR_CONFOCAL))
+        return histogram && s->view.n_bins >= kHbmFilmBins ? Kind::PathHbm : Kind::Path;
     if (r->kernel == TRHIP_KERNEL_WAVEFRONT) return Kind::Wavefront;
     if (r->kernel == TRHIP_KERNEL_DEFERRED) return Kind::Deferred;
     if (s->view.sensor != TRHIP_SENSOR_CONFOCAL) return Kind::Path;
@@ -513,68 +525,63 @@ Kind forward_kind(const trhip_scene* s, const trhip_render_desc* r)
                                                                                                  : Kind::Path;
 }
 
-// Scratch of the deferred form's sample chunks (partial tiles and per-tile
-// counters), grown on demand and kept by the scene (which one stream uses at
-// a time).  Nothing is allocated while the stream is being captured into a
+// Scratch of the deferred form's sample chunks (the partial films of chunks
+// 1..), grown on demand and kept by the scene (which one stream uses at a
+// time).  Nothing is allocated while the stream is being captured into a
 // graph: *ready stays false and the launch keeps one chunk per tile, which
 // renders the same film.
-hipError_t ensure_chunk_scratch(trhip_scene* sc, size_t floats, size_t tiles, hipStream_t s, bool* ready)
+hipError_t ensure_chunk_scratch(trhip_scene* sc, size_t floats, hipStream_t s, bool* ready)
 {
     *ready = false;
-    if (sc->chunk_scratch_floats >= floats && sc->tile_count_n >= tiles) {
+    if (sc->chunk_scratch_floats >= floats) {
         *ready = true;
         return hipSuccess;
     }
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     hipError_t e = hipStreamIsCapturing(s, &cs);
     if (e != hipSuccess || cs != hipStreamCaptureStatusNone) return e;
-    e = hipStreamSynchronize(s);  // earlier launches may still use the old buffers
+    e = hipStreamSynchronize(s);  // earlier launches may still use the old buffer
     if (e != hipSuccess) return e;
     (void)hipFree(sc->d_chunk_scratch);
-    (void)hipFree(sc->d_tile_count);
     sc->d_chunk_scratch = nullptr;
-    sc->d_tile_count = nullptr;
     sc->chunk_scratch_floats = 0;
-    sc->tile_count_n = 0;
     e = hipMalloc(&sc->d_chunk_scratch, floats * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc(&sc->d_tile_count, tiles * sizeof(uint32_t));
-    if (e == hipSuccess) e = trhip::launch_zero_u32(sc->d_tile_count, tiles, s);
-    if (e != hipSuccess) {
-        (void)hipFree(sc->d_chunk_scratch);
-        (void)hipFree(sc->d_tile_count);
-        sc->d_chunk_scratch = nullptr;
-        sc->d_tile_count = nullptr;
-        return e;
-    }
+    if (e != hipSuccess) return e;
     sc->chunk_scratch_floats = floats;
-    sc->tile_count_n = tiles;
     *ready = true;
     return hipSuccess;
+}
+
+// floats of the chunk scratch: (chunks - 1) partial films, steady and oow
+size_t chunk_scratch_floats(const trhip::LaunchArgs& L, uint32_t chunks, uint32_t words)
+{
+    return (size_t)(chunks - 1) * ((size_t)L.n_pixels * words + 2ull * L.n_pixels);
 }
 
 hipError_t launch_forward(trhip_scene* sc, Kind kind, trhip::LaunchArgs L, uint32_t block, hipStream_t stream,
                           unsigned long long* counts)
 {
     switch (kind) {
+    case Kind::PathFixed: return trhip::launch_render_fixed(sc->view, L, block, stream);
+    case Kind::PathHbm: return trhip::launch_render_hbm(sc->view, L, block, stream, counts);
     case Kind::Wavefront: return trhip::launch_render_wavefront(sc->view, L, block, stream, counts);
     case Kind::Deferred: {
         uint32_t chunk_spp = L.spp;
         const uint32_t chunks = trhip::deferred_chunks(L.spp, block, &chunk_spp);
+        const uint32_t words = L.n_freq ? 2 * L.n_freq : sc->view.n_bins;
         if (chunks > 1) {
-            const size_t tiles = (L.n_pixels + L.tile_pixels - 1) / L.tile_pixels;
-            const uint32_t words = L.n_freq ? 2 * L.n_freq : sc->view.n_bins;
-            const size_t floats = tiles * chunks * ((size_t)L.tile_pixels * words + 2ull * L.tile_pixels);
             bool ready = false;
-            const hipError_t e = ensure_chunk_scratch(sc, floats, tiles, stream, &ready);
+            const hipError_t e = ensure_chunk_scratch(sc, chunk_scratch_floats(L, chunks, words), stream, &ready);
             if (e != hipSuccess) return e;
             if (ready) {
                 L.chunks = chunks;
                 L.chunk_spp = chunk_spp;
                 L.chunk_scratch = sc->d_chunk_scratch;
-                L.tile_count = sc->d_tile_count;
             }
         }
-        return trhip::launch_render_deferred(sc->view, L, block, stream, counts);
+        hipError_t e = trhip::launch_render_deferred(sc->view, L, block, stream, counts);
+        if (e == hipSuccess && L.chunks > 1) e = trhip::launch_add_planes(L, words, stream);
+        return e;
     }
     default: return trhip::launch_render(sc->view, L, block, stream, counts);
     }
@@ -595,6 +602,7 @@ void fill_launch(const trhip_scene* s, const trhip_render_desc* r, uint32_t tile
     L->chunks = 1;
     L->chunk_spp = r->spp;
     L->norm = 1.0f / (float)(r->norm_spp ? r->norm_spp : r->spp);
+    L->norm_spp = r->norm_spp ? r->norm_spp : r->spp;
     L->albedo = r->albedo_override ? r->albedo_override : s->d_albedo;
     L->rough_eval = r->roughness_override ? r->roughness_override : s->d_rough;
     L->rough_sample = (r->flags & TRHIP_FLAG_FROZEN_PROPOSAL) ? s->d_rough : L->rough_eval;
@@ -650,7 +658,7 @@ trhip_status trhip_scene_create(const trhip_scene_desc* desc, void* stream, trhi
     }
     if (e == hipSuccess && any_dielectric) e = upload(&sc->d_ior, desc->ior, nt, s);
     if (e == hipSuccess && any_delay) e = upload(&sc->d_delay, desc->delay, nt, s);
-    if (e == hipSuccess) e = hipMalloc(&sc->d_grad, 2ull * nt * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&sc->d_grad, 4ull * nt * sizeof(double));
     if (e == hipSuccess)
         e = trhip::build_bvh(d_tri9, nt, desc->bvh_builder == TRHIP_BVH_LBVH ? trhip::kBuilderLbvh : trhip::kBuilderPloc,
                              s, &sc->bvh);
@@ -668,7 +676,7 @@ trhip_status trhip_scene_create(const trhip_scene_desc* desc, void* stream, trhi
         g_live.insert(sc);
     }
     sc->device_bytes = (size_t)sc->bvh.n_internal * sizeof(trhip::BvhNode) + (size_t)nt * sizeof(trhip::TriRec) +
-                       (size_t)nt * (1 + 4 + 4 + 16) + (sc->d_scan ? 13ull * sc->n_pixels + 4ull * nt + (size_t)kAreaRegions * (12ull * nt + 4ull * (sc->guide_cells + 1) + 8) : 0) +
+                       (size_t)nt * (1 + 4 + 4 + 32) + (sc->d_scan ? 13ull * sc->n_pixels + 4ull * nt + (size_t)kAreaRegions * (12ull * nt + 4ull * (sc->guide_cells + 1) + 8) : 0) +
                        (sc->d_ior ? 4ull * nt : 0) + (sc->d_delay ? 4ull * nt : 0);
     *out = sc;
     return TRHIP_OK;
@@ -729,6 +737,8 @@ trhip_status trhip_render_phasor(trhip_scene* scene, const trhip_render_desc* re
     trhip_status st = check_scene(scene);
     if (st != TRHIP_OK) return st;
     if ((st = validate_render(scene, render)) != TRHIP_OK) return st;
+    if (render->flags & TRHIP_FLAG_DETERMINISTIC)
+        return fail(TRHIP_ERR_UNSUPPORTED, "DETERMINISTIC applies to the forward render and the backward pass, not the phasor film");
     if (!phasor) return fail(TRHIP_ERR_INVALID_ARG, "phasor is NULL");
     if (!freqs || n_freq == 0 || n_freq > trhip::kMaxFreq)
         return fail(TRHIP_ERR_INVALID_ARG, "freqs must hold 1..%u frequencies", trhip::kMaxFreq);
@@ -736,7 +746,7 @@ trhip_status trhip_render_phasor(trhip_scene* scene, const trhip_render_desc* re
         if (!std::isfinite(freqs[j])) return fail(TRHIP_ERR_INVALID_ARG, "freqs[%u] is not finite", j);
     if (render->kernel == TRHIP_KERNEL_WAVEFRONT)
         return fail(TRHIP_ERR_UNSUPPORTED, "the wavefront form has no phasor film");
-    const Kind kind = forward_kind(scene, render);
+    const Kind kind = forward_kind(scene, render, false);
     uint32_t tile = 0, block = 0;
     if ((st = choose_shape(scene, render, kind, &tile, &block, 2 * n_freq)) != TRHIP_OK) return st;
     trhip::LaunchArgs L;
@@ -758,6 +768,8 @@ trhip_status trhip_render_transient_tangent(trhip_scene* scene, const trhip_rend
     trhip_status st = check_scene(scene);
     if (st != TRHIP_OK) return st;
     if ((st = validate_render(scene, render)) != TRHIP_OK) return st;
+    if (render->flags & TRHIP_FLAG_DETERMINISTIC)
+        return fail(TRHIP_ERR_UNSUPPORTED, "DETERMINISTIC applies to the forward render and the backward pass, not the forward-mode render");
     if (!film || !dfilm) return fail(TRHIP_ERR_INVALID_ARG, "film and dfilm must be non-NULL");
     uint32_t tile = 0, block = 0;
     if ((st = choose_shape(scene, render, Kind::Tangent, &tile, &block)) != TRHIP_OK) return st;
@@ -779,6 +791,8 @@ trhip_status trhip_render_transient_counted(trhip_scene* scene, const trhip_rend
     trhip_status st = check_scene(scene);
     if (st != TRHIP_OK) return st;
     if ((st = validate_render(scene, render)) != TRHIP_OK) return st;
+    if (render->flags & TRHIP_FLAG_DETERMINISTIC)
+        return fail(TRHIP_ERR_UNSUPPORTED, "DETERMINISTIC applies to the forward render and the backward pass, not the counting build");
     if (!film || !counts) return fail(TRHIP_ERR_INVALID_ARG, "film and counts must be non-NULL");
     const Kind kind = forward_kind(scene, render);
     uint32_t tile = 0, block = 0;
@@ -813,6 +827,8 @@ trhip_status trhip_render_transient_records(trhip_scene* scene, const trhip_rend
     trhip_status st = check_scene(scene);
     if (st != TRHIP_OK) return st;
     if ((st = validate_render(scene, render)) != TRHIP_OK) return st;
+    if (render->flags & TRHIP_FLAG_DETERMINISTIC)
+        return fail(TRHIP_ERR_UNSUPPORTED, "DETERMINISTIC applies to the forward render and the backward pass, not the recording build");
     if (!film || !pixel_mask || !n_records)
         return fail(TRHIP_ERR_INVALID_ARG, "film, pixel_mask and n_records must be non-NULL");
     if (capacity > 0 && !records) return fail(TRHIP_ERR_INVALID_ARG, "records is NULL with capacity > 0");
@@ -871,7 +887,10 @@ trhip_status trhip_render_transient_backward(trhip_scene* scene, const trhip_ren
     if (render->flags & TRHIP_FLAG_ACCUMULATE)
         return fail(TRHIP_ERR_INVALID_ARG, "ACCUMULATE does not apply to the backward pass");
     uint32_t tile = 0, block = 0;
-    if ((st = choose_shape(scene, render, primal_film ? Kind::BackwardPrimal : Kind::Backward, &tile, &block)) !=
+    const bool fixed = (render->flags & TRHIP_FLAG_DETERMINISTIC) != 0;
+    const Kind kind = fixed ? (primal_film ? Kind::BackwardPrimalFixed : Kind::BackwardFixed)
+                            : (primal_film ? Kind::BackwardPrimal : Kind::Backward);
+    if ((st = choose_shape(scene, render, kind, &tile, &block)) !=
         TRHIP_OK)
         return st;
     hipStream_t s = (hipStream_t)stream;
@@ -881,6 +900,7 @@ trhip_status trhip_render_transient_backward(trhip_scene* scene, const trhip_ren
     L.grad_film = grad_film;
     L.g_alb = scene->d_grad;
     L.g_rough = scene->d_grad + nt;
+    L.g_fixed = fixed ? reinterpret_cast<unsigned long long*>(scene->d_grad) : nullptr;
     L.primal = primal_film;
     // single trace with a register stash when a path has few continuations,
     // path replay otherwise (or when asked for with TRHIP_KERNEL_PATH)
@@ -888,10 +908,15 @@ trhip_status trhip_render_transient_backward(trhip_scene* scene, const trhip_ren
                                                                     : (int)render->max_depth - 1;
     int max_cont = 0;
     if (render->kernel != TRHIP_KERNEL_PATH) max_cont = (vmax - 1 <= 2) ? 2 : (vmax - 1 <= 7 ? 7 : 0);
-    hipError_t e = trhip::launch_zero_f64(scene->d_grad, 2 * nt, s);
+    hipError_t e = trhip::launch_zero_f64(scene->d_grad, (fixed ? 4 : 2) * nt, s);
     if (e == hipSuccess) e = trhip::launch_backward(scene->view, L, block, max_cont, s);
-    if (e == hipSuccess) e = trhip::launch_f64_to_f32(scene->d_grad, grad_albedo, nt, s);
-    if (e == hipSuccess) e = trhip::launch_f64_to_f32(scene->d_grad + nt, grad_roughness, nt, s);
+    if (fixed) {
+        if (e == hipSuccess) e = trhip::launch_fixed_to_f32(L.g_fixed, grad_albedo, nt, s);
+        if (e == hipSuccess) e = trhip::launch_fixed_to_f32(L.g_fixed + 2 * nt, grad_roughness, nt, s);
+    } else {
+        if (e == hipSuccess) e = trhip::launch_f64_to_f32(scene->d_grad, grad_albedo, nt, s);
+        if (e == hipSuccess) e = trhip::launch_f64_to_f32(scene->d_grad + nt, grad_roughness, nt, s);
+    }
     if (e != hipSuccess) return hip_fail(e, "backward launch");
     return TRHIP_OK;
 }
@@ -902,23 +927,41 @@ trhip_status trhip_render_transient_backward(trhip_scene* scene, const trhip_ren
 // batched persistent rendering
 // ---------------------------------------------------------------------------
 constexpr uint32_t kBatchMagic = 0x54524842u;  // "TRHB"
+constexpr uint64_t kBatchKernelRevision = 3;   // bump when the persistent kernel's performance model changes
+
+// The scenes of a batch are split into classes by stack-link width (16-bit
+// links and buffer loads up to 32,768 triangles, 32-bit links above) and
+// film length (up to kBatchLongFilm bins, or more).  Each class has its own
+// persistent launch with its own shape, so that one large scene does not put
+// every scene on 32-bit links and the longest film does not size every
+// workgroup's LDS; the classes' launches follow one another in the batch's
+// graph, the costliest first.
+constexpr uint32_t kBatchLongFilm = 640;
+
+struct BatchClass {
+    std::vector<uint32_t> order;  // scene indices in processing order (largest cost first)
+    double cost;
+    bool short_links;
+    uint32_t depth;               // deepest BVH of the class
+    uint32_t* d_item_start;
+    uint32_t* d_order;
+    uint32_t* d_cursor;
+    trhip::BatchTables tables;
+    uint32_t block, tile, groups;  // groups: per CU while tuning, workgroups once captured
+    bool deferred;
+    size_t lds;
+    uint32_t timed;
+    float best_ms;
+};
 
 struct trhip_batch {
     uint32_t magic;
     std::vector<trhip_scene*> scenes;
     std::vector<trhip::SceneView> views;
-    std::vector<trhip::LaunchArgs> args;   // tile_pixels filled per shape
-    std::vector<uint32_t> order;           // processing order (largest cost first)
+    std::vector<trhip::LaunchArgs> args;  // tile_pixels filled by the shape of the scene's class
     trhip::SceneView* d_views;
     trhip::LaunchArgs* d_args;
-    uint32_t* d_item_start;
-    uint32_t* d_order;
-    uint32_t* d_cursor;
-    trhip::BatchTables tables;
-    uint32_t block, tile, groups, depth;
-    bool short_links;  // every scene's stack links fit 16 bits
-    bool deferred;
-    size_t lds;
+    std::vector<BatchClass> classes;
     hipGraph_t graph;
     hipGraphExec_t exec;
     trhip_batch_info info;
@@ -929,6 +972,51 @@ namespace {
 std::mutex g_batch_mutex;
 std::unordered_set<const trhip_batch*> g_live_batches;
 std::unordered_map<uint64_t, std::array<uint32_t, 4>> g_tune_cache;  // key -> block, tile, groups, deferred
+
+// The tuner's choices also persist across processes, one line per class
+// shape ("key block tile groups deferred", hex key) in the file named by
+// TRHIP_TUNE_CACHE, else ~/.cache/trhip/batch_tune.txt; a missing or
+// unreadable file is ignored.
+std::string tune_cache_path()
+{
+    if (const char* p = getenv("TRHIP_TUNE_CACHE")) return p;
+    const char* home = getenv("HOME");
+    return home ? std::string(home) + "/.cache/trhip/batch_tune.txt" : std::string();
+}
+
+bool tune_cache_load(uint64_t key, std::array<uint32_t, 4>* out)
+{
+    const std::string path = tune_cache_path();
+    if (path.empty()) return false;
+    FILE* f = fopen(path.c_str(), "r");
+    if (!f) return false;
+    unsigned long long k = 0;
+    unsigned a = 0, b = 0, c = 0, d = 0;
+    bool found = false;
+    while (fscanf(f, "%llx %u %u %u %u", &k, &a, &b, &c, &d) == 5)
+        if (k == key && a && b && c) {
+            *out = {a, b, c, d};  // the last line of a key wins
+            found = true;
+        }
+    fclose(f);
+    return found;
+}
+
+void tune_cache_store(uint64_t key, const std::array<uint32_t, 4>& v)
+{
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos && slash > 0) {
+        const std::string dir = path.substr(0, slash);
+        for (size_t i = 1; i <= dir.size(); ++i)
+            if (i == dir.size() || dir[i] == '/') (void)mkdir(dir.substr(0, i).c_str(), 0755);
+    }
+    if (FILE* f = fopen(path.c_str(), "a")) {
+        fprintf(f, "%016llx %u %u %u %u\n", (unsigned long long)key, v[0], v[1], v[2], v[3]);
+        fclose(f);
+    }
+}
 
 bool batch_live(const trhip_batch* b)
 {
@@ -942,70 +1030,192 @@ void free_batch(trhip_batch* b)
     if (b->graph) (void)hipGraphDestroy(b->graph);
     (void)hipFree(b->d_views);
     (void)hipFree(b->d_args);
-    (void)hipFree(b->d_item_start);
-    (void)hipFree(b->d_order);
-    (void)hipFree(b->d_cursor);
+    for (BatchClass& c : b->classes) {
+        (void)hipFree(c.d_item_start);
+        (void)hipFree(c.d_order);
+        (void)hipFree(c.d_cursor);
+    }
     b->magic = 0;
     delete b;
 }
 
-// shape -> tables on the device; returns false if the LDS does not fit
-hipError_t stage_shape(trhip_batch* b, uint32_t block, uint32_t tile, uint32_t groups, bool deferred, hipStream_t s,
-                       bool* fits)
+// Pixels per work item of a scene with T bins: `fixed` if the caller set it,
+// else the scale times 1,026 floats of LDS film (a pixel of 1,024 bins)
+// divided by the scene's film floats per pixel, so that scenes with fewer
+// bins take more pixels per item.
+uint32_t batch_tile(uint32_t fixed, uint32_t scale, uint32_t T)
 {
-    const uint32_t n = (uint32_t)b->scenes.size();
+    if (fixed) return fixed;
+    return std::max<uint32_t>(1u, (scale * 1026u) / (T + 2u));
+}
+
+// a class's shape -> its tables on the device; *fits false if the LDS does
+// not fit (nothing staged then)
+hipError_t stage_shape(trhip_batch* b, BatchClass& c, uint32_t block, uint32_t tile_fixed, uint32_t scale,
+                       uint32_t groups, bool deferred, hipStream_t s, bool* fits)
+{
+    const uint32_t n = (uint32_t)c.order.size();
     std::vector<uint32_t> start(n + 1, 0);
     uint32_t film_words = 0;
+    *fits = true;
     for (uint32_t k = 0; k < n; ++k) {
-        const uint32_t i = b->order[k];
-        const uint32_t P = b->scenes[i]->n_pixels, T = b->views[i].n_bins;
-        start[k + 1] = start[k] + (P + tile - 1) / tile;
-        film_words = std::max<uint32_t>(film_words, tile * T + 2 * tile);
+        const uint32_t i = c.order[k];
+        const uint32_t T = b->views[i].n_bins;
+        const uint32_t tp = std::min<uint32_t>(batch_tile(tile_fixed, scale, T), b->scenes[i]->n_pixels);
+        b->args[i].tile_pixels = tp;
+        film_words = std::max<uint32_t>(film_words, tp * T + 2 * tp);
+        if ((uint64_t)tp * b->args[i].spp >= (1ull << 32)) *fits = false;
+        start[k + 1] = start[k] + (b->scenes[i]->n_pixels + tp - 1) / tp;
     }
-    const size_t lds = trhip::batch_lds_bytes(film_words, block, b->depth * (b->short_links ? 2u : 4u), deferred);
-    *fits = lds <= kLdsBudget;
-    for (uint32_t i = 0; i < n; ++i) b->args[i].tile_pixels = tile;
-    for (uint32_t i = 0; i < n; ++i)
-        if ((uint64_t)tile * b->args[i].spp >= (1ull << 32)) *fits = false;
+    const size_t lds = trhip::batch_lds_bytes(film_words, block, c.depth * (c.short_links ? 2u : 4u), deferred);
+    *fits = *fits && lds <= kLdsBudget;
     if (!*fits) return hipSuccess;
-    hipError_t e = hipMemcpyAsync(b->d_args, b->args.data(), n * sizeof(trhip::LaunchArgs), hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(b->d_args, b->args.data(), b->args.size() * sizeof(trhip::LaunchArgs),
+                                  hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_item_start, start.data(), (n + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(c.d_item_start, start.data(), (n + 1) * sizeof(uint32_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    b->tables.views = b->d_views;
-    b->tables.args = b->d_args;
-    b->tables.item_start = b->d_item_start;
-    b->tables.order = b->d_order;
-    b->tables.n_scenes = n;
-    b->tables.n_items = start[n];
-    b->tables.film_words = film_words;
-    b->tables.cursor = b->d_cursor;
-    b->block = block;
-    b->tile = tile;
-    b->groups = groups;
-    b->deferred = deferred;
-    b->lds = lds;
+    c.tables.views = b->d_views;
+    c.tables.args = b->d_args;
+    c.tables.item_start = c.d_item_start;
+    c.tables.order = c.d_order;
+    c.tables.n_scenes = n;
+    c.tables.n_items = start[n];
+    c.tables.film_words = film_words;
+    c.tables.cursor = c.d_cursor;
+    c.block = block;
+    c.tile = tile_fixed ? tile_fixed : scale;
+    c.groups = groups;
+    c.deferred = deferred;
+    c.lds = lds;
     return e;
 }
 
-uint64_t tune_key(const trhip_batch* b, int device, const trhip_batch_opts& o)
+uint64_t tune_key(const trhip_batch* b, const BatchClass& c, int device, const trhip_batch_opts& o)
 {
     uint64_t h = 1469598103934665603ull;
     auto mix = [&](uint64_t v) { h = (h ^ v) * 1099511628211ull; };
+    // the kernels' build and the GPU model: a cached shape is only reused
+    // for the same library and device type
+    for (const char* ch = trhip_version(); *ch; ++ch) mix((uint64_t)*ch);
+    mix(kBatchKernelRevision);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess)
+        for (const char* ch = prop.gcnArchName; *ch; ++ch) mix((uint64_t)*ch);
     mix((uint64_t)device);
     mix(o.block_size);
     mix(o.tile_pixels);
     mix(o.groups_per_cu);
     mix(o.kernel);
-    for (size_t i = 0; i < b->scenes.size(); ++i) {
+    for (uint32_t i : c.order) {
         mix(b->scenes[i]->n_pixels);
         mix(b->views[i].n_bins);
         mix(b->views[i].n_tris);
         mix(b->views[i].stack_depth);
         mix(b->args[i].spp);
         mix(b->args[i].max_depth);
+        mix(b->args[i].flags);
     }
     return h;
+}
+
+// picks (tunes, or loads) the launch shape of one class and stages it
+hipError_t shape_class(trhip_batch* b, BatchClass& c, const trhip_batch_opts& o, int device, int n_cu, hipStream_t s,
+                       bool* ok)
+{
+    *ok = false;
+    const std::vector<uint32_t> blocks = o.block_size ? std::vector<uint32_t>{o.block_size}
+                                                      : std::vector<uint32_t>{64, 128, 256};
+    // the tile dimension: pixels per item if the caller fixed it, else the
+    // scale of batch_tile
+    const std::vector<uint32_t> tiles = o.tile_pixels ? std::vector<uint32_t>{o.tile_pixels}
+                                                      : std::vector<uint32_t>{1, 2, 4};
+    const std::vector<uint32_t> gpcs = o.groups_per_cu ? std::vector<uint32_t>{o.groups_per_cu}
+                                                       : std::vector<uint32_t>{4, 5, 8};
+    const std::vector<uint32_t> forms = o.kernel ? std::vector<uint32_t>{o.kernel}
+                                                 : std::vector<uint32_t>{TRHIP_KERNEL_PATH, TRHIP_KERNEL_DEFERRED};
+    std::array<uint32_t, 4> best{0, 0, 0, 0};
+    const uint64_t key = tune_key(b, c, device, o);
+    bool cached = false;
+    {
+        std::lock_guard<std::mutex> lock(g_batch_mutex);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            best = it->second;
+            cached = true;
+        } else if (o.autotune && tune_cache_load(key, &best)) {
+            g_tune_cache[key] = best;
+            cached = true;
+        }
+    }
+    hipError_t e = hipSuccess;
+    c.timed = 0;
+    c.best_ms = 0.0f;
+    if (!cached && o.autotune) {
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        e = hipEventCreate(&ev0);
+        if (e == hipSuccess) e = hipEventCreate(&ev1);
+        float best_t = 0.0f;
+        for (uint32_t form : forms)
+            for (uint32_t bs : blocks)
+                for (uint32_t tp : tiles)
+                    for (uint32_t g : gpcs) {
+                        if (e != hipSuccess) break;
+                        bool fits = false;
+                        const bool dfr = form == TRHIP_KERNEL_DEFERRED;
+                        e = stage_shape(b, c, bs, o.tile_pixels, tp, g, dfr, s, &fits);
+                        if (e != hipSuccess || !fits) continue;
+                        const uint32_t groups = std::max<uint32_t>(1u, (uint32_t)n_cu * g);
+                        e = trhip::launch_batch(c.tables, groups, bs, c.depth, c.short_links, dfr, s);  // warm-up
+                        float ms = 0.0f;
+                        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {  // the faster of two launches
+                            e = hipEventRecord(ev0, s);
+                            if (e == hipSuccess) e = trhip::launch_batch(c.tables, groups, bs, c.depth, c.short_links,
+                                                                         dfr, s);
+                            if (e == hipSuccess) e = hipEventRecord(ev1, s);
+                            if (e == hipSuccess) e = hipEventSynchronize(ev1);
+                            float t = 0.0f;
+                            if (e == hipSuccess) e = hipEventElapsedTime(&t, ev0, ev1);
+                            ms = rep == 0 ? t : std::min(ms, t);
+                        }
+                        if (e != hipSuccess) break;
+                        ++c.timed;
+                        if (best[0] == 0 || ms < best_t) {
+                            best_t = ms;
+                            best = {bs, tp, g, dfr ? 1u : 0u};
+                        }
+                    }
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (e != hipSuccess) return e;
+        c.best_ms = best_t;
+        if (best[0]) {
+            std::lock_guard<std::mutex> lock(g_batch_mutex);
+            g_tune_cache[key] = best;
+            tune_cache_store(key, best);
+        }
+    }
+    if (best[0] == 0) {
+        // untuned default: deferred form, the largest block whose LDS fits,
+        // scale 1, 8 groups per CU
+        const bool dfr = o.kernel != TRHIP_KERNEL_PATH;
+        for (uint32_t bs : {256u, 128u, 64u}) {
+            if (o.block_size && bs != o.block_size) continue;
+            bool fits = false;
+            const uint32_t g = o.groups_per_cu ? o.groups_per_cu : 8u;
+            e = stage_shape(b, c, bs, o.tile_pixels, o.tile_pixels ? o.tile_pixels : 1u, g, dfr, s, &fits);
+            if (e != hipSuccess) return e;
+            if (fits) {
+                best = {bs, o.tile_pixels ? o.tile_pixels : 1u, g, dfr ? 1u : 0u};
+                break;
+            }
+        }
+    }
+    if (!best[0]) return hipSuccess;
+    bool fits = false;
+    e = stage_shape(b, c, best[0], o.tile_pixels, best[1], best[2], best[3] != 0, s, &fits);
+    *ok = e == hipSuccess && fits;
+    return e;
 }
 
 }  // namespace
@@ -1045,136 +1255,81 @@ trhip_status trhip_batch_create(trhip_scene* const* scenes, const trhip_render_d
     b->scenes.assign(scenes, scenes + n_scenes);
     b->views.resize(n_scenes);
     b->args.resize(n_scenes);
-    b->depth = 1;
-    b->short_links = true;
     std::vector<double> cost(n_scenes);
     for (uint32_t i = 0; i < n_scenes; ++i) {
         b->views[i] = scenes[i]->view;
         fill_launch(scenes[i], &renders[i], 1, &b->args[i]);
         b->args[i].film = films[i];
-        b->depth = std::max(b->depth, scenes[i]->view.stack_depth);
-        b->short_links = b->short_links && trhip::short_stack(scenes[i]->view.n_tris);
         cost[i] = (double)scenes[i]->n_pixels * renders[i].spp * (double)(scenes[i]->view.stack_depth + 4);
     }
-    b->order.resize(n_scenes);
-    for (uint32_t i = 0; i < n_scenes; ++i) b->order[i] = i;
-    std::stable_sort(b->order.begin(), b->order.end(), [&](uint32_t a, uint32_t c) { return cost[a] > cost[c]; });
+    // classes by link width and film length, scenes in decreasing cost
+    std::vector<uint32_t> idx(n_scenes);
+    for (uint32_t i = 0; i < n_scenes; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t c) { return cost[a] > cost[c]; });
+    for (uint32_t i : idx) {
+        const bool sl = trhip::short_stack(scenes[i]->view.n_tris);
+        const bool lf = scenes[i]->view.n_bins > kBatchLongFilm;
+        BatchClass* c = nullptr;
+        for (BatchClass& k : b->classes)
+            if (k.short_links == sl && (b->views[k.order[0]].n_bins > kBatchLongFilm) == lf) c = &k;
+        if (!c) {
+            b->classes.emplace_back();
+            c = &b->classes.back();
+            c->cost = 0.0;
+            c->short_links = sl;
+            c->depth = 1;
+        }
+        c->order.push_back(i);
+        c->cost += cost[i];
+        c->depth = std::max(c->depth, scenes[i]->view.stack_depth);
+    }
+    std::stable_sort(b->classes.begin(), b->classes.end(),
+                     [](const BatchClass& x, const BatchClass& y) { return x.cost > y.cost; });
     int device = 0, n_cu = 0;
     hipError_t e = hipGetDevice(&device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
     if (e == hipSuccess) e = hipMalloc(&b->d_views, n_scenes * sizeof(trhip::SceneView));
     if (e == hipSuccess) e = hipMalloc(&b->d_args, n_scenes * sizeof(trhip::LaunchArgs));
-    if (e == hipSuccess) e = hipMalloc(&b->d_item_start, (n_scenes + 1) * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMalloc(&b->d_order, n_scenes * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMalloc(&b->d_cursor, sizeof(uint32_t));
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_views, b->views.data(), n_scenes * sizeof(trhip::SceneView), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_order, b->order.data(), n_scenes * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    for (BatchClass& c : b->classes) {
+        const size_t n = c.order.size();
+        if (e == hipSuccess) e = hipMalloc(&c.d_item_start, (n + 1) * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&c.d_order, n * sizeof(uint32_t));
+        if (e == hipSuccess) e = hipMalloc(&c.d_cursor, sizeof(uint32_t));
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c.d_order, c.order.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         free_batch(b);
         return hip_fail(e, "batch tables");
     }
-
-    // candidate shapes: the fields the caller left 0
-    const std::vector<uint32_t> blocks = o.block_size ? std::vector<uint32_t>{o.block_size}
-                                                      : std::vector<uint32_t>{64, 128, 256};
-    const std::vector<uint32_t> tiles = o.tile_pixels ? std::vector<uint32_t>{o.tile_pixels}
-                                                      : std::vector<uint32_t>{1, 2, 4};
-    const std::vector<uint32_t> gpcs = o.groups_per_cu ? std::vector<uint32_t>{o.groups_per_cu}
-                                                       : std::vector<uint32_t>{4, 8};
-    const std::vector<uint32_t> forms = o.kernel ? std::vector<uint32_t>{o.kernel}
-                                                 : std::vector<uint32_t>{TRHIP_KERNEL_PATH, TRHIP_KERNEL_DEFERRED};
-    std::array<uint32_t, 4> best{0, 0, 0, 0};
-    float best_ms = 0.0f;
-    const uint64_t key = tune_key(b, device, o);
-    bool cached = false;
-    {
-        std::lock_guard<std::mutex> lock(g_batch_mutex);
-        auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) {
-            best = it->second;
-            cached = true;
-        }
-    }
     const auto t0 = std::chrono::steady_clock::now();
-    uint32_t timed = 0;
-    if (!cached && o.autotune) {
-        hipEvent_t ev0 = nullptr, ev1 = nullptr;
-        e = hipEventCreate(&ev0);
-        if (e == hipSuccess) e = hipEventCreate(&ev1);
-        float best_t = 0.0f;
-        for (uint32_t form : forms)
-        for (uint32_t bs : blocks)
-            for (uint32_t tp : tiles)
-                for (uint32_t g : gpcs) {
-                    if (e != hipSuccess) break;
-                    bool fits = false;
-                    const bool dfr = form == TRHIP_KERNEL_DEFERRED;
-                    e = stage_shape(b, bs, tp, g, dfr, s, &fits);
-                    if (e != hipSuccess || !fits) continue;
-                    const uint32_t groups = std::max<uint32_t>(1u, (uint32_t)n_cu * g);
-                    e = trhip::launch_batch(b->tables, groups, bs, b->depth, b->short_links, dfr, s);  // warm-up
-                    if (e == hipSuccess) e = hipEventRecord(ev0, s);
-                    if (e == hipSuccess) e = trhip::launch_batch(b->tables, groups, bs, b->depth, b->short_links, dfr, s);
-                    if (e == hipSuccess) e = hipEventRecord(ev1, s);
-                    if (e == hipSuccess) e = hipEventSynchronize(ev1);
-                    float ms = 0.0f;
-                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
-                    if (e != hipSuccess) break;
-                    ++timed;
-                    if (best[0] == 0 || ms < best_t) {
-                        best_t = ms;
-                        best = {bs, tp, g, dfr ? 1u : 0u};
-                    }
-                }
-        if (ev0) (void)hipEventDestroy(ev0);
-        if (ev1) (void)hipEventDestroy(ev1);
+    for (BatchClass& c : b->classes) {
+        bool ok = false;
+        e = shape_class(b, c, o, device, n_cu, s, &ok);
         if (e != hipSuccess) {
             free_batch(b);
-            return hip_fail(e, "batch autotune");
+            return hip_fail(e, "batch autotune / staging");
         }
-        best_ms = best_t;
-        if (best[0]) {
-            std::lock_guard<std::mutex> lock(g_batch_mutex);
-            g_tune_cache[key] = best;
-        }
-    }
-    if (best[0] == 0) {
-        // untuned default: deferred form, the largest block whose LDS fits,
-        // 1 pixel per item, 8 groups per CU
-        const bool dfr = o.kernel != TRHIP_KERNEL_PATH;
-        for (uint32_t bs : {256u, 128u, 64u}) {
-            if (o.block_size && bs != o.block_size) continue;
-            bool fits = false;
-            e = stage_shape(b, bs, o.tile_pixels ? o.tile_pixels : 1u, o.groups_per_cu ? o.groups_per_cu : 8u, dfr, s,
-                            &fits);
-            if (e != hipSuccess || fits) {
-                best = {bs, o.tile_pixels ? o.tile_pixels : 1u, o.groups_per_cu ? o.groups_per_cu : 8u, dfr ? 1u : 0u};
-                break;
-            }
+        if (!ok) {
+            free_batch(b);
+            return fail(TRHIP_ERR_UNSUPPORTED, "no batch launch shape fits in %zu bytes of LDS", kLdsBudget);
         }
     }
-    const float tune_ms =
-        std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    bool fits = false;
-    if (e == hipSuccess && best[0]) e = stage_shape(b, best[0], best[1], best[2], best[3] != 0, s, &fits);
-    if (e != hipSuccess) {
-        free_batch(b);
-        return hip_fail(e, "batch staging");
-    }
-    if (!best[0] || !fits) {
-        free_batch(b);
-        return fail(TRHIP_ERR_UNSUPPORTED, "no batch launch shape fits in %zu bytes of LDS", kLdsBudget);
-    }
-    // capture [cursor reset -> persistent kernel] once
-    const uint32_t groups = std::max<uint32_t>(1u, (uint32_t)n_cu * b->groups);
+    const float tune_ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    // capture [cursor reset -> persistent kernel] of every class once
     hipStream_t cs = nullptr;
     e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t le = trhip::launch_batch(b->tables, groups, b->block, b->depth, b->short_links, b->deferred, cs);
+        hipError_t le = hipSuccess;
+        for (BatchClass& c : b->classes) {
+            c.groups = std::max<uint32_t>(1u, (uint32_t)n_cu * c.groups);
+            if (le == hipSuccess)
+                le = trhip::launch_batch(c.tables, c.groups, c.block, c.depth, c.short_links, c.deferred, cs);
+        }
         e = hipStreamEndCapture(cs, &b->graph);
         if (e == hipSuccess) e = le;
     }
@@ -1184,18 +1339,26 @@ trhip_status trhip_batch_create(trhip_scene* const* scenes, const trhip_render_d
         free_batch(b);
         return hip_fail(e, "batch graph capture");
     }
-    b->groups = groups;
+    const BatchClass& c0 = b->classes[0];
     b->info.n_scenes = n_scenes;
-    b->info.n_items = b->tables.n_items;
-    b->info.block_size = b->block;
-    b->info.tile_pixels = b->tile;
-    b->info.groups = groups;
-    b->info.kernel = b->deferred ? TRHIP_KERNEL_DEFERRED : TRHIP_KERNEL_PATH;
-    b->info.stack_depth = b->depth;
-    b->info.lds_bytes = b->lds;
-    b->info.candidates = timed;
-    b->info.tune_ms = timed ? tune_ms : 0.0f;
-    b->info.best_ms = best_ms;
+    b->info.n_items = 0;
+    b->info.candidates = 0;
+    b->info.best_ms = 0.0f;
+    b->info.stack_depth = 1;
+    b->info.lds_bytes = 0;
+    for (const BatchClass& c : b->classes) {
+        b->info.n_items += c.tables.n_items;
+        b->info.candidates += c.timed;
+        b->info.best_ms += c.best_ms;
+        b->info.stack_depth = std::max(b->info.stack_depth, c.depth);
+        b->info.lds_bytes = std::max(b->info.lds_bytes, c.lds);
+    }
+    b->info.block_size = c0.block;
+    b->info.tile_pixels = c0.tile;
+    b->info.groups = c0.groups;
+    b->info.kernel = c0.deferred ? TRHIP_KERNEL_DEFERRED : TRHIP_KERNEL_PATH;
+    b->info.tune_ms = b->info.candidates ? tune_ms : 0.0f;
+    b->info.n_classes = (uint32_t)b->classes.size();
     b->magic = kBatchMagic;
     {
         std::lock_guard<std::mutex> lock(g_batch_mutex);

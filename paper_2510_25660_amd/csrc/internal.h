@@ -47,7 +47,17 @@ constexpr int kWorkCounters = 10;
 size_t render_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes);
 size_t wavefront_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes);
 size_t backward_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes,
-                          bool primal);
+                          bool primal, bool fixed);
+// path per lane with the film in HBM (float atomics, no LDS film; zero-fills
+// the outputs first unless accumulating); LDS = the lanes' stacks
+size_t hbm_lds_bytes(uint32_t block, uint32_t stack_bytes);
+hipError_t launch_render_hbm(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
+                             unsigned long long* counts = nullptr);
+// deterministic forward render (path per lane, fixed-point tile sums)
+size_t fixed_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes);
+hipError_t launch_render_fixed(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream);
+// fixed-point sums (two 64-bit words each, as the deterministic kernels hold them) to FP32
+hipError_t launch_fixed_to_f32(const unsigned long long* src, float* dst, size_t n, hipStream_t stream);
 
 // counts: optional device uint64[7] receiving the work counters (node
 // visits, triangle tests, closest rays, shadow rays, vertices, Philox draws,
@@ -57,26 +67,29 @@ hipError_t launch_render(const SceneView& S, const LaunchArgs& L, uint32_t block
 hipError_t launch_render_wavefront(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
                                    unsigned long long* counts = nullptr);
 // max_cont 2 or 7: single-trace adjoint with a per-path stash of that many
-// continuation vertices; anything else: path replay (two traces per path)
+// continuation vertices; anything else: path replay (two traces per path).
+// L.g_fixed set: deterministic fixed-point gradient sums ([2][n_tris][2]
+// words) instead of FP64 atomics into L.g_alb, L.g_rough
 hipError_t launch_backward(const SceneView& S, const LaunchArgs& L, uint32_t block, int max_cont, hipStream_t stream);
 size_t tangent_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes);
 // forward-mode render: film and its derivative along (tan_albedo, tan_rough)
 hipError_t launch_render_tangent(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream);
 size_t deferred_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes);
 size_t batch_lds_bytes(uint32_t film_words, uint32_t block, uint32_t stack_bytes, bool deferred);
-// resets the cursor and launches the persistent kernel (groups workgroups);
-// short_links: every scene of the batch has 16-bit stack links
-hipError_t launch_batch(const BatchTables& B, uint32_t groups, uint32_t block, uint32_t stack_depth,
-                        bool short_links, bool deferred, hipStream_t stream);
+// resets the cursor and launches the persistent kernel (groups workgroups)
+// for scenes that all have 16-bit (short_links) or all 32-bit stack links,
+// stack_depth the deepest of their BVHs
+hipError_t launch_batch(const BatchTables& B, uint32_t groups, uint32_t block, uint32_t stack_depth, bool short_links,
+                        bool deferred, hipStream_t stream);
 hipError_t launch_render_deferred(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
                                   unsigned long long* counts = nullptr);
 // sample chunks per tile of the deferred form (sets the samples per chunk);
-// chunks > 1 need L.chunk_scratch (tiles * chunks * (tile_pixels * words +
-// 2 * tile_pixels) floats) and L.tile_count (tiles counters, zero between
-// launches)
+// chunks > 1 need L.chunk_scratch ((chunks - 1) * (n_pixels * words +
+// 2 * n_pixels) floats, words = floats of one pixel's film), and after the
+// render launch_add_planes, which adds those partial films to the outputs
 constexpr uint32_t kMaxChunks = 4;
 uint32_t deferred_chunks(uint32_t spp, uint32_t block, uint32_t* chunk_spp);
-hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t stream);
+hipError_t launch_add_planes(const LaunchArgs& L, uint32_t words, hipStream_t stream);
 hipError_t launch_zero_f64(double* p, size_t n, hipStream_t stream);
 // out[i] = Poisson(scale * film[i]) / scale (noise.hip)
 hipError_t launch_poisson(const float* film, float* out, uint64_t n, float scale, uint64_t seed, hipStream_t stream);

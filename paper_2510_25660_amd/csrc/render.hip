@@ -4,9 +4,12 @@
 // traces every sample of those pixels, one path per lane at a time.  The
 // tile's film rows live in LDS, so contributions are LDS atomics and the
 // tile is written to HBM once, with coalesced stores, at the end: no film
-// zero-fill pass and no HBM atomics.  The BVH traversal stack of each lane
-// lives in LDS (stride = block size, so a wave's pushes are contiguous),
-// with 16-bit links when the scene is small enough, 32-bit otherwise.
+// zero-fill pass and no HBM atomics.  (When the deferred form splits a
+// tile's samples over several workgroups, the extra ones leave their partial
+// tiles in a scratch film that a second pass adds, still without atomics.)
+// The BVH traversal stack of each lane lives in LDS (stride = block size, so
+// a wave's pushes are contiguous), with 16-bit links when the scene is small
+// enough, 32-bit otherwise.
 //
 // Path construction (arXiv 2510.25660, Sec. 3): paths are traced from the
 // sensor (pinhole camera, or the scan point on the relay wall for the
@@ -905,6 +908,122 @@ struct FilmSink {
     __device__ __forceinline__ void continuation(int, int, float, float) {}
 };
 
+// ---------------------------------------------------------------------------
+// Deterministic accumulation (TRHIP_FLAG_DETERMINISTIC).  Every film
+// contribution and every gradient term is added as a 128-bit two's-complement
+// fixed-point number with 64 fraction bits, held in two 64-bit words: the low
+// words' atomic add returns the old value, and a wrap-around carries 1 into
+// the high word.  Integer addition is associative and the number of
+// wrap-arounds of the low word is fixed by the total, so the final sums do
+// not depend on the order of the atomics, the launch shape or the kernel's
+// scheduling.  A film bin is then the exact sum of its FP32 contributions
+// (exact for contributions of at least 2^-41; smaller ones are truncated to
+// multiples of 2^-64), rounded once; values and sums must stay below 2^63.
+// ---------------------------------------------------------------------------
+struct Fixed128 {
+    uint64_t lo, hi;
+};
+
+// x * 2^64 truncated toward zero (saturated at |x| >= 2^63; NaN gives 0)
+__device__ __forceinline__ Fixed128 to_fixed(double x)
+{
+    Fixed128 f{0ull, 0ull};
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const int e = (int)((b >> 52) & 0x7ffu);
+    if (e == 0 || x != x) return f;
+    const uint64_t m = (b & 0xfffffffffffffull) | 0x10000000000000ull;  // |x| = m 2^(e - 1075)
+    const int s = e - 1075 + 64;                                          // |x| 2^64 = m 2^s
+    if (s > 74) {
+        f.lo = ~0ull;
+        f.hi = 0x7fffffffffffffffull;
+    } else if (s >= 64) {
+        f.hi = m << (s - 64);
+    } else if (s > 0) {
+        f.lo = m << s;
+        f.hi = m >> (64 - s);
+    } else if (s > -53) {
+        f.lo = m >> (-s);
+    }
+    if (b >> 63) {
+        f.lo = ~f.lo + 1ull;
+        f.hi = ~f.hi + (f.lo == 0ull ? 1ull : 0ull);
+    }
+    return f;
+}
+
+__device__ __forceinline__ double from_fixed(uint64_t lo, uint64_t hi)
+{
+    return (double)(int64_t)hi + (double)lo * 0x1p-64;
+}
+
+// cell[0], cell[1]: low and high word (LDS or global memory)
+__device__ __forceinline__ void fixed_add(unsigned long long* cell, Fixed128 f)
+{
+    if ((f.lo | f.hi) == 0ull) return;
+    const unsigned long long old = atomicAdd(cell, (unsigned long long)f.lo);
+    const uint64_t h = f.hi + ((old + f.lo < old) ? 1ull : 0ull);
+    if (h) atomicAdd(cell + 1, (unsigned long long)h);
+}
+
+struct FixedFilmSink {
+    static constexpr bool kWantsGradients = false;
+    unsigned long long* row;     // LDS film row of the pixel, two words per bin
+    unsigned long long* steady;  // two words
+    unsigned long long* oow;
+    __device__ __forceinline__ void contribution(int, int, float c, int bin, float, float, float)
+    {
+        const Fixed128 f = to_fixed((double)c);
+        if (bin >= 0) fixed_add(row + 2 * bin, f);
+        else fixed_add(oow, f);
+        fixed_add(steady, f);
+    }
+    __device__ __forceinline__ void continuation(int, int, float, float) {}
+};
+
+// Deterministic form of render_tile (path per lane): the tile's film,
+// steady and out-of-window sums in fixed point in LDS ([TP][T][2], [TP][2],
+// [TP][2] words), each written as sum / norm_spp rounded to FP32.
+template <class W, class TallyT>
+__device__ __forceinline__ void render_tile_fixed(const SceneView& S, const LaunchArgs& L, uint32_t p0,
+                                                  unsigned long long* q, W* stk, int stride, TallyT& tally)
+{
+    const uint32_t T = S.n_bins;
+    const uint32_t TP = L.tile_pixels;
+    unsigned long long* qfilm = q;
+    unsigned long long* qsteady = q + 2ull * TP * T;
+    unsigned long long* qoow = qsteady + 2 * TP;
+    const uint32_t npix = min(TP, L.n_pixels - p0);
+    for (uint32_t i = threadIdx.x; i < 2 * (TP * T + 2 * TP); i += blockDim.x) q[i] = 0ull;
+    __syncthreads();
+    const uint32_t work = npix * L.spp;
+    for (uint32_t w = threadIdx.x; w < work; w += blockDim.x) {
+        const uint32_t pl = w / L.spp;
+        const uint32_t s = w - pl * L.spp;
+        FixedFilmSink sink{qfilm + 2ull * pl * T, qsteady + 2 * pl, qoow + 2 * pl};
+        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, sink, tally);
+    }
+    __syncthreads();
+    const bool acc = (L.flags & kFlagAccumulate) != 0;
+    const double n = (double)L.norm_spp;
+    auto value = [&](const unsigned long long* c) { return (float)(from_fixed(c[0], c[1]) / n); };
+    const size_t base = (size_t)p0 * T;
+    for (uint32_t i = threadIdx.x; i < npix * T; i += blockDim.x) {
+        const float v = value(qfilm + 2 * i);
+        L.film[base + i] = acc ? L.film[base + i] + v : v;
+    }
+    if (threadIdx.x < npix) {
+        const uint32_t p = p0 + threadIdx.x;
+        if (L.steady) {
+            const float v = value(qsteady + 2 * threadIdx.x);
+            L.steady[p] = acc ? L.steady[p] + v : v;
+        }
+        if (L.oow) {
+            const float v = value(qoow + 2 * threadIdx.x);
+            L.oow[p] = acc ? L.oow[p] + v : v;
+        }
+    }
+}
+
 // Renders one tile of pixels [p0, p0 + tile_pixels) with all their samples:
 // LDS film rows (zeroed here), paths traced one per lane, then one
 // coalesced write (or accumulate) of the tile to HBM.  lds_film holds
@@ -964,6 +1083,55 @@ __device__ __forceinline__ void render_tile(const SceneView& S, const LaunchArgs
             L.oow[p] = acc ? L.oow[p] + v : v;
         }
     }
+}
+
+// Path per lane with the film in HBM: every contribution, scaled by 1/N, is
+// a float atomic add into the film itself (zeroed beforehand unless
+// accumulating), so the workgroup keeps no film in LDS, only its lanes'
+// stacks.  For long films (1,024 bins of a 1M-triangle scene: 4 KB per
+// pixel) the LDS film is what limits the workgroups a CU holds; a pixel's
+// row stays in L2 while its tile renders, so its atomics are served there.
+struct HbmFilmSink {
+    static constexpr bool kWantsGradients = false;
+    float* row;  // HBM film row of the current pixel
+    float norm;
+    float steady, oow;  // register partial sums of the current pixel (unnormalised)
+    __device__ __forceinline__ void contribution(int, int, float c, int bin, float, float, float)
+    {
+        if (bin >= 0) unsafeAtomicAdd(row + bin, c * norm);
+        else oow += c;
+        steady += c;
+    }
+    __device__ __forceinline__ void continuation(int, int, float, float) {}
+};
+
+template <class W, class TallyT>
+__device__ __forceinline__ void render_tile_hbm(const SceneView& S, const LaunchArgs& L, uint32_t p0, W* stk,
+                                                int stride, TallyT& tally)
+{
+    const uint32_t T = S.n_bins;
+    const uint32_t npix = min(L.tile_pixels, L.n_pixels - p0);
+    const uint32_t work = npix * L.spp;
+    uint32_t cur = 0xffffffffu;
+    HbmFilmSink sink{nullptr, L.norm, 0.0f, 0.0f};
+    auto flush = [&]() {
+        if (cur == 0xffffffffu) return;
+        if (L.steady) unsafeAtomicAdd(L.steady + p0 + cur, sink.steady * L.norm);
+        if (L.oow) unsafeAtomicAdd(L.oow + p0 + cur, sink.oow * L.norm);
+    };
+    for (uint32_t w = threadIdx.x; w < work; w += blockDim.x) {
+        const uint32_t pl = w / L.spp;
+        const uint32_t s = w - pl * L.spp;
+        if (pl != cur) {
+            flush();
+            cur = pl;
+            sink.row = L.film + (size_t)(p0 + pl) * T;
+            sink.steady = 0.0f;
+            sink.oow = 0.0f;
+        }
+        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, sink, tally);
+    }
+    flush();
 }
 
 // Same tile, deferred form.  Phase 1 takes the tile's samples in batches
@@ -1266,44 +1434,23 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
     const size_t fbase = (size_t)p0 * T;
     const uint32_t nvals = npix * T;
     const bool acc = (L.flags & kFlagAccumulate) != 0;
-    if (L.chunks > 1) {
-        // Other workgroups hold other samples of these pixels.  Every chunk
-        // leaves its partial tile (film rows, steady, oow; unnormalised) in
-        // its slot of the scratch; the last of the tile's chunks to finish
-        // adds the partials up in chunk order and writes the tile once with
-        // plain stores, then re-arms the tile's counter for the next launch.
-        // (Adding the partials into the film with device-scope atomics cost
-        // one 64-byte memory write per atomic: 10x the film's bytes.)
-        const uint32_t words = TP * T + 2 * TP;
-        float* slots = L.chunk_scratch + (size_t)tile * L.chunks * words;
-        for (uint32_t i = tid; i < words; i += nb) slots[(size_t)chunk * words + i] = lds_film[i];
-        __threadfence();
-        __syncthreads();
-        if (tid == 0) fh.count[1] = (atomicAdd(L.tile_count + tile, 1u) == L.chunks - 1) ? 1u : 0u;
-        __syncthreads();
-        if (!fh.count[1]) return;
-        __threadfence();
-        auto total = [&](uint32_t i) {
-            float v = 0.0f;
-            for (uint32_t c = 0; c < L.chunks; ++c) v = v + (c == chunk ? lds_film[i] : slots[(size_t)c * words + i]);
-            return v;
-        };
-        for (uint32_t i = tid; i < nvals; i += nb) {
-            const float v = total(i) * L.norm;
-            L.film[fbase + i] = acc ? L.film[fbase + i] + v : v;
-        }
+    if (chunk > 0) {
+        // Other workgroups hold other samples of these pixels.  Chunk 0
+        // writes the film as a single workgroup would; chunk c > 0 leaves
+        // its normalised partial tile in plane c - 1 of the scratch (the
+        // film's layout, then steady and oow), which a second pass adds to
+        // the film in chunk order.  (Adding the partials into the film with
+        // device-scope atomics cost one 64-byte memory write per atomic,
+        // 10x the film's bytes; a last-finisher reduction inside the kernel
+        // needs device-scope fences, which write back and invalidate the
+        // XCD's whole L2 and with it the BVH.)
+        const size_t film_n = (size_t)L.n_pixels * T;
+        float* plane = L.chunk_scratch + (size_t)(chunk - 1) * (film_n + 2ull * L.n_pixels);
+        for (uint32_t i = tid; i < nvals; i += nb) plane[fbase + i] = tfilm[i] * L.norm;
         if (tid < npix) {
-            const uint32_t p = p0 + tid;
-            if (L.steady) {
-                const float v = total(TP * T + tid) * L.norm;
-                L.steady[p] = acc ? L.steady[p] + v : v;
-            }
-            if (L.oow) {
-                const float v = total(TP * T + TP + tid) * L.norm;
-                L.oow[p] = acc ? L.oow[p] + v : v;
-            }
+            plane[film_n + p0 + tid] = tsteady[tid] * L.norm;
+            plane[film_n + L.n_pixels + p0 + tid] = toow[tid] * L.norm;
         }
-        if (tid == 0) L.tile_count[tile] = 0u;
         return;
     }
     for (uint32_t i = tid; i < nvals; i += nb) {
@@ -1395,12 +1542,35 @@ __global__ void __launch_bounds__(256) k_render(SceneView S, LaunchArgs L, unsig
     tally.flush(counts);
 }
 
+template <int kMode, class W>
+__global__ void __launch_bounds__(256) k_render_hbm(SceneView S, LaunchArgs L, unsigned long long* counts)
+{
+    Tally<kMode> tally;
+    extern __shared__ float lds[];
+    W* stk = reinterpret_cast<W*>(lds) + threadIdx.x;
+    render_tile_hbm(S, L, tile_first_pixel(S, L, L.tile_pixels), stk, (int)blockDim.x, tally);
+    tally.flush(counts);
+}
+
+template <class W>
+__global__ void __launch_bounds__(256) k_render_fixed(SceneView S, LaunchArgs L)
+{
+    Tally<kPlain> tally;
+    extern __shared__ float lds[];
+    const uint32_t TP = L.tile_pixels;
+    unsigned long long* q = reinterpret_cast<unsigned long long*>(lds);
+    W* stk = reinterpret_cast<W*>(q + 2ull * (TP * S.n_bins + 2 * TP)) + threadIdx.x;
+    render_tile_fixed(S, L, tile_first_pixel(S, L, TP), q, stk, (int)blockDim.x, tally);
+}
+
 // ---------------------------------------------------------------------------
 // batched persistent form: many scenes, one launch
 // ---------------------------------------------------------------------------
 // Work items are (scene, pixel tile) pairs numbered scene by scene in the
 // processing order; a workgroup pops items from a global cursor until they
-// run out, so scenes of very different cost balance themselves.
+// run out, so scenes of very different cost balance themselves.  One launch
+// serves scenes of one stack-link width W (the batch splits its scenes into
+// classes); the tile width is each scene's own.
 template <bool kDeferred, class W>
 __global__ void __launch_bounds__(256) k_batch(BatchTables B)
 {
@@ -1427,8 +1597,8 @@ __global__ void __launch_bounds__(256) k_batch(BatchTables B)
         // NLOS area sampling needs no first-hit traversal to defer: such
         // scenes take the path-per-lane tile (same LDS film and stacks)
         if (kDeferred && !(args[scene].flags & kFlagNlosArea))
-            render_tile_deferred<false>(views[scene], args[scene], tile, 0u, lds, nullptr, fh,
-                                        stk, (int)blockDim.x, tally);
+            render_tile_deferred<false>(views[scene], args[scene], tile, 0u, lds, nullptr, fh, stk, (int)blockDim.x,
+                                        tally);
         else
             render_tile(views[scene], args[scene], tile * args[scene].tile_pixels, lds, nullptr, stk,
                         (int)blockDim.x, tally);
@@ -1664,60 +1834,105 @@ struct AdjointSumSink {
 };
 
 // Per-workgroup gradient cache in LDS.  The paths of a tile keep meeting
-// the same triangles, so instead of one FP64 global atomic per vertex and
+// the same triangles, so instead of one global atomic per vertex and
 // parameter, a workgroup sums its gradients in an open-addressing table of
 // kGradSlots slots keyed by triangle (LDS atomics), and adds each touched
 // triangle's two sums to the global gradients once, at the end of the tile.
 // A triangle that finds no slot within kGradProbes probes goes straight to
-// the global gradients.  Layout from an 8-byte aligned base: FP64 albedo
-// sums, FP64 roughness sums, int keys (-1 = empty).
+// the global gradients.  GradF64 sums in FP64 (layout from an 8-byte aligned
+// base: albedo sums, roughness sums, int keys, -1 = empty); GradFixed, the
+// deterministic form, in 128-bit fixed point (albedo [slot][2] words,
+// roughness [slot][2] words, int keys), with global sums [2][n_tris][2].
 constexpr uint32_t kGradSlots = 512;
 constexpr int kGradProbes = 8;
-constexpr uint32_t kGradCacheFloats = kGradSlots * 5;  // 2 doubles + 1 int per slot, in 4-byte words
 
-__device__ __forceinline__ void grad_add(double* cache, double* g_alb, double* g_rough, int k, double a, double r)
+__device__ __forceinline__ int grad_slot(int* key, int k)
 {
-    if (a == 0.0 && r == 0.0) return;
-    double* ga = cache;
-    double* gr = cache + kGradSlots;
-    int* key = reinterpret_cast<int*>(cache + 2 * kGradSlots);
     const uint32_t h = ((uint32_t)k * 2654435761u) >> 23;
     for (int p = 0; p < kGradProbes; ++p) {
         const uint32_t slot = (h + (uint32_t)p) & (kGradSlots - 1);
         int cur = key[slot];
         if (cur == -1) cur = atomicCAS(key + slot, -1, k);
-        if (cur == -1 || cur == k) {
-            if (a != 0.0) unsafeAtomicAdd(ga + slot, a);
-            if (r != 0.0) unsafeAtomicAdd(gr + slot, r);
-            return;
+        if (cur == -1 || cur == k) return (int)slot;
+    }
+    return -1;
+}
+
+struct GradF64 {
+    static constexpr uint32_t kFloats = kGradSlots * 5;  // 2 doubles + 1 int per slot, in 4-byte words
+    double* cache;
+    double* g_alb;
+    double* g_rough;
+    __device__ __forceinline__ GradF64(float* lds, const SceneView&, const LaunchArgs& L)
+        : cache(reinterpret_cast<double*>(lds)), g_alb(L.g_alb), g_rough(L.g_rough)
+    {
+    }
+    __device__ __forceinline__ int* key() const { return reinterpret_cast<int*>(cache + 2 * kGradSlots); }
+    __device__ __forceinline__ void add(int k, double a, double r)
+    {
+        if (a == 0.0 && r == 0.0) return;
+        const int slot = grad_slot(key(), k);
+        double* ga = slot >= 0 ? cache + slot : g_alb + k;
+        double* gr = slot >= 0 ? cache + kGradSlots + slot : g_rough + k;
+        if (a != 0.0) unsafeAtomicAdd(ga, a);
+        if (r != 0.0) unsafeAtomicAdd(gr, r);
+    }
+    __device__ __forceinline__ void clear()
+    {
+        for (uint32_t i = threadIdx.x; i < kGradSlots; i += blockDim.x) {
+            cache[i] = 0.0;
+            cache[kGradSlots + i] = 0.0;
+            key()[i] = -1;
         }
     }
-    if (a != 0.0) unsafeAtomicAdd(g_alb + k, a);
-    if (r != 0.0) unsafeAtomicAdd(g_rough + k, r);
-}
-
-__device__ __forceinline__ void grad_cache_clear(double* cache)
-{
-    int* key = reinterpret_cast<int*>(cache + 2 * kGradSlots);
-    for (uint32_t i = threadIdx.x; i < kGradSlots; i += blockDim.x) {
-        cache[i] = 0.0;
-        cache[kGradSlots + i] = 0.0;
-        key[i] = -1;
+    // after a barrier: the table's sums to the global gradients
+    __device__ __forceinline__ void flush() const
+    {
+        for (uint32_t i = threadIdx.x; i < kGradSlots; i += blockDim.x) {
+            const int k = key()[i];
+            if (k < 0) continue;
+            if (cache[i] != 0.0) unsafeAtomicAdd(g_alb + k, cache[i]);
+            if (cache[kGradSlots + i] != 0.0) unsafeAtomicAdd(g_rough + k, cache[kGradSlots + i]);
+        }
     }
-}
+};
 
-// after a barrier: the table's sums to the global gradients
-__device__ __forceinline__ void grad_cache_flush(const double* cache, double* g_alb, double* g_rough)
-{
-    const int* key = reinterpret_cast<const int*>(cache + 2 * kGradSlots);
-    for (uint32_t i = threadIdx.x; i < kGradSlots; i += blockDim.x) {
-        const int k = key[i];
-        if (k < 0) continue;
-        if (cache[i] != 0.0) unsafeAtomicAdd(g_alb + k, cache[i]);
-        if (cache[kGradSlots + i] != 0.0) unsafeAtomicAdd(g_rough + k, cache[kGradSlots + i]);
+struct GradFixed {
+    static constexpr uint32_t kFloats = kGradSlots * 9;  // 4 words of 8 bytes + 1 int per slot
+    unsigned long long* cache;
+    unsigned long long* g;  // [2][n_tris][2]
+    uint32_t n_tris;
+    __device__ __forceinline__ GradFixed(float* lds, const SceneView& S, const LaunchArgs& L)
+        : cache(reinterpret_cast<unsigned long long*>(lds)), g(L.g_fixed), n_tris(S.n_tris)
+    {
     }
-}
+    __device__ __forceinline__ int* key() const { return reinterpret_cast<int*>(cache + 4 * kGradSlots); }
+    __device__ __forceinline__ void add(int k, double a, double r)
+    {
+        if (a == 0.0 && r == 0.0) return;
+        const int slot = grad_slot(key(), k);
+        unsigned long long* ga = slot >= 0 ? cache + 2 * slot : g + 2ull * k;
+        unsigned long long* gr = slot >= 0 ? cache + 2 * (kGradSlots + slot) : g + 2ull * (n_tris + k);
+        fixed_add(ga, to_fixed(a));
+        fixed_add(gr, to_fixed(r));
+    }
+    __device__ __forceinline__ void clear()
+    {
+        for (uint32_t i = threadIdx.x; i < 4 * kGradSlots; i += blockDim.x) cache[i] = 0ull;
+        for (uint32_t i = threadIdx.x; i < kGradSlots; i += blockDim.x) key()[i] = -1;
+    }
+    __device__ __forceinline__ void flush() const
+    {
+        for (uint32_t i = threadIdx.x; i < kGradSlots; i += blockDim.x) {
+            const int k = key()[i];
+            if (k < 0) continue;
+            fixed_add(g + 2ull * k, Fixed128{cache[2 * i], cache[2 * i + 1]});
+            fixed_add(g + 2ull * (n_tris + k), Fixed128{cache[2 * (kGradSlots + i)], cache[2 * (kGradSlots + i) + 1]});
+        }
+    }
+};
 
+template <class Acc>
 struct AdjointScatterSink {
     static constexpr bool kWantsGradients = true;
     const float* delta;
@@ -1725,9 +1940,7 @@ struct AdjointScatterSink {
     float norm;
     double total;       // A from pass 1
     double prefix;      // sum of a_j so far
-    double* g_alb;
-    double* g_rough;
-    double* cache;      // the workgroup's LDS gradient table
+    Acc* acc;           // the workgroup's gradient table
     __device__ __forceinline__ void contribution(int, int k, float c, int bin, float, float g_alb_nee,
                                                  float g_rough_nee)
     {
@@ -1735,12 +1948,12 @@ struct AdjointScatterSink {
         if (primal_row) atomicAdd(primal_row + bin, c);
         const double a = (double)delta[bin] * (double)c * (double)norm;
         prefix += a;
-        if (k >= 0 && a != 0.0) grad_add(cache, g_alb, g_rough, k, a * (double)g_alb_nee, a * (double)g_rough_nee);
+        if (k >= 0 && a != 0.0) acc->add(k, a * (double)g_alb_nee, a * (double)g_rough_nee);
     }
     __device__ __forceinline__ void continuation(int, int k, float g_alb_c, float g_rough_c)
     {
         const double rest = total - prefix;
-        if (rest != 0.0) grad_add(cache, g_alb, g_rough, k, rest * (double)g_alb_c, rest * (double)g_rough_c);
+        if (rest != 0.0) acc->add(k, rest * (double)g_alb_c, rest * (double)g_rough_c);
     }
 };
 
@@ -1821,7 +2034,7 @@ __global__ void __launch_bounds__(256) k_render_tangent(SceneView S, LaunchArgs 
     }
 }
 
-template <class W>
+template <class W, class Acc>
 __global__ void __launch_bounds__(256) k_backward(SceneView S, LaunchArgs L)
 {
     Tally<kPlain> tally;
@@ -1829,8 +2042,8 @@ __global__ void __launch_bounds__(256) k_backward(SceneView S, LaunchArgs L)
     const uint32_t T = S.n_bins;
     const uint32_t TP = L.tile_pixels;
     const bool want_primal = L.primal != nullptr;
-    double* cache = reinterpret_cast<double*>(lds);
-    float* tdelta = lds + kGradCacheFloats;
+    Acc acc(lds, S, L);
+    float* tdelta = lds + Acc::kFloats;
     float* tprimal = tdelta + (size_t)TP * T;
     W* stk = reinterpret_cast<W*>(tprimal + (want_primal ? (size_t)TP * T : 0)) + threadIdx.x;
     const int stride = (int)blockDim.x;
@@ -1841,7 +2054,7 @@ __global__ void __launch_bounds__(256) k_backward(SceneView S, LaunchArgs L)
         tdelta[i] = (i < npix * T) ? L.grad_film[base + i] : 0.0f;
         if (want_primal) tprimal[i] = 0.0f;
     }
-    grad_cache_clear(cache);
+    acc.clear();
     __syncthreads();
 
     const uint32_t work = npix * L.spp;
@@ -1851,12 +2064,12 @@ __global__ void __launch_bounds__(256) k_backward(SceneView S, LaunchArgs L)
         const float* drow = tdelta + (size_t)pl * T;
         AdjointSumSink first{drow, L.norm, 0.0};
         trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, first, tally);
-        AdjointScatterSink second{drow, want_primal ? tprimal + (size_t)pl * T : nullptr, L.norm, first.total, 0.0,
-                                  L.g_alb, L.g_rough, cache};
+        AdjointScatterSink<Acc> second{drow, want_primal ? tprimal + (size_t)pl * T : nullptr, L.norm, first.total,
+                                       0.0, &acc};
         trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, second, tally);
     }
     __syncthreads();
-    grad_cache_flush(cache, L.g_alb, L.g_rough);
+    acc.flush();
     if (want_primal)
         for (uint32_t i = threadIdx.x; i < npix * T; i += blockDim.x) L.primal[base + i] = tprimal[i] * L.norm;
 }
@@ -1868,15 +2081,13 @@ __global__ void __launch_bounds__(256) k_backward(SceneView S, LaunchArgs L)
 // every stashed vertex).  At the end of the path every stashed vertex adds
 // a_v dlogf_nee + R_v dlogf_cont to its triangle: the same gradient as path
 // replay, from one trace.  The stash lives in registers (static indices).
-template <int kMaxCont>
+template <int kMaxCont, class Acc>
 struct AdjointStashSink {
     static constexpr bool kWantsGradients = true;
     const float* delta;
     float* primal_row;
     float norm;
-    double* g_alb;
-    double* g_rough;
-    double* cache;  // the workgroup's LDS gradient table
+    Acc* acc;  // the workgroup's gradient table
     int nv = 0;
     int k[kMaxCont];
     float ca[kMaxCont], cr[kMaxCont], na[kMaxCont], nr[kMaxCont], R[kMaxCont];
@@ -1918,19 +2129,19 @@ struct AdjointStashSink {
     }
     __device__ __forceinline__ void finish()
     {
-        if (pending) grad_add(cache, g_alb, g_rough, pk, (double)pa, (double)pr);
+        if (pending) acc->add(pk, (double)pa, (double)pr);
 #pragma unroll
         for (int i = 0; i < kMaxCont; ++i)
             if (i < nv) {
                 const double ga = (double)na[i] + (double)R[i] * (double)ca[i];
                 const double gr = (double)nr[i] + (double)R[i] * (double)cr[i];
-                grad_add(cache, g_alb, g_rough, k[i], ga, gr);
+                acc->add(k[i], ga, gr);
             }
     }
 };
 
 // Four waves per SIMD (at most 128 VGPRs) instead of three.
-template <int kMaxCont, class W>
+template <int kMaxCont, class W, class Acc>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
 k_backward_stash(SceneView S, LaunchArgs L)
 {
@@ -1939,8 +2150,8 @@ k_backward_stash(SceneView S, LaunchArgs L)
     const uint32_t T = S.n_bins;
     const uint32_t TP = L.tile_pixels;
     const bool want_primal = L.primal != nullptr;
-    double* cache = reinterpret_cast<double*>(lds);
-    float* tdelta = lds + kGradCacheFloats;
+    Acc acc(lds, S, L);
+    float* tdelta = lds + Acc::kFloats;
     float* tprimal = tdelta + (size_t)TP * T;
     W* stk = reinterpret_cast<W*>(tprimal + (want_primal ? (size_t)TP * T : 0)) + threadIdx.x;
     const int stride = (int)blockDim.x;
@@ -1951,32 +2162,31 @@ k_backward_stash(SceneView S, LaunchArgs L)
         tdelta[i] = (i < npix * T) ? L.grad_film[base + i] : 0.0f;
         if (want_primal) tprimal[i] = 0.0f;
     }
-    grad_cache_clear(cache);
+    acc.clear();
     __syncthreads();
     const uint32_t work = npix * L.spp;
     for (uint32_t w = threadIdx.x; w < work; w += blockDim.x) {
         const uint32_t pl = w / L.spp;
         const uint32_t s = w - pl * L.spp;
-        AdjointStashSink<kMaxCont> sink;
+        AdjointStashSink<kMaxCont, Acc> sink;
         sink.delta = tdelta + (size_t)pl * T;
         sink.primal_row = want_primal ? tprimal + (size_t)pl * T : nullptr;
         sink.norm = L.norm;
-        sink.g_alb = L.g_alb;
-        sink.g_rough = L.g_rough;
-        sink.cache = cache;
+        sink.acc = &acc;
         trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, sink, tally);
         sink.finish();
     }
     __syncthreads();
-    grad_cache_flush(cache, L.g_alb, L.g_rough);
+    acc.flush();
     if (want_primal)
         for (uint32_t i = threadIdx.x; i < npix * T; i += blockDim.x) L.primal[base + i] = tprimal[i] * L.norm;
 }
 
-__global__ void k_zero_u32(uint32_t* p, size_t n)
+
+__global__ void k_zero_f32(float* p, size_t n)
 {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        p[i] = 0u;
+        p[i] = 0.0f;
 }
 
 __global__ void k_zero_f64(double* p, size_t n)
@@ -2020,9 +2230,16 @@ hipError_t launch_render_tangent(const SceneView& S, const LaunchArgs& L, uint32
     return hipGetLastError();
 }
 
-size_t backward_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes, bool primal)
+size_t backward_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes, bool primal,
+                          bool fixed)
 {
-    return (size_t)kGradCacheFloats * sizeof(float) + (size_t)tile_pixels * n_bins * sizeof(float) * (primal ? 2 : 1) +
+    return (size_t)(fixed ? GradFixed::kFloats : GradF64::kFloats) * sizeof(float) +
+           (size_t)tile_pixels * n_bins * sizeof(float) * (primal ? 2 : 1) + (size_t)block * stack_bytes;
+}
+
+size_t fixed_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes)
+{
+    return ((size_t)tile_pixels * n_bins + 2ull * tile_pixels) * 2 * sizeof(unsigned long long) +
            (size_t)block * stack_bytes;
 }
 
@@ -2060,6 +2277,24 @@ void launch_render_w(const SceneView& S, const LaunchArgs& L, uint32_t block, si
     case kCounting: hipLaunchKernelGGL((k_render<kCounting, W>), grid, dim3(block), lds, stream, S, L, counts); break;
     default: hipLaunchKernelGGL((k_render<kPlain, W>), grid, dim3(block), lds, stream, S, L, counts);
     }
+}
+
+template <class W>
+void launch_hbm_w(const SceneView& S, const LaunchArgs& L, uint32_t block, size_t lds, hipStream_t stream,
+                  unsigned long long* counts)
+{
+    const dim3 grid(tiles_of(L));
+    switch (mode_of(L, counts)) {
+    case kRecording: hipLaunchKernelGGL((k_render_hbm<kRecording, W>), grid, dim3(block), lds, stream, S, L, counts); break;
+    case kCounting: hipLaunchKernelGGL((k_render_hbm<kCounting, W>), grid, dim3(block), lds, stream, S, L, counts); break;
+    default: hipLaunchKernelGGL((k_render_hbm<kPlain, W>), grid, dim3(block), lds, stream, S, L, counts);
+    }
+}
+
+void launch_fill_zero(float* p, size_t n, hipStream_t stream)
+{
+    const unsigned g = (unsigned)std::min<size_t>(4096, (n + 255) / 256 + 1);
+    hipLaunchKernelGGL(k_zero_f32, dim3(g), dim3(256), 0, stream, p, n);
 }
 
 template <class W>
@@ -2104,27 +2339,18 @@ void launch_deferred_w(const SceneView& S, const LaunchArgs& L, uint32_t block, 
 
 
 
-template <class W>
+template <class W, class Acc>
 void launch_backward_w(const SceneView& S, const LaunchArgs& L, uint32_t block, int max_cont, size_t lds,
                        hipStream_t stream)
 {
     if (max_cont == 2)
-        hipLaunchKernelGGL((k_backward_stash<2, W>), dim3(tiles_of(L)), dim3(block), lds, stream, S, L);
+        hipLaunchKernelGGL((k_backward_stash<2, W, Acc>), dim3(tiles_of(L)), dim3(block), lds, stream, S, L);
     else if (max_cont == 7)
-        hipLaunchKernelGGL((k_backward_stash<7, W>), dim3(tiles_of(L)), dim3(block), lds, stream, S, L);
+        hipLaunchKernelGGL((k_backward_stash<7, W, Acc>), dim3(tiles_of(L)), dim3(block), lds, stream, S, L);
     else
-        hipLaunchKernelGGL((k_backward<W>), dim3(tiles_of(L)), dim3(block), lds, stream, S, L);
+        hipLaunchKernelGGL((k_backward<W, Acc>), dim3(tiles_of(L)), dim3(block), lds, stream, S, L);
 }
 
-template <class W>
-void launch_batch_w(const BatchTables& B, uint32_t groups, uint32_t block, size_t lds, bool deferred,
-                    hipStream_t stream)
-{
-    if (deferred)
-        hipLaunchKernelGGL((k_batch<true, W>), dim3(groups), dim3(block), lds, stream, B);
-    else
-        hipLaunchKernelGGL((k_batch<false, W>), dim3(groups), dim3(block), lds, stream, B);
-}
 
 }  // namespace
 
@@ -2137,6 +2363,24 @@ hipError_t launch_render(const SceneView& S, const LaunchArgs& L, uint32_t block
         launch_render_w<uint16_t>(S, L, block, lds, stream, counts);
     else
         launch_render_w<uint32_t>(S, L, block, lds, stream, counts);
+    return hipGetLastError();
+}
+
+size_t hbm_lds_bytes(uint32_t block, uint32_t stack_bytes) { return (size_t)block * stack_bytes; }
+
+hipError_t launch_render_hbm(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
+                             unsigned long long* counts)
+{
+    if ((L.flags & kFlagAccumulate) == 0) {
+        launch_fill_zero(L.film, (size_t)L.n_pixels * S.n_bins, stream);
+        if (L.steady) launch_fill_zero(L.steady, L.n_pixels, stream);
+        if (L.oow) launch_fill_zero(L.oow, L.n_pixels, stream);
+    }
+    const size_t lds = hbm_lds_bytes(block, stack_lane_bytes(S.n_tris, S.stack_depth));
+    if (short_stack(S.n_tris))
+        launch_hbm_w<uint16_t>(S, L, block, lds, stream, counts);
+    else
+        launch_hbm_w<uint32_t>(S, L, block, lds, stream, counts);
     return hipGetLastError();
 }
 
@@ -2167,6 +2411,35 @@ hipError_t launch_render_deferred(const SceneView& S, const LaunchArgs& L, uint3
     return hipGetLastError();
 }
 
+namespace {
+// film += sum over planes c of plane[c] (the partial tiles of chunks 1..),
+// in chunk order; steady and oow likewise when present
+__global__ void k_add_planes(float* __restrict__ film, float* __restrict__ steady, float* __restrict__ oow,
+                             const float* __restrict__ planes, size_t film_n, uint32_t n_pixels, uint32_t n_planes)
+{
+    const size_t per = film_n + 2ull * n_pixels;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < per; i += (size_t)gridDim.x * blockDim.x) {
+        float* dst = i < film_n ? film + i : (i < film_n + n_pixels ? steady : oow);
+        if (i >= film_n) {
+            if (!dst) continue;
+            dst += (i - film_n) % n_pixels;
+        }
+        float v = *dst;
+        for (uint32_t c = 0; c < n_planes; ++c) v = v + planes[c * per + i];
+        *dst = v;
+    }
+}
+}  // namespace
+
+hipError_t launch_add_planes(const LaunchArgs& L, uint32_t words, hipStream_t stream)
+{
+    const size_t n = (size_t)L.n_pixels * words + 2ull * L.n_pixels;
+    const unsigned g = (unsigned)std::min<size_t>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL(k_add_planes, dim3(g), dim3(256), 0, stream, L.film, L.steady, L.oow, L.chunk_scratch,
+                       (size_t)L.n_pixels * words, L.n_pixels, L.chunks - 1);
+    return hipGetLastError();
+}
+
 // Sample chunks of the deferred form: a tile with more samples than one sort
 // batch (kSortPerLane * block) is split into at most kMaxChunks chunks of
 // whole batches, one workgroup each (measured on the confocal workload, 4096
@@ -2185,31 +2458,57 @@ uint32_t deferred_chunks(uint32_t spp, uint32_t block, uint32_t* chunk_spp)
 
 hipError_t launch_backward(const SceneView& S, const LaunchArgs& L, uint32_t block, int max_cont, hipStream_t stream)
 {
+    const bool fixed = L.g_fixed != nullptr;
     const size_t lds = backward_lds_bytes(L.tile_pixels, S.n_bins, block, stack_lane_bytes(S.n_tris, S.stack_depth),
-                                          L.primal != nullptr);
-    if (short_stack(S.n_tris))
-        launch_backward_w<uint16_t>(S, L, block, max_cont, lds, stream);
-    else
-        launch_backward_w<uint32_t>(S, L, block, max_cont, lds, stream);
+                                          L.primal != nullptr, fixed);
+    if (short_stack(S.n_tris)) {
+        if (fixed) launch_backward_w<uint16_t, GradFixed>(S, L, block, max_cont, lds, stream);
+        else launch_backward_w<uint16_t, GradF64>(S, L, block, max_cont, lds, stream);
+    } else {
+        if (fixed) launch_backward_w<uint32_t, GradFixed>(S, L, block, max_cont, lds, stream);
+        else launch_backward_w<uint32_t, GradF64>(S, L, block, max_cont, lds, stream);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchTables& B, uint32_t groups, uint32_t block, uint32_t stack_depth,
-                        bool short_links, bool deferred, hipStream_t stream)
+hipError_t launch_render_fixed(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream)
+{
+    const size_t lds = fixed_lds_bytes(L.tile_pixels, S.n_bins, block, stack_lane_bytes(S.n_tris, S.stack_depth));
+    const dim3 grid(tiles_of(L));
+    if (short_stack(S.n_tris))
+        hipLaunchKernelGGL((k_render_fixed<uint16_t>), grid, dim3(block), lds, stream, S, L);
+    else
+        hipLaunchKernelGGL((k_render_fixed<uint32_t>), grid, dim3(block), lds, stream, S, L);
+    return hipGetLastError();
+}
+
+namespace {
+__global__ void k_fixed_to_f32(const unsigned long long* __restrict__ s, float* __restrict__ d, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        d[i] = (float)from_fixed(s[2 * i], s[2 * i + 1]);
+}
+}  // namespace
+
+hipError_t launch_fixed_to_f32(const unsigned long long* src, float* dst, size_t n, hipStream_t stream)
+{
+    const unsigned g = (unsigned)std::min<size_t>(1024, (n + 255) / 256 + 1);
+    hipLaunchKernelGGL(k_fixed_to_f32, dim3(g), dim3(256), 0, stream, src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchTables& B, uint32_t groups, uint32_t block, uint32_t stack_depth, bool short_links,
+                        bool deferred, hipStream_t stream)
 {
     hipLaunchKernelGGL(k_reset_cursor, dim3(1), dim3(64), 0, stream, B.cursor);
     const size_t lds = batch_lds_bytes(B.film_words, block, stack_depth * (short_links ? 2u : 4u), deferred);
-    if (short_links)
-        launch_batch_w<uint16_t>(B, groups, block, lds, deferred, stream);
-    else
-        launch_batch_w<uint32_t>(B, groups, block, lds, deferred, stream);
-    return hipGetLastError();
-}
-
-hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t stream)
-{
-    const unsigned g = (unsigned)std::min<size_t>(1024, (n + 255) / 256 + 1);
-    hipLaunchKernelGGL(k_zero_u32, dim3(g), dim3(256), 0, stream, p, n);
+    if (short_links) {
+        if (deferred) hipLaunchKernelGGL((k_batch<true, uint16_t>), dim3(groups), dim3(block), lds, stream, B);
+        else hipLaunchKernelGGL((k_batch<false, uint16_t>), dim3(groups), dim3(block), lds, stream, B);
+    } else {
+        if (deferred) hipLaunchKernelGGL((k_batch<true, uint32_t>), dim3(groups), dim3(block), lds, stream, B);
+        else hipLaunchKernelGGL((k_batch<false, uint32_t>), dim3(groups), dim3(block), lds, stream, B);
+    }
     return hipGetLastError();
 }
 

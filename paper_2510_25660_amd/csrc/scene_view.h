@@ -86,6 +86,7 @@ constexpr uint32_t kFlagPixelCentre = 1u << 0;
 constexpr uint32_t kFlagAccumulate = 1u << 1;
 constexpr uint32_t kFlagFrozen = 1u << 2;
 constexpr uint32_t kFlagNlosArea = 1u << 3;
+constexpr uint32_t kFlagDeterministic = 1u << 4;
 
 // One next-event contribution of the recording build (32 bytes; the layout
 // of trhip_record): the path's pixel or scan point and sample index, the
@@ -107,9 +108,9 @@ struct LaunchArgs {
     uint32_t tile_pixels, n_pixels;
     uint32_t chunks;            // sample chunks per tile (deferred form), one workgroup each
     uint32_t chunk_spp;         // samples per chunk
-    float* chunk_scratch;       // chunks > 1: partial tiles, [tile][chunk][tile_pixels * words + 2 * tile_pixels]
-    uint32_t* tile_count;       // chunks > 1: finished chunks per tile (zero between launches)
+    float* chunk_scratch;       // chunks > 1: partial films of chunks 1.., [chunk - 1][n_pixels * words + 2 * n_pixels]
     float norm;                 // 1 / norm_spp
+    uint32_t norm_spp;          // the film's divisor N
     const float* albedo;        // evaluation albedo (caller order)
     const float* rough_eval;    // evaluation roughness
     const float* rough_sample;  // sampling roughness (== rough_eval unless frozen)
@@ -119,6 +120,7 @@ struct LaunchArgs {
     const float* grad_film;     // backward
     double* g_alb;
     double* g_rough;
+    unsigned long long* g_fixed;  // deterministic backward: fixed-point sums [2][n_tris][2] (else NULL)
     float* primal;
     const float* tan_albedo;    // forward mode: direction of the albedo (caller order), may be NULL
     const float* tan_rough;     // forward mode: direction of the roughness, may be NULL

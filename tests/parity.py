@@ -2,9 +2,12 @@
 import numpy as np
 
 # Floating-point bar: 1e-4 relative on every pixel-bin holding at least 1e-3
-# of the film's peak; the set of non-zero bins must match exactly (a bin is
-# non-zero iff some contribution landed in it, so this compares the bin
-# indices of all contributions).
+# of the film's peak, and the set of non-zero bins must match exactly.  On
+# films this is necessary, not sufficient, for identical bin indices: a
+# contribution moved between two bins that both hold others would pass.  The
+# bin of every single contribution is compared by tests/test_gpu_records.py,
+# which diffs the recording build's (pixel, sample, vertex, bin, value, time)
+# records against the oracle's.
 REL_TOL = 1e-4
 PEAK_FRACTION = 1e-3
 # Every other bin (a sum of a few FP32 terms, added in LDS in arbitrary

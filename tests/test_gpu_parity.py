@@ -175,8 +175,8 @@ def test_accumulate_split_ranges(tr):
 
 
 def test_kernel_forms_agree(tr):
-    """Path-per-lane and wavefront forms give the same film (same paths,
-    FP32 sums in a different order) with identical non-zero bins."""
+    """Path-per-lane, deferred and wavefront forms give the same film (same
+    paths, FP32 sums in a different order) with identical non-zero bins."""
     sc = scenes.large_scene(cells=32, sphere_freq=5, grid=3, width=48, height=40, n_bins=512, bin_width=0.01,
                             spp=8)
     _announce("path vs deferred vs wavefront")

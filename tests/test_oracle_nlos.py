@@ -1,5 +1,8 @@
 """Pins of the oracle's NLOS area sampling (confocal, Sec. 4.5): the hidden
-vertex drawn uniformly by area and connected to the scan point.
+vertex drawn on the triangles off the relay wall's plane, each with a
+probability proportional to its area times its squared geometry term
+towards the mean scan point of the scan point's region (plus a floor), the
+point uniform within it, and connected to the scan point.
 
 * A square plane z = d centred in front of the scan point: every OPL bin
   whose radius stays inside the square's inscribed circle receives the disk
