@@ -480,6 +480,10 @@ trhip_status choose_shape(const trhip_scene* s, const trhip_render_desc* r, Kind
         return t;
     };
     uint32_t tp = r->tile_pixels;
+    // Film in HBM on a scene too large for an XCD's L2: 64-lane workgroups
+    // of one pixel (for >= 64 spp), whose tiles the 8 x 8 pixel-block order
+    // keeps together (1M-triangle scene: +8.5 % over 256 lanes).
+    if (kind == Kind::PathHbm && !r->block_size && !r->tile_pixels && !trhip::short_stack(s->view.n_tris)) bs = 64;
     if (!tp) {
         tp = tile_for(bs);
         // The path-per-lane kernel holds kPathWavesPerSimd waves per SIMD by
@@ -508,15 +512,22 @@ trhip_status choose_shape(const trhip_scene* s, const trhip_render_desc* r, Kind
 // most first rays leave the scene (confocal NLOS: +25%) and costs when
 // nearly all of them hit (closed pinhole scenes: -28%), so the automatic
 // choice follows the sensor; the wavefront form is never faster here.
-// Film length from which the path form keeps the film in HBM (no LDS film).
-constexpr uint32_t kHbmFilmBins = 0xffffffffu;
+// Film length from which the path form keeps the film in HBM (no LDS film)
+// on scenes too large for 16-bit stack links: there a pixel's LDS row of
+// 2 KB or more next to the deep 32-bit stacks is what limits the workgroups
+// per CU (1M-triangle scene: 1,024 bins 256 -> 366 Mpath-samples/s, 512
+// bins 297 -> 367); on small scenes the LDS film is as fast or faster (box
+// room, 512 bins: 965 against 881).
+constexpr uint32_t kHbmFilmBins = 512;
+
+bool hbm_film(const trhip_scene* s) { return s->view.n_bins >= kHbmFilmBins && !trhip::short_stack(s->view.n_tris); }
 
 // histogram: a time histogram (the phasor film keeps its tile film in LDS)
 Kind forward_kind(const trhip_scene* s, const trhip_render_desc* r, bool histogram = true)
 {
     if (r->flags & TRHIP_FLAG_DETERMINISTIC) return Kind::PathFixed;
     if (r->kernel == TRHIP_KERNEL_PATH || (r->kernel == TRHIP_KERNEL_AUTO && s->view.sensor != TRHIP_SENSOR_CONFOCAL))
-        return histogram && s->view.n_bins >= kHbmFilmBins ? Kind::PathHbm : Kind::Path;
+        return histogram && hbm_film(s) ? Kind::PathHbm : Kind::Path;
     if (r->kernel == TRHIP_KERNEL_WAVEFRONT) return Kind::Wavefront;
     if (r->kernel == TRHIP_KERNEL_DEFERRED) return Kind::Deferred;
     if (s->view.sensor != TRHIP_SENSOR_CONFOCAL) return Kind::Path;

@@ -253,3 +253,33 @@ def test_deferred_sample_chunks(tr, oracle_mod):
     assert ((a != 0) == (b != 0)).all()
     np.testing.assert_allclose(b, a, rtol=1e-5, atol=0)
     np.testing.assert_allclose(st2.cpu().numpy(), st.cpu().numpy(), rtol=1e-5)
+
+
+def test_hbm_film_accumulate_and_oracle(tr, oracle_mod):
+    """A scene above the 16-bit link limit with a long film takes the path
+    form with the film in HBM (float atomics, no LDS film): two accumulated
+    sample ranges equal one render, and sampled pixels equal the oracle's
+    film, steady image and out-of-window mass."""
+    import torch
+    sc = scenes.large_scene(cells=128, sphere_freq=8, grid=3, width=48, height=40, n_bins=512, bin_width=0.01,
+                            spp=8)
+    assert sc.n_tris > 32768
+    _announce(f"hbm film nt={sc.n_tris} 48x40x512")
+    with tr.upload(sc) as dev:
+        st, film, oow = tr.render_transient(dev, return_oow=True)
+        st2, film2, oow2 = tr.render_transient(dev, spp=4, norm_spp=8, return_oow=True)
+        tr.render_transient(dev, spp=4, sample_offset=4, norm_spp=8, accumulate=True, film=film2, steady=st2,
+                            oow=oow2)
+        torch.cuda.synchronize()
+        a, b = film.cpu().numpy(), film2.cpu().numpy()
+        assert ((a != 0) == (b != 0)).all()
+        np.testing.assert_allclose(b, a, rtol=2e-6, atol=1e-9)
+        np.testing.assert_allclose(st2.cpu().numpy(), st.cpu().numpy(), rtol=2e-6)
+        g_film = a.reshape(sc.n_pixels, sc.n_bins)
+        g_st, g_oow = st.cpu().numpy().ravel(), oow.cpu().numpy().ravel()
+    pix = np.sort(np.random.default_rng(9).choice(sc.n_pixels, 48, replace=False)).astype(np.int32)
+    o_film, o_st, o_oow = oracle_mod.Oracle(sc).render(pixels=pix)
+    compare_films(g_film[pix], o_film)
+    compare_vec(g_st[pix], o_st, what="steady")
+    if np.abs(o_oow).max() > 0:
+        compare_vec(g_oow[pix], o_oow, what="oow")
