@@ -300,6 +300,26 @@ trhip_status trhip_render_transient(trhip_scene* scene, const trhip_render_desc*
                                     float* steady, float* oow, void* stream);
 
 /*
+ * trhip_render_transient for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, same render (same paths, same film up to the
+ * rounding of the sums), and no allocation of any kind: where the kernel
+ * needs scratch memory (the deferred form's sample chunks keep the partial
+ * films of all but the first sample chunk of a pixel), it uses a 32 MiB
+ * device array that the library holds on every GPU it runs on until the
+ * process ends, instead of the buffer trhip_render_transient allocates on
+ * first use.  Renders whose scratch would exceed 32 MiB return
+ * TRHIP_ERR_UNSUPPORTED (the confocal 64 x 64 scan with 512 bins at 4096 spp
+ * needs about 8.4 MB).
+ * All calls on one GPU share that array: calls that overlap in time on one
+ * GPU (other streams, other threads) race and must be serialised by the
+ * caller.  The scene's device must be the current one (else INVALID_ARG).
+ * Errors: as trhip_render_transient.
+ */
+trhip_status trhip_render_transient_noalloc(trhip_scene* scene, const trhip_render_desc* render, float* film,
+                                            float* steady, float* oow, void* stream);
+
+/*
  * Backward mode (Sec. 4.4, Eqs. 15-17): given grad_film = dL/dfilm (DEVICE,
  * same layout as the film), writes dL/d(albedo) and dL/d(roughness) per
  * triangle (DEVICE float[n_triangles], overwritten; roughness gradients of

@@ -31,7 +31,7 @@ EXPORTED_SYMBOLS = (
     "trhip_render_transient_backward", "trhip_render_transient_counted", "trhip_status_string",
     "trhip_last_error", "trhip_version", "trhip_batch_create", "trhip_batch_render", "trhip_batch_get_info",
     "trhip_batch_destroy", "trhip_poisson_noise", "trhip_render_phasor", "trhip_render_transient_tangent",
-    "trhip_render_transient_records", "trhip_numerics_probe",
+    "trhip_render_transient_records", "trhip_numerics_probe", "trhip_render_transient_noalloc",
 )
 
 PROBES = {"sincos2pi": 0, "log1m": 1, "philox": 2, "div": 3, "sqrt": 4}
@@ -184,6 +184,8 @@ def lib():
         L.trhip_render_transient_records.argtypes = [vp, C.POINTER(RenderDesc), vp, vp, C.c_uint64,
                                                      C.POINTER(C.c_uint64), vp, vp, vp, vp]
         L.trhip_render_transient_records.restype = C.c_int
+        L.trhip_render_transient_noalloc.argtypes = [vp, C.POINTER(RenderDesc), vp, vp, vp, vp]
+        L.trhip_render_transient_noalloc.restype = C.c_int
         L.trhip_numerics_probe.argtypes = [C.c_int32, vp, vp, C.c_uint64, C.c_uint64, vp]
         L.trhip_numerics_probe.restype = C.c_int
         L.trhip_poisson_noise.argtypes = [vp, vp, C.c_uint64, C.c_float, C.c_uint64, vp]

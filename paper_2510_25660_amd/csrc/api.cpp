@@ -740,6 +740,101 @@ trhip_status trhip_render_transient(trhip_scene* scene, const trhip_render_desc*
     return TRHIP_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// allocation-free forward render
+// ---------------------------------------------------------------------------
+// Scratch of trhip_render_transient_noalloc: the deferred form's partial
+// tiles and per-tile counters, in a device array that every GPU the library
+// runs on holds from the library's load until the process ends.  Host code
+// never uses the array's name as an address: each device's copy is looked up
+// once with hipGetSymbolAddress and kept in g_scratch_ptr.
+constexpr size_t kStaticScratchBytes = 32ull << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mutex;
+std::unordered_map<int, unsigned char*> g_scratch_ptr;  // device -> its copy of `scratch`
+
+// with `device` current
+hipError_t static_scratch(int device, unsigned char** out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    const auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<unsigned char*>(p);
+    *out = static_cast<unsigned char*>(p);
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+trhip_status trhip_render_transient_noalloc(trhip_scene* scene, const trhip_render_desc* render, float* film,
+                                            float* steady, float* oow, void* stream)
+{
+    trhip_status st = check_scene(scene);
+    if (st != TRHIP_OK) return st;
+    if ((st = validate_render(scene, render)) != TRHIP_OK) return st;
+    if (!film) return fail(TRHIP_ERR_INVALID_ARG, "film is NULL");
+    const Kind kind = forward_kind(scene, render);
+    uint32_t tile = 0, block = 0;
+    if ((st = choose_shape(scene, render, kind, &tile, &block)) != TRHIP_OK) return st;
+    trhip::LaunchArgs L;
+    fill_launch(scene, render, tile, &L);
+    L.film = film;
+    L.steady = steady;
+    L.oow = oow;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    switch (kind) {
+    case Kind::PathFixed: e = trhip::launch_render_fixed(scene->view, L, block, s); break;
+    case Kind::PathHbm: e = trhip::launch_render_hbm(scene->view, L, block, s, nullptr); break;
+    case Kind::Wavefront: e = trhip::launch_render_wavefront(scene->view, L, block, s, nullptr); break;
+    case Kind::Deferred: {
+        uint32_t chunk_spp = L.spp;
+        const uint32_t chunks = trhip::deferred_chunks(L.spp, block, &chunk_spp);
+        const uint32_t words = scene->view.n_bins;
+        if (chunks > 1) {
+            const size_t need = chunk_scratch_floats(L, chunks, words) * sizeof(float);
+            if (need > kStaticScratchBytes)
+                return fail(TRHIP_ERR_UNSUPPORTED,
+                            "this render needs %zu bytes of scratch; the allocation-free render holds %zu "
+                            "(use trhip_render_transient, or fewer samples per pixel per call)",
+                            need, kStaticScratchBytes);
+            int dev = -1;
+            e = hipGetDevice(&dev);
+            if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+            if (dev != scene->device)
+                return fail(TRHIP_ERR_INVALID_ARG, "the scene lives on device %d, device %d is current", scene->device,
+                            dev);
+            unsigned char* base = nullptr;
+            e = static_scratch(dev, &base);
+            if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+            L.chunks = chunks;
+            L.chunk_spp = chunk_spp;
+            L.chunk_scratch = reinterpret_cast<float*>(base);
+        }
+        // every plane of the scratch is written in full before it is read
+        e = trhip::launch_render_deferred(scene->view, L, block, s, nullptr);
+        if (e == hipSuccess && L.chunks > 1) e = trhip::launch_add_planes(L, words, s);
+        break;
+    }
+    default: e = trhip::launch_render(scene->view, L, block, s, nullptr);
+    }
+    if (e != hipSuccess) return hip_fail(e, "render launch");
+    return TRHIP_OK;
+}
+
 static_assert(TRHIP_MAX_FREQS == trhip::kMaxFreq, "phasor frequency limit");
 
 trhip_status trhip_render_phasor(trhip_scene* scene, const trhip_render_desc* render, const float* freqs,
