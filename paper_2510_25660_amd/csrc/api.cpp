@@ -466,7 +466,9 @@ uint32_t lane_stack_bytes(const trhip_scene* s) { return trhip::stack_lane_bytes
 trhip_status choose_shape(const trhip_scene* s, const trhip_render_desc* r, Kind kind, uint32_t* tile,
                           uint32_t* block, uint32_t words = 0)
 {
-    const uint32_t T = words ? words : s->view.n_bins, depth = lane_stack_bytes(s);
+    const uint32_t T = words ? words : s->view.n_bins;
+    const uint32_t depth = kind == Kind::PathHbm ? trhip::hbm_stack_lane_bytes(s->view.n_tris, s->view.stack_depth)
+                                                 : lane_stack_bytes(s);
     uint32_t bs = r->block_size ? r->block_size : kMaxBlock;
     if (!r->block_size) {
         // small per-tile work: narrower groups keep more of them in flight

@@ -40,6 +40,22 @@ inline uint32_t stack_lane_bytes(uint32_t n_tris, uint32_t stack_depth)
     return stack_depth * (short_stack(n_tris) ? 2u : 4u);
 }
 
+// The HBM-film path form keeps the first kSplitStackLds words of a 32-bit
+// stack in LDS and the deeper ones in per-lane scratch memory, for trees of
+// at most kSplitStackLds + kSplitStackDeep levels (deeper trees keep the
+// whole stack in LDS).  LDS bytes of one lane's stack in that form:
+constexpr uint32_t kSplitStackLds = 16;
+constexpr uint32_t kSplitStackDeep = 48;
+inline bool split_stack(uint32_t n_tris, uint32_t stack_depth)
+{
+    return !short_stack(n_tris) && stack_depth <= kSplitStackLds + kSplitStackDeep;
+}
+inline uint32_t hbm_stack_lane_bytes(uint32_t n_tris, uint32_t stack_depth)
+{
+    return split_stack(n_tris, stack_depth) ? 4u * (stack_depth < kSplitStackLds ? stack_depth : kSplitStackLds)
+                                            : stack_lane_bytes(n_tris, stack_depth);
+}
+
 // entries of the counting build's output (TRHIP_COUNT_N)
 constexpr int kWorkCounters = 10;
 

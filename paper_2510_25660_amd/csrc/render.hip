@@ -244,6 +244,44 @@ struct Tally<kCounting> {
 __device__ __forceinline__ int link_of(uint32_t w) { return (int)w; }
 __device__ __forceinline__ int link_of(uint16_t w) { return (int)(int16_t)w; }
 
+// A lane's traversal stack: one BVH link per level, word i at p[i * stride]
+// in LDS.  16-bit words also select buffer loads for nodes and triangles
+// (their offsets fit in 32 bits).
+template <class W>
+struct LdsStack {
+    static constexpr bool kBuf = sizeof(W) == 2;
+    W* p;
+    int stride;
+    __device__ __forceinline__ int cap(const SceneView& S) const { return (int)S.stack_depth; }
+    __device__ __forceinline__ void put(int sp, int link) { p[sp * stride] = (W)link; }
+    __device__ __forceinline__ int get(int sp) const { return link_of(p[sp * stride]); }
+};
+
+// The first kLds words in LDS, the deeper ones in a per-lane array in
+// scratch memory.  A traversal's stack stays far below the tree's depth (the
+// far children pending at one time), so the deep words are rarely touched,
+// while the LDS a wave holds shrinks and more waves fit on a CU.  For trees
+// of at most kLds + kDeep levels; cap() keeps every access inside both parts
+// for any tree.
+template <int kLds, int kDeep>
+struct SplitStack {
+    static constexpr bool kBuf = false;
+    // The LDS part carries its address space in its type, so that the two
+    // parts are never read through one generic (flat) pointer.
+    __attribute__((address_space(3))) uint32_t* p;
+    int stride;
+    int* deep;  // kDeep words, a local array of the kernel (scratch)
+    __device__ __forceinline__ int cap(const SceneView& S) const { return min((int)S.stack_depth, kLds + kDeep); }
+    __device__ __forceinline__ void put(int sp, int link)
+    {
+        if (sp < kLds)
+            p[sp * stride] = (uint32_t)link;
+        else
+            deep[sp - kLds] = link;
+    }
+    __device__ __forceinline__ int get(int sp) const { return sp < kLds ? (int)p[sp * stride] : deep[sp - kLds]; }
+};
+
 // Closest accepted triangle: smallest t, then smallest caller index.  A
 // triangle is accepted at t only if t is not before the entry of its own
 // padded box (the box stored for it in its parent), which makes the result
@@ -294,15 +332,15 @@ __device__ __forceinline__ void closest_begin(const SceneView& S, const Ray& r, 
 }
 
 // Visits one internal node; returns true once the traversal has finished.
-template <class W, class TallyT>
-__device__ __forceinline__ bool closest_step(const SceneView& S, const Ray& r, int exclude, W* stk, int stride,
+template <class St, class TallyT>
+__device__ __forceinline__ bool closest_step(const SceneView& S, const Ray& r, int exclude, St& stk,
                                              ClosestTrav& c, TallyT& tally)
 {
     if (c.visits >= S.n_tris) return true;
     ++c.visits;
     tally.add(kTallyNodes);
     tally.wave(kTallyWaveNodes);
-    constexpr bool kBuf = sizeof(W) == 2;
+    constexpr bool kBuf = St::kBuf;
     const NodeRec nd = load_node<kBuf>(S, c.node);
     const float4 a = nd.a, b = nd.b, d = nd.d, l = nd.l;
     const int c0 = __float_as_int(l.x), c1 = __float_as_int(l.y);
@@ -321,9 +359,9 @@ __device__ __forceinline__ bool closest_step(const SceneView& S, const Ray& r, i
     }
     h0 = h0 && tn0 <= c.h.t;
     h1 = h1 && tn1 <= c.h.t;
-    if (h0 && h1 && c.sp < (int)S.stack_depth) {
+    if (h0 && h1 && c.sp < stk.cap(S)) {
         const bool first0 = tn0 <= tn1;
-        stk[c.sp * stride] = (W)(first0 ? c1 : c0);
+        stk.put(c.sp, first0 ? c1 : c0);
         ++c.sp;
         c.node = first0 ? c0 : c1;
     } else if (h0) {
@@ -333,17 +371,17 @@ __device__ __forceinline__ bool closest_step(const SceneView& S, const Ray& r, i
     } else {
         if (c.sp == 0) return true;
         --c.sp;
-        c.node = link_of(stk[c.sp * stride]);
+        c.node = stk.get(c.sp);
     }
     return false;
 }
 
-template <class W, class TallyT>
-__device__ Hit closest_hit(const SceneView& S, const Ray& r, int exclude, W* stk, int stride, TallyT& tally)
+template <class St, class TallyT>
+__device__ Hit closest_hit(const SceneView& S, const Ray& r, int exclude, St& stk, TallyT& tally)
 {
     ClosestTrav c;
     closest_begin(S, r, exclude, c, tally);
-    while (!closest_step(S, r, exclude, stk, stride, c, tally)) {
+    while (!closest_step(S, r, exclude, stk, c, tally)) {
     }
     return c.h;
 }
@@ -360,9 +398,8 @@ __device__ __forceinline__ bool leaf_blocks(const SceneView& S, const Ray& r, in
 }
 
 // any accepted triangle other than `exclude` with t < tmax
-template <class W, class TallyT>
-__device__ bool occluded(const SceneView& S, const Ray& r, int exclude, float tmax, W* stk, int stride,
-                         TallyT& tally)
+template <class St, class TallyT>
+__device__ bool occluded(const SceneView& S, const Ray& r, int exclude, float tmax, St& stk, TallyT& tally)
 {
     tally.add(kTallyShadow);
     if (S.root < 0) {
@@ -372,8 +409,8 @@ __device__ bool occluded(const SceneView& S, const Ray& r, int exclude, float tm
     }
     int node = S.root;
     int sp = 0;
-    constexpr bool kBuf = sizeof(W) == 2;
-    const int max_sp = (int)S.stack_depth;
+    constexpr bool kBuf = St::kBuf;
+    const int max_sp = stk.cap(S);
     for (uint32_t visits = 0; visits < S.n_tris; ++visits) {
         const NodeRec nd = load_node<kBuf>(S, node);
         const float4 a = nd.a, b = nd.b, c = nd.d, l = nd.l;
@@ -394,7 +431,7 @@ __device__ bool occluded(const SceneView& S, const Ray& r, int exclude, float tm
             h1 = false;
         }
         if (h0 && h1 && sp < max_sp) {
-            stk[sp * stride] = (W)c1;
+            stk.put(sp, c1);
             ++sp;
             node = c0;
         } else if (h0) {
@@ -404,7 +441,7 @@ __device__ bool occluded(const SceneView& S, const Ray& r, int exclude, float tm
         } else {
             if (sp == 0) return false;
             --sp;
-            node = link_of(stk[sp * stride]);
+            node = stk.get(sp);
         }
     }
     return false;
@@ -804,9 +841,9 @@ __device__ __forceinline__ void shade_vertex(const SceneView& S, const LaunchArg
 // bin, d log f factors of the connection) and every continuation (triangle,
 // d log f factors of the sampled direction).  Triangles are caller indices;
 // -1 marks a medium vertex.
-template <class Sink, class W, class TallyT>
+template <class Sink, class St, class TallyT>
 __device__ void continue_path(const SceneView& S, const LaunchArgs& L, uint32_t pix, uint32_t sample, PathState& ps,
-                              Hit h, W* stk, int stride, Sink& sink, TallyT& tally)
+                              Hit h, St& stk, Sink& sink, TallyT& tally)
 {
     const int vmax = last_vertex(S, L);
     while (true) {
@@ -819,7 +856,7 @@ __device__ void continue_path(const SceneView& S, const LaunchArgs& L, uint32_t 
         shade_vertex<Sink::kWantsGradients>(S, L, pix, sample, ps, h, t_hit, med, nee, cont, tally);
         bool blocked = true;
         if (nee.valid) {
-            blocked = occluded(S, make_ray(nee.so, nee.sd), nee.excl, nee.tmax, stk, stride, tally);
+            blocked = occluded(S, make_ray(nee.so, nee.sd), nee.excl, nee.tmax, stk, tally);
             if (!blocked) {
                 tally.add(kTallyContrib);
                 tally.record(L, pix, sample, v, nee.k, nee.c, nee.bin, nee.tof);
@@ -831,31 +868,31 @@ __device__ void continue_path(const SceneView& S, const LaunchArgs& L, uint32_t 
         // only if the first segment is unoccluded: the shadow test back to
         // the scan point runs along it
         if (v == 1 && (L.flags & kFlagNlosArea)) {
-            if (!nee.valid) blocked = occluded(S, make_ray(nee.so, nee.sd), nee.excl, nee.tmax, stk, stride, tally);
+            if (!nee.valid) blocked = occluded(S, make_ray(nee.so, nee.sd), nee.excl, nee.tmax, stk, tally);
             if (blocked) break;
         }
         if (cont.k >= 0) sink.continuation(v, cont.k, cont.g_alb, cont.g_rough);
         if (ps.v > vmax) break;
-        h = closest_hit(S, make_ray(ps.o, ps.d), ps.prev, stk, stride, tally);
+        h = closest_hit(S, make_ray(ps.o, ps.d), ps.prev, stk, tally);
     }
 }
 
 // Traces one whole path (Philox block 0 generation, then vertex by vertex).
-template <class Sink, class W, class TallyT>
-__device__ void trace_path(const SceneView& S, const LaunchArgs& L, uint32_t pix, uint32_t sample, W* stk,
-                           int stride, Sink& sink, TallyT& tally)
+template <class Sink, class St, class TallyT>
+__device__ void trace_path(const SceneView& S, const LaunchArgs& L, uint32_t pix, uint32_t sample, St& stk,
+                           Sink& sink, TallyT& tally)
 {
     tally.add(kTallyDraws);
     PathState ps;
     if (L.flags & kFlagNlosArea) {
         Hit h;
-        if (begin_area(S, L, pix, sample, ps, h)) continue_path(S, L, pix, sample, ps, h, stk, stride, sink, tally);
+        if (begin_area(S, L, pix, sample, ps, h)) continue_path(S, L, pix, sample, ps, h, stk, sink, tally);
         return;
     }
     begin_path(S, L, pix, sample, ps);
     if (last_vertex(S, L) < 1) return;
-    const Hit h = closest_hit(S, make_ray(ps.o, ps.d), ps.prev, stk, stride, tally);
-    continue_path(S, L, pix, sample, ps, h, stk, stride, sink, tally);
+    const Hit h = closest_hit(S, make_ray(ps.o, ps.d), ps.prev, stk, tally);
+    continue_path(S, L, pix, sample, ps, h, stk, sink, tally);
 }
 
 // ---------------------------------------------------------------------------
@@ -983,9 +1020,9 @@ struct FixedFilmSink {
 // Deterministic form of render_tile (path per lane): the tile's film,
 // steady and out-of-window sums in fixed point in LDS ([TP][T][2], [TP][2],
 // [TP][2] words), each written as sum / norm_spp rounded to FP32.
-template <class W, class TallyT>
+template <class St, class TallyT>
 __device__ __forceinline__ void render_tile_fixed(const SceneView& S, const LaunchArgs& L, uint32_t p0,
-                                                  unsigned long long* q, W* stk, int stride, TallyT& tally)
+                                                  unsigned long long* q, St& stk, TallyT& tally)
 {
     const uint32_t T = S.n_bins;
     const uint32_t TP = L.tile_pixels;
@@ -1000,7 +1037,7 @@ __device__ __forceinline__ void render_tile_fixed(const SceneView& S, const Laun
         const uint32_t pl = w / L.spp;
         const uint32_t s = w - pl * L.spp;
         FixedFilmSink sink{qfilm + 2ull * pl * T, qsteady + 2 * pl, qoow + 2 * pl};
-        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, sink, tally);
+        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, sink, tally);
     }
     __syncthreads();
     const bool acc = (L.flags & kFlagAccumulate) != 0;
@@ -1028,9 +1065,9 @@ __device__ __forceinline__ void render_tile_fixed(const SceneView& S, const Laun
 // LDS film rows (zeroed here), paths traced one per lane, then one
 // coalesced write (or accumulate) of the tile to HBM.  lds_film holds
 // tile_pixels * n_bins + 2 * tile_pixels floats; stk is the lane's stack.
-template <class W, class TallyT>
+template <class St, class TallyT>
 __device__ __forceinline__ void render_tile(const SceneView& S, const LaunchArgs& L, uint32_t p0, float* lds_film,
-                                            const float* freq, W* stk, int stride, TallyT& tally)
+                                            const float* freq, St& stk, TallyT& tally)
 {
     const uint32_t T = film_words(S, L);
     const uint32_t TP = L.tile_pixels;
@@ -1057,7 +1094,7 @@ __device__ __forceinline__ void render_tile(const SceneView& S, const LaunchArgs
             sink.steady = 0.0f;
             sink.oow = 0.0f;
         }
-        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, sink, tally);
+        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, sink, tally);
     }
     if (cur != 0xffffffffu) {
         atomicAdd(tsteady + cur, sink.steady);
@@ -1105,9 +1142,9 @@ struct HbmFilmSink {
     __device__ __forceinline__ void continuation(int, int, float, float) {}
 };
 
-template <class W, class TallyT>
-__device__ __forceinline__ void render_tile_hbm(const SceneView& S, const LaunchArgs& L, uint32_t p0, W* stk,
-                                                int stride, TallyT& tally)
+template <class St, class TallyT>
+__device__ __forceinline__ void render_tile_hbm(const SceneView& S, const LaunchArgs& L, uint32_t p0, St& stk,
+                                                TallyT& tally)
 {
     const uint32_t T = S.n_bins;
     const uint32_t npix = min(L.tile_pixels, L.n_pixels - p0);
@@ -1129,7 +1166,7 @@ __device__ __forceinline__ void render_tile_hbm(const SceneView& S, const Launch
             sink.steady = 0.0f;
             sink.oow = 0.0f;
         }
-        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, sink, tally);
+        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, sink, tally);
     }
     flush();
 }
@@ -1226,9 +1263,9 @@ constexpr int kRefill = 32;
 // with a reserved buffer slot (released if it leaves the scene), so the
 // buffer never overflows; a wave returns once it can start no ray and has
 // none in flight.  No barrier inside.
-template <class W, class TallyT>
+template <class St, class TallyT>
 __device__ __forceinline__ void trace_first_hits(const SceneView& S, const LaunchArgs& L, uint32_t p0,
-                                                 const DeferredLds& fh, uint32_t nvalid, W* stk, int stride,
+                                                 const DeferredLds& fh, uint32_t nvalid, St& stk,
                                                  TallyT& tally)
 {
     const uint32_t cap = 2 * blockDim.x;
@@ -1260,7 +1297,7 @@ __device__ __forceinline__ void trace_first_hits(const SceneView& S, const Launc
         }
         if (!__any(active)) break;
         while (active) {
-            if (closest_step(S, r, ps.prev, stk, stride, c, tally)) {
+            if (closest_step(S, r, ps.prev, stk, c, tally)) {
                 float t_hit;
                 bool med;
                 if (resolve_event(S, ps, c.h, t_hit, med)) {
@@ -1282,10 +1319,10 @@ __device__ __forceinline__ void trace_first_hits(const SceneView& S, const Launc
 // kArea: NLOS area sampling, whose first vertex needs no traversal; the
 // batch is sorted by area_cell and each lane follows the sorted paths
 // directly (phase 1b and 2 in one).
-template <bool kArea, class W, class TallyT>
+template <bool kArea, class St, class TallyT>
 __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const LaunchArgs& L, uint32_t tile,
                                                      uint32_t chunk, float* lds_film, const float* freq,
-                                                     const DeferredLds& fh, W* stk, int stride, TallyT& tally)
+                                                     const DeferredLds& fh, St& stk, TallyT& tally)
 {
     const uint32_t p0 = tile * L.tile_pixels;
     const uint32_t T = film_words(S, L);
@@ -1379,7 +1416,7 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
                 PathState ps;
                 Hit h;
                 if (begin_area(S, L, p0 + pl, sample, ps, h))
-                    continue_path(S, L, p0 + pl, sample, ps, h, stk, stride, sink, tally);
+                    continue_path(S, L, p0 + pl, sample, ps, h, stk, sink, tally);
             }
             __syncthreads();  // the next batch reuses the order
             continue;
@@ -1388,7 +1425,7 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
         // holds a block's worth (or at the end of the tile)
         const bool last_batch = base + batch >= work;
         for (;;) {
-            trace_first_hits(S, L, p0, fh, nvalid, stk, stride, tally);
+            trace_first_hits(S, L, p0, fh, nvalid, stk, tally);
             __syncthreads();
             const uint32_t n = fh.count[0];
             const bool exhausted = fh.count[2] >= nvalid;
@@ -1413,7 +1450,7 @@ __device__ __forceinline__ void render_tile_deferred(const SceneView& S, const L
                     h.t = fh.t[jj];
                     h.prim = fh.prim[jj];
                     h.sorted = fh.sorted[jj];
-                    continue_path(S, L, p0 + pl, sample, ps, h, stk, stride, sink, tally);
+                    continue_path(S, L, p0 + pl, sample, ps, h, stk, sink, tally);
                 }
                 __syncthreads();
                 if (tid == 0) {
@@ -1524,8 +1561,8 @@ k_render_deferred(SceneView S, LaunchArgs L, unsigned long long* counts)
     load_freqs(L, s_freq);
     float* after_film = lds + (size_t)TP * film_words(S, L) + 2 * TP;
     const DeferredLds fh = carve_deferred(after_film, blockDim.x);
-    W* stk = reinterpret_cast<W*>(after_film + deferred_words(blockDim.x)) + threadIdx.x;
-    render_tile_deferred<kArea>(S, Lc, tile, chunk, lds, s_freq, fh, stk, (int)blockDim.x, tally);
+    LdsStack<W> stk{reinterpret_cast<W*>(after_film + deferred_words(blockDim.x)) + threadIdx.x, (int)blockDim.x};
+    render_tile_deferred<kArea>(S, Lc, tile, chunk, lds, s_freq, fh, stk, tally);
     tally.flush(counts);
 }
 
@@ -1537,21 +1574,38 @@ __global__ void __launch_bounds__(256) k_render(SceneView S, LaunchArgs L, unsig
     const uint32_t TP = L.tile_pixels;
     __shared__ float s_freq[kMaxFreq];
     load_freqs(L, s_freq);
-    W* stk = reinterpret_cast<W*>(lds + (size_t)TP * film_words(S, L) + 2 * TP) + threadIdx.x;
-    render_tile(S, L, tile_first_pixel(S, L, TP), lds, s_freq, stk, (int)blockDim.x, tally);
+    LdsStack<W> stk{reinterpret_cast<W*>(lds + (size_t)TP * film_words(S, L) + 2 * TP) + threadIdx.x, (int)blockDim.x};
+    render_tile(S, L, tile_first_pixel(S, L, TP), lds, s_freq, stk, tally);
     tally.flush(counts);
 }
 
 // Five waves per SIMD (at most 96 VGPRs, a few spills): with no LDS film a
-// CU holds the stacks of 20 waves (1M-triangle scene: +16 % over four).
+// CU holds the whole stacks of 20 waves.
 template <int kMode, class W>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 k_render_hbm(SceneView S, LaunchArgs L, unsigned long long* counts)
 {
     Tally<kMode> tally;
     extern __shared__ float lds[];
-    W* stk = reinterpret_cast<W*>(lds) + threadIdx.x;
-    render_tile_hbm(S, L, tile_first_pixel(S, L, L.tile_pixels), stk, (int)blockDim.x, tally);
+    LdsStack<W> stk{reinterpret_cast<W*>(lds) + threadIdx.x, (int)blockDim.x};
+    render_tile_hbm(S, L, tile_first_pixel(S, L, L.tile_pixels), stk, tally);
+    tally.flush(counts);
+}
+
+// 32-bit links with the split stack: 4 KB of LDS per 64-lane workgroup, so
+// eight waves per SIMD fit (at most 64 VGPRs, more spills; 1M-triangle
+// scene: +21 % over five waves with whole stacks in LDS).
+template <int kMode>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+k_render_hbm_split(SceneView S, LaunchArgs L, unsigned long long* counts)
+{
+    Tally<kMode> tally;
+    extern __shared__ float lds[];
+    int deep[kSplitStackDeep];
+    SplitStack<(int)kSplitStackLds, (int)kSplitStackDeep> stk{
+        (__attribute__((address_space(3))) uint32_t*)(reinterpret_cast<uint32_t*>(lds) + threadIdx.x),
+        (int)blockDim.x, deep};
+    render_tile_hbm(S, L, tile_first_pixel(S, L, L.tile_pixels), stk, tally);
     tally.flush(counts);
 }
 
@@ -1562,8 +1616,8 @@ __global__ void __launch_bounds__(256) k_render_fixed(SceneView S, LaunchArgs L)
     extern __shared__ float lds[];
     const uint32_t TP = L.tile_pixels;
     unsigned long long* q = reinterpret_cast<unsigned long long*>(lds);
-    W* stk = reinterpret_cast<W*>(q + 2ull * (TP * S.n_bins + 2 * TP)) + threadIdx.x;
-    render_tile_fixed(S, L, tile_first_pixel(S, L, TP), q, stk, (int)blockDim.x, tally);
+    LdsStack<W> stk{reinterpret_cast<W*>(q + 2ull * (TP * S.n_bins + 2 * TP)) + threadIdx.x, (int)blockDim.x};
+    render_tile_fixed(S, L, tile_first_pixel(S, L, TP), q, stk, tally);
 }
 
 // ---------------------------------------------------------------------------
@@ -1581,7 +1635,8 @@ __global__ void __launch_bounds__(256) k_batch(BatchTables B)
     __shared__ uint32_t s_item;
     Tally<kPlain> tally;
     const DeferredLds fh = carve_deferred(lds + B.film_words, blockDim.x);
-    W* stk = reinterpret_cast<W*>(lds + B.film_words + (kDeferred ? deferred_words(blockDim.x) : 0)) + threadIdx.x;
+    LdsStack<W> stk{reinterpret_cast<W*>(lds + B.film_words + (kDeferred ? deferred_words(blockDim.x) : 0)) + threadIdx.x,
+                    (int)blockDim.x};
     while (true) {
         if (threadIdx.x == 0) s_item = atomicAdd(B.cursor, 1u);
         __syncthreads();
@@ -1600,11 +1655,10 @@ __global__ void __launch_bounds__(256) k_batch(BatchTables B)
         // NLOS area sampling needs no first-hit traversal to defer: such
         // scenes take the path-per-lane tile (same LDS film and stacks)
         if (kDeferred && !(args[scene].flags & kFlagNlosArea))
-            render_tile_deferred<false>(views[scene], args[scene], tile, 0u, lds, nullptr, fh, stk, (int)blockDim.x,
+            render_tile_deferred<false>(views[scene], args[scene], tile, 0u, lds, nullptr, fh, stk,
                                         tally);
         else
-            render_tile(views[scene], args[scene], tile * args[scene].tile_pixels, lds, nullptr, stk,
-                        (int)blockDim.x, tally);
+            render_tile(views[scene], args[scene], tile * args[scene].tile_pixels, lds, nullptr, stk, tally);
         __syncthreads();
     }
 }
@@ -1694,7 +1748,7 @@ __global__ void __launch_bounds__(256) k_render_wf(SceneView S, LaunchArgs L, un
     float* tsteady = lds + (size_t)TP * T;
     float* toow = tsteady + TP;
     const WfSlots w = carve_slots(toow + TP, nb);
-    W* stk = reinterpret_cast<W*>(toow + TP + (size_t)kWfWords * nb) + tid;
+    LdsStack<W> stk{reinterpret_cast<W*>(toow + TP + (size_t)kWfWords * nb) + tid, nb};
     const uint32_t p0 = tile_first_pixel(S, L, TP);
     const uint32_t npix = min(TP, L.n_pixels - p0);
     for (uint32_t i = tid; i < TP * T + 2 * TP; i += nb) lds[i] = 0.0f;
@@ -1728,7 +1782,7 @@ __global__ void __launch_bounds__(256) k_render_wf(SceneView S, LaunchArgs L, un
         for (int j = tid; j < nr; j += nb) {
             const int i = w.ray_q[j];
             const PathState ps = load_state(w, i);
-            const Hit h = closest_hit(S, make_ray(ps.o, ps.d), ps.prev, stk, nb, tally);
+            const Hit h = closest_hit(S, make_ray(ps.o, ps.d), ps.prev, stk, tally);
             float t_hit;
             bool med;
             if (resolve_event(S, ps, h, t_hit, med)) {
@@ -1780,7 +1834,7 @@ __global__ void __launch_bounds__(256) k_render_wf(SceneView S, LaunchArgs L, un
         for (int j = tid; j < ns; j += nb) {
             const int i = w.sh_q[j];
             const Ray sh = make_ray(v3(w.sox[i], w.soy[i], w.soz[i]), v3(w.sdx[i], w.sdy[i], w.sdz[i]));
-            if (!occluded(S, sh, w.sexcl[i], w.stmax[i], stk, nb, tally)) {
+            if (!occluded(S, sh, w.sexcl[i], w.stmax[i], stk, tally)) {
                 tally.add(kTallyContrib);
                 const float c = w.sc[i];
                 const int bin = w.sbin[i];
@@ -2006,8 +2060,7 @@ __global__ void __launch_bounds__(256) k_render_tangent(SceneView S, LaunchArgs 
     float* tfilm = lds;
     float* tdfilm = lds + (size_t)TP * T;
     float* tsteady = tdfilm + (size_t)TP * T;
-    W* stk = reinterpret_cast<W*>(tsteady + TP) + threadIdx.x;
-    const int stride = (int)blockDim.x;
+    LdsStack<W> stk{reinterpret_cast<W*>(tsteady + TP) + threadIdx.x, (int)blockDim.x};
     const uint32_t p0 = tile_first_pixel(S, L, TP);
     const uint32_t npix = min(TP, L.n_pixels - p0);
     for (uint32_t i = threadIdx.x; i < 2 * TP * T + TP; i += blockDim.x) lds[i] = 0.0f;
@@ -2018,7 +2071,7 @@ __global__ void __launch_bounds__(256) k_render_tangent(SceneView S, LaunchArgs 
         const uint32_t pl = w / L.spp;
         const uint32_t s = w - pl * L.spp;
         TangentSink sink{tfilm + (size_t)pl * T, tdfilm + (size_t)pl * T, L.tan_albedo, L.tan_rough, 0.0f, 0.0f};
-        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, sink, tally);
+        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, sink, tally);
         atomicAdd(tsteady + pl, sink.steady);
     }
     __syncthreads();
@@ -2048,8 +2101,8 @@ __global__ void __launch_bounds__(256) k_backward(SceneView S, LaunchArgs L)
     Acc acc(lds, S, L);
     float* tdelta = lds + Acc::kFloats;
     float* tprimal = tdelta + (size_t)TP * T;
-    W* stk = reinterpret_cast<W*>(tprimal + (want_primal ? (size_t)TP * T : 0)) + threadIdx.x;
-    const int stride = (int)blockDim.x;
+    LdsStack<W> stk{reinterpret_cast<W*>(tprimal + (want_primal ? (size_t)TP * T : 0)) + threadIdx.x,
+                    (int)blockDim.x};
     const uint32_t p0 = tile_first_pixel(S, L, TP);
     const uint32_t npix = min(TP, L.n_pixels - p0);
     const size_t base = (size_t)p0 * T;
@@ -2066,10 +2119,10 @@ __global__ void __launch_bounds__(256) k_backward(SceneView S, LaunchArgs L)
         const uint32_t s = w - pl * L.spp;
         const float* drow = tdelta + (size_t)pl * T;
         AdjointSumSink first{drow, L.norm, 0.0};
-        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, first, tally);
+        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, first, tally);
         AdjointScatterSink<Acc> second{drow, want_primal ? tprimal + (size_t)pl * T : nullptr, L.norm, first.total,
                                        0.0, &acc};
-        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, second, tally);
+        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, second, tally);
     }
     __syncthreads();
     acc.flush();
@@ -2156,8 +2209,8 @@ k_backward_stash(SceneView S, LaunchArgs L)
     Acc acc(lds, S, L);
     float* tdelta = lds + Acc::kFloats;
     float* tprimal = tdelta + (size_t)TP * T;
-    W* stk = reinterpret_cast<W*>(tprimal + (want_primal ? (size_t)TP * T : 0)) + threadIdx.x;
-    const int stride = (int)blockDim.x;
+    LdsStack<W> stk{reinterpret_cast<W*>(tprimal + (want_primal ? (size_t)TP * T : 0)) + threadIdx.x,
+                    (int)blockDim.x};
     const uint32_t p0 = tile_first_pixel(S, L, TP);
     const uint32_t npix = min(TP, L.n_pixels - p0);
     const size_t base = (size_t)p0 * T;
@@ -2176,7 +2229,7 @@ k_backward_stash(SceneView S, LaunchArgs L)
         sink.primal_row = want_primal ? tprimal + (size_t)pl * T : nullptr;
         sink.norm = L.norm;
         sink.acc = &acc;
-        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, stride, sink, tally);
+        trace_path(S, L, p0 + pl, L.sample_offset + s, stk, sink, tally);
         sink.finish();
     }
     __syncthreads();
@@ -2379,11 +2432,23 @@ hipError_t launch_render_hbm(const SceneView& S, const LaunchArgs& L, uint32_t b
         if (L.steady) launch_fill_zero(L.steady, L.n_pixels, stream);
         if (L.oow) launch_fill_zero(L.oow, L.n_pixels, stream);
     }
-    const size_t lds = hbm_lds_bytes(block, stack_lane_bytes(S.n_tris, S.stack_depth));
-    if (short_stack(S.n_tris))
+    const size_t lds = hbm_lds_bytes(block, hbm_stack_lane_bytes(S.n_tris, S.stack_depth));
+    if (short_stack(S.n_tris)) {
         launch_hbm_w<uint16_t>(S, L, block, lds, stream, counts);
-    else
+    } else if (split_stack(S.n_tris, S.stack_depth)) {
+        const dim3 grid(tiles_of(L));
+        switch (mode_of(L, counts)) {
+        case kRecording:
+            hipLaunchKernelGGL((k_render_hbm_split<kRecording>), grid, dim3(block), lds, stream, S, L, counts);
+            break;
+        case kCounting:
+            hipLaunchKernelGGL((k_render_hbm_split<kCounting>), grid, dim3(block), lds, stream, S, L, counts);
+            break;
+        default: hipLaunchKernelGGL((k_render_hbm_split<kPlain>), grid, dim3(block), lds, stream, S, L, counts);
+        }
+    } else {
         launch_hbm_w<uint32_t>(S, L, block, lds, stream, counts);
+    }
     return hipGetLastError();
 }
 
