@@ -479,6 +479,24 @@ def plane_scene(h=1.0, albedo=0.6, half=50.0, width=16, height=16, n_bins=8192, 
                    spp=1, max_depth=2, name="plane", **cam)
 
 
+def layered_scene(n_layers=2 ** 18, spacing=1e-5, half=4.0, width=16, height=16, n_bins=512, bin_width=0.01,
+                  spp=4) -> Scene:
+    """n_layers parallel quads y = -i * spacing under a point light, seen from
+    above.  Every camera ray crosses the boxes of all layers, so its
+    closest-hit traversal keeps a far child pending at nearly every level of
+    the tree: the deepest traversal stacks any scene of this size produces."""
+    v0, f0 = quad([-half, 0, -half], [-half, 0, half], [half, 0, half], [half, 0, -half])
+    ys = 0.0 - spacing * np.arange(n_layers, dtype=np.float64)
+    verts = np.tile(v0, (n_layers, 1))
+    verts[:, 1] = np.repeat(ys, 4)
+    faces = (f0[None, :, :] + 4 * np.arange(n_layers)[:, None, None]).reshape(-1, 3)
+    nt = faces.shape[0]
+    cam = look_at([0.1, 2.0, 0.05], [0.1, 0.0, 0.05], [0, 0, -1], 50.0, width, height)
+    return _finish(verts, faces, np.full(nt, MAT_LAMBERT), np.full(nt, 0.7), np.full(nt, 0.3), n_bins=n_bins,
+                   bin_width=bin_width, bin_start=2.0, width=width, height=height, light_pos=(0.5, 1.5, -0.3),
+                   light_intensity=1.0, spp=spp, max_depth=3, name="layers", **cam)
+
+
 def parallel_plane_confocal(d=0.5, half=40.0, grid=4, n_bins=2048, bin_width=0.0024,
                             bin_start=0.9, albedo=0.7, spp=4096) -> Scene:
     """Relay wall z=0 (scan grid over [-0.05, 0.05]^2) facing a large

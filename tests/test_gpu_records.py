@@ -49,6 +49,7 @@ def _scene(name):
             "box": lambda: scenes.box_scene(),
             "confocal": lambda: scenes.confocal_nlos(),
             "large": lambda: scenes.large_scene(),
+            "layers": lambda: scenes.layered_scene(),
             "glass": lambda: scenes.glass_box_scene(delay_mean=0.05, width=24, height=24),
             "fog_small": lambda: scenes.large_scene(cells=24, sphere_freq=4, grid=3, width=40, height=30,
                                                     n_bins=256, bin_width=0.02, spp=8),
@@ -181,3 +182,27 @@ def test_records_capacity_and_mask(tr):
         _, ref = tr.render_transient(dev)
         torch.cuda.synchronize()
         np.testing.assert_allclose(film.cpu().numpy(), ref.cpu().numpy(), rtol=1e-5, atol=0)
+
+
+def test_records_deep_stacks(tr, oracle_mod):
+    """262,144 stacked layers (524,288 triangles, 512 bins): the path form
+    keeps the film in HBM and splits each lane's stack between 16 words of
+    LDS and scratch memory.  Every camera ray crosses all layers' boxes, so
+    its traversal holds about as many pending far children as the tree has
+    levels and uses the scratch words on every ray; the contributions must
+    still match the oracle's (own median-split BVH) bit for bit."""
+    sc = _scene("layers")
+    with tr.upload(sc) as dev:
+        depth = dev.info()["bvh_depth"]
+    assert 16 + 2 < depth <= 16 + 48, f"tree depth {depth}: the scene no longer reaches the scratch words"
+    g, o, sc = _run(tr, oracle_mod, "layers", _pixels(sc.n_pixels, 32, 9), "path", spp=8)
+    compare_records(g, o, what="layers path")
+    _announce("layers: whole film against the LDS-stack path form")
+    import torch
+    with tr.upload(sc) as dev:
+        _, film = tr.render_transient(dev, kernel="path")
+        _, film_w = tr.render_transient(dev, kernel="wavefront")
+        torch.cuda.synchronize()
+        a, b = film.cpu().numpy(), film_w.cpu().numpy()
+    assert np.count_nonzero(a) > 0
+    np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-7 * float(np.abs(b).max()))
