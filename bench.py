@@ -55,7 +55,7 @@ WORKLOADS = {
     "box": dict(desc="box room 34 tris, 64x64 pinhole, 256 bins x 0.01 m from 0, 16 spp, max depth 4, FP32"),
     "large": dict(desc="terrain + 49 displaced spheres 998,608 tris, fog sigma_t 0.1, 512x512, 1024 bins x 5 mm "
                        "from 4.5 m, 64 spp, max depth 8, FP32",
-                  traffic="k_render_hbm_large_terrain_spheres_fog_512x512x1024_64spp_hbm_traffic.txt"),
+                  traffic="k_render_hbm_split_large_terrain_spheres_fog_512x512x1024_64spp_hbm_traffic.txt"),
     "glass": dict(desc="box room 34 tris with a glass box (index 1.5) and fluorescent room walls (scattering delay "
                        "mean 5 cm), 64x64 pinhole, 256 bins x 0.01 m from 0, 16 spp, max depth 8, FP32"),
     "batched": dict(desc="256 confocal NLOS scenes: blob triangles log-uniform 1k-50k, scan grids 16^2-64^2, "
@@ -347,7 +347,8 @@ def measure_single(tr, name, args, shape, extras):
     form = args.kernel if args.kernel != "auto" else ("deferred" if sc.sensor == 1 else "path")
     kernel_name = {"path": "k_render", "deferred": "k_render_deferred", "wavefront": "k_render_wf"}[form]
     if form == "path" and sc.sensor == 0 and sc.n_bins >= 512 and sc.n_tris > 32768:
-        kernel_name = "k_render_hbm"  # the path form keeps long films of large scenes in HBM
+        # the path form keeps long films of large scenes in HBM, with split stacks up to 64 levels
+        kernel_name = "k_render_hbm_split" if info["bvh_depth"] <= 64 else "k_render_hbm"
     res = {"value": round(paths / (ms_per_step * 1e-3) / 1e6, 3), "ms_per_step": round(ms_per_step, 4),
            "config": {"workload": WORKLOADS[name]["desc"], "paths_per_step": paths,
                       "triangles": info["n_triangles"], "bvh_depth": info["bvh_depth"]},
