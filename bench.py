@@ -222,10 +222,10 @@ def host_cpu():
     return usable, os.cpu_count() or 1, model
 
 
-def cpu_baseline(sc, stride_all=2, stride_one=32):
+def cpu_baseline(sc, stride_all=1, stride_one=16):
     """The unchanged oracle on the host cores over a bounded sample of the
-    workload: every `stride_all`-th pixel (or scan point) at the full spp on
-    all usable cores, and every `stride_one`-th on one thread."""
+    workload: one pixel (or scan point) in `stride_all` at the full spp on
+    all usable cores, and one in `stride_one` on one thread."""
     import oracle
     usable, total, model = host_cpu()
     O = oracle.Oracle(sc)
@@ -238,14 +238,16 @@ def cpu_baseline(sc, stride_all=2, stride_one=32):
         out[label] = (len(pix), dt, threads)
     n_all, dt_all, th = out["all"]
     n_one, dt_one, _ = out["one"]
+
+    def sample(stride, n):
+        which = f"all {n} pixels" if stride == 1 else f"one pixel in {stride} ({n} of {sc.n_pixels})"
+        return f"{which} at the full {sc.spp} spp"
+
     return {"value": round(n_all * sc.spp / dt_all / 1e6, 4), "unit": "Mpath-samples/s", "cores": th,
-            "kind": "oracle",
-            "sample": f"every {stride_all}th pixel ({n_all} of {sc.n_pixels}) at the full {sc.spp} spp, "
-                      f"threads over pixels",
+            "kind": "oracle", "sample": sample(stride_all, n_all) + ", threads over pixels",
             "seconds": round(dt_all, 2), "host_nproc": total, "host_usable_cores": usable, "host_cpu_model": model,
             "one_thread": {"value": round(n_one * sc.spp / dt_one / 1e6, 4), "unit": "Mpath-samples/s",
-                           "sample": f"every {stride_one}th pixel ({n_one}) at {sc.spp} spp",
-                           "seconds": round(dt_one, 2)}}
+                           "sample": sample(stride_one, n_one), "seconds": round(dt_one, 2)}}
 
 
 def roofline_of(counts, launch_ms, kernel, traffic=None, algorithmic_bytes=None):
