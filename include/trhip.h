@@ -438,9 +438,10 @@ trhip_status trhip_numerics_probe(int32_t op, const void* in, void* out, uint64_
  * estimated cost (largest first), from a global cursor.  The classes'
  * cursor resets and persistent kernels are captured once into a hipGraph,
  * so trhip_batch_render is one graph launch.  tile_pixels, when the caller
- * sets it, is every scene's pixels per item; when chosen, a scene with T
- * bins takes max(1, floor(s * 1026 / (T + 2))) pixels per item for its
- * class's scale s (so longer films take fewer pixels), and the info reports s.
+ * sets it, is every scene's pixels per item; when chosen, each class takes
+ * either one pixel count for all its scenes or, for a scale s, max(1,
+ * floor(s * 1026 / (T + 2))) pixels per item for a scene with T bins (so
+ * longer films take fewer pixels).
  *
  * scenes: HOST array of n_scenes live scene handles; renders: HOST array of
  * n_scenes render descriptions (overrides must be NULL; flags may only hold
@@ -469,7 +470,8 @@ typedef struct {
 typedef struct {
     uint32_t n_scenes;
     uint32_t n_items;       /* work items per render, all classes */
-    uint32_t block_size, tile_pixels, groups; /* shape of the costliest class (tile_pixels: see below) */
+    uint32_t block_size, tile_pixels, groups; /* shape of the costliest class (tile_pixels: of its
+                                                 costliest scene) */
     uint32_t kernel;        /* TRHIP_KERNEL_PATH or TRHIP_KERNEL_DEFERRED, costliest class */
     uint32_t stack_depth;   /* deepest BVH of the batch */
     size_t lds_bytes;       /* dynamic LDS per workgroup, the largest class */

@@ -1035,7 +1035,7 @@ trhip_status trhip_render_transient_backward(trhip_scene* scene, const trhip_ren
 // batched persistent rendering
 // ---------------------------------------------------------------------------
 constexpr uint32_t kBatchMagic = 0x54524842u;  // "TRHB"
-constexpr uint64_t kBatchKernelRevision = 3;   // bump when the persistent kernel's performance model changes
+constexpr uint64_t kBatchKernelRevision = 4;   // bump when the persistent kernel's performance model changes
 
 // The scenes of a batch are split into classes by stack-link width (16-bit
 // links and buffer loads up to 32,768 triangles, 32-bit links above) and
@@ -1147,20 +1147,21 @@ void free_batch(trhip_batch* b)
     delete b;
 }
 
-// Pixels per work item of a scene with T bins: `fixed` if the caller set it,
-// else the scale times 1,026 floats of LDS film (a pixel of 1,024 bins)
-// divided by the scene's film floats per pixel, so that scenes with fewer
-// bins take more pixels per item.
-uint32_t batch_tile(uint32_t fixed, uint32_t scale, uint32_t T)
+// A class's tile choice: a scale s (codes 1, 2, 4: a scene with T bins
+// takes s * 1,026 floats of LDS film, a pixel of 1,024 bins, divided by its
+// film floats per pixel, so that scenes with fewer bins take more pixels per
+// item) or a pixel count p for every scene of the class (kFixedTile | p).
+constexpr uint32_t kFixedTile = 0x100u;
+uint32_t batch_tile(uint32_t code, uint32_t T)
 {
-    if (fixed) return fixed;
-    return std::max<uint32_t>(1u, (scale * 1026u) / (T + 2u));
+    if (code & kFixedTile) return code & (kFixedTile - 1u);
+    return std::max<uint32_t>(1u, (code * 1026u) / (T + 2u));
 }
 
 // a class's shape -> its tables on the device; *fits false if the LDS does
 // not fit (nothing staged then)
-hipError_t stage_shape(trhip_batch* b, BatchClass& c, uint32_t block, uint32_t tile_fixed, uint32_t scale,
-                       uint32_t groups, bool deferred, hipStream_t s, bool* fits)
+hipError_t stage_shape(trhip_batch* b, BatchClass& c, uint32_t block, uint32_t tile_code, uint32_t groups,
+                       bool deferred, hipStream_t s, bool* fits)
 {
     const uint32_t n = (uint32_t)c.order.size();
     std::vector<uint32_t> start(n + 1, 0);
@@ -1169,7 +1170,7 @@ hipError_t stage_shape(trhip_batch* b, BatchClass& c, uint32_t block, uint32_t t
     for (uint32_t k = 0; k < n; ++k) {
         const uint32_t i = c.order[k];
         const uint32_t T = b->views[i].n_bins;
-        const uint32_t tp = std::min<uint32_t>(batch_tile(tile_fixed, scale, T), b->scenes[i]->n_pixels);
+        const uint32_t tp = std::min<uint32_t>(batch_tile(tile_code, T), b->scenes[i]->n_pixels);
         b->args[i].tile_pixels = tp;
         film_words = std::max<uint32_t>(film_words, tp * T + 2 * tp);
         if ((uint64_t)tp * b->args[i].spp >= (1ull << 32)) *fits = false;
@@ -1192,7 +1193,7 @@ hipError_t stage_shape(trhip_batch* b, BatchClass& c, uint32_t block, uint32_t t
     c.tables.film_words = film_words;
     c.tables.cursor = c.d_cursor;
     c.block = block;
-    c.tile = tile_fixed ? tile_fixed : scale;
+    c.tile = b->args[c.order[0]].tile_pixels;  // pixels per item of the costliest scene
     c.groups = groups;
     c.deferred = deferred;
     c.lds = lds;
@@ -1234,10 +1235,11 @@ hipError_t shape_class(trhip_batch* b, BatchClass& c, const trhip_batch_opts& o,
     *ok = false;
     const std::vector<uint32_t> blocks = o.block_size ? std::vector<uint32_t>{o.block_size}
                                                       : std::vector<uint32_t>{64, 128, 256};
-    // the tile dimension: pixels per item if the caller fixed it, else the
-    // scale of batch_tile
-    const std::vector<uint32_t> tiles = o.tile_pixels ? std::vector<uint32_t>{o.tile_pixels}
-                                                      : std::vector<uint32_t>{1, 2, 4};
+    // the tile choices (batch_tile): the caller's pixels per item, else three
+    // scales and three pixel counts
+    const std::vector<uint32_t> tiles =
+        o.tile_pixels ? std::vector<uint32_t>{kFixedTile | o.tile_pixels}
+                      : std::vector<uint32_t>{1, 2, 4, kFixedTile | 2, kFixedTile | 4, kFixedTile | 8};
     const std::vector<uint32_t> gpcs = o.groups_per_cu ? std::vector<uint32_t>{o.groups_per_cu}
                                                        : std::vector<uint32_t>{4, 5, 8};
     const std::vector<uint32_t> forms = o.kernel ? std::vector<uint32_t>{o.kernel}
@@ -1271,7 +1273,7 @@ hipError_t shape_class(trhip_batch* b, BatchClass& c, const trhip_batch_opts& o,
                         if (e != hipSuccess) break;
                         bool fits = false;
                         const bool dfr = form == TRHIP_KERNEL_DEFERRED;
-                        e = stage_shape(b, c, bs, o.tile_pixels, tp, g, dfr, s, &fits);
+                        e = stage_shape(b, c, bs, tp, g, dfr, s, &fits);
                         if (e != hipSuccess || !fits) continue;
                         const uint32_t groups = std::max<uint32_t>(1u, (uint32_t)n_cu * g);
                         e = trhip::launch_batch(c.tables, groups, bs, c.depth, c.short_links, dfr, s);  // warm-up
@@ -1311,17 +1313,18 @@ hipError_t shape_class(trhip_batch* b, BatchClass& c, const trhip_batch_opts& o,
             if (o.block_size && bs != o.block_size) continue;
             bool fits = false;
             const uint32_t g = o.groups_per_cu ? o.groups_per_cu : 8u;
-            e = stage_shape(b, c, bs, o.tile_pixels, o.tile_pixels ? o.tile_pixels : 1u, g, dfr, s, &fits);
+            const uint32_t code = o.tile_pixels ? (kFixedTile | o.tile_pixels) : 1u;
+            e = stage_shape(b, c, bs, code, g, dfr, s, &fits);
             if (e != hipSuccess) return e;
             if (fits) {
-                best = {bs, o.tile_pixels ? o.tile_pixels : 1u, g, dfr ? 1u : 0u};
+                best = {bs, code, g, dfr ? 1u : 0u};
                 break;
             }
         }
     }
     if (!best[0]) return hipSuccess;
     bool fits = false;
-    e = stage_shape(b, c, best[0], o.tile_pixels, best[1], best[2], best[3] != 0, s, &fits);
+    e = stage_shape(b, c, best[0], best[1], best[2], best[3] != 0, s, &fits);
     *ok = e == hipSuccess && fits;
     return e;
 }
