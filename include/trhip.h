@@ -294,6 +294,11 @@ trhip_status trhip_scene_get_info(const trhip_scene* scene, trhip_scene_info* in
  * optional DEVICE float[n_pixels]: the steady image (every contribution)
  * and the mass that fell outside the film window.  All three are
  * normalised by 1/norm_spp and overwritten unless TRHIP_FLAG_ACCUMULATE.
+ * The path form of a scene with more than 32,768 triangles and a film of
+ * 512 bins or more adds into the film in HBM, with each lane's traversal
+ * stack split between LDS and scratch memory for trees of at most 64
+ * levels; the environment variable TRHIP_SPLIT_STACK=0 (read at every call)
+ * keeps whole stacks in LDS there.  The results do not depend on it.
  * Errors: BAD_HANDLE, INVALID_ARG, UNSUPPORTED (launch shape beyond LDS), HIP.
  */
 trhip_status trhip_render_transient(trhip_scene* scene, const trhip_render_desc* render, float* film,

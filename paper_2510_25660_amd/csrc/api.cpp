@@ -517,9 +517,10 @@ trhip_status choose_shape(const trhip_scene* s, const trhip_render_desc* r, Kind
 // Film length from which the path form keeps the film in HBM (no LDS film)
 // on scenes too large for 16-bit stack links: there a pixel's LDS row of
 // 2 KB or more next to the deep 32-bit stacks is what limits the workgroups
-// per CU (1M-triangle scene: 1,024 bins 256 -> 366 Mpath-samples/s, 512
-// bins 297 -> 367); on small scenes the LDS film is as fast or faster (box
-// room, 512 bins: 965 against 881).
+// per CU (1M-triangle scene: 1,024 bins 256 -> 366 Mpath-samples/s with
+// whole stacks in LDS, 442 with split stacks; 512 bins 297 -> 367); on small
+// scenes the LDS film is as fast or faster (box room, 512 bins: 965 against
+// 881).
 constexpr uint32_t kHbmFilmBins = 512;
 
 bool hbm_film(const trhip_scene* s) { return s->view.n_bins >= kHbmFilmBins && !trhip::short_stack(s->view.n_tris); }

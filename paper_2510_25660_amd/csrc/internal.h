@@ -44,11 +44,14 @@ inline uint32_t stack_lane_bytes(uint32_t n_tris, uint32_t stack_depth)
 // stack in LDS and the deeper ones in per-lane scratch memory, for trees of
 // at most kSplitStackLds + kSplitStackDeep levels (deeper trees keep the
 // whole stack in LDS).  LDS bytes of one lane's stack in that form:
+// The environment variable TRHIP_SPLIT_STACK=0 keeps whole stacks in LDS
+// (read at every launch).
 constexpr uint32_t kSplitStackLds = 16;
 constexpr uint32_t kSplitStackDeep = 48;
+bool split_stack_enabled();
 inline bool split_stack(uint32_t n_tris, uint32_t stack_depth)
 {
-    return !short_stack(n_tris) && stack_depth <= kSplitStackLds + kSplitStackDeep;
+    return !short_stack(n_tris) && stack_depth <= kSplitStackLds + kSplitStackDeep && split_stack_enabled();
 }
 inline uint32_t hbm_stack_lane_bytes(uint32_t n_tris, uint32_t stack_depth)
 {

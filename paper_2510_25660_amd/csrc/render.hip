@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "device_math.h"
 
@@ -2423,6 +2424,12 @@ hipError_t launch_render(const SceneView& S, const LaunchArgs& L, uint32_t block
 }
 
 size_t hbm_lds_bytes(uint32_t block, uint32_t stack_bytes) { return (size_t)block * stack_bytes; }
+
+bool split_stack_enabled()
+{
+    const char* v = std::getenv("TRHIP_SPLIT_STACK");
+    return !(v && v[0] == '0' && v[1] == '\0');
+}
 
 hipError_t launch_render_hbm(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream,
                              unsigned long long* counts)

@@ -206,3 +206,23 @@ def test_records_deep_stacks(tr, oracle_mod):
         a, b = film.cpu().numpy(), film_w.cpu().numpy()
     assert np.count_nonzero(a) > 0
     np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-7 * float(np.abs(b).max()))
+
+
+def test_records_large_whole_lds_stacks(tr, oracle_mod, monkeypatch):
+    """The 1M-triangle fog scene's path form with whole stacks in LDS
+    (TRHIP_SPLIT_STACK=0: the kernel kept for trees deeper than the split
+    stack holds), contribution by contribution against the oracle, and its
+    film against the split-stack render's."""
+    import torch
+    monkeypatch.setenv("TRHIP_SPLIT_STACK", "0")
+    g, o, sc = _run(tr, oracle_mod, "large", _pixels(512 * 512, 16, 10), "path")
+    compare_records(g, o, value_ulps=4, what="large path, whole LDS stacks")
+    _announce("large: film with whole LDS stacks against split stacks")
+    with tr.upload(sc) as dev:
+        _, a = tr.render_transient(dev, kernel="path", spp=8)
+        monkeypatch.setenv("TRHIP_SPLIT_STACK", "1")
+        _, b = tr.render_transient(dev, kernel="path", spp=8)
+        torch.cuda.synchronize()
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+    assert np.count_nonzero(a) > 0
+    np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6 * float(np.abs(b).max()))
