@@ -365,6 +365,7 @@ void fill_view(trhip_scene* s, const trhip_scene_desc* d)
     std::memset(&v, 0, sizeof(v));
     v.nodes = s->bvh.nodes;
     v.tris = s->bvh.tris;
+    v.compact = s->bvh.compact ? 1u : 0u;
     v.mat = s->d_mat;
     v.albedo = s->d_albedo;
     v.rough = s->d_rough;
@@ -676,7 +677,7 @@ trhip_status trhip_scene_create(const trhip_scene_desc* desc, void* stream, trhi
     if (e == hipSuccess)
         e = trhip::build_bvh(d_tri9, nt, desc->bvh_builder == TRHIP_BVH_LBVH ? trhip::kBuilderLbvh : trhip::kBuilderPloc,
                              s, &sc->bvh);
-    if (e == hipSuccess && sc->d_sorted_of) e = trhip::launch_sorted_of(sc->bvh.tris, nt, sc->d_sorted_of, s);
+    if (e == hipSuccess && sc->d_sorted_of) e = trhip::launch_sorted_of(sc->bvh.tris, sc->bvh.compact, nt, sc->d_sorted_of, s);
     if (e == hipSuccess && sc->d_sorted_of) e = hipStreamSynchronize(s);
     (void)hipFree(d_tri9);
     if (e != hipSuccess) {
@@ -689,7 +690,9 @@ trhip_status trhip_scene_create(const trhip_scene_desc* desc, void* stream, trhi
         std::lock_guard<std::mutex> lock(g_live_mutex);
         g_live.insert(sc);
     }
-    sc->device_bytes = (size_t)sc->bvh.n_internal * sizeof(trhip::BvhNode) + (size_t)nt * sizeof(trhip::TriRec) +
+    sc->device_bytes = (size_t)sc->bvh.n_internal * (sc->bvh.compact ? sizeof(trhip::CompactNode)
+                                                                      : sizeof(trhip::BvhNode)) +
+                       (size_t)nt * (sc->bvh.compact ? sizeof(trhip::TriRecBox) : sizeof(trhip::TriRec)) +
                        (size_t)nt * (1 + 4 + 4 + 32) + (sc->d_scan ? 13ull * sc->n_pixels + 4ull * nt + (size_t)kAreaRegions * (12ull * nt + 4ull * (sc->guide_cells + 1) + 8) : 0) +
                        (sc->d_ior ? 4ull * nt : 0) + (sc->d_delay ? 4ull * nt : 0);
     *out = sc;

@@ -207,6 +207,65 @@ __global__ void k_layout(int n, const int32_t* __restrict__ child, const float* 
     nodes[i] = nd;
 }
 
+// FP16 bit patterns of the largest half <= x and the smallest half >= x
+// (round to nearest, then one step toward the bound when it overshot; the
+// conversion back to FP32 is exact)
+__device__ __forceinline__ uint16_t half_bits(_Float16 h) { return __builtin_bit_cast(uint16_t, h); }
+__device__ __forceinline__ float half_value(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
+__device__ __forceinline__ uint16_t half_down(float x)
+{
+    uint16_t b = half_bits((_Float16)x);
+    if (half_value(b) > x) b = (b == 0x0000u) ? (uint16_t)0x8001u : (b & 0x8000u) ? (uint16_t)(b + 1u) : (uint16_t)(b - 1u);
+    return b;
+}
+__device__ __forceinline__ uint16_t half_up(float x)
+{
+    uint16_t b = half_bits((_Float16)x);
+    if (half_value(b) < x) b = (b == 0x8000u) ? (uint16_t)0x0001u : (b & 0x8000u) ? (uint16_t)(b - 1u) : (uint16_t)(b + 1u);
+    return b;
+}
+
+__global__ void k_layout_compact(int n, const int32_t* __restrict__ child, const float* __restrict__ tri_box,
+                                 const uint32_t* __restrict__ ids, const float* __restrict__ node_box,
+                                 CompactNode* __restrict__ nodes)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    float l0[3], h0[3], l1[3], h1[3];
+    const int32_t c0 = child[2 * i], c1 = child[2 * i + 1];
+    child_box(c0, tri_box, ids, node_box, l0, h0);
+    child_box(c1, tri_box, ids, node_box, l1, h1);
+    CompactNode nd;
+    for (int a = 0; a < 3; ++a) {
+        nd.box[a] = half_down(l0[a]);
+        nd.box[3 + a] = half_up(h0[a]);
+        nd.box[6 + a] = half_down(l1[a]);
+        nd.box[9 + a] = half_up(h1[a]);
+    }
+    nd.child0 = c0;
+    nd.child1 = c1;
+    nodes[i] = nd;
+}
+
+// compact layout: the record with the triangle's padded box
+__global__ void k_tris_box(int n, const float* __restrict__ tri9, const uint32_t* __restrict__ ids,
+                           const float* __restrict__ tri_box, TriRecBox* __restrict__ out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const uint32_t k = ids[j];
+    const float* t = tri9 + 9ull * k;
+    const float* b = tri_box + 6ull * k;
+    TriRecBox r;
+    r.v0x = t[0]; r.v0y = t[1]; r.v0z = t[2];
+    r.prim = k;
+    r.e1x = t[3] - t[0]; r.e1y = t[4] - t[1]; r.e1z = t[5] - t[2];
+    r.e2x = t[6] - t[0]; r.e2y = t[7] - t[1]; r.e2z = t[8] - t[2];
+    r.lox = b[0]; r.loy = b[1]; r.loz = b[2];
+    r.hix = b[3]; r.hiy = b[4]; r.hiz = b[5];
+    out[j] = r;
+}
+
 __global__ void k_tris(int n, const float* __restrict__ tri9, const uint32_t* __restrict__ ids,
                        TriRec* __restrict__ out)
 {
@@ -415,8 +474,9 @@ hipError_t build_bvh(const float* d_tri9, uint32_t nt, int builder, hipStream_t 
     TR_CHECK(hipMalloc(&parent_leaf, (size_t)nt * sizeof(int32_t)));
     TR_CHECK(hipMalloc(&arrivals, (size_t)ni * sizeof(uint32_t)));
     TR_CHECK(hipMalloc(&depth, sizeof(uint32_t)));
-    TR_CHECK(hipMalloc(&out->nodes, (size_t)ni * sizeof(BvhNode)));
-    TR_CHECK(hipMalloc(&out->tris, (size_t)nt * sizeof(TriRec)));
+    out->compact = !short_stack(nt);
+    TR_CHECK(hipMalloc(&out->nodes, (size_t)ni * (out->compact ? sizeof(CompactNode) : sizeof(BvhNode))));
+    TR_CHECK(hipMalloc(&out->tris, (size_t)nt * (out->compact ? sizeof(TriRecBox) : sizeof(TriRec))));
 
     k_init_stats<<<1, 64, 0, stream>>>(stats);
     {
@@ -485,10 +545,19 @@ hipError_t build_bvh(const float* d_tri9, uint32_t nt, int builder, hipStream_t 
         k_parents<<<blocks_for(n - 1, 256), 256, 0, stream>>>(n - 1, child, parent_int, parent_leaf);
     }
     if (n > 1) {
-        k_layout<<<blocks_for(n - 1, 256), 256, 0, stream>>>(n, child, tri_box, ids_sorted, node_box, out->nodes);
+        if (out->compact)
+            k_layout_compact<<<blocks_for(n - 1, 256), 256, 0, stream>>>(n, child, tri_box, ids_sorted, node_box,
+                                                                         static_cast<CompactNode*>(out->nodes));
+        else
+            k_layout<<<blocks_for(n - 1, 256), 256, 0, stream>>>(n, child, tri_box, ids_sorted, node_box,
+                                                                 static_cast<BvhNode*>(out->nodes));
         k_depth<<<blocks_for(n, 256), 256, 0, stream>>>(n, parent_int, parent_leaf, depth);
     }
-    k_tris<<<blocks_for(n, 256), 256, 0, stream>>>(n, d_tri9, ids_sorted, out->tris);
+    if (out->compact)
+        k_tris_box<<<blocks_for(n, 256), 256, 0, stream>>>(n, d_tri9, ids_sorted, tri_box,
+                                                            static_cast<TriRecBox*>(out->tris));
+    else
+        k_tris<<<blocks_for(n, 256), 256, 0, stream>>>(n, d_tri9, ids_sorted, static_cast<TriRec*>(out->tris));
     TR_CHECK(hipGetLastError());
     TR_CHECK(hipMemcpyAsync(host_stats, stats, sizeof(host_stats), hipMemcpyDeviceToHost, stream));
     TR_CHECK(hipMemcpyAsync(&host_depth, depth, sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
@@ -528,18 +597,22 @@ done:
 namespace {
 
 // inverse of the BVH order: out[caller index] = BVH-order index
-__global__ void k_sorted_of(uint32_t n, const TriRec* __restrict__ tris, uint32_t* __restrict__ out)
+__global__ void k_sorted_of(uint32_t n, const uint32_t* __restrict__ prim, uint32_t stride_words,
+                            uint32_t* __restrict__ out)
 {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < n) out[tris[j].prim] = j;
+    if (j < n) out[prim[(size_t)j * stride_words]] = j;
 }
 
 }  // namespace
 
-hipError_t launch_sorted_of(const TriRec* tris, uint32_t nt, uint32_t* out, hipStream_t stream)
+hipError_t launch_sorted_of(const void* tris, bool compact, uint32_t nt, uint32_t* out, hipStream_t stream)
 {
     if (nt == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sorted_of, dim3((nt + 255) / 256), dim3(256), 0, stream, nt, tris, out);
+    // the caller index is word 3 of either record
+    const uint32_t* prim = static_cast<const uint32_t*>(tris) + 3;
+    const uint32_t stride = (uint32_t)((compact ? sizeof(TriRecBox) : sizeof(TriRec)) / 4);
+    hipLaunchKernelGGL(k_sorted_of, dim3((nt + 255) / 256), dim3(256), 0, stream, nt, prim, stride, out);
     return hipGetLastError();
 }
 

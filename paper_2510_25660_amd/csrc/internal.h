@@ -10,8 +10,9 @@
 namespace trhip {
 
 struct BvhBuild {
-    BvhNode* nodes;
-    TriRec* tris;
+    void* nodes;   // BvhNode[] or, when compact, CompactNode[]
+    void* tris;    // TriRec[] or, when compact, TriRecBox[]
+    bool compact;  // more than kShortStackMaxTris triangles
     int32_t root;
     float root_lo[3], root_hi[3];
     uint32_t n_internal;
@@ -27,7 +28,7 @@ constexpr int kBuilderLbvh = 1;
 hipError_t build_bvh(const float* d_tri9, uint32_t nt, int builder, hipStream_t stream, BvhBuild* out);
 
 // out[tris[j].prim] = j for the nt triangle records of a built BVH
-hipError_t launch_sorted_of(const TriRec* tris, uint32_t nt, uint32_t* out, hipStream_t stream);
+hipError_t launch_sorted_of(const void* tris, bool compact, uint32_t nt, uint32_t* out, hipStream_t stream);
 
 // Traversal stacks hold one BVH link per level.  With at most 32,768
 // triangles every link (internal node index, or ~sorted triangle index)

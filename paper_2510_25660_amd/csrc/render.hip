@@ -117,25 +117,36 @@ __device__ __forceinline__ TriRec tri_of(float4 a, float4 b, float4 c)
     return t;
 }
 
-// the triangle record of a leaf test
+// The record of a leaf test.  kBuf: the TriRec layout of scenes with 16-bit
+// links, by buffer loads.  Otherwise the compact layout's TriRecBox: its
+// first three 16-byte words hold what TriRec holds, the fourth (with the .w
+// of the second and third) the triangle's padded box, returned in lo/hi.
 template <bool kBuf>
-__device__ __forceinline__ TriRec leaf_tri(const SceneView& S, int j)
+__device__ __forceinline__ TriRec leaf_tri(const SceneView& S, int j, vec3& lo, vec3& hi)
 {
     if constexpr (kBuf) {
         const __amdgpu_buffer_rsrc_t R = buffer_of(S.tris, S.n_tris * (uint32_t)sizeof(TriRec));
         const uint32_t off = (uint32_t)j * (uint32_t)sizeof(TriRec);
         return tri_of(buffer_f4(R, off), buffer_f4(R, off + 16u), buffer_f4(R, off + 32u));
     } else {
-        const float4* p = reinterpret_cast<const float4*>(S.tris + j);
-        return tri_of(p[0], p[1], p[2]);
+        const float4* p = reinterpret_cast<const float4*>(S.tris) + 4 * (size_t)j;
+        const float4 a = p[0], b = p[1], c = p[2], d = p[3];
+        lo = v3(b.w, c.w, d.x);
+        hi = v3(d.y, d.z, d.w);
+        return tri_of(a, b, c);
     }
 }
 
-// the 64-byte node n: child boxes in a, b, d; links in l.x, l.y
+// the node n, child boxes in a, b, d (lo0 hi0 lo1 hi1, xyz each); links in l.x, l.y
 struct NodeRec {
     float4 a, b, d, l;
 };
 
+__device__ __forceinline__ float half_lo(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu)); }
+__device__ __forceinline__ float half_hi(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)); }
+
+// kBuf: the 64-byte BvhNode by buffer loads; otherwise the 32-byte
+// CompactNode, whose FP16 bounds convert to FP32 exactly
 template <bool kBuf>
 __device__ __forceinline__ NodeRec load_node(const SceneView& S, int n)
 {
@@ -148,24 +159,21 @@ __device__ __forceinline__ NodeRec load_node(const SceneView& S, int n)
         v.d = buffer_f4(R, off + 32u);
         v.l = buffer_f4(R, off + 48u);
     } else {
-        const float4* nodes = reinterpret_cast<const float4*>(S.nodes);
-        v.a = nodes[4 * n + 0];
-        v.b = nodes[4 * n + 1];
-        v.d = nodes[4 * n + 2];
-        v.l = nodes[4 * n + 3];
+        const uint4* q = reinterpret_cast<const uint4*>(S.nodes) + 2 * (size_t)n;
+        const uint4 q0 = q[0], q1 = q[1];
+        v.a = make_float4(half_lo(q0.x), half_hi(q0.x), half_lo(q0.y), half_hi(q0.y));
+        v.b = make_float4(half_lo(q0.z), half_hi(q0.z), half_lo(q0.w), half_hi(q0.w));
+        v.d = make_float4(half_lo(q1.x), half_hi(q1.x), half_lo(q1.y), half_hi(q1.y));
+        v.l = make_float4(__uint_as_float(q1.z), __uint_as_float(q1.w), 0.0f, 0.0f);
     }
     return v;
 }
 
-__device__ __forceinline__ TriRec load_tri(const TriRec* __restrict__ tris, int j)
+// a hit triangle's record (v0, edges, caller index), either layout
+__device__ __forceinline__ TriRec load_tri(const SceneView& S, int j)
 {
-    const float4* p = reinterpret_cast<const float4*>(tris + j);
-    const float4 a = p[0], b = p[1], c = p[2];
-    TriRec t;
-    t.v0x = a.x; t.v0y = a.y; t.v0z = a.z; t.prim = __float_as_uint(a.w);
-    t.e1x = b.x; t.e1y = b.y; t.e1z = b.z; t.unused0 = 0.0f;
-    t.e2x = c.x; t.e2y = c.y; t.e2z = c.z; t.unused1 = 0.0f;
-    return t;
+    const float4* p = reinterpret_cast<const float4*>(S.tris) + (size_t)j * (S.compact ? 4u : 3u);
+    return tri_of(p[0], p[1], p[2]);
 }
 
 struct Hit {
@@ -284,16 +292,25 @@ struct SplitStack {
 };
 
 // Closest accepted triangle: smallest t, then smallest caller index.  A
-// triangle is accepted at t only if t is not before the entry of its own
-// padded box (the box stored for it in its parent), which makes the result
-// independent of the traversal order.
-template <bool kBuf = false, class TallyT>
+// triangle is accepted at t only if its padded box's slab interval is
+// non-empty and reaches t >= 0 and t is not before the box's entry, which
+// makes the result independent of the traversal order.  With 16-bit links
+// the padded box is the one stored for the triangle in its parent, tested
+// there (tn: its entry); in the compact layout the parent's FP16 box only
+// admitted the triangle, and the padded box comes with the record.
+template <bool kBuf, class TallyT>
 __device__ __forceinline__ void leaf_closest(const SceneView& S, const Ray& r, int sorted, float tn, int exclude,
                                              Hit& h, TallyT& tally)
 {
     tally.add(kTallyTris);
     tally.wave(kTallyWaveTris);
-    const TriRec tr = leaf_tri<kBuf>(S, sorted);
+    vec3 lo, hi;
+    const TriRec tr = leaf_tri<kBuf>(S, sorted, lo, hi);
+    if constexpr (!kBuf) {
+        float tf;
+        slab(r, lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, tn, tf);
+        if (!(tn <= tf && tf >= 0.0f && tn <= h.t)) return;
+    }
     const int prim = (int)tr.prim;
     float t;
     if (!intersect_tri<kBuf>(r, tr, exclude, t) || tn > t) return;
@@ -327,7 +344,7 @@ __device__ __forceinline__ void closest_begin(const SceneView& S, const Ray& r, 
     if (S.root < 0) {  // a single triangle: no internal node to visit
         float tn, tf;
         slab(r, S.root_lo[0], S.root_lo[1], S.root_lo[2], S.root_hi[0], S.root_hi[1], S.root_hi[2], tn, tf);
-        if (tn <= tf && tf >= 0.0f) leaf_closest(S, r, ~S.root, tn, exclude, c.h, tally);
+        if (tn <= tf && tf >= 0.0f) leaf_closest<true>(S, r, ~S.root, tn, exclude, c.h, tally);
         c.visits = S.n_tris;
     }
 }
@@ -387,13 +404,19 @@ __device__ Hit closest_hit(const SceneView& S, const Ray& r, int exclude, St& st
     return c.h;
 }
 
-template <bool kBuf = false, class TallyT>
+template <bool kBuf, class TallyT>
 __device__ __forceinline__ bool leaf_blocks(const SceneView& S, const Ray& r, int sorted, float tn, int exclude,
                                             float tmax, TallyT& tally)
 {
     tally.add(kTallyTris);
     tally.wave(kTallyWaveTris);
-    const TriRec tr = leaf_tri<kBuf>(S, sorted);
+    vec3 lo, hi;
+    const TriRec tr = leaf_tri<kBuf>(S, sorted, lo, hi);
+    if constexpr (!kBuf) {
+        float tf;
+        slab(r, lo.x, lo.y, lo.z, hi.x, hi.y, hi.z, tn, tf);
+        if (!(tn <= tf && tf >= 0.0f && tn <= tmax)) return false;
+    }
     float t;
     return intersect_tri<kBuf>(r, tr, exclude, t) && !(tn > t) && t < tmax;
 }
@@ -406,7 +429,7 @@ __device__ bool occluded(const SceneView& S, const Ray& r, int exclude, float tm
     if (S.root < 0) {
         float tn, tf;
         slab(r, S.root_lo[0], S.root_lo[1], S.root_lo[2], S.root_hi[0], S.root_hi[1], S.root_hi[2], tn, tf);
-        return tn <= tf && tf >= 0.0f && tn <= tmax && leaf_blocks(S, r, ~S.root, tn, exclude, tmax, tally);
+        return tn <= tf && tf >= 0.0f && tn <= tmax && leaf_blocks<true>(S, r, ~S.root, tn, exclude, tmax, tally);
     }
     int node = S.root;
     int sp = 0;
@@ -566,7 +589,7 @@ __device__ __forceinline__ bool begin_area(const SceneView& S, const LaunchArgs&
     const uint32_t region = S.area_region[pix];
     const uint32_t lo = area_pick(S, region, u.u0);
     const uint32_t j = S.sorted_of[lo];
-    const TriRec tr = load_tri(S.tris, j);
+    const TriRec tr = load_tri(S, (int)j);
     const vec3 e1 = v3(tr.e1x, tr.e1y, tr.e1z), e2 = v3(tr.e2x, tr.e2y, tr.e2z);
     const float su = sqrtf(u.u1);
     const float b1 = su * (1.0f - u.u2), b2 = su * u.u2;
@@ -727,7 +750,7 @@ __device__ __forceinline__ void shade_vertex(const SceneView& S, const LaunchArg
     }
     // surface vertex: two-sided, shading normal = geometric normal flipped
     // toward wo
-    const TriRec tr = load_tri(S.tris, h.sorted);
+    const TriRec tr = load_tri(S, h.sorted);
     const vec3 ng = normalize(cross(v3(tr.e1x, tr.e1y, tr.e1z), v3(tr.e2x, tr.e2y, tr.e2z)));
     const vec3 n = (dot(ng, wo) < 0.0f) ? neg(ng) : ng;
     if (!(dot(n, wo) > 0.0f)) return;

@@ -28,9 +28,33 @@ struct alignas(16) TriRec {
 };
 static_assert(sizeof(TriRec) == 48, "TriRec must be 48 bytes");
 
+// Scenes with more than 32,768 triangles (32-bit stack links) use a compact
+// layout, so that a node visit issues two 16-byte loads instead of four.
+// CompactNode, 32 bytes: both children's boxes as FP16 bit patterns rounded
+// outward (lo down, hi up: each contains the FP32 box it stands for) in the
+// order lo0x lo0y lo0z hi0x hi0y hi0z lo1x lo1y lo1z hi1x hi1y hi1z, then
+// the two links.  Traversal only: a leaf's FP16 box contains its padded
+// box, so every triangle the padded box admits is still reached.
+struct alignas(16) CompactNode {
+    uint16_t box[12];
+    int32_t child0, child1;
+};
+static_assert(sizeof(CompactNode) == 32, "CompactNode must be 32 bytes");
+
+// TriRecBox, 64 bytes: TriRec's v0, prim, e1, e2 with the triangle's padded
+// box (lo, hi) in the remaining words, for the acceptance rule.
+struct alignas(16) TriRecBox {
+    float v0x, v0y, v0z;
+    uint32_t prim;
+    float e1x, e1y, e1z, lox;
+    float e2x, e2y, e2z, loy;
+    float loz, hix, hiy, hiz;
+};
+static_assert(sizeof(TriRecBox) == 64, "TriRecBox must be 64 bytes");
+
 struct SceneView {
-    const BvhNode* nodes;
-    const TriRec* tris;
+    const void* nodes;       // BvhNode[], or CompactNode[] when compact
+    const void* tris;        // TriRec[], or TriRecBox[] when compact
     const uint8_t* mat;      // caller order
     const float* albedo;     // caller order
     const float* rough;      // caller order
@@ -39,6 +63,7 @@ struct SceneView {
     float root_lo[3], root_hi[3];
     uint32_t n_tris;
     uint32_t stack_depth;    // longest root-to-leaf path (edges), >= 1
+    uint32_t compact;        // 1: CompactNode / TriRecBox layout (more than 32,768 triangles)
 
     int32_t sensor;          // 0 pinhole, 1 confocal
     uint32_t width, height;
