@@ -7,7 +7,9 @@
 // Construction of BVHs, Octrees, and k-d Trees", HPG 2012), boxes are
 // refitted bottom-up with one atomic arrival counter per node, and the
 // result is laid out as 64-byte two-child nodes plus 48-byte triangles in
-// Morton order.  Every box is a union of padded triangle boxes, so a box
+// Morton order (scenes with more than 32,768 triangles: 32-byte nodes with
+// FP16 child boxes rounded outward, plus 64-byte triangles that carry their
+// padded boxes).  Every box is a union of padded triangle boxes, so a box
 // always contains the padded boxes of all triangles below it.
 #include <hip/hip_runtime.h>
 #include <hipcub/hipcub.hpp>

@@ -6,10 +6,12 @@
 // tile is written to HBM once, with coalesced stores, at the end: no film
 // zero-fill pass and no HBM atomics.  (When the deferred form splits a
 // tile's samples over several workgroups, the extra ones leave their partial
-// tiles in a scratch film that a second pass adds, still without atomics.)
-// The BVH traversal stack of each lane lives in LDS (stride = block size, so
-// a wave's pushes are contiguous), with 16-bit links when the scene is small
-// enough, 32-bit otherwise.
+// tiles in a scratch film that a second pass adds, still without atomics.
+// The path form on long films of large scenes is the exception: it adds
+// into the film in HBM.)  The BVH traversal stack of each lane lives in LDS
+// (stride = block size, so a wave's pushes are contiguous), with 16-bit
+// links when the scene is small enough, 32-bit otherwise (then, in the
+// HBM-film form, split between LDS and scratch).
 //
 // Path construction (arXiv 2510.25660, Sec. 3): paths are traced from the
 // sensor (pinhole camera, or the scan point on the relay wall for the
@@ -92,7 +94,8 @@ __device__ __forceinline__ bool intersect_tri(const Ray& r, const TriRec& tr, in
 // triangle records span a few MB) fetch them with buffer loads: a 32-bit
 // byte offset against a descriptor held in scalar registers, where a global
 // load needs a 64-bit address per lane (the 48-byte record stride costs a
-// quarter-rate 64-bit multiply).  Larger scenes use global loads.  The
+// quarter-rate 64-bit multiply).  Larger scenes use global loads (and the
+// compact layout).  The
 // descriptor has stride 0 (raw, byte-addressed), `bytes` as its range (a
 // load past it returns zeros instead of faulting) and 0x00020000 as its
 // fourth word, the value for untyped 32-bit access on gfx9-family GPUs
