@@ -76,6 +76,8 @@ struct trhip_scene {
     double* d_grad;  // backward workspace: 2 * n_tris doubles, or [2][n_tris][2] fixed-point words (4 * n_tris)
     // deferred form with sample chunks: partial films of chunks 1..
     float* d_chunk_scratch;
+    unsigned long long* d_fixed_film;  // deterministic HBM-film form (allocated on first use)
+    size_t fixed_film_words;
     size_t chunk_scratch_floats;
     // confocal: NLOS area-sampling tables, one set per scan region
     double* d_area_cdf;      // [region][n_tris] prefix sums of the weights (caller order)
@@ -121,6 +123,7 @@ void free_scene(trhip_scene* s)
     (void)hipFree(s->d_delay);
     (void)hipFree(s->d_grad);
     (void)hipFree(s->d_chunk_scratch);
+    (void)hipFree(s->d_fixed_film);
     (void)hipFree(s->d_area_cdf);
     (void)hipFree(s->d_area_invp);
     (void)hipFree(s->d_sorted_of);
@@ -439,7 +442,7 @@ trhip_status validate_render(const trhip_scene* s, const trhip_render_desc* r)
 }
 
 enum class Kind { Path, Wavefront, Deferred, Backward, BackwardPrimal, Tangent, PathFixed, BackwardFixed,
-                  BackwardPrimalFixed, PathHbm };
+                  BackwardPrimalFixed, PathHbm, PathFixedHbm };
 
 // stack: LDS bytes of one lane's traversal stack
 size_t lds_bytes(Kind kind, uint32_t tp, uint32_t T, uint32_t bs, uint32_t stack)
@@ -451,6 +454,9 @@ size_t lds_bytes(Kind kind, uint32_t tp, uint32_t T, uint32_t bs, uint32_t stack
     case Kind::Backward: return trhip::backward_lds_bytes(tp, T, bs, stack, false, false);
     case Kind::Tangent: return trhip::tangent_lds_bytes(tp, T, bs, stack);
     case Kind::PathFixed: return trhip::fixed_lds_bytes(tp, T, bs, stack);
+    // the HBM form needs only its stacks; the shape must also fit the LDS
+    // form, which renders instead when the scratch film cannot be allocated
+    case Kind::PathFixedHbm: return trhip::fixed_lds_bytes(tp, T, bs, stack);
     case Kind::PathHbm: return trhip::hbm_lds_bytes(bs, stack);
     case Kind::BackwardFixed: return trhip::backward_lds_bytes(tp, T, bs, stack, false, true);
     case Kind::BackwardPrimalFixed: return trhip::backward_lds_bytes(tp, T, bs, stack, true, true);
@@ -486,7 +492,9 @@ trhip_status choose_shape(const trhip_scene* s, const trhip_render_desc* r, Kind
     // Film in HBM on a scene too large for an XCD's L2: 64-lane workgroups
     // of one pixel (for >= 64 spp), whose tiles the 8 x 8 pixel-block order
     // keeps together (1M-triangle scene: +8.5 % over 256 lanes).
-    if (kind == Kind::PathHbm && !r->block_size && !r->tile_pixels && !trhip::short_stack(s->view.n_tris)) bs = 64;
+    if ((kind == Kind::PathHbm || kind == Kind::PathFixedHbm) && !r->block_size && !r->tile_pixels &&
+        !trhip::short_stack(s->view.n_tris))
+        bs = 64;
     if (!tp) {
         tp = tile_for(bs);
         // The path-per-lane kernel holds kPathWavesPerSimd waves per SIMD by
@@ -529,7 +537,7 @@ bool hbm_film(const trhip_scene* s) { return s->view.n_bins >= kHbmFilmBins && !
 // histogram: a time histogram (the phasor film keeps its tile film in LDS)
 Kind forward_kind(const trhip_scene* s, const trhip_render_desc* r, bool histogram = true)
 {
-    if (r->flags & TRHIP_FLAG_DETERMINISTIC) return Kind::PathFixed;
+    if (r->flags & TRHIP_FLAG_DETERMINISTIC) return histogram && hbm_film(s) ? Kind::PathFixedHbm : Kind::PathFixed;
     if (r->kernel == TRHIP_KERNEL_PATH || (r->kernel == TRHIP_KERNEL_AUTO && s->view.sensor != TRHIP_SENSOR_CONFOCAL))
         return histogram && hbm_film(s) ? Kind::PathHbm : Kind::Path;
     if (r->kernel == TRHIP_KERNEL_WAVEFRONT) return Kind::Wavefront;
@@ -567,6 +575,31 @@ hipError_t ensure_chunk_scratch(trhip_scene* sc, size_t floats, hipStream_t s, b
     return hipSuccess;
 }
 
+// Fixed-point film of the deterministic HBM-film form, grown on demand and
+// kept by the scene like the chunk scratch (nothing allocated under graph
+// capture: the LDS form then renders the same sums).
+hipError_t ensure_fixed_film(trhip_scene* sc, size_t words, hipStream_t s, bool* ready)
+{
+    *ready = false;
+    if (sc->fixed_film_words >= words) {
+        *ready = true;
+        return hipSuccess;
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cs);
+    if (e != hipSuccess || cs != hipStreamCaptureStatusNone) return e;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    (void)hipFree(sc->d_fixed_film);
+    sc->d_fixed_film = nullptr;
+    sc->fixed_film_words = 0;
+    e = hipMalloc(&sc->d_fixed_film, words * sizeof(unsigned long long));
+    if (e != hipSuccess) return e;
+    sc->fixed_film_words = words;
+    *ready = true;
+    return hipSuccess;
+}
+
 // floats of the chunk scratch: (chunks - 1) partial films, steady and oow
 size_t chunk_scratch_floats(const trhip::LaunchArgs& L, uint32_t chunks, uint32_t words)
 {
@@ -578,6 +611,15 @@ hipError_t launch_forward(trhip_scene* sc, Kind kind, trhip::LaunchArgs L, uint3
 {
     switch (kind) {
     case Kind::PathFixed: return trhip::launch_render_fixed(sc->view, L, block, stream);
+    case Kind::PathFixedHbm: {
+        bool ready = false;
+        const hipError_t e = ensure_fixed_film(sc, trhip::fixed_film_words(L.n_pixels, sc->view.n_bins), stream,
+                                               &ready);
+        if (e != hipSuccess) return e;
+        if (!ready) return trhip::launch_render_fixed(sc->view, L, block, stream);  // same sums, LDS form
+        L.fixed_film = sc->d_fixed_film;
+        return trhip::launch_render_fixed_hbm(sc->view, L, block, stream);
+    }
     case Kind::PathHbm: return trhip::launch_render_hbm(sc->view, L, block, stream, counts);
     case Kind::Wavefront: return trhip::launch_render_wavefront(sc->view, L, block, stream, counts);
     case Kind::Deferred: {
@@ -803,7 +845,8 @@ trhip_status trhip_render_transient_noalloc(trhip_scene* scene, const trhip_rend
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipSuccess;
     switch (kind) {
-    case Kind::PathFixed: e = trhip::launch_render_fixed(scene->view, L, block, s); break;
+    case Kind::PathFixed:
+    case Kind::PathFixedHbm: e = trhip::launch_render_fixed(scene->view, L, block, s); break;  // no scratch film
     case Kind::PathHbm: e = trhip::launch_render_hbm(scene->view, L, block, s, nullptr); break;
     case Kind::Wavefront: e = trhip::launch_render_wavefront(scene->view, L, block, s, nullptr); break;
     case Kind::Deferred: {

@@ -77,6 +77,9 @@ hipError_t launch_render_hbm(const SceneView& S, const LaunchArgs& L, uint32_t b
 size_t fixed_lds_bytes(uint32_t tile_pixels, uint32_t n_bins, uint32_t block, uint32_t stack_bytes);
 hipError_t launch_render_fixed(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream);
 // fixed-point sums (two 64-bit words each, as the deterministic kernels hold them) to FP32
+// deterministic forward with the film in HBM: 64-bit words of L.fixed_film
+size_t fixed_film_words(uint32_t n_pixels, uint32_t n_bins);
+hipError_t launch_render_fixed_hbm(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream);
 hipError_t launch_fixed_to_f32(const unsigned long long* src, float* dst, size_t n, hipStream_t stream);
 
 // counts: optional device uint64[7] receiving the work counters (node

@@ -1044,6 +1044,26 @@ struct FixedFilmSink {
     __device__ __forceinline__ void continuation(int, int, float, float) {}
 };
 
+// The HBM fixed-point film: film and out-of-window sums by 64-bit atomics,
+// the pixel's steady sum exact in a register pair (two's complement, the
+// carry taken by hand) until the lane moves to another pixel.
+struct FixedHbmSink {
+    static constexpr bool kWantsGradients = false;
+    unsigned long long* row;  // HBM fixed-point film row of the pixel, two words per bin
+    unsigned long long* oow;  // two words
+    unsigned long long steady_lo, steady_hi;
+    __device__ __forceinline__ void contribution(int, int, float c, int bin, float, float, float)
+    {
+        const Fixed128 f = to_fixed((double)c);
+        if (bin >= 0) fixed_add(row + 2 * bin, f);
+        else fixed_add(oow, f);
+        const unsigned long long lo = steady_lo + f.lo;
+        steady_hi += f.hi + (lo < steady_lo ? 1ull : 0ull);
+        steady_lo = lo;
+    }
+    __device__ __forceinline__ void continuation(int, int, float, float) {}
+};
+
 // Deterministic form of render_tile (path per lane): the tile's film,
 // steady and out-of-window sums in fixed point in LDS ([TP][T][2], [TP][2],
 // [TP][2] words), each written as sum / norm_spp rounded to FP32.
@@ -1086,6 +1106,43 @@ __device__ __forceinline__ void render_tile_fixed(const SceneView& S, const Laun
             L.oow[p] = acc ? L.oow[p] + v : v;
         }
     }
+}
+
+// Deterministic form with the film in HBM (long films of large scenes,
+// where a fixed-point LDS row of 16 bytes per bin would leave few waves per
+// CU): the fixed-point sums of the whole launch live in L.fixed_film
+// (zeroed beforehand), added to with 64-bit atomics, and a second pass
+// (k_fixed_film_out) rounds each once, as render_tile_fixed does.
+template <class St, class TallyT>
+__device__ __forceinline__ void render_tile_fixed_hbm(const SceneView& S, const LaunchArgs& L, uint32_t p0, St& stk,
+                                                      TallyT& tally)
+{
+    const uint32_t T = S.n_bins;
+    unsigned long long* qfilm = L.fixed_film;
+    unsigned long long* qsteady = qfilm + 2ull * L.n_pixels * T;
+    unsigned long long* qoow = qsteady + 2ull * L.n_pixels;
+    const uint32_t npix = min(L.tile_pixels, L.n_pixels - p0);
+    const uint32_t work = npix * L.spp;
+    uint32_t cur = 0xffffffffu;
+    FixedHbmSink sink{nullptr, nullptr, 0ull, 0ull};
+    auto flush = [&]() {
+        if (cur != 0xffffffffu) fixed_add(qsteady + 2 * ((size_t)p0 + cur), Fixed128{sink.steady_lo, sink.steady_hi});
+    };
+    for (uint32_t w = threadIdx.x; w < work; w += blockDim.x) {
+        const uint32_t pl = w / L.spp;
+        const uint32_t s = w - pl * L.spp;
+        const size_t p = (size_t)p0 + pl;
+        if (pl != cur) {
+            flush();
+            cur = pl;
+            sink.row = qfilm + 2 * p * T;
+            sink.oow = qoow + 2 * p;
+            sink.steady_lo = 0ull;
+            sink.steady_hi = 0ull;
+        }
+        trace_path(S, L, (uint32_t)p, L.sample_offset + s, stk, sink, tally);
+    }
+    flush();
 }
 
 // Renders one tile of pixels [p0, p0 + tile_pixels) with all their samples:
@@ -1634,6 +1691,50 @@ k_render_hbm_split(SceneView S, LaunchArgs L, unsigned long long* counts)
         (int)blockDim.x, deep};
     render_tile_hbm(S, L, tile_first_pixel(S, L, L.tile_pixels), stk, tally);
     tally.flush(counts);
+}
+
+// the deterministic HBM-film form: split stacks at eight waves per SIMD, or
+// whole stacks in LDS (deeper trees) at five, as k_render_hbm_split and
+// k_render_hbm
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8)))
+k_render_fixed_hbm_split(SceneView S, LaunchArgs L)
+{
+    Tally<kPlain> tally;
+    extern __shared__ float lds[];
+    int deep[kSplitStackDeep];
+    SplitStack<(int)kSplitStackLds, (int)kSplitStackDeep> stk{
+        (__attribute__((address_space(3))) uint32_t*)(reinterpret_cast<uint32_t*>(lds) + threadIdx.x),
+        (int)blockDim.x, deep};
+    render_tile_fixed_hbm(S, L, tile_first_pixel(S, L, L.tile_pixels), stk, tally);
+}
+
+template <class W>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+k_render_fixed_hbm(SceneView S, LaunchArgs L)
+{
+    Tally<kPlain> tally;
+    extern __shared__ float lds[];
+    LdsStack<W> stk{reinterpret_cast<W*>(lds) + threadIdx.x, (int)blockDim.x};
+    render_tile_fixed_hbm(S, L, tile_first_pixel(S, L, L.tile_pixels), stk, tally);
+}
+
+// each film, steady and oow sum of L.fixed_film / norm_spp, rounded to FP32
+// once, written (or added, when accumulating) to the outputs
+__global__ void k_fixed_film_out(LaunchArgs L, uint32_t T)
+{
+    const size_t nf = (size_t)L.n_pixels * T;
+    const size_t n = nf + 2ull * L.n_pixels;
+    const bool acc = (L.flags & kFlagAccumulate) != 0;
+    const double norm = (double)L.norm_spp;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        float* dst;
+        if (i < nf) dst = L.film + i;
+        else if (i < nf + L.n_pixels) dst = L.steady ? L.steady + (i - nf) : nullptr;
+        else dst = L.oow ? L.oow + (i - nf - L.n_pixels) : nullptr;
+        if (!dst) continue;
+        const float v = (float)(from_fixed(L.fixed_film[2 * i], L.fixed_film[2 * i + 1]) / norm);
+        *dst = acc ? *dst + v : v;
+    }
 }
 
 template <class W>
@@ -2580,6 +2681,25 @@ hipError_t launch_render_fixed(const SceneView& S, const LaunchArgs& L, uint32_t
         hipLaunchKernelGGL((k_render_fixed<uint16_t>), grid, dim3(block), lds, stream, S, L);
     else
         hipLaunchKernelGGL((k_render_fixed<uint32_t>), grid, dim3(block), lds, stream, S, L);
+    return hipGetLastError();
+}
+
+size_t fixed_film_words(uint32_t n_pixels, uint32_t n_bins) { return 2ull * ((size_t)n_pixels * n_bins + 2ull * n_pixels); }
+
+hipError_t launch_render_fixed_hbm(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream)
+{
+    launch_fill_zero(reinterpret_cast<float*>(L.fixed_film), 2 * fixed_film_words(L.n_pixels, S.n_bins), stream);
+    const dim3 grid(tiles_of(L));
+    const size_t lds = hbm_lds_bytes(block, hbm_stack_lane_bytes(S.n_tris, S.stack_depth));
+    if (short_stack(S.n_tris))
+        hipLaunchKernelGGL((k_render_fixed_hbm<uint16_t>), grid, dim3(block), lds, stream, S, L);
+    else if (split_stack(S.n_tris, S.stack_depth))
+        hipLaunchKernelGGL(k_render_fixed_hbm_split, grid, dim3(block), lds, stream, S, L);
+    else
+        hipLaunchKernelGGL((k_render_fixed_hbm<uint32_t>), grid, dim3(block), lds, stream, S, L);
+    const size_t n = (size_t)L.n_pixels * S.n_bins + 2ull * L.n_pixels;
+    const unsigned g = (unsigned)std::min<size_t>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL(k_fixed_film_out, dim3(g), dim3(256), 0, stream, L, S.n_bins);
     return hipGetLastError();
 }
 

@@ -146,6 +146,9 @@ struct LaunchArgs {
     double* g_alb;
     double* g_rough;
     unsigned long long* g_fixed;  // deterministic backward: fixed-point sums [2][n_tris][2] (else NULL)
+    // deterministic forward with the film in HBM: fixed-point film, steady
+    // and oow of the launch, [n_pixels][n_bins][2], [n_pixels][2], [n_pixels][2]
+    unsigned long long* fixed_film;
     float* primal;
     const float* tan_albedo;    // forward mode: direction of the albedo (caller order), may be NULL
     const float* tan_rough;     // forward mode: direction of the roughness, may be NULL

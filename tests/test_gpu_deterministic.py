@@ -193,3 +193,31 @@ def test_deterministic_rejected_elsewhere(tr):
                      lambda: tr.render_transient_counted(dev, deterministic=True)):
             with pytest.raises(tr.TrhipError):
                 call()
+
+
+def test_hbm_film_form_equals_lds_form(tr):
+    """Long films of large scenes (the 1M-triangle fog scene, 1,024 bins)
+    keep the deterministic fixed-point sums in a film in HBM; the
+    allocation-free entry renders the same sums in the LDS tile form.  Exact
+    sums rounded once do not depend on the form: the two must agree bit for
+    bit (film, steady, out-of-window)."""
+    import ctypes as C
+    import torch
+    from paper_2510_25660_amd._binding import check, lib
+    sc = scenes.large_scene(spp=8)
+    _announce("deterministic large: HBM fixed-point film against the LDS form")
+    outs = []
+    with tr.upload(sc) as dev:
+        r = tr.make_render_desc(dev, deterministic=True)
+        stream = torch.cuda.current_stream().cuda_stream
+        for fn in (lib().trhip_render_transient, lib().trhip_render_transient_noalloc):
+            film = torch.full((sc.n_pixels, sc.n_bins), float("nan"), device="cuda", dtype=torch.float32)
+            steady = torch.full((sc.n_pixels,), float("nan"), device="cuda", dtype=torch.float32)
+            oow = torch.full((sc.n_pixels,), float("nan"), device="cuda", dtype=torch.float32)
+            check(fn(dev.handle, C.byref(r), film.data_ptr(), steady.data_ptr(), oow.data_ptr(), stream))
+            torch.cuda.synchronize()
+            outs.append([film.cpu().numpy(), steady.cpu().numpy(), oow.cpu().numpy()])
+    (fa, sa, oa), (fb, sb, ob) = outs
+    assert np.isfinite(fa).all() and fa.sum() > 0
+    for a, b, what in ((fa, fb, "film"), (sa, sb, "steady"), (oa, ob, "oow")):
+        assert np.array_equal(_bits(a), _bits(b)), f"{what} differs between the HBM and LDS forms"
