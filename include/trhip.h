@@ -76,12 +76,19 @@ enum {
  * magnitude >= 2^-41 (smaller ones are truncated to multiples of 2^-64),
  * divided by N and rounded: it differs from an FP64 sum in path order only
  * by that sum's own rounding.  Values and sums must stay below 2^63 in
- * magnitude.  Accepted by trhip_render_transient (the path form runs; a
- * render->kernel other than AUTO or PATH is UNSUPPORTED) and
+ * magnitude.  Accepted by trhip_render_transient and
+ * trhip_render_transient_noalloc (the path form runs; a render->kernel
+ * other than AUTO or PATH is UNSUPPORTED) and
  * trhip_render_transient_backward (gradients; primal_film is not covered);
- * the other entry points return UNSUPPORTED.  About 2x the LDS of the
- * default film per pixel of a tile, so the automatic shape takes fewer
- * pixels per workgroup.
+ * the other entry points return UNSUPPORTED.  The fixed-point tile film
+ * takes about 2x the LDS of the default film per pixel, so the automatic
+ * shape takes fewer pixels per workgroup; where the path form keeps the
+ * film in HBM (more than 32,768 triangles and 512 bins or more),
+ * trhip_render_transient instead keeps the fixed-point sums of the whole
+ * launch in a buffer of 16 bytes per bin that the scene allocates on first
+ * use and keeps (not while the stream is being captured, and never in
+ * trhip_render_transient_noalloc: those render the LDS form, with the same
+ * result bit for bit).
  */
 
 /*
