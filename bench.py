@@ -313,6 +313,14 @@ def measure_single(tr, name, args, shape, extras):
                                       args.warmup)
                 forms[form] = round(paths / (ms / args.steps * 1e-3) / 1e6, 3)
             out["kernel_forms_mpaths_per_s"] = forms
+        if extras and not args.no_deterministic:
+            # TRHIP_FLAG_DETERMINISTIC on the same workload (fixed-point sums,
+            # bit-reproducible): a few renders
+            n_det = max(2, args.steps // 4)
+            ms, _ = time_launches(lambda: tr.render_transient(dev, film=film, steady=steady, deterministic=True),
+                                  n_det, 1)
+            out["deterministic"] = {"ms_per_step": round(ms / n_det, 4),
+                                    "mpaths_per_s": round(paths / (ms / n_det * 1e-3) / 1e6, 3)}
         if extras and args.phasor_freqs and sc.sensor == 1:
             # the same paths into a phasor film (Sec. 4.3) instead of the histogram
             freqs = list(np.linspace(0.5, 16.6, args.phasor_freqs))
@@ -426,6 +434,7 @@ def main():
     ap.add_argument("--phasor-freqs", type=int, default=16,
                     help="also time the frequency-space film with this many frequencies (0: skip)")
     ap.add_argument("--no-nlos-area", action="store_true", help="skip the NLOS area-sampling measurement")
+    ap.add_argument("--no-deterministic", action="store_true", help="skip the deterministic-sums measurement")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run a device copy of this many MiB (reference kernel for HBM byte counters)")
     args = ap.parse_args()
