@@ -226,3 +226,25 @@ def test_records_large_whole_lds_stacks(tr, oracle_mod, monkeypatch):
         a, b = a.cpu().numpy(), b.cpu().numpy()
     assert np.count_nonzero(a) > 0
     np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6 * float(np.abs(b).max()))
+
+
+@pytest.mark.parametrize("scale", [1e-5, 1e5])
+def test_records_compact_layout_extreme_scales(tr, oracle_mod, scale):
+    """The compact layout (scenes above 32,768 triangles) stores child boxes
+    as FP16 rounded outward.  Scaled by 1e5, coordinates pass FP16's largest
+    finite value (boxes become infinite); scaled by 1e-5, layers 1e-10 apart
+    share their FP16 bounds.  Traversal gets slower, the result must not
+    change: contributions identical to the oracle's."""
+    import dataclasses
+    base = scenes.layered_scene(n_layers=16385, spp=2)
+    k = np.float32(scale)
+    sc = dataclasses.replace(
+        base, vertices=(base.vertices * k).astype(np.float32),
+        cam_origin=tuple(float(np.float32(v) * k) for v in base.cam_origin),
+        light_pos=tuple(float(np.float32(v) * k) for v in base.light_pos),
+        bin_start=float(np.float32(base.bin_start) * k), bin_width=float(np.float32(base.bin_width) * k))
+    _announce(f"records compact layout at scale {scale}: {sc.n_tris} tris")
+    name = f"layers_scaled_{scale}"
+    _SCENES[name] = sc
+    g, o, _ = _run(tr, oracle_mod, name, _pixels(sc.n_pixels, 24, 11), "path")
+    compare_records(g, o, what=f"layers x{scale:g}")
