@@ -50,6 +50,7 @@ def _scene(name):
             "confocal": lambda: scenes.confocal_nlos(),
             "large": lambda: scenes.large_scene(),
             "layers": lambda: scenes.layered_scene(),
+            "confocal_big": lambda: scenes.confocal_nlos(grid=16, n_tris=40000, spp=512),
             "glass": lambda: scenes.glass_box_scene(delay_mean=0.05, width=24, height=24),
             "fog_small": lambda: scenes.large_scene(cells=24, sphere_freq=4, grid=3, width=40, height=30,
                                                     n_bins=256, bin_width=0.02, spp=8),
@@ -142,6 +143,16 @@ def test_records_confocal_area_sampling(tr, oracle_mod, kernel):
     """Confocal NLOS at full size with NLOS area sampling, 8 scan points."""
     g, o, sc = _run(tr, oracle_mod, "confocal", _pixels(64 * 64, 8, 3), kernel, nlos_area=True)
     compare_records(g, o, what=f"confocal area sampling {kernel}")
+
+
+@pytest.mark.parametrize("kernel", ["path", "deferred"])
+def test_records_area_sampling_compact_layout(tr, oracle_mod, kernel):
+    """NLOS area sampling on a 40,000-triangle blob (32-bit links, compact
+    layout: the sampled triangle is read from the 64-byte records through
+    the caller-to-BVH-order map), cosine sampling too, 8 scan points."""
+    for area in (True, False):
+        g, o, sc = _run(tr, oracle_mod, "confocal_big", _pixels(16 * 16, 8, 12), kernel, nlos_area=area)
+        compare_records(g, o, what=f"confocal 40k tris {kernel} area={area}")
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
