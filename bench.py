@@ -74,14 +74,11 @@ def active_lanes(counts):
             for k, w in (("nodes", "nodes"), ("tris", "tris"), ("vertices", "vertices"))}
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch of the render kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, or None when there is none or the kernel
-    sources changed after the counters were taken."""
+def profile_fields(name):
+    """The `key: value` lines of a committed rocprofv3 summary in profiles/,
+    or None when there is none or the kernel sources changed after the
+    counters were taken."""
     import hashlib
-    name = WORKLOADS[workload].get("traffic")
-    if not name:
-        return None
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -91,7 +88,36 @@ def measured_traffic(workload):
     fields = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line)
     if fields.get("kernel_sources_sha1", "").strip() != h.hexdigest():
         return None
-    return int(float(fields["traffic_bytes_per_launch"]))
+    return fields
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the render kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (None when stale or absent)."""
+    name = WORKLOADS[workload].get("traffic")
+    fields = profile_fields(name) if name else None
+    return int(float(fields["traffic_bytes_per_launch"])) if fields else None
+
+
+def measured_issue(workload):
+    """VALU issue of the render kernel from the committed SQ and memory-pipe
+    summaries: the fraction of SIMD cycles issuing a VALU instruction
+    (4 cycles per wave64 instruction on a 16-lane SIMD, 1,024 SIMDs,
+    GRBM_GUI_ACTIVE / 8 cycles per XCD) and the fraction of lanes active in
+    them; None when stale or absent."""
+    name = WORKLOADS[workload].get("traffic")
+    if not name:
+        return None
+    sq = profile_fields(name.replace("_hbm_traffic.txt", "_sq_counters.txt"))
+    mem = profile_fields(name.replace("_hbm_traffic.txt", "_memory_pipe.txt"))
+    if not sq or not mem:
+        return None
+    num = lambda f, k: float(f[k].split()[0])
+    active = num(sq, "SQ_ACTIVE_INST_VALU")
+    cycles = num(mem, "GRBM_GUI_ACTIVE") / 8
+    return {"valu_issue_frac": round(4 * active / (1024 * cycles), 3),
+            "active_lane_frac": round(num(sq, "SQ_THREAD_CYCLES_VALU") / (64 * active), 3),
+            "source": "profiles/ (rocprofv3 SQ and GRBM counters of the same kernel sources)"}
 
 
 def make_scene(name):
@@ -365,6 +391,9 @@ def measure_single(tr, name, args, shape, extras):
            "scene_upload_and_bvh_build_ms": round(upload_ms, 2),
            "roofline": roofline_of(counts, launch_ms, kernel_name, measured_traffic(name),
                                    algorithmic_bytes(sc, info))}
+    issue = measured_issue(name)
+    if issue:
+        res["roofline"]["issue"] = issue
     res.update(out)
     return res, sc
 
