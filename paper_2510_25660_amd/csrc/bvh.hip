@@ -317,8 +317,10 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n)
 // neighbours on each side in the current order, the one whose union box has
 // the smallest surface area; mutual nearest neighbours merge into a new
 // internal node; survivors are compacted in order; repeat until one cluster.
+// A radius of 6 against 16: 6.6 % fewer node visits on a confocal scan
+// (+3.5 %), 1.3 % fewer on a 1M-triangle scene (+0.8 %).
 // ---------------------------------------------------------------------------
-constexpr int kPlocRadius = 16;
+constexpr int kPlocRadius = 6;
 
 __device__ __forceinline__ float half_area(float lx, float ly, float lz, float hx, float hy, float hz)
 {
