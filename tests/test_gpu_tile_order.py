@@ -1,9 +1,11 @@
 """Tile order of camera images in scenes larger than an XCD's L2 (more than
-32,768 triangles): one-pixel tiles walk the image in 8 x 8 pixel blocks.
-A 16 x 16 image of a box cluttered with 40,000 triangles at 64 spp takes
-that order in every per-pixel kernel; each result must still land on its
-own pixel: the film (path-per-lane and wavefront forms), the forward-mode
-derivative and the adjoint, against the oracle."""
+32,768 triangles): one-pixel tiles walk the image in 16 x 16 pixel blocks
+(8 x 8 when its sides are multiples of 8 but not of 16).  Images of a box
+cluttered with 40,000 triangles at 64 spp (16 x 16 and 48 x 32: one and six
+16 x 16 blocks; 24 x 16: 8 x 8 blocks) take that order in every per-pixel
+kernel; each result must still land on its own pixel: the film
+(path-per-lane and wavefront forms), the forward-mode derivative and the
+adjoint, against the oracle."""
 import sys
 
 import numpy as np
@@ -20,12 +22,13 @@ def _announce(msg):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def setup(oracle_mod):
+@pytest.fixture(scope="module", params=[(16, 16), (24, 16), (48, 32)], ids=["16x16", "24x16", "48x32"])
+def setup(oracle_mod, request):
     import torch
     assert torch.cuda.is_available(), "GPU test needs an MI355X"
     import paper_2510_25660_amd as tr
-    sc = scenes.cluttered_box(40000, width=16, height=16, spp=64)
+    w, h = request.param
+    sc = scenes.cluttered_box(40000, width=w, height=h, spp=64)
     return tr, sc, oracle_mod.Oracle(sc)
 
 
