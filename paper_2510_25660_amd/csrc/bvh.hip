@@ -239,10 +239,10 @@ __global__ void k_layout_compact(int n, const int32_t* __restrict__ child, const
     child_box(c1, tri_box, ids, node_box, l1, h1);
     CompactNode nd;
     for (int a = 0; a < 3; ++a) {
-        nd.box[a] = half_down(l0[a]);
-        nd.box[3 + a] = half_up(h0[a]);
-        nd.box[6 + a] = half_down(l1[a]);
-        nd.box[9 + a] = half_up(h1[a]);
+        nd.box[2 * a] = half_down(l0[a]);
+        nd.box[2 * a + 1] = half_up(h0[a]);
+        nd.box[6 + 2 * a] = half_down(l1[a]);
+        nd.box[6 + 2 * a + 1] = half_up(h1[a]);
     }
     nd.child0 = c0;
     nd.child1 = c1;

@@ -38,6 +38,7 @@ namespace {
 
 struct Ray {
     vec3 o, d, inv, oi;
+    uint32_t rx, ry, rz;  // 16 where the direction's component is negative, else 0
 };
 
 __device__ __forceinline__ float guard(float x) { return (fabsf(x) < 1e-30f) ? copysignf(1e-30f, x) : x; }
@@ -49,6 +50,9 @@ __device__ __forceinline__ Ray make_ray(vec3 o, vec3 d)
     r.d = d;
     r.inv = v3(1.0f / guard(d.x), 1.0f / guard(d.y), 1.0f / guard(d.z));
     r.oi = v3(o.x * r.inv.x, o.y * r.inv.y, o.z * r.inv.z);
+    r.rx = (r.inv.x < 0.0f) ? 16u : 0u;
+    r.ry = (r.inv.y < 0.0f) ? 16u : 0u;
+    r.rz = (r.inv.z < 0.0f) ? 16u : 0u;
     return r;
 }
 
@@ -140,36 +144,51 @@ __device__ __forceinline__ TriRec leaf_tri(const SceneView& S, int j, vec3& lo, 
     }
 }
 
-// the node n, child boxes in a, b, d (lo0 hi0 lo1 hi1, xyz each); links in l.x, l.y
-struct NodeRec {
-    float4 a, b, d, l;
-};
-
 __device__ __forceinline__ float half_lo(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu)); }
 __device__ __forceinline__ float half_hi(uint32_t w) { return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16)); }
 
-// kBuf: the 64-byte BvhNode by buffer loads; otherwise the 32-byte
-// CompactNode, whose FP16 bounds convert to FP32 exactly
-template <bool kBuf>
-__device__ __forceinline__ NodeRec load_node(const SceneView& S, int n)
+// Entry and exit of a CompactNode child box whose axes are the (lo, hi) FP16
+// pairs wx, wy, wz.  Rotating a pair by 16 bits where the ray's direction is
+// negative puts that axis's entry plane in the low half: a correctly rounded
+// fma is monotone in its first argument, so the planes come out already
+// ordered, the same values the min/max of the two planes give (slab), with
+// no ordering instructions.
+__device__ __forceinline__ void slab_h(const Ray& r, uint32_t wx, uint32_t wy, uint32_t wz, float& tn, float& tf)
 {
-    NodeRec v;
+    wx = __builtin_rotateright32(wx, r.rx);
+    wy = __builtin_rotateright32(wy, r.ry);
+    wz = __builtin_rotateright32(wz, r.rz);
+    const float nx = fmaf(half_lo(wx), r.inv.x, -r.oi.x), fx = fmaf(half_hi(wx), r.inv.x, -r.oi.x);
+    const float ny = fmaf(half_lo(wy), r.inv.y, -r.oi.y), fy = fmaf(half_hi(wy), r.inv.y, -r.oi.y);
+    const float nz = fmaf(half_lo(wz), r.inv.z, -r.oi.z), fz = fmaf(half_hi(wz), r.inv.z, -r.oi.z);
+    tn = fmaxf(fmaxf(nx, ny), nz);
+    tf = fminf(fminf(fx, fy), fz);
+}
+
+// The internal node n: entry and exit of both child boxes, and the links.
+// kBuf: the 64-byte BvhNode by buffer loads; otherwise the 32-byte
+// CompactNode.
+template <bool kBuf>
+__device__ __forceinline__ void node_boxes(const SceneView& S, const Ray& r, int n, float& tn0, float& tf0,
+                                           float& tn1, float& tf1, int& c0, int& c1)
+{
     if constexpr (kBuf) {
         const __amdgpu_buffer_rsrc_t R = buffer_of(S.nodes, S.n_tris * 64u);
         const uint32_t off = (uint32_t)n << 6;
-        v.a = buffer_f4(R, off);
-        v.b = buffer_f4(R, off + 16u);
-        v.d = buffer_f4(R, off + 32u);
-        v.l = buffer_f4(R, off + 48u);
+        const float4 a = buffer_f4(R, off), b = buffer_f4(R, off + 16u), d = buffer_f4(R, off + 32u),
+                     l = buffer_f4(R, off + 48u);
+        slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tn0, tf0);
+        slab(r, b.z, b.w, d.x, d.y, d.z, d.w, tn1, tf1);
+        c0 = __float_as_int(l.x);
+        c1 = __float_as_int(l.y);
     } else {
         const uint4* q = reinterpret_cast<const uint4*>(S.nodes) + 2 * (size_t)n;
         const uint4 q0 = q[0], q1 = q[1];
-        v.a = make_float4(half_lo(q0.x), half_hi(q0.x), half_lo(q0.y), half_hi(q0.y));
-        v.b = make_float4(half_lo(q0.z), half_hi(q0.z), half_lo(q0.w), half_hi(q0.w));
-        v.d = make_float4(half_lo(q1.x), half_hi(q1.x), half_lo(q1.y), half_hi(q1.y));
-        v.l = make_float4(__uint_as_float(q1.z), __uint_as_float(q1.w), 0.0f, 0.0f);
+        slab_h(r, q0.x, q0.y, q0.z, tn0, tf0);
+        slab_h(r, q0.w, q1.x, q1.y, tn1, tf1);
+        c0 = (int)q1.z;
+        c1 = (int)q1.w;
     }
-    return v;
 }
 
 // a hit triangle's record (v0, edges, caller index), either layout
@@ -257,16 +276,17 @@ __device__ __forceinline__ int link_of(uint32_t w) { return (int)w; }
 __device__ __forceinline__ int link_of(uint16_t w) { return (int)(int16_t)w; }
 
 // A lane's traversal stack: one BVH link per level, word i at p[i * stride]
-// in LDS.  16-bit words also select buffer loads for nodes and triangles
-// (their offsets fit in 32 bits).
+// in LDS (a 24-bit product: a full-rate multiply, where a 32-bit one takes
+// four passes).  16-bit words also select buffer loads for nodes and
+// triangles (their offsets fit in 32 bits).
 template <class W>
 struct LdsStack {
     static constexpr bool kBuf = sizeof(W) == 2;
     W* p;
     int stride;
     __device__ __forceinline__ int cap(const SceneView& S) const { return (int)S.stack_depth; }
-    __device__ __forceinline__ void put(int sp, int link) { p[sp * stride] = (W)link; }
-    __device__ __forceinline__ int get(int sp) const { return link_of(p[sp * stride]); }
+    __device__ __forceinline__ void put(int sp, int link) { p[__umul24((uint32_t)sp, (uint32_t)stride)] = (W)link; }
+    __device__ __forceinline__ int get(int sp) const { return link_of(p[__umul24((uint32_t)sp, (uint32_t)stride)]); }
 };
 
 // The first kLds words in LDS, the deeper ones in a per-lane array in
@@ -287,11 +307,14 @@ struct SplitStack {
     __device__ __forceinline__ void put(int sp, int link)
     {
         if (sp < kLds)
-            p[sp * stride] = (uint32_t)link;
+            p[__umul24((uint32_t)sp, (uint32_t)stride)] = (uint32_t)link;
         else
             deep[sp - kLds] = link;
     }
-    __device__ __forceinline__ int get(int sp) const { return sp < kLds ? (int)p[sp * stride] : deep[sp - kLds]; }
+    __device__ __forceinline__ int get(int sp) const
+    {
+        return sp < kLds ? (int)p[__umul24((uint32_t)sp, (uint32_t)stride)] : deep[sp - kLds];
+    }
 };
 
 // Closest accepted triangle: smallest t, then smallest caller index.  A
@@ -362,12 +385,9 @@ __device__ __forceinline__ bool closest_step(const SceneView& S, const Ray& r, i
     tally.add(kTallyNodes);
     tally.wave(kTallyWaveNodes);
     constexpr bool kBuf = St::kBuf;
-    const NodeRec nd = load_node<kBuf>(S, c.node);
-    const float4 a = nd.a, b = nd.b, d = nd.d, l = nd.l;
-    const int c0 = __float_as_int(l.x), c1 = __float_as_int(l.y);
     float tn0, tf0, tn1, tf1;
-    slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tn0, tf0);
-    slab(r, b.z, b.w, d.x, d.y, d.z, d.w, tn1, tf1);
+    int c0, c1;
+    node_boxes<kBuf>(S, r, c.node, tn0, tf0, tn1, tf1, c0, c1);
     bool h0 = tn0 <= tf0 && tf0 >= 0.0f && tn0 <= c.h.t;
     bool h1 = tn1 <= tf1 && tf1 >= 0.0f && tn1 <= c.h.t;
     if (h0 && c0 < 0) {
@@ -439,12 +459,9 @@ __device__ bool occluded(const SceneView& S, const Ray& r, int exclude, float tm
     constexpr bool kBuf = St::kBuf;
     const int max_sp = stk.cap(S);
     for (uint32_t visits = 0; visits < S.n_tris; ++visits) {
-        const NodeRec nd = load_node<kBuf>(S, node);
-        const float4 a = nd.a, b = nd.b, c = nd.d, l = nd.l;
-        const int c0 = __float_as_int(l.x), c1 = __float_as_int(l.y);
         float tn0, tf0, tn1, tf1;
-        slab(r, a.x, a.y, a.z, a.w, b.x, b.y, tn0, tf0);
-        slab(r, b.z, b.w, c.x, c.y, c.z, c.w, tn1, tf1);
+        int c0, c1;
+        node_boxes<kBuf>(S, r, node, tn0, tf0, tn1, tf1, c0, c1);
         tally.add(kTallyNodes);
         tally.wave(kTallyWaveNodes);
         bool h0 = tn0 <= tf0 && tf0 >= 0.0f && tn0 <= tmax;

@@ -32,8 +32,8 @@ static_assert(sizeof(TriRec) == 48, "TriRec must be 48 bytes");
 // layout, so that a node visit issues two 16-byte loads instead of four.
 // CompactNode, 32 bytes: both children's boxes as FP16 bit patterns rounded
 // outward (lo down, hi up: each contains the FP32 box it stands for) in the
-// order lo0x lo0y lo0z hi0x hi0y hi0z lo1x lo1y lo1z hi1x hi1y hi1z, then
-// the two links.  Traversal only: a leaf's FP16 box contains its padded
+// order lo0x hi0x lo0y hi0y lo0z hi0z lo1x hi1x lo1y hi1y lo1z hi1z (one
+// 32-bit word per child and axis, lo in its low half), then the two links.  Traversal only: a leaf's FP16 box contains its padded
 // box, so every triangle the padded box admits is still reached.
 struct alignas(16) CompactNode {
     uint16_t box[12];
