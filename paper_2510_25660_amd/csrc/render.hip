@@ -1069,16 +1069,44 @@ struct FixedFilmSink {
 // The HBM fixed-point film: film and out-of-window sums by 64-bit atomics,
 // the pixel's steady sum exact in a register pair (two's complement, the
 // carry taken by hand) until the lane moves to another pixel.
+// The HBM form's sums: four 64-bit words per sum, word k adding up the
+// 32-bit limbs k of the 128-bit values, so that every atomic is a plain add
+// whose old value no lane waits for (the LDS form's carry needs it).  The
+// value of one FP32 contribution has at most 24 significant bits and so
+// touches at most two limbs (four if negative).  The words stay exact for
+// fewer than 2^32 adds per sum, and the sum is the value of the words
+// below, modulo 2^128: the same integer as the two-word form's.
+constexpr uint32_t kLimbWords = 4;
+
+__device__ __forceinline__ void limb_add(unsigned long long* cell, Fixed128 f)
+{
+    const uint64_t l0 = f.lo & 0xffffffffull, l1 = f.lo >> 32, l2 = f.hi & 0xffffffffull, l3 = f.hi >> 32;
+    if (l0) atomicAdd(cell, (unsigned long long)l0);
+    if (l1) atomicAdd(cell + 1, (unsigned long long)l1);
+    if (l2) atomicAdd(cell + 2, (unsigned long long)l2);
+    if (l3) atomicAdd(cell + 3, (unsigned long long)l3);
+}
+
+// w0 + w1 2^32 + w2 2^64 + w3 2^96 modulo 2^128
+__device__ __forceinline__ Fixed128 limb_value(uint64_t w0, uint64_t w1, uint64_t w2, uint64_t w3)
+{
+    Fixed128 f;
+    const uint64_t t = w1 << 32;
+    f.lo = w0 + t;
+    f.hi = (f.lo < t ? 1ull : 0ull) + (w1 >> 32) + w2 + (w3 << 32);
+    return f;
+}
+
 struct FixedHbmSink {
     static constexpr bool kWantsGradients = false;
-    unsigned long long* row;  // HBM fixed-point film row of the pixel, two words per bin
-    unsigned long long* oow;  // two words
+    unsigned long long* row;  // HBM fixed-point film row of the pixel, kLimbWords words per bin
+    unsigned long long* oow;  // kLimbWords words
     unsigned long long steady_lo, steady_hi;
     __device__ __forceinline__ void contribution(int, int, float c, int bin, float, float, float)
     {
         const Fixed128 f = to_fixed((double)c);
-        if (bin >= 0) fixed_add(row + 2 * bin, f);
-        else fixed_add(oow, f);
+        if (bin >= 0) limb_add(row + kLimbWords * bin, f);
+        else limb_add(oow, f);
         const unsigned long long lo = steady_lo + f.lo;
         steady_hi += f.hi + (lo < steady_lo ? 1ull : 0ull);
         steady_lo = lo;
@@ -1133,22 +1161,24 @@ __device__ __forceinline__ void render_tile_fixed(const SceneView& S, const Laun
 // Deterministic form with the film in HBM (long films of large scenes,
 // where a fixed-point LDS row of 16 bytes per bin would leave few waves per
 // CU): the fixed-point sums of the whole launch live in L.fixed_film
-// (zeroed beforehand), added to with 64-bit atomics, and a second pass
-// (k_fixed_film_out) rounds each once, as render_tile_fixed does.
+// (zeroed beforehand) as limb words (limb_add), and a second pass
+// (k_fixed_film_out) rounds each once, as render_tile_fixed does.  For
+// spp * max_depth < 2^32 (the adds one sum can receive).
 template <class St, class TallyT>
 __device__ __forceinline__ void render_tile_fixed_hbm(const SceneView& S, const LaunchArgs& L, uint32_t p0, St& stk,
                                                       TallyT& tally)
 {
     const uint32_t T = S.n_bins;
     unsigned long long* qfilm = L.fixed_film;
-    unsigned long long* qsteady = qfilm + 2ull * L.n_pixels * T;
-    unsigned long long* qoow = qsteady + 2ull * L.n_pixels;
+    unsigned long long* qsteady = qfilm + (size_t)kLimbWords * L.n_pixels * T;
+    unsigned long long* qoow = qsteady + (size_t)kLimbWords * L.n_pixels;
     const uint32_t npix = min(L.tile_pixels, L.n_pixels - p0);
     const uint32_t work = npix * L.spp;
     uint32_t cur = 0xffffffffu;
     FixedHbmSink sink{nullptr, nullptr, 0ull, 0ull};
     auto flush = [&]() {
-        if (cur != 0xffffffffu) fixed_add(qsteady + 2 * ((size_t)p0 + cur), Fixed128{sink.steady_lo, sink.steady_hi});
+        if (cur != 0xffffffffu)
+            limb_add(qsteady + kLimbWords * ((size_t)p0 + cur), Fixed128{sink.steady_lo, sink.steady_hi});
     };
     for (uint32_t w = threadIdx.x; w < work; w += blockDim.x) {
         const uint32_t pl = w / L.spp;
@@ -1157,8 +1187,8 @@ __device__ __forceinline__ void render_tile_fixed_hbm(const SceneView& S, const 
         if (pl != cur) {
             flush();
             cur = pl;
-            sink.row = qfilm + 2 * p * T;
-            sink.oow = qoow + 2 * p;
+            sink.row = qfilm + kLimbWords * p * T;
+            sink.oow = qoow + kLimbWords * p;
             sink.steady_lo = 0ull;
             sink.steady_hi = 0ull;
         }
@@ -1760,7 +1790,10 @@ __global__ void k_fixed_film_out(LaunchArgs L, uint32_t T)
         else if (i < nf + L.n_pixels) dst = L.steady ? L.steady + (i - nf) : nullptr;
         else dst = L.oow ? L.oow + (i - nf - L.n_pixels) : nullptr;
         if (!dst) continue;
-        const float v = (float)(from_fixed(L.fixed_film[2 * i], L.fixed_film[2 * i + 1]) / norm);
+        const ulonglong2* w = reinterpret_cast<const ulonglong2*>(L.fixed_film + kLimbWords * i);
+        const ulonglong2 a = w[0], b = w[1];
+        const Fixed128 f = limb_value(a.x, a.y, b.x, b.y);
+        const float v = (float)(from_fixed(f.lo, f.hi) / norm);
         *dst = acc ? *dst + v : v;
     }
 }
@@ -2712,7 +2745,10 @@ hipError_t launch_render_fixed(const SceneView& S, const LaunchArgs& L, uint32_t
     return hipGetLastError();
 }
 
-size_t fixed_film_words(uint32_t n_pixels, uint32_t n_bins) { return 2ull * ((size_t)n_pixels * n_bins + 2ull * n_pixels); }
+size_t fixed_film_words(uint32_t n_pixels, uint32_t n_bins)
+{
+    return (size_t)kLimbWords * ((size_t)n_pixels * n_bins + 2ull * n_pixels);
+}
 
 hipError_t launch_render_fixed_hbm(const SceneView& S, const LaunchArgs& L, uint32_t block, hipStream_t stream)
 {
