@@ -195,17 +195,21 @@ def test_deterministic_rejected_elsewhere(tr):
                 call()
 
 
-def test_hbm_film_form_equals_lds_form(tr):
+@pytest.mark.parametrize("intensity", [1.0, 1e12, 1e-9])
+def test_hbm_film_form_equals_lds_form(tr, intensity):
     """Long films of large scenes (the 1M-triangle fog scene, 1,024 bins)
-    keep the deterministic fixed-point sums in a film in HBM; the
-    allocation-free entry renders the same sums in the LDS tile form.  Exact
-    sums rounded once do not depend on the form: the two must agree bit for
-    bit (film, steady, out-of-window)."""
+    keep the deterministic fixed-point sums in a film in HBM, as 32-bit
+    limb words; the allocation-free entry renders the same sums in the LDS
+    tile form (two words and a carry).  Exact sums rounded once do not
+    depend on the form: the two must agree bit for bit (film, steady,
+    out-of-window).  The light's intensity moves the contributions' bits
+    across every limb of the 128-bit sums."""
     import ctypes as C
+    import dataclasses
     import torch
     from paper_2510_25660_amd._binding import check, lib
-    sc = scenes.large_scene(spp=8)
-    _announce("deterministic large: HBM fixed-point film against the LDS form")
+    sc = dataclasses.replace(scenes.large_scene(spp=8), light_intensity=intensity)
+    _announce(f"deterministic large, intensity {intensity}: HBM fixed-point film against the LDS form")
     outs = []
     with tr.upload(sc) as dev:
         r = tr.make_render_desc(dev, deterministic=True)
