@@ -87,8 +87,9 @@ enum {
  * trhip_render_transient instead keeps the fixed-point sums of the whole
  * launch in a buffer of 32 bytes per bin that the scene allocates on first
  * use and keeps (not while the stream is being captured, not for spp *
- * max_depth >= 2^32, and never in trhip_render_transient_noalloc: those
- * render the LDS form, with the same result bit for bit).
+ * max_depth >= 2^32, not when the device cannot hold it, and never in
+ * trhip_render_transient_noalloc: those render the LDS form, with the same
+ * result bit for bit).
  */
 
 /*

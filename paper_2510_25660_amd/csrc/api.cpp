@@ -569,6 +569,11 @@ hipError_t ensure_chunk_scratch(trhip_scene* sc, size_t floats, hipStream_t s, b
     sc->d_chunk_scratch = nullptr;
     sc->chunk_scratch_floats = 0;
     e = hipMalloc(&sc->d_chunk_scratch, floats * sizeof(float));
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {  // one chunk per tile renders the same film
+        (void)hipGetLastError();
+        sc->d_chunk_scratch = nullptr;
+        return hipSuccess;
+    }
     if (e != hipSuccess) return e;
     sc->chunk_scratch_floats = floats;
     *ready = true;
@@ -594,6 +599,11 @@ hipError_t ensure_fixed_film(trhip_scene* sc, size_t words, hipStream_t s, bool*
     sc->d_fixed_film = nullptr;
     sc->fixed_film_words = 0;
     e = hipMalloc(&sc->d_fixed_film, words * sizeof(unsigned long long));
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {  // the LDS form renders the same sums
+        (void)hipGetLastError();
+        sc->d_fixed_film = nullptr;
+        return hipSuccess;
+    }
     if (e != hipSuccess) return e;
     sc->fixed_film_words = words;
     *ready = true;
