@@ -239,6 +239,28 @@ def test_records_large_whole_lds_stacks(tr, oracle_mod, monkeypatch):
     np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6 * float(np.abs(b).max()))
 
 
+@pytest.mark.parametrize("kernel", ["path", "deferred"])
+def test_records_compact_layout_axis_rays(tr, oracle_mod, kernel):
+    """The compact layout's node test orders each axis's two planes by the
+    sign of the ray's direction (the FP16 pair rotated where it is
+    negative).  Seen straight down the stacked layers through pixel
+    centres of an odd-sized image, the middle row and column cast rays with
+    a zero direction component, and the centre pixel a ray along the axis:
+    every contribution must still match the oracle's."""
+    import dataclasses
+    base = scenes.layered_scene(n_layers=16385, width=15, height=15, spp=2)
+    sc = dataclasses.replace(base, **scenes.look_at([0.0, 2.0, 0.0], [0.0, 0.0, 0.0], [0.0, 0.0, -1.0], 50.0,
+                                                      15, 15))
+    assert sc.cam_fwd == (0.0, -1.0, 0.0) and sc.cam_right == (1.0, 0.0, 0.0)
+    name = "layers_axis"
+    _SCENES[name] = sc
+    _announce(f"records compact layout, axis-aligned rays: {sc.n_tris} tris, {kernel}")
+    g, o, _ = _run(tr, oracle_mod, name, np.arange(sc.n_pixels, dtype=np.int64), kernel, pixel_centre=True)
+    centre = (sc.height // 2) * sc.width + sc.width // 2
+    assert np.count_nonzero(o["pixel"] == centre) > 0
+    compare_records(g, o, what=f"layers, axis-aligned rays ({kernel})")
+
+
 @pytest.mark.parametrize("scale", [1e-5, 1e5])
 def test_records_compact_layout_extreme_scales(tr, oracle_mod, scale):
     """The compact layout (scenes above 32,768 triangles) stores child boxes
