@@ -390,13 +390,18 @@ __device__ __forceinline__ bool closest_step(const SceneView& S, const Ray& r, i
     node_boxes<kBuf>(S, r, c.node, tn0, tf0, tn1, tf1, c0, c1);
     bool h0 = tn0 <= tf0 && tf0 >= 0.0f && tn0 <= c.h.t;
     bool h1 = tn1 <= tf1 && tf1 >= 0.0f && tn1 <= c.h.t;
-    if (h0 && c0 < 0) {
-        leaf_closest<kBuf>(S, r, ~c0, tn0, exclude, c.h, tally);
-        h0 = false;
-    }
-    if (h1 && c1 < 0) {
-        leaf_closest<kBuf>(S, r, ~c1, tn1, exclude, c.h, tally);
-        h1 = false;
+    // Leaf children: each lane tests its first pending leaf, then its
+    // second, so that lanes whose leaves hang in different children share
+    // one pass of the test instead of taking one each.  The closest hit
+    // does not depend on the order of the tests.
+    bool l0 = h0 && c0 < 0, l1 = h1 && c1 < 0;
+    h0 = h0 && c0 >= 0;
+    h1 = h1 && c1 >= 0;
+    while (l0 || l1) {
+        const bool first = l0;
+        leaf_closest<kBuf>(S, r, first ? ~c0 : ~c1, first ? tn0 : tn1, exclude, c.h, tally);
+        l1 = l1 && first;  // the second leaf stays pending only after the first
+        l0 = false;
     }
     h0 = h0 && tn0 <= c.h.t;
     h1 = h1 && tn1 <= c.h.t;
@@ -466,13 +471,16 @@ __device__ bool occluded(const SceneView& S, const Ray& r, int exclude, float tm
         tally.wave(kTallyWaveNodes);
         bool h0 = tn0 <= tf0 && tf0 >= 0.0f && tn0 <= tmax;
         bool h1 = tn1 <= tf1 && tf1 >= 0.0f && tn1 <= tmax;
-        if (h0 && c0 < 0) {
-            if (leaf_blocks<kBuf>(S, r, ~c0, tn0, exclude, tmax, tally)) return true;
-            h0 = false;
-        }
-        if (h1 && c1 < 0) {
-            if (leaf_blocks<kBuf>(S, r, ~c1, tn1, exclude, tmax, tally)) return true;
-            h1 = false;
+        // leaf children, one pass per pending leaf shared by the wave's
+        // lanes (as in closest_step)
+        bool l0 = h0 && c0 < 0, l1 = h1 && c1 < 0;
+        h0 = h0 && c0 >= 0;
+        h1 = h1 && c1 >= 0;
+        while (l0 || l1) {
+            const bool first = l0;
+            if (leaf_blocks<kBuf>(S, r, first ? ~c0 : ~c1, first ? tn0 : tn1, exclude, tmax, tally)) return true;
+            l1 = l1 && first;
+            l0 = false;
         }
         if (h0 && h1 && sp < max_sp) {
             // large scenes (compact layout): the nearer child first
