@@ -911,23 +911,21 @@ __device__ void continue_path(const SceneView& S, const LaunchArgs& L, uint32_t 
         Nee nee;
         Cont cont;
         shade_vertex<Sink::kWantsGradients>(S, L, pix, sample, ps, h, t_hit, med, nee, cont, tally);
+        // A path drawn by NLOS area sampling continues from its hidden vertex
+        // only if the first segment is unoccluded: the shadow test back to
+        // the scan point runs along it, so a lane needs that test for its
+        // contribution, its continuation or both.  One call serves both, so
+        // the lanes of a wave share one traversal.
+        const bool area_first = v == 1 && (L.flags & kFlagNlosArea) && cont.alive;
         bool blocked = true;
-        if (nee.valid) {
-            blocked = occluded(S, make_ray(nee.so, nee.sd), nee.excl, nee.tmax, stk, tally);
-            if (!blocked) {
-                tally.add(kTallyContrib);
-                tally.record(L, pix, sample, v, nee.k, nee.c, nee.bin, nee.tof);
-                sink.contribution(v, nee.k, nee.c, nee.bin, nee.tof, nee.g_alb, nee.g_rough);
-            }
+        if (nee.valid || area_first) blocked = occluded(S, make_ray(nee.so, nee.sd), nee.excl, nee.tmax, stk, tally);
+        if (nee.valid && !blocked) {
+            tally.add(kTallyContrib);
+            tally.record(L, pix, sample, v, nee.k, nee.c, nee.bin, nee.tof);
+            sink.contribution(v, nee.k, nee.c, nee.bin, nee.tof, nee.g_alb, nee.g_rough);
         }
         if (!cont.alive) break;
-        // a path drawn by NLOS area sampling continues from its hidden vertex
-        // only if the first segment is unoccluded: the shadow test back to
-        // the scan point runs along it
-        if (v == 1 && (L.flags & kFlagNlosArea)) {
-            if (!nee.valid) blocked = occluded(S, make_ray(nee.so, nee.sd), nee.excl, nee.tmax, stk, tally);
-            if (blocked) break;
-        }
+        if (area_first && blocked) break;
         if (cont.k >= 0) sink.continuation(v, cont.k, cont.g_alb, cont.g_rough);
         if (ps.v > vmax) break;
         h = closest_hit(S, make_ray(ps.o, ps.d), ps.prev, stk, tally);
