@@ -85,9 +85,9 @@ enum {
  * shape takes fewer pixels per workgroup; where the path form keeps the
  * film in HBM (more than 32,768 triangles and 512 bins or more),
  * trhip_render_transient instead keeps the fixed-point sums of the whole
- * launch in a buffer of 32 bytes per bin that the scene allocates on first
+ * launch in a buffer of 24 bytes per bin that the scene allocates on first
  * use and keeps (not while the stream is being captured, not for spp *
- * max_depth >= 2^32, not when the device cannot hold it, and never in
+ * max_depth >= 2^21, not when the device cannot hold it, and never in
  * trhip_render_transient_noalloc: those render the LDS form, with the same
  * result bit for bit).
  */

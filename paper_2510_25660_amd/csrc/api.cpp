@@ -622,8 +622,8 @@ hipError_t launch_forward(trhip_scene* sc, Kind kind, trhip::LaunchArgs L, uint3
     switch (kind) {
     case Kind::PathFixed: return trhip::launch_render_fixed(sc->view, L, block, stream);
     case Kind::PathFixedHbm: {
-        // the HBM form's limb words stay exact for fewer than 2^32 adds per sum
-        if ((uint64_t)L.spp * L.max_depth >= (1ull << 32)) return trhip::launch_render_fixed(sc->view, L, block, stream);
+        // the HBM form's limb words stay exact for fewer than 2^21 adds per sum
+        if ((uint64_t)L.spp * L.max_depth >= (1ull << 21)) return trhip::launch_render_fixed(sc->view, L, block, stream);
         bool ready = false;
         const hipError_t e = ensure_fixed_film(sc, trhip::fixed_film_words(L.n_pixels, sc->view.n_bins), stream,
                                                &ready);

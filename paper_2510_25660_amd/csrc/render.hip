@@ -1075,31 +1075,34 @@ struct FixedFilmSink {
 // The HBM fixed-point film: film and out-of-window sums by 64-bit atomics,
 // the pixel's steady sum exact in a register pair (two's complement, the
 // carry taken by hand) until the lane moves to another pixel.
-// The HBM form's sums: four 64-bit words per sum, word k adding up the
-// 32-bit limbs k of the 128-bit values, so that every atomic is a plain add
-// whose old value no lane waits for (the LDS form's carry needs it).  The
-// value of one FP32 contribution has at most 24 significant bits and so
-// touches at most two limbs (four if negative).  The words stay exact for
-// fewer than 2^32 adds per sum, and the sum is the value of the words
-// below, modulo 2^128: the same integer as the two-word form's.
-constexpr uint32_t kLimbWords = 4;
+// The HBM form's sums: three 64-bit words per sum, word k adding up the
+// 43-bit limbs k (bits 43k and up) of the 128-bit values, so that every
+// atomic is a plain add whose old value no lane waits for (the LDS form's
+// carry needs it).  The value of one FP32 contribution has at most 24
+// significant bits and so touches at most two limbs (three if negative).
+// The words stay exact for fewer than 2^21 adds per sum, and the sum is the
+// value of the words below, modulo 2^128: the same integer as the two-word
+// form's.
+constexpr uint32_t kLimbWords = 3;
+constexpr uint64_t kLimbMask = (1ull << 43) - 1ull;
 
 __device__ __forceinline__ void limb_add(unsigned long long* cell, Fixed128 f)
 {
-    const uint64_t l0 = f.lo & 0xffffffffull, l1 = f.lo >> 32, l2 = f.hi & 0xffffffffull, l3 = f.hi >> 32;
+    const uint64_t l0 = f.lo & kLimbMask;
+    const uint64_t l1 = (f.lo >> 43) | ((f.hi & ((1ull << 22) - 1ull)) << 21);
+    const uint64_t l2 = f.hi >> 22;
     if (l0) atomicAdd(cell, (unsigned long long)l0);
     if (l1) atomicAdd(cell + 1, (unsigned long long)l1);
     if (l2) atomicAdd(cell + 2, (unsigned long long)l2);
-    if (l3) atomicAdd(cell + 3, (unsigned long long)l3);
 }
 
-// w0 + w1 2^32 + w2 2^64 + w3 2^96 modulo 2^128
-__device__ __forceinline__ Fixed128 limb_value(uint64_t w0, uint64_t w1, uint64_t w2, uint64_t w3)
+// w0 + w1 2^43 + w2 2^86 modulo 2^128
+__device__ __forceinline__ Fixed128 limb_value(uint64_t w0, uint64_t w1, uint64_t w2)
 {
     Fixed128 f;
-    const uint64_t t = w1 << 32;
+    const uint64_t t = w1 << 43;
     f.lo = w0 + t;
-    f.hi = (f.lo < t ? 1ull : 0ull) + (w1 >> 32) + w2 + (w3 << 32);
+    f.hi = (f.lo < t ? 1ull : 0ull) + (w1 >> 21) + (w2 << 22);
     return f;
 }
 
@@ -1169,7 +1172,7 @@ __device__ __forceinline__ void render_tile_fixed(const SceneView& S, const Laun
 // CU): the fixed-point sums of the whole launch live in L.fixed_film
 // (zeroed beforehand) as limb words (limb_add), and a second pass
 // (k_fixed_film_out) rounds each once, as render_tile_fixed does.  For
-// spp * max_depth < 2^32 (the adds one sum can receive).
+// spp * max_depth < 2^21 (the adds one sum can receive).
 template <class St, class TallyT>
 __device__ __forceinline__ void render_tile_fixed_hbm(const SceneView& S, const LaunchArgs& L, uint32_t p0, St& stk,
                                                       TallyT& tally)
@@ -1796,9 +1799,8 @@ __global__ void k_fixed_film_out(LaunchArgs L, uint32_t T)
         else if (i < nf + L.n_pixels) dst = L.steady ? L.steady + (i - nf) : nullptr;
         else dst = L.oow ? L.oow + (i - nf - L.n_pixels) : nullptr;
         if (!dst) continue;
-        const ulonglong2* w = reinterpret_cast<const ulonglong2*>(L.fixed_film + kLimbWords * i);
-        const ulonglong2 a = w[0], b = w[1];
-        const Fixed128 f = limb_value(a.x, a.y, b.x, b.y);
+        const unsigned long long* w = L.fixed_film + kLimbWords * i;
+        const Fixed128 f = limb_value(w[0], w[1], w[2]);
         const float v = (float)(from_fixed(f.lo, f.hi) / norm);
         *dst = acc ? *dst + v : v;
     }

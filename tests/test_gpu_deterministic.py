@@ -198,7 +198,7 @@ def test_deterministic_rejected_elsewhere(tr):
 @pytest.mark.parametrize("intensity", [1.0, 1e12, 1e-9])
 def test_hbm_film_form_equals_lds_form(tr, intensity):
     """Long films of large scenes (the 1M-triangle fog scene, 1,024 bins)
-    keep the deterministic fixed-point sums in a film in HBM, as 32-bit
+    keep the deterministic fixed-point sums in a film in HBM, as 43-bit
     limb words; the allocation-free entry renders the same sums in the LDS
     tile form (two words and a carry).  Exact sums rounded once do not
     depend on the form: the two must agree bit for bit (film, steady,
